@@ -1,0 +1,171 @@
+/*
+ * mg.h -- C ABI of the MI355X geometric-multigrid library (libmg.so).
+ *
+ * Solves A x = b for the discrete Poisson-type operators of J. T. Wallis,
+ * "Methods toward better Multigrid Solver Convergence" (KAIST, 2008), with the
+ * recursive multigrid algorithm MG(l, u, g) of its section "The Multigrid
+ * Technique" run as the F-cycle named in its Abstract:
+ *   - the 5-point finite-difference operator -(eps_x u_xx + eps_y u_yy)
+ *     (Abstract: Poisson problem; section "Anisotropies": -alpha u_xx - beta u_yy);
+ *   - the 9-point bilinear (Q1) operator -div(diag(kx, ky) grad u) with
+ *     per-cell coefficients, as produced by mapping a curved domain such as a
+ *     polar annulus to the unit square (Introduction, "Some Typical Problems";
+ *     section "Different coordinate systems");
+ *   - smoothers x <- x - omega C^{-1} (A x - b) (section "Smoothers") with
+ *     C = D (damped Jacobi) or C = D + L (Gauss-Seidel, section "The choice
+ *     of C") in red-black (5-point) or four-colour (9-point) order;
+ *   - full-weighting restriction, bilinear prolongation, correction weight
+ *     omega_l = 1 and an exact (Cholesky) solve on the coarsest grid.
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments named x, rhs, r, u, lam, kx, ky, dL_dk are HIP DEVICE
+ *     pointers owned by the caller.  The library never frees them and never
+ *     keeps them beyond the call (coefficients are copied at setup).
+ *   - Node arrays are row-major [ny][nx], x fastest, no padding, FP64.  They
+ *     hold every stored node, including Dirichlet boundary nodes.  A
+ *     Dirichlet boundary node is not an unknown: its value is taken as zero,
+ *     rhs entries there are ignored, and mg_solve writes zero there.
+ *   - Cell arrays are row-major [ncy][ncx] with ncx = nx - 1 cells along x
+ *     and ncy = ny - 1 (Dirichlet y) or ny (periodic y) cells along y; cell
+ *     (ci, cj) has the nodes (ci..ci+1, cj..cj+1), the y index wrapping when
+ *     y is periodic.
+ *   - Every argument check happens before any device work.  A negative status
+ *     means the call did nothing (x untouched); mg_last_error() then holds a
+ *     message.  A positive status is a numerical outcome and x holds the last
+ *     iterate.
+ *   - Work is ordered on the stream given in mg_options.stream (NULL = the
+ *     null stream); mg_solve and mg_residual synchronise that stream once
+ *     before returning.  A handle must not be used by two threads at once.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_handle_s* mg_handle;
+
+typedef enum {
+  MG_OK = 0,              /* converged: ||b - A x|| <= tol * ||b - A x0|| */
+  MG_NOT_CONVERGED = 1,   /* max_cycles reached; x = last iterate */
+  MG_DIVERGED = 2,        /* residual non-finite or > 1e6 * initial; x = last iterate */
+  MG_EINVAL = -1,         /* invalid argument; nothing done */
+  MG_ENOMEM = -2,         /* device allocation failed */
+  MG_EDEVICE = -3,        /* a HIP call failed */
+  MG_EUNSUPPORTED = -4    /* valid but unsupported combination (see mg_last_error) */
+} mg_status;
+
+enum { MG_COEF_CONST5 = 0, MG_COEF_CELL9 = 1 };
+enum { MG_CYCLE_F = 0, MG_CYCLE_V = 1 };
+enum { MG_SMOOTH_JACOBI = 0, MG_SMOOTH_RBGS = 1, MG_SMOOTH_GS4C = 2 };
+enum { MG_PREC_FP64 = 0, MG_PREC_MIXED = 1 };
+
+/* Grid: stored node counts and domain lengths.  A Dirichlet direction has
+ * n = 2^k m + 1 nodes (h = l / (n - 1)); the periodic direction has n = 2^k m
+ * nodes (h = l / n).  Only y may be periodic (periodic_x must be 0). */
+typedef struct {
+  int32_t nx, ny;
+  int32_t periodic_x, periodic_y;
+  double lx, ly;
+} mg_grid;
+
+/* Operator.
+ * MG_COEF_CONST5: 5-point FD for -(eps_x u_xx + eps_y u_yy); kx, ky unused.
+ * MG_COEF_CELL9 : Q1 FEM for -div(diag(kx, ky) grad u), divided by hx*hy
+ *   ("FD scaling", so b is the nodal value of f when f is lumped).  kx, ky are
+ *   device cell arrays; ky may equal kx.  With kx_1d_along_x = 1 they hold
+ *   ncx values (coefficients that vary along x only, e.g. the polar annulus),
+ *   else ncy*ncx values.  Coarse 9-point operators are Galerkin R A P. */
+typedef struct {
+  int32_t kind;
+  double eps_x, eps_y;
+  const double* kx;
+  const double* ky;
+  int32_t kx_1d_along_x;
+} mg_coeffs;
+
+/* Options.  nu_pre, nu_post in [0, 8].  omega: Jacobi damping (Gauss-Seidel
+ * uses omega = 1).  precision MG_PREC_MIXED runs every cycle in FP32 inside an
+ * FP64 defect-correction loop (x, rhs stay FP64 at the boundary).
+ * coarse_cta_nodes: levels with at most this many stored nodes run inside one
+ * persistent workgroup (0 = library default).  stream: hipStream_t. */
+typedef struct {
+  int32_t cycle;
+  int32_t smoother;
+  int32_t nu_pre, nu_post;
+  double omega;
+  int32_t precision;
+  int32_t coarse_cta_nodes;
+  void* stream;
+} mg_options;
+
+/* Solve report.  history (nullable, host) receives the residual norms
+ * ||b - A x_k||, k = 0..cycles; it must hold max_cycles + 1 doubles. */
+typedef struct {
+  int32_t cycles;
+  double res0, res, rel_res;
+  double rho_last, rho_mean;   /* last and geometric-mean convergence factor */
+  double seconds;              /* device time of the solve (hipEvents) */
+  double* history;
+} mg_info;
+
+/* Build the level hierarchy (shapes, operators, coarsest Cholesky factor) and
+ * allocate the level buffers.  levels = 0 coarsens until a Dirichlet
+ * direction has 3 nodes or the periodic one 4; levels > 0 asks for exactly
+ * that many levels (MG_EINVAL if the grid cannot provide them).  Multigrid
+ * algorithm, "The Multigrid Technique": A_l for every level l. */
+mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, int32_t levels,
+                   const mg_options* opts, mg_handle* out);
+
+/* Cycle from x (in: start vector x0, out: solution) until
+ * ||b - A x_k||_2 <= tol * ||b - A x_0||_2 over the unknowns, max_cycles is
+ * reached or the iteration diverges.  tol > 0, max_cycles >= 1.  rhs and x
+ * are FP64 device arrays [ny][nx].  info may be NULL. */
+mg_status mg_solve(mg_handle h, const double* rhs, double* x, double tol, int32_t max_cycles,
+                   mg_info* info);
+
+/* r = rhs - A x on the finest level (r nullable: device array [ny][nx], zero at
+ * Dirichlet boundary nodes) and *norm2 = ||r||_2 over the unknowns (host). */
+mg_status mg_residual(mg_handle h, const double* rhs, const double* x, double* r, double* norm2);
+
+/* Adjoint gradient for MG_COEF_CELL9 problems: dL_dk[c] = -lam_e^T K_c u_e per
+ * cell, where K_c = dA/dk_c is the cell's element matrix for a unit
+ * coefficient in both directions (kx = ky = k), u the solution of A u = b and
+ * lam the solution of A lam = dL/du (A is symmetric).  u, lam: device node
+ * arrays [ny][nx]; dL_dk: device cell array [ncy][ncx]. */
+mg_status mg_coeff_grad(mg_handle h, const double* u, const double* lam, double* dL_dk);
+
+/* Batched: nprob independent 5-point problems (MG_COEF_CONST5 only) with
+ * their own grids (square or not, all coarsening to the same coarsest shape)
+ * and their own eps_x, eps_y.  grids, coeffs: host arrays of nprob entries.
+ * One sequence of launches serves every problem; converged problems are masked. */
+mg_status mg_setup_batched(const mg_grid* grids, const mg_coeffs* coeffs, int32_t nprob,
+                           const mg_options* opts, mg_handle* out);
+
+/* rhs, x: host arrays of nprob device pointers.  info: host array of nprob
+ * entries or NULL.  Returns MG_OK if every problem converged, else the largest
+ * positive status among the problems. */
+mg_status mg_solve_batched(mg_handle h, const double* const* rhs, double* const* x, double tol,
+                           int32_t max_cycles, mg_info* info);
+
+/* Frees everything the handle owns (never caller memory).  NULL is accepted. */
+mg_status mg_destroy(mg_handle h);
+
+const char* mg_status_string(mg_status s);
+
+/* Message of the last failed call on this handle (or of the last failed
+ * mg_setup* on this thread when h is NULL). */
+const char* mg_last_error(mg_handle h);
+
+/* Number of levels and the stored shape of level l (0 = finest). */
+mg_status mg_level_shape(mg_handle h, int32_t l, int32_t* nx, int32_t* ny);
+int32_t mg_num_levels(mg_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG_H */

@@ -1,0 +1,59 @@
+// Host-visible launchers of the multigrid kernels (mg_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mg_device.h"
+
+namespace mg {
+
+constexpr int MAX_COARSE_UNKNOWNS = 1024;  // coarsest grid solved by a dense Cholesky factor
+constexpr int SUB_NT = 1024;               // threads of the single-workgroup coarse-level kernel
+constexpr int MAX_NORM_BLOCKS = 1024;      // workgroups of a residual-norm reduction
+constexpr double DIVERGENCE_FACTOR = 1.0e6;
+
+enum NormMode { NORM_INIT = 0, NORM_CHECK = 1, NORM_RESID = 2 };
+
+// Stored shape of a level plus its number of rows that carry unknowns.
+struct LevelShape {
+  int nx, ny, py, nrows;
+};
+
+template <typename T>
+hipError_t launch_colour(const Level<T>* Ls, const LevelShape& s, int c, int ncol, int nslots, hipStream_t st);
+template <typename T>
+hipError_t launch_jacobi(const Level<T>* Ls, const LevelShape& s, int dir, T omega, int nslots, hipStream_t st);
+template <typename T>
+hipError_t launch_copy(const Level<T>* Ls, const LevelShape& s, int nslots, hipStream_t st);
+template <typename T>
+hipError_t launch_dr(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& c, int nslots, hipStream_t st);
+template <typename T>
+hipError_t launch_prolong(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& f, int nslots, hipStream_t st);
+template <typename T>
+hipError_t launch_coarse(const Level<T>* Ls, const double* const* chol, int n, int nslots, hipStream_t st);
+template <typename T>
+hipError_t launch_subcycle(const Level<T>* levs, int nlev, const DOp* prog, const int* beg, const int* cnt,
+                           const double* const* chol, int ncu, T omega, int ncol, int nslots, hipStream_t st);
+template <typename T>
+hipError_t launch_resnorm(const Level<T>* Ls, const LevelShape& s, int mode, T* rout, float* r32, int p32, int nslots,
+                          hipStream_t st);
+
+int norm_blocks(const LevelShape& s);
+
+hipError_t launch_outer_update(const Level<double>* L64, const Level<float>* L32, const LevelShape& s, int nslots,
+                               hipStream_t st);
+hipError_t launch_zero_boundary(double* x, int nx, int ny, int pitch, int py, hipStream_t st);
+hipError_t launch_q1_bands(double* band, int bstride, int bpitch, int nrows, int nx, int ny, int py, const double* kx,
+                           const double* ky, int kpitch, double hx, double hy, hipStream_t st);
+hipError_t launch_rap(double* cband, int cbstride, int cbpitch, int cnrows, int ncx, int ncy, const double* fband,
+                      int fbstride, int fbpitch, int nxf, int nyf, int py, hipStream_t st);
+hipError_t launch_dense_coarse(double* A, int n, int nx, int ny, int py, int kind, double cx, double cy, double dg,
+                               const double* band, int bstride, int bpitch, hipStream_t st);
+hipError_t launch_cholesky(double* A, int n, int* info, hipStream_t st);
+hipError_t launch_count_bad(const double* v, long n, int* count, hipStream_t st);
+hipError_t launch_count_nonfinite(const double* v, int nx, int ny, int pitch, int py, int* count, hipStream_t st);
+hipError_t launch_to_float(const double* s, float* d, long n, hipStream_t st);
+hipError_t launch_coeff_grad(const double* u, const double* lam, double* g, int nx, int ny, int py, double hx,
+                             double hy, hipStream_t st);
+
+}  // namespace mg

@@ -1,0 +1,727 @@
+// HIP kernels of the multigrid cycle for gfx950 (CDNA4, wave64).
+//
+// Launch convention: blockIdx.z selects the problem slot; `Ls` points at the
+// level descriptor of that slot for the level the op acts on (Ls[slot]).  A
+// kernel returns at once when its problem's solve is finished (st->done),
+// which lets the host queue many cycles without waiting for the stopping test.
+#include "mg_kernels.h"
+
+namespace mg {
+
+constexpr int NT = 256;  // threads per workgroup of the per-op kernels
+
+// --------------------------------------------------------------------------- node sets
+
+// Nodes of colour c (ncol = 2: (i + j) mod 2 == c; ncol = 4: i mod 2 == c & 1 and
+// j mod 2 == c >> 1) are enumerated as (row r, slot k) with nk slots per row.
+template <typename T>
+struct ColourSet {
+  int nk, nrows, j0, jstep;
+  __device__ ColourSet(const Level<T>& L, int c, int ncol) {
+    nk = (L.nx - 1) / 2 + 1;
+    const int lo = row_lo(L), hi = row_hi(L);
+    if (ncol == 2) {
+      j0 = lo;
+      jstep = 1;
+      nrows = hi - lo + 1;
+    } else {
+      const int par = c >> 1;
+      j0 = lo + ((lo & 1) != par ? 1 : 0);
+      jstep = 2;
+      nrows = j0 > hi ? 0 : (hi - j0) / 2 + 1;
+    }
+  }
+  __device__ int count() const { return nk * nrows; }
+  // returns false when the slot falls outside [1, nx - 2]
+  __device__ bool node(const Level<T>& L, int c, int ncol, int idx, int& i, int& j) const {
+    const int r = idx / nk;
+    const int k = idx - r * nk;
+    j = j0 + r * jstep;
+    const int par = ncol == 2 ? ((c + j) & 1) : (c & 1);
+    i = 2 * k + par;
+    return i >= 1 && i <= L.nx - 2;
+  }
+};
+
+// --------------------------------------------------------------------------- op bodies
+// Each body processes the op's nodes idx = tid, tid + nth, ...
+
+template <typename T>
+__device__ void body_colour(const Level<T>& L, int c, int ncol, int tid, int nth) {
+  ColourSet<T> S(L, c, ncol);
+  const int n = S.count();
+  for (int idx = tid; idx < n; idx += nth) {
+    int i, j;
+    if (!S.node(L, c, ncol, idx, i, j)) continue;
+    const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
+    L.x[(size_t)j * L.pitch + i] = gs_value(L, L.x, L.b, i, j, jm, jp);
+  }
+}
+
+template <typename T>
+__device__ void body_jacobi(const Level<T>& L, int dir, T omega, int tid, int nth) {
+  const T* src = dir == 0 ? L.x : L.t;
+  T* dst = dir == 0 ? L.t : L.x;
+  const int lo = row_lo(L), nr = row_hi(L) - lo + 1, ni = L.nx - 2;
+  const int n = nr * ni;
+  for (int idx = tid; idx < n; idx += nth) {
+    const int r = idx / ni;
+    const int i = idx - r * ni + 1;
+    const int j = lo + r;
+    const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
+    dst[(size_t)j * L.pitch + i] = jacobi_value(L, src, L.b, i, j, jm, jp, omega);
+  }
+}
+
+template <typename T>
+__device__ void body_copy(const Level<T>& L, int tid, int nth) {
+  const int lo = row_lo(L), nr = row_hi(L) - lo + 1, ni = L.nx - 2;
+  const int n = nr * ni;
+  for (int idx = tid; idx < n; idx += nth) {
+    const int r = idx / ni;
+    const size_t p = (size_t)(lo + r) * L.pitch + (idx - r * ni + 1);
+    L.x[p] = L.t[p];
+  }
+}
+
+template <typename T>
+__device__ void body_dr(const Level<T>& F, const Level<T>& C, int tid, int nth) {
+  const int lo = row_lo(C), nr = row_hi(C) - lo + 1, ni = C.nx - 2;
+  const int n = nr * ni;
+  for (int idx = tid; idx < n; idx += nth) {
+    const int r = idx / ni;
+    const int I = idx - r * ni + 1;
+    const int J = lo + r;
+    const size_t p = (size_t)J * C.pitch + I;
+    C.b[p] = restrict_defect(F, F.x, F.b, I, J);
+    C.x[p] = (T)0;
+  }
+}
+
+template <typename T>
+__device__ void body_prolong(const Level<T>& F, const Level<T>& C, int tid, int nth) {
+  const int lo = row_lo(F), nr = row_hi(F) - lo + 1, ni = F.nx - 2;
+  const int n = nr * ni;
+  for (int idx = tid; idx < n; idx += nth) {
+    const int r = idx / ni;
+    const int i = idx - r * ni + 1;
+    const int j = lo + r;
+    F.x[(size_t)j * F.pitch + i] += prolong_value(C.x, C.pitch, C.ny, C.py, i, j);
+  }
+}
+
+// Exact solve with the Cholesky factor Lc (n x n, row-major, lower) of the
+// coarsest operator, unknowns numbered row by row.  One workgroup; `g` is
+// LDS scratch of n doubles.
+template <typename T>
+__device__ void body_coarse(const Level<T>& L, const double* __restrict__ Lc, int n, double* g, int tid, int nth) {
+  const int lo = row_lo(L), ni = L.nx - 2;
+  for (int k = tid; k < n; k += nth) {
+    const int r = k / ni;
+    g[k] = (double)L.b[(size_t)(lo + r) * L.pitch + (k - r * ni + 1)];
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {  // forward: L y = g
+    if (tid == 0) g[k] = g[k] / Lc[(size_t)k * n + k];
+    __syncthreads();
+    const double gk = g[k];
+    for (int r = k + 1 + tid; r < n; r += nth) g[r] -= Lc[(size_t)r * n + k] * gk;
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {  // backward: L^T x = y
+    if (tid == 0) g[k] = g[k] / Lc[(size_t)k * n + k];
+    __syncthreads();
+    const double gk = g[k];
+    for (int r = tid; r < k; r += nth) g[r] -= Lc[(size_t)k * n + r] * gk;
+    __syncthreads();
+  }
+  for (int k = tid; k < n; k += nth) {
+    const int r = k / ni;
+    L.x[(size_t)(lo + r) * L.pitch + (k - r * ni + 1)] = (T)g[k];
+  }
+}
+
+// --------------------------------------------------------------------------- per-op kernels
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_colour(const Level<T>* __restrict__ Ls, int c, int ncol) {
+  const Level<T> L = Ls[blockIdx.z];
+  if (L.st->done) return;
+  body_colour(L, c, ncol, blockIdx.x * NT + threadIdx.x, gridDim.x * NT);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_jacobi(const Level<T>* __restrict__ Ls, int dir, T omega) {
+  const Level<T> L = Ls[blockIdx.z];
+  if (L.st->done) return;
+  body_jacobi(L, dir, omega, blockIdx.x * NT + threadIdx.x, gridDim.x * NT);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_copy(const Level<T>* __restrict__ Ls) {
+  const Level<T> L = Ls[blockIdx.z];
+  if (L.st->done) return;
+  body_copy(L, blockIdx.x * NT + threadIdx.x, gridDim.x * NT);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_dr(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs) {
+  const Level<T> F = Fs[blockIdx.z];
+  if (F.st->done) return;
+  const Level<T> C = Cs[blockIdx.z];
+  body_dr(F, C, blockIdx.x * NT + threadIdx.x, gridDim.x * NT);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_prolong(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs) {
+  const Level<T> F = Fs[blockIdx.z];
+  if (F.st->done) return;
+  const Level<T> C = Cs[blockIdx.z];
+  body_prolong(F, C, blockIdx.x * NT + threadIdx.x, gridDim.x * NT);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_coarse(const Level<T>* __restrict__ Ls, const double* const* __restrict__ chol,
+                                               int n) {
+  __shared__ double g[MAX_COARSE_UNKNOWNS];
+  const Level<T> L = Ls[blockIdx.z];
+  if (L.st->done) return;
+  body_coarse(L, chol[blockIdx.z], n, g, threadIdx.x, NT);
+}
+
+// Single-workgroup interpreter: runs ops [beg[slot], beg[slot] + cnt[slot]) of
+// `prog` on the level array of its slot (levs + slot * nlev), one barrier
+// between ops.  Used for every level small enough that a launch per op would
+// cost more than the op itself.
+template <typename T>
+__global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict__ levs, int nlev,
+                                                     const DOp* __restrict__ prog, const int* __restrict__ beg,
+                                                     const int* __restrict__ cnt, const double* const* __restrict__ chol,
+                                                     int ncu, T omega, int ncol) {
+  __shared__ double g[MAX_COARSE_UNKNOWNS];
+  const int slot = blockIdx.z;
+  const Level<T>* Ls = levs + (size_t)slot * nlev;
+  if (Ls[0].st->done) return;
+  const int b0 = beg[slot], nops = cnt[slot];
+  const int tid = threadIdx.x;
+  for (int k = 0; k < nops; ++k) {
+    const DOp op = prog[b0 + k];
+    const Level<T> L = Ls[op.level];
+    switch (op.type) {
+      case OP_COLOR: body_colour(L, op.arg, ncol, tid, SUB_NT); break;
+      case OP_JACOBI: body_jacobi(L, op.arg, omega, tid, SUB_NT); break;
+      case OP_COPY: body_copy(L, tid, SUB_NT); break;
+      case OP_DR: body_dr(L, Ls[op.level + 1], tid, SUB_NT); break;
+      case OP_PROLONG: body_prolong(L, Ls[op.level + 1], tid, SUB_NT); break;
+      case OP_COARSE: body_coarse(L, chol[slot], ncu, g, tid, SUB_NT); break;
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------------------- residual norm
+
+// Workgroup sum of v (fixed tree order); result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
+  }
+  __syncthreads();
+  return s;
+}
+
+// Finishes a norm reduction: the last workgroup to arrive sums the partials
+// in index order and applies the stopping test.
+__device__ void finish_norm(SolveState* st, double part, int nblocks, int mode) {
+  __shared__ int is_last;
+  if (threadIdx.x == 0) {
+    st->partial[blockIdx.x] = part;
+    __threadfence();
+    const unsigned prev = atomicAdd(&st->counter, 1u);
+    is_last = (prev == (unsigned)nblocks - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    volatile double* pp = st->partial;
+    for (int k = 0; k < nblocks; ++k) s += pp[k];
+    const double nrm = sqrt(s);
+    st->counter = 0u;
+    st->prev = st->last;
+    st->last = nrm;
+    if (mode == NORM_INIT) {
+      st->r0 = nrm;
+      st->cycles = 0;
+      if (st->hist_cap > 0) st->history[0] = nrm;
+      st->done = (nrm == 0.0) ? 1 : 0;
+    } else if (mode == NORM_CHECK) {
+      const int c = st->cycles + 1;
+      st->cycles = c;
+      if (c < st->hist_cap) st->history[c] = nrm;
+      if (nrm <= st->tol * st->r0)
+        st->done = 1;
+      else if (!(nrm <= DIVERGENCE_FACTOR * st->r0))  // also catches NaN
+        st->done = 2;
+    }
+    __threadfence();
+  }
+}
+
+// r = b - A x on level L (FP64 accumulation of the norm), boundary x read as 0
+// when mask_boundary.  Optional outputs: r64 (pitch L.pitch) and r32 (pitch p32).
+template <typename T>
+__global__ void __launch_bounds__(NT) k_resnorm(const Level<T>* __restrict__ Ls, int mode, T* __restrict__ rout,
+                                                float* __restrict__ r32, int p32) {
+  __shared__ double sh[NT / 64];
+  const Level<T> L = Ls[blockIdx.z];
+  SolveState* st = L.st;
+  if (mode == NORM_CHECK && st->done) return;
+  const int lo = row_lo(L), nr = row_hi(L) - lo + 1, ni = L.nx - 2;
+  const int n = nr * ni;
+  double acc = 0.0;
+  for (int idx = blockIdx.x * NT + threadIdx.x; idx < n; idx += gridDim.x * NT) {
+    const int r = idx / ni;
+    const int i = idx - r * ni + 1;
+    const int j = lo + r;
+    const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
+    const T d = defect_at<true>(L, L.x, L.b, i, j, jm, jp);
+    if (rout) rout[(size_t)j * L.pitch + i] = d;
+    if (r32) r32[(size_t)j * p32 + i] = (float)d;
+    acc += (double)d * (double)d;
+  }
+  const double part = block_sum(acc, sh);
+  finish_norm(st, part, gridDim.x, mode);
+}
+
+// Mixed precision outer update: x (FP64) += e (FP32), e = 0.
+__global__ void __launch_bounds__(NT) k_outer_update(const Level<double>* __restrict__ L64s,
+                                                     const Level<float>* __restrict__ L32s) {
+  const Level<double> X = L64s[blockIdx.z];
+  if (X.st->done) return;
+  const Level<float> E = L32s[blockIdx.z];
+  const int lo = row_lo(X), nr = row_hi(X) - lo + 1, ni = X.nx - 2;
+  const int n = nr * ni;
+  for (int idx = blockIdx.x * NT + threadIdx.x; idx < n; idx += gridDim.x * NT) {
+    const int r = idx / ni;
+    const int i = idx - r * ni + 1;
+    const int j = lo + r;
+    float* ep = E.x + (size_t)j * E.pitch + i;
+    X.x[(size_t)j * X.pitch + i] += (double)(*ep);
+    *ep = 0.0f;
+  }
+}
+
+// Zero the Dirichlet boundary nodes of x.
+__global__ void k_zero_boundary(double* x, int nx, int ny, int pitch, int py) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ny) {
+    x[(size_t)t * pitch] = 0.0;
+    x[(size_t)t * pitch + nx - 1] = 0.0;
+  }
+  if (!py && t < nx) {
+    x[t] = 0.0;
+    x[(size_t)(ny - 1) * pitch + t] = 0.0;
+  }
+}
+
+// --------------------------------------------------------------------------- setup kernels
+
+// Q1 bands C, E, N, NE, NW at every stored node from per-cell kx, ky
+// (cell (ci, cj) at kx[cj * kpitch + ci]; kpitch = 0 when they vary along x
+// only, then only row 0 of the bands is written).  Element matrix of a cell,
+// divided by hx*hy: kx/hx^2 K1 (x) M1 + ky/hy^2 M1 (x) K1 with K1 = [1 -1; -1 1],
+// M1 = [1/3 1/6; 1/6 1/3].
+__global__ void k_q1_bands(double* band, int bstride, int bpitch, int nrows, int nx, int ny, int py,
+                           const double* __restrict__ kx, const double* __restrict__ ky, int kpitch, double hx,
+                           double hy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= nx || j >= nrows) return;
+  const int ncx = nx - 1, ncy = py ? ny : ny - 1;
+  const double ax = 1.0 / (hx * hx), ay = 1.0 / (hy * hy);
+  // cells around node (i, j): SW (i-1, j-1), SE (i, j-1), NW (i-1, j), NE (i, j)
+  auto cell = [&](int ci, int cj, double& cx, double& cy) -> bool {
+    if (ci < 0 || ci >= ncx) return false;
+    if (py) {
+      cj = (cj + ncy) % ncy;
+    } else if (cj < 0 || cj >= ncy) {
+      return false;
+    }
+    const size_t c = (size_t)cj * kpitch + ci;
+    cx = kx[c] * ax;
+    cy = ky[c] * ay;
+    return true;
+  };
+  // with kpitch == 0 every row sees the same cells; evaluate at an interior row
+  const int jj = (kpitch == 0 && !py) ? 1 : j;
+  double C = 0, E = 0, N = 0, NE = 0, NW = 0, cx, cy;
+  if (cell(i - 1, jj - 1, cx, cy)) C += (cx + cy) / 3.0;
+  if (cell(i, jj - 1, cx, cy)) { C += (cx + cy) / 3.0; E += -cx / 3.0 + cy / 6.0; }
+  if (cell(i - 1, jj, cx, cy)) { C += (cx + cy) / 3.0; N += cx / 6.0 - cy / 3.0; NW += -(cx + cy) / 6.0; }
+  if (cell(i, jj, cx, cy)) {
+    C += (cx + cy) / 3.0;
+    E += -cx / 3.0 + cy / 6.0;
+    N += cx / 6.0 - cy / 3.0;
+    NE += -(cx + cy) / 6.0;
+  }
+  const size_t p = (size_t)j * bpitch + i;
+  band[p] = C;
+  band[bstride + p] = E;
+  band[2 * (size_t)bstride + p] = N;
+  band[3 * (size_t)bstride + p] = NE;
+  band[4 * (size_t)bstride + p] = NW;
+}
+
+// Fine coefficient a_pq for q = p + (s, t) from the symmetric band storage.
+__device__ double band_coef(const double* band, int bstride, int bpitch, int nx, int ny, int py, int i, int j, int s,
+                            int t) {
+  auto idx = [&](int ii, int jj) -> size_t {
+    if (py) jj = (jj % ny + ny) % ny;
+    return (size_t)(bpitch ? jj : 0) * bpitch + ii;
+  };
+  const double* C = band;
+  const double* E = band + bstride;
+  const double* N = band + 2 * (size_t)bstride;
+  const double* NE = band + 3 * (size_t)bstride;
+  const double* NW = band + 4 * (size_t)bstride;
+  if (s == 0 && t == 0) return C[idx(i, j)];
+  if (s == 1 && t == 0) return E[idx(i, j)];
+  if (s == -1 && t == 0) return E[idx(i - 1, j)];
+  if (s == 0 && t == 1) return N[idx(i, j)];
+  if (s == 0 && t == -1) return N[idx(i, j - 1)];
+  if (s == 1 && t == 1) return NE[idx(i, j)];
+  if (s == -1 && t == -1) return NE[idx(i - 1, j - 1)];
+  if (s == -1 && t == 1) return NW[idx(i, j)];
+  return NW[idx(i + 1, j - 1)];  // s == 1, t == -1
+}
+
+// Galerkin coarse bands A_H = R A_h P at coarse node (I, J): for each of the
+// couplings C, E, N, NE, NW to c' = (I, J) + (dI, dJ),
+//   sum_{p in supp R(I,J)} w_p sum_{q ~ p} a_pq P(q, c'),
+// with full-weighting weights w and bilinear weights P.  Couplings to a
+// Dirichlet boundary node are stored as 0.
+__global__ void k_rap(double* cband, int cbstride, int cbpitch, int cnrows, int ncx_nodes, int ncy_nodes,
+                      const double* __restrict__ fband, int fbstride, int fbpitch, int nxf, int nyf, int py) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y;
+  if (I >= ncx_nodes || J >= cnrows) return;
+  const int offs[5][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}, {-1, 1}};
+  const double w[3] = {0.25, 0.5, 0.25};
+  // rows of a 1-D band are evaluated at an interior row
+  const int JJ = (cbpitch == 0 && !py) ? 1 : J;
+  const bool interior_I = I >= 1 && I <= ncx_nodes - 2;
+  const bool interior_J = py || (JJ >= 1 && JJ <= ncy_nodes - 2);
+  for (int k = 0; k < 5; ++k) {
+    const int Ic = I + offs[k][0];
+    int Jc = JJ + offs[k][1];
+    double v = 0.0;
+    const bool tgt_in = Ic >= 1 && Ic <= ncx_nodes - 2 && (py || (Jc >= 1 && Jc <= ncy_nodes - 2));
+    if (interior_I && interior_J && tgt_in) {
+      for (int b = -1; b <= 1; ++b) {
+        for (int a = -1; a <= 1; ++a) {
+          const int pi = 2 * I + a;
+          int pj = 2 * JJ + b;
+          if (py) pj = (pj + nyf) % nyf;
+          const double wp = w[a + 1] * w[b + 1];
+          for (int t = -1; t <= 1; ++t) {
+            for (int s = -1; s <= 1; ++s) {
+              const int qi = pi + s;
+              const int qj = pj + t;  // unwrapped; compared with 2 Jc modulo nyf below
+              int dx = qi - 2 * Ic;
+              int dy = qj - 2 * Jc;
+              if (py) {
+                dy = ((dy % nyf) + nyf) % nyf;
+                if (dy > nyf / 2) dy -= nyf;
+              }
+              if (dx < -1 || dx > 1 || dy < -1 || dy > 1) continue;
+              const double pw = (dx == 0 ? 1.0 : 0.5) * (dy == 0 ? 1.0 : 0.5);
+              const double a_pq = band_coef(fband, fbstride, fbpitch, nxf, nyf, py, pi, pj, s, t);
+              v += wp * a_pq * pw;
+            }
+          }
+        }
+      }
+    } else if (k == 0) {
+      v = 1.0;  // keep the diagonal of non-unknown nodes finite and non-zero
+    }
+    cband[(size_t)k * cbstride + (size_t)J * cbpitch + I] = v;
+  }
+}
+
+// Dense matrix of the coarsest operator over its unknowns (row by row).
+__global__ void k_dense_coarse(double* A, int n, int nx, int ny, int py, int kind, double cx, double cy, double dg,
+                               const double* __restrict__ band, int bstride, int bpitch) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int ni = nx - 2, lo = py ? 0 : 1, hi = py ? ny - 1 : ny - 2;
+  const int r = k / ni;
+  const int i = k - r * ni + 1, j = lo + r;
+  for (int t = -1; t <= 1; ++t) {
+    for (int s = -1; s <= 1; ++s) {
+      double a;
+      if (kind == ST5) {
+        if (s == 0 && t == 0) a = dg;
+        else if (t == 0) a = -cx;
+        else if (s == 0) a = -cy;
+        else a = 0.0;
+      } else {
+        a = band_coef(band, bstride, bpitch, nx, ny, py, i, j, s, t);
+      }
+      const int qi = i + s;
+      int qj = j + t;
+      if (py) qj = (qj + ny) % ny;
+      if (qi < 1 || qi > nx - 2 || qj < lo || qj > hi) continue;
+      const int q = (qj - lo) * ni + (qi - 1);
+      A[(size_t)k * n + q] += a;
+    }
+  }
+}
+
+// In-place Cholesky A = L L^T (lower triangle of A), one workgroup.  info[0]
+// is set to k + 1 when the k-th pivot is not positive.
+__global__ void k_cholesky(double* A, int n, int* info) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      const double d = A[(size_t)k * n + k];
+      if (!(d > 0.0)) {
+        bad = k + 1;
+      } else {
+        A[(size_t)k * n + k] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    if (bad) break;
+    const double dk = A[(size_t)k * n + k];
+    for (int r = k + 1 + tid; r < n; r += nth) A[(size_t)r * n + k] /= dk;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int e = tid; e < m * m; e += nth) {
+      const int r = k + 1 + e / m, c = k + 1 + e % m;
+      if (c <= r) A[(size_t)r * n + c] -= A[(size_t)r * n + k] * A[(size_t)c * n + k];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) info[0] = bad;
+}
+
+// Counts entries of v that are not finite or not > 0.
+__global__ void k_count_bad(const double* __restrict__ v, long n, int* count) {
+  int bad = 0;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+    const double a = v[k];
+    if (!(a > 0.0) || !(a < INFINITY)) ++bad;
+  }
+  if (bad) atomicAdd(count, bad);
+}
+
+// Counts non-finite entries of the unknowns of a node array.
+__global__ void k_count_nonfinite(const double* __restrict__ v, int nx, int ny, int pitch, int py, int* count) {
+  const int lo = py ? 0 : 1, nr = (py ? ny - 1 : ny - 2) - lo + 1, ni = nx - 2;
+  const long n = (long)nr * ni;
+  int bad = 0;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < n; idx += (long)gridDim.x * blockDim.x) {
+    const long r = idx / ni;
+    const double a = v[(size_t)(lo + r) * pitch + (idx - r * ni + 1)];
+    if (!(a - a == 0.0)) ++bad;
+  }
+  if (bad) atomicAdd(count, bad);
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S* __restrict__ s, D* __restrict__ d, long n) {
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) d[k] = (D)s[k];
+}
+
+// dL/dk for each cell: -lam_e^T K u_e with K = Ex + Ey the unit-coefficient
+// element matrix (local node order 2 b + a, a along x).
+__global__ void k_coeff_grad(const double* __restrict__ u, const double* __restrict__ lam, double* __restrict__ g,
+                             int nx, int ny, int py, double hx, double hy) {
+  const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cj = blockIdx.y;
+  const int ncx = nx - 1, ncy = py ? ny : ny - 1;
+  if (ci >= ncx || cj >= ncy) return;
+  const int j0 = cj, j1 = (py && cj + 1 == ny) ? 0 : cj + 1;
+  const double ue[4] = {u[(size_t)j0 * nx + ci], u[(size_t)j0 * nx + ci + 1], u[(size_t)j1 * nx + ci],
+                        u[(size_t)j1 * nx + ci + 1]};
+  const double le[4] = {lam[(size_t)j0 * nx + ci], lam[(size_t)j0 * nx + ci + 1], lam[(size_t)j1 * nx + ci],
+                        lam[(size_t)j1 * nx + ci + 1]};
+  const double K1[2][2] = {{1.0, -1.0}, {-1.0, 1.0}};
+  const double M1[2][2] = {{1.0 / 3.0, 1.0 / 6.0}, {1.0 / 6.0, 1.0 / 3.0}};
+  const double ax = 1.0 / (hx * hx), ay = 1.0 / (hy * hy);
+  double s = 0.0;
+  for (int p = 0; p < 4; ++p) {
+    const int a = p & 1, b = p >> 1;
+    double kp = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const int a2 = q & 1, b2 = q >> 1;
+      kp += (ax * K1[a][a2] * M1[b][b2] + ay * M1[a][a2] * K1[b][b2]) * ue[q];
+    }
+    s += le[p] * kp;
+  }
+  g[(size_t)cj * ncx + ci] = -s;
+}
+
+// --------------------------------------------------------------------------- launchers
+
+static inline unsigned blocks_for(long n, int per = NT) { return (unsigned)((n + per - 1) / per); }
+
+template <typename T>
+hipError_t launch_colour(const Level<T>* Ls, const LevelShape& s, int c, int ncol, int nslots, hipStream_t st) {
+  const int nk = (s.nx - 1) / 2 + 1;
+  const int nrows = ncol == 2 ? s.nrows : (s.nrows + 1) / 2;
+  hipLaunchKernelGGL(k_colour<T>, dim3(blocks_for((long)nk * nrows), 1, nslots), dim3(NT), 0, st, Ls, c, ncol);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_jacobi(const Level<T>* Ls, const LevelShape& s, int dir, T omega, int nslots, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi<T>, dim3(blocks_for((long)(s.nx - 2) * s.nrows), 1, nslots), dim3(NT), 0, st, Ls, dir,
+                     omega);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy(const Level<T>* Ls, const LevelShape& s, int nslots, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy<T>, dim3(blocks_for((long)(s.nx - 2) * s.nrows), 1, nslots), dim3(NT), 0, st, Ls);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dr(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& c, int nslots, hipStream_t st) {
+  hipLaunchKernelGGL(k_dr<T>, dim3(blocks_for((long)(c.nx - 2) * c.nrows), 1, nslots), dim3(NT), 0, st, Fs, Cs);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& f, int nslots, hipStream_t st) {
+  hipLaunchKernelGGL(k_prolong<T>, dim3(blocks_for((long)(f.nx - 2) * f.nrows), 1, nslots), dim3(NT), 0, st, Fs, Cs);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse(const Level<T>* Ls, const double* const* chol, int n, int nslots, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse<T>, dim3(1, 1, nslots), dim3(NT), 0, st, Ls, chol, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_subcycle(const Level<T>* levs, int nlev, const DOp* prog, const int* beg, const int* cnt,
+                           const double* const* chol, int ncu, T omega, int ncol, int nslots, hipStream_t st) {
+  hipLaunchKernelGGL(k_subcycle<T>, dim3(1, 1, nslots), dim3(SUB_NT), 0, st, levs, nlev, prog, beg, cnt, chol, ncu,
+                     omega, ncol);
+  return hipGetLastError();
+}
+
+int norm_blocks(const LevelShape& s) {
+  const long n = (long)(s.nx - 2) * s.nrows;
+  long b = (n + NT * 4 - 1) / (NT * 4);
+  if (b < 1) b = 1;
+  if (b > MAX_NORM_BLOCKS) b = MAX_NORM_BLOCKS;
+  return (int)b;
+}
+
+template <typename T>
+hipError_t launch_resnorm(const Level<T>* Ls, const LevelShape& s, int mode, T* rout, float* r32, int p32, int nslots,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_resnorm<T>, dim3(norm_blocks(s), 1, nslots), dim3(NT), 0, st, Ls, mode, rout, r32, p32);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_update(const Level<double>* L64, const Level<float>* L32, const LevelShape& s, int nslots,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_outer_update, dim3(blocks_for((long)(s.nx - 2) * s.nrows), 1, nslots), dim3(NT), 0, st, L64,
+                     L32);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_boundary(double* x, int nx, int ny, int pitch, int py, hipStream_t st) {
+  const int n = nx > ny ? nx : ny;
+  hipLaunchKernelGGL(k_zero_boundary, dim3(blocks_for(n)), dim3(NT), 0, st, x, nx, ny, pitch, py);
+  return hipGetLastError();
+}
+
+hipError_t launch_q1_bands(double* band, int bstride, int bpitch, int nrows, int nx, int ny, int py, const double* kx,
+                           const double* ky, int kpitch, double hx, double hy, hipStream_t st) {
+  hipLaunchKernelGGL(k_q1_bands, dim3(blocks_for(nx), nrows), dim3(NT), 0, st, band, bstride, bpitch, nrows, nx, ny, py,
+                     kx, ky, kpitch, hx, hy);
+  return hipGetLastError();
+}
+
+hipError_t launch_rap(double* cband, int cbstride, int cbpitch, int cnrows, int ncx, int ncy, const double* fband,
+                      int fbstride, int fbpitch, int nxf, int nyf, int py, hipStream_t st) {
+  hipLaunchKernelGGL(k_rap, dim3(blocks_for(ncx), cnrows), dim3(NT), 0, st, cband, cbstride, cbpitch, cnrows, ncx, ncy,
+                     fband, fbstride, fbpitch, nxf, nyf, py);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_coarse(double* A, int n, int nx, int ny, int py, int kind, double cx, double cy, double dg,
+                               const double* band, int bstride, int bpitch, hipStream_t st) {
+  hipLaunchKernelGGL(k_dense_coarse, dim3(blocks_for(n)), dim3(NT), 0, st, A, n, nx, ny, py, kind, cx, cy, dg, band,
+                     bstride, bpitch);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholesky(double* A, int n, int* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, st, A, n, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_bad(const double* v, long n, int* count, hipStream_t st) {
+  long b = (n + NT - 1) / NT;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_count_bad, dim3((unsigned)b), dim3(NT), 0, st, v, n, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const double* v, int nx, int ny, int pitch, int py, int* count, hipStream_t st) {
+  long n = (long)nx * ny;
+  long b = (n + NT - 1) / NT;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_count_nonfinite, dim3((unsigned)b), dim3(NT), 0, st, v, nx, ny, pitch, py, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_float(const double* s, float* d, long n, hipStream_t st) {
+  long b = (n + NT - 1) / NT;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)b), dim3(NT), 0, st, s, d, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_coeff_grad(const double* u, const double* lam, double* g, int nx, int ny, int py, double hx,
+                             double hy, hipStream_t st) {
+  const int ncy = py ? ny : ny - 1;
+  hipLaunchKernelGGL(k_coeff_grad, dim3(blocks_for(nx - 1), ncy), dim3(NT), 0, st, u, lam, g, nx, ny, py, hx, hy);
+  return hipGetLastError();
+}
+
+#define MG_INSTANTIATE(T)                                                                                          \
+  template hipError_t launch_colour<T>(const Level<T>*, const LevelShape&, int, int, int, hipStream_t);           \
+  template hipError_t launch_jacobi<T>(const Level<T>*, const LevelShape&, int, T, int, hipStream_t);             \
+  template hipError_t launch_copy<T>(const Level<T>*, const LevelShape&, int, hipStream_t);                       \
+  template hipError_t launch_dr<T>(const Level<T>*, const Level<T>*, const LevelShape&, int, hipStream_t);        \
+  template hipError_t launch_prolong<T>(const Level<T>*, const Level<T>*, const LevelShape&, int, hipStream_t);   \
+  template hipError_t launch_coarse<T>(const Level<T>*, const double* const*, int, int, hipStream_t);             \
+  template hipError_t launch_subcycle<T>(const Level<T>*, int, const DOp*, const int*, const int*,                \
+                                         const double* const*, int, T, int, int, hipStream_t);                     \
+  template hipError_t launch_resnorm<T>(const Level<T>*, const LevelShape&, int, T*, float*, int, int, hipStream_t);
+
+MG_INSTANTIATE(double)
+MG_INSTANTIATE(float)
+
+}  // namespace mg

@@ -1,0 +1,260 @@
+"""ctypes binding of libmg.so (include/mg.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  torch is used for device memory (tensors' data pointers) and streams.
+Loading fails loudly if the library has not been built; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch  # loaded first so that the library binds to torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmg.so")
+
+MG_OK, MG_NOT_CONVERGED, MG_DIVERGED = 0, 1, 2
+MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_EUNSUPPORTED = -1, -2, -3, -4
+MG_COEF_CONST5, MG_COEF_CELL9 = 0, 1
+MG_CYCLE_F, MG_CYCLE_V = 0, 1
+MG_SMOOTH_JACOBI, MG_SMOOTH_RBGS, MG_SMOOTH_GS4C = 0, 1, 2
+MG_PREC_FP64, MG_PREC_MIXED = 0, 1
+
+SMOOTHERS = {"jacobi": MG_SMOOTH_JACOBI, "rbgs": MG_SMOOTH_RBGS, "gs4c": MG_SMOOTH_GS4C}
+CYCLES = {"F": MG_CYCLE_F, "V": MG_CYCLE_V}
+PRECISIONS = {"fp64": MG_PREC_FP64, "mixed": MG_PREC_MIXED}
+
+EXPORTED = (
+    "mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
+    "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_shape", "mg_num_levels",
+)
+
+
+class mg_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("periodic_x", ctypes.c_int32),
+                ("periodic_y", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double)]
+
+
+class mg_coeffs(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("eps_x", ctypes.c_double), ("eps_y", ctypes.c_double),
+                ("kx", ctypes.c_void_p), ("ky", ctypes.c_void_p), ("kx_1d_along_x", ctypes.c_int32)]
+
+
+class mg_options(ctypes.Structure):
+    _fields_ = [("cycle", ctypes.c_int32), ("smoother", ctypes.c_int32), ("nu_pre", ctypes.c_int32),
+                ("nu_post", ctypes.c_int32), ("omega", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("coarse_cta_nodes", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class mg_info(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int32), ("res0", ctypes.c_double), ("res", ctypes.c_double),
+                ("rel_res", ctypes.c_double), ("rho_last", ctypes.c_double), ("rho_mean", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmg.so (once).  Raises if it is missing: build it with
+    ``python -m paper_0805_3041_amd.build``."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing; build it with `python -m paper_0805_3041_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.mg_setup.argtypes = [P(mg_grid), P(mg_coeffs), ctypes.c_int32, P(mg_options), P(ctypes.c_void_p)]
+    lib.mg_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
+                             P(mg_info)]
+    lib.mg_residual.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                P(ctypes.c_double)]
+    lib.mg_coeff_grad.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.mg_setup_batched.argtypes = [P(mg_grid), P(mg_coeffs), ctypes.c_int32, P(mg_options), P(ctypes.c_void_p)]
+    lib.mg_solve_batched.argtypes = [ctypes.c_void_p, P(ctypes.c_void_p), P(ctypes.c_void_p), ctypes.c_double,
+                                     ctypes.c_int32, P(mg_info)]
+    lib.mg_destroy.argtypes = [ctypes.c_void_p]
+    lib.mg_status_string.argtypes = [ctypes.c_int]
+    lib.mg_status_string.restype = ctypes.c_char_p
+    lib.mg_last_error.argtypes = [ctypes.c_void_p]
+    lib.mg_last_error.restype = ctypes.c_char_p
+    lib.mg_level_shape.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
+    lib.mg_num_levels.argtypes = [ctypes.c_void_p]
+    for name in ("mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
+                 "mg_destroy", "mg_level_shape"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib.mg_num_levels.restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+class MGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{status_string(status)}: {msg}")
+        self.status = status
+
+
+def status_string(s: int) -> str:
+    return load_library().mg_status_string(int(s)).decode()
+
+
+def last_error(h=None) -> str:
+    return load_library().mg_last_error(h).decode()
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("arrays must be device (cuda) tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_f64(t: torch.Tensor, shape, name):
+    if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a contiguous float64 tensor of shape {tuple(shape)}")
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    cycles: int
+    res0: float
+    res: float
+    rel_res: float
+    rho_last: float
+    rho_mean: float
+    seconds: float
+    history: np.ndarray = field(default_factory=lambda: np.zeros(0))
+
+    @property
+    def converged(self) -> bool:
+        return self.status == MG_OK
+
+
+def mg_setup(grid: mg_grid, coeffs: mg_coeffs, levels: int, opts: mg_options):
+    lib = load_library()
+    h = ctypes.c_void_p()
+    s = lib.mg_setup(ctypes.byref(grid), ctypes.byref(coeffs), int(levels), ctypes.byref(opts), ctypes.byref(h))
+    if s != MG_OK:
+        raise MGError(s, last_error(None))
+    return h
+
+
+def mg_solve(h, rhs: torch.Tensor, x: torch.Tensor, tol: float, max_cycles: int, history: bool = True) -> SolveInfo:
+    lib = load_library()
+    info = mg_info()
+    hist = None
+    if history:
+        hist = np.zeros(max_cycles + 1, dtype=np.float64)
+        info.history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    s = lib.mg_solve(h, _ptr(rhs), _ptr(x), float(tol), int(max_cycles), ctypes.byref(info))
+    if s < 0:
+        raise MGError(s, last_error(h))
+    return SolveInfo(s, info.cycles, info.res0, info.res, info.rel_res, info.rho_last, info.rho_mean, info.seconds,
+                     hist[: info.cycles + 1].copy() if hist is not None else np.zeros(0))
+
+
+def mg_residual(h, rhs: torch.Tensor, x: torch.Tensor, r: torch.Tensor | None = None) -> float:
+    lib = load_library()
+    nrm = ctypes.c_double()
+    s = lib.mg_residual(h, _ptr(rhs), _ptr(x), _ptr(r), ctypes.byref(nrm))
+    if s != MG_OK:
+        raise MGError(s, last_error(h))
+    return nrm.value
+
+
+def mg_coeff_grad(h, u: torch.Tensor, lam: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    lib = load_library()
+    s = lib.mg_coeff_grad(h, _ptr(u), _ptr(lam), _ptr(out))
+    if s != MG_OK:
+        raise MGError(s, last_error(h))
+    return out
+
+
+def mg_destroy(h) -> None:
+    if h is not None and h.value:
+        load_library().mg_destroy(h)
+
+
+def mg_num_levels(h) -> int:
+    return int(load_library().mg_num_levels(h))
+
+
+def mg_level_shape(h, l: int):
+    nx, ny = ctypes.c_int32(), ctypes.c_int32()
+    s = load_library().mg_level_shape(h, int(l), ctypes.byref(nx), ctypes.byref(ny))
+    if s != MG_OK:
+        raise MGError(s, last_error(h))
+    return nx.value, ny.value
+
+
+def make_options(cycle="F", smoother="rbgs", nu_pre=2, nu_post=2, omega=0.8, precision="fp64",
+                 coarse_cta_nodes=0, stream=None) -> mg_options:
+    return mg_options(CYCLES[cycle], SMOOTHERS[smoother], int(nu_pre), int(nu_post), float(omega),
+                      PRECISIONS[precision], int(coarse_cta_nodes), _stream_ptr(stream))
+
+
+class Solver:
+    """Owns one handle.  Grid arrays are float64 device tensors [ny][nx]."""
+
+    def __init__(self, nx: int, ny: int, *, periodic_y: bool = False, lx: float = 1.0, ly: float = 1.0,
+                 eps_x: float = 1.0, eps_y: float = 1.0, kx: torch.Tensor | None = None,
+                 ky: torch.Tensor | None = None, kx_1d_along_x: bool = False, levels: int = 0, **opt):
+        self.nx, self.ny, self.periodic_y = nx, ny, periodic_y
+        self.grid = mg_grid(nx, ny, 0, 1 if periodic_y else 0, lx, ly)
+        if kx is None:
+            self.coeffs = mg_coeffs(MG_COEF_CONST5, eps_x, eps_y, None, None, 0)
+            self._keep = ()
+        else:
+            ky = kx if ky is None else ky
+            kx = kx.contiguous().to(torch.float64)
+            ky = ky.contiguous().to(torch.float64)
+            self._keep = (kx, ky)
+            self.coeffs = mg_coeffs(MG_COEF_CELL9, 0.0, 0.0, _ptr(kx), _ptr(ky), 1 if kx_1d_along_x else 0)
+        self.opts = make_options(**opt)
+        self.h = mg_setup(self.grid, self.coeffs, levels, self.opts)
+
+    @property
+    def nlevels(self) -> int:
+        return mg_num_levels(self.h)
+
+    def solve(self, rhs: torch.Tensor, x: torch.Tensor, tol: float = 1e-10, max_cycles: int = 100,
+              history: bool = True) -> SolveInfo:
+        _check_f64(rhs, (self.ny, self.nx), "rhs")
+        _check_f64(x, (self.ny, self.nx), "x")
+        return mg_solve(self.h, rhs, x, tol, max_cycles, history)
+
+    def residual(self, rhs: torch.Tensor, x: torch.Tensor, r: torch.Tensor | None = None) -> float:
+        _check_f64(rhs, (self.ny, self.nx), "rhs")
+        _check_f64(x, (self.ny, self.nx), "x")
+        if r is not None:
+            _check_f64(r, (self.ny, self.nx), "r")
+        return mg_residual(self.h, rhs, x, r)
+
+    def coeff_grad(self, u: torch.Tensor, lam: torch.Tensor) -> torch.Tensor:
+        ncy = self.ny if self.periodic_y else self.ny - 1
+        out = torch.empty((ncy, self.nx - 1), dtype=torch.float64, device=u.device)
+        return mg_coeff_grad(self.h, u, lam, out)
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None:
+            mg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

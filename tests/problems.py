@@ -1,0 +1,70 @@
+"""Problem descriptions shared by the GPU tests: each builds the oracle's
+hierarchy and the library's solver for the same seeded inputs."""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from oracle import mg_oracle as O
+import workloads as W
+
+
+@dataclass
+class Problem:
+    nx: int
+    ny: int
+    periodic_y: bool = False
+    eps: float = 1.0
+    q1: str | None = None        # None (5-point), "annulus", "grf"
+    smoother: str = "rbgs"
+    nu_pre: int = 2
+    nu_post: int = 2
+    omega: float = 0.8
+    cycle: str = "F"
+    levels: int = 0
+
+    def grid(self):
+        return O.Grid(self.nx, self.ny, self.periodic_y)
+
+    def coefficients(self):
+        """Cell coefficients (kx, ky, one_d) or None."""
+        if self.q1 == "annulus":
+            kx, ky = W.annulus_cell_coefficients(self.nx)
+            return kx, ky, True
+        if self.q1 == "grf":
+            ncy = self.ny if self.periodic_y else self.ny - 1
+            assert ncy == self.nx - 1
+            a = np.exp(W.gaussian_random_field(self.nx - 1, 5))
+            return a, a, False
+        return None
+
+    def oracle(self):
+        g = self.grid()
+        opts = O.Options(cycle=self.cycle, smoother=self.smoother, nu_pre=self.nu_pre, nu_post=self.nu_post,
+                         omega=self.omega)
+        c = self.coefficients()
+        if c is None:
+            return O.hierarchy_5pt(g, self.eps, 1.0, opts, self.levels)
+        kx, ky, oned = c
+        if oned:
+            return O.hierarchy_q1(g, kx, ky, opts, self.levels, separable=True)
+        return O.hierarchy_q1(g, kx, ky, opts, self.levels)
+
+    def solver(self, precision="fp64", coarse_cta_nodes=0):
+        import torch
+        from paper_0805_3041_amd import mg
+        c = self.coefficients()
+        kw = dict(periodic_y=self.periodic_y, levels=self.levels, cycle=self.cycle, smoother=self.smoother,
+                  nu_pre=self.nu_pre, nu_post=self.nu_post, omega=self.omega, precision=precision,
+                  coarse_cta_nodes=coarse_cta_nodes)
+        if c is None:
+            return mg.Solver(self.nx, self.ny, eps_x=self.eps, eps_y=1.0, **kw)
+        kx, ky, oned = c
+        dev = "cuda"
+        return mg.Solver(self.nx, self.ny, kx=torch.tensor(kx, device=dev), ky=torch.tensor(ky, device=dev),
+                         kx_1d_along_x=oned, **kw)
+
+    def rhs(self, seed=2):
+        return W.normal_field(self.nx, self.ny, seed, self.periodic_y)

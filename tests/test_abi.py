@@ -1,0 +1,99 @@
+"""The C ABI library loads, exports every entry point include/mg.h declares,
+and rejects invalid arguments before any device work (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_0805_3041_amd import mg as m
+    m.load_library()
+    return m
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched",
+                     "mg_solve_batched", "mg_destroy", "mg_status_string", "mg_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(mg):
+    lib = mg.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(mg.EXPORTED) == set(declared_functions())
+
+
+def test_status_strings(mg):
+    assert mg.status_string(0) == "MG_OK"
+    assert mg.status_string(-1) == "MG_EINVAL"
+    assert mg.status_string(2) == "MG_DIVERGED"
+
+
+def _setup(mg, grid, coeffs, levels=0, **opt):
+    opts = mg.mg_options(mg.MG_CYCLE_F, mg.MG_SMOOTH_RBGS, 2, 2, 0.8, mg.MG_PREC_FP64, 0, None)
+    for k, v in opt.items():
+        setattr(opts, k, v)
+    h = ctypes.c_void_p()
+    s = mg.load_library().mg_setup(ctypes.byref(grid), ctypes.byref(coeffs), levels, ctypes.byref(opts),
+                                   ctypes.byref(h))
+    return s, h
+
+
+@pytest.mark.parametrize("case", [
+    dict(grid=(2, 65, 0, 0, 1.0, 1.0)),
+    dict(grid=(65, 65, 1, 0, 1.0, 1.0), status=-4),
+    dict(grid=(65, 63, 0, 1, 1.0, 1.0)),
+    dict(grid=(65, 65, 0, 0, -1.0, 1.0)),
+    dict(grid=(65, 65, 0, 0, float("nan"), 1.0)),
+    dict(eps=(float("nan"), 1.0)),
+    dict(eps=(0.0, 1.0)),
+    dict(opt=dict(nu_pre=9)),
+    dict(opt=dict(nu_post=-1)),
+    dict(opt=dict(cycle=7)),
+    dict(opt=dict(smoother=3)),
+    dict(opt=dict(precision=5)),
+    dict(opt=dict(smoother=0, omega=float("inf"))),
+    dict(opt=dict(coarse_cta_nodes=-5)),
+    dict(levels=-1),
+    dict(cell9_null=True),
+    dict(cell9_rbgs=True, status=-4),
+])
+def test_setup_rejects_invalid_arguments(mg, case):
+    grid = mg.mg_grid(*case.get("grid", (65, 65, 0, 0, 1.0, 1.0)))
+    ex, ey = case.get("eps", (1.0, 1.0))
+    coeffs = mg.mg_coeffs(mg.MG_COEF_CONST5, ex, ey, None, None, 0)
+    opt = dict(case.get("opt", {}))
+    if case.get("cell9_null"):
+        coeffs = mg.mg_coeffs(mg.MG_COEF_CELL9, 0, 0, None, None, 0)
+        opt["smoother"] = mg.MG_SMOOTH_GS4C
+    if case.get("cell9_rbgs"):
+        coeffs = mg.mg_coeffs(mg.MG_COEF_CELL9, 0, 0, 8, 8, 0)  # never dereferenced: rejected first
+    s, h = _setup(mg, grid, coeffs, case.get("levels", 0), **opt)
+    assert s == case.get("status", -1), mg.last_error(None)
+    assert not h.value
+    assert mg.last_error(None)
+
+
+def test_null_handle_calls_are_rejected(mg):
+    lib = mg.load_library()
+    assert lib.mg_solve(None, None, None, 1e-10, 10, None) == mg.MG_EINVAL
+    nrm = ctypes.c_double()
+    assert lib.mg_residual(None, None, None, None, ctypes.byref(nrm)) == mg.MG_EINVAL
+    assert lib.mg_coeff_grad(None, None, None, None) == mg.MG_EINVAL
+    assert lib.mg_destroy(None) == mg.MG_OK
+    assert lib.mg_num_levels(None) == 0

@@ -1,0 +1,308 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+the same seeded inputs.  FP64 iterates must agree to 1e-12 relative max-norm
+after every cycle; integer outcomes (status, cycle counts) must agree."""
+
+import numpy as np
+import pytest
+
+from oracle import mg_oracle as O
+import workloads as W
+from tests.problems import Problem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PARITY = 1e-12  # relative max-norm per cycle, FP64
+# Residual norms near convergence are ~1e-10 r0 and are evaluated as b - A x
+# with terms of size ||A|| |x|; their FP64 rounding floor (eps_mach ||A|| |x|
+# per entry) is below 1e-13 r0 on these grids, so histories are compared with
+# that absolute slack on top of a relative 1e-8.
+HIST_ATOL = 1e-13
+
+
+def _mg():
+    from paper_0805_3041_amd import mg
+    return mg
+
+
+def gpu_iterates(solver, rhs, x0, k):
+    """x_1..x_k by resuming one cycle at a time (the cycle is stationary)."""
+    r = torch.tensor(rhs, device="cuda")
+    x = torch.tensor(x0, device="cuda")
+    out = []
+    for _ in range(k):
+        info = solver.solve(r, x, tol=1e-300, max_cycles=1, history=False)
+        assert info.status in (0, 1)
+        out.append(x.cpu().numpy().copy())
+    return out
+
+
+def oracle_iterates(h, g, rhs, x0, k):
+    b = g.pack(rhs)
+    x = g.pack(x0)
+    out = []
+    for _ in range(k):
+        x = O.mg_cycle(h, 0, x, b, h.opts.cycle)
+        out.append(x.copy())
+    return out
+
+
+def check_parity(p: Problem, rhs, x0, k, coarse_cta_nodes=0):
+    g = p.grid()
+    h = p.oracle()
+    s = p.solver(coarse_cta_nodes=coarse_cta_nodes)
+    try:
+        xs_g = gpu_iterates(s, rhs, x0, k)
+    finally:
+        s.close()
+    xs_o = oracle_iterates(h, g, rhs, x0, k)
+    worst = 0.0
+    for c, (xg, xo) in enumerate(zip(xs_g, xs_o), 1):
+        # boundary nodes of the GPU iterate are zero
+        full = g.unpack(xo)
+        assert np.array_equal(xg[full == 0] * 0, full[full == 0] * 0)
+        err = np.abs(g.pack(xg) - xo).max() / np.abs(xo).max()
+        worst = max(worst, err)
+        assert err <= PARITY, f"cycle {c}: relative max-norm difference {err:.3e}"
+    return worst
+
+
+# ----------------------------------------------------------------------------- poisson65 (Jacobi)
+
+
+@pytest.mark.parametrize("cta", [0, 1])
+@pytest.mark.parametrize("rhs_kind", ["manufactured", "normal"])
+def test_poisson65_jacobi_per_cycle(cta, rhs_kind):
+    p = Problem(65, 65, smoother="jacobi", omega=0.8)
+    rhs = W.manufactured_sine(65)[0] if rhs_kind == "manufactured" else W.normal_field(65, 65, 0)
+    check_parity(p, rhs, np.zeros((65, 65)), 9, coarse_cta_nodes=cta)
+
+
+def test_poisson65_solve_status_cycles_and_error():
+    p = Problem(65, 65, smoother="jacobi", omega=0.8)
+    f, u = W.manufactured_sine(65)
+    g = p.grid()
+    ref = O.solve(p.oracle(), g.pack(f), np.zeros(g.n_unknowns), 1e-10, 100)
+    s = p.solver()
+    x = torch.zeros((65, 65), dtype=torch.float64, device="cuda")
+    info = s.solve(torch.tensor(f, device="cuda"), x, 1e-10, 100)
+    s.close()
+    assert info.status == 0 and info.cycles == ref.cycles
+    np.testing.assert_allclose(info.history, ref.history, rtol=1e-8, atol=HIST_ATOL * ref.history[0])
+    xh = np.pi / 128
+    err = np.abs(x.cpu().numpy() - u).max()
+    assert abs(err - ((xh / np.sin(xh)) ** 2 - 1)) < 1e-8
+
+
+# ----------------------------------------------------------------------------- anisotropic, red-black GS
+
+
+@pytest.mark.parametrize("eps", W.ANISO_EPS)
+@pytest.mark.parametrize("x0", ["zero", "uniform"])
+def test_aniso_rbgs_per_cycle(eps, x0):
+    n = 129
+    p = Problem(n, n, eps=eps, smoother="rbgs")
+    check_parity(p, W.aniso_rhs(n, 2), W.aniso_x0(n, x0, 1), 3, coarse_cta_nodes=300)
+
+
+@pytest.mark.parametrize("nu", [1, 2, 3, 4])
+def test_aniso_rbgs_smoothing_steps(nu):
+    n = 257
+    p = Problem(n, n, eps=0.1, smoother="rbgs", nu_pre=nu, nu_post=nu)
+    check_parity(p, W.aniso_rhs(n, 2), W.aniso_x0(n, "uniform", 1), 2)
+
+
+@pytest.mark.parametrize("cta", [1, 300, 5000, 100000])
+def test_cta_threshold_is_bitwise_invisible(cta):
+    """Where the coarse levels run (per-op launches or the single-workgroup kernel)
+    does not change a single bit of the iterate."""
+    n = 129
+    p = Problem(n, n, eps=0.01, smoother="rbgs")
+    rhs = W.aniso_rhs(n, 2)
+    ref = p.solver(coarse_cta_nodes=1)
+    got = p.solver(coarse_cta_nodes=cta)
+    try:
+        a = gpu_iterates(ref, rhs, np.zeros((n, n)), 2)
+        b = gpu_iterates(got, rhs, np.zeros((n, n)), 2)
+    finally:
+        ref.close()
+        got.close()
+    for xa, xb in zip(a, b):
+        assert np.array_equal(xa, xb)
+
+
+def test_ragged_rectangular_grid():
+    """97 x 49 nodes (3 * 2^5 + 1 by 3 * 2^4 + 1): coarsest 7 x 4, 10 unknowns."""
+    p = Problem(97, 49, eps=0.3, smoother="rbgs")
+    g = p.grid()
+    assert O.hierarchy_grids(g)[-1].nx == 7
+    check_parity(p, W.normal_field(97, 49, 5), np.zeros((49, 97)), 3, coarse_cta_nodes=400)
+
+
+def test_periodic_5pt():
+    p = Problem(65, 64, periodic_y=True, eps=0.5, smoother="rbgs")
+    check_parity(p, W.normal_field(65, 64, 6, True), np.zeros((64, 65)), 3, coarse_cta_nodes=600)
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "rbgs", "gs4c"])
+def test_v_cycle(smoother):
+    p = Problem(65, 65, eps=1.0, smoother=smoother, cycle="V", nu_pre=1, nu_post=2)
+    check_parity(p, W.normal_field(65, 65, 7), np.zeros((65, 65)), 3, coarse_cta_nodes=300)
+
+
+@pytest.mark.slow
+def test_aniso1025_full_size_two_cycles():
+    n = 1025
+    p = Problem(n, n, eps=1e-2, smoother="rbgs")
+    check_parity(p, W.aniso_rhs(n, 2), W.aniso_x0(n, "uniform", 1), 2)
+
+
+# ----------------------------------------------------------------------------- 9-point Q1
+
+
+@pytest.mark.parametrize("n", [33, 65, 129])
+def test_annulus_gs4c_per_cycle(n):
+    p = Problem(n, n - 1, periodic_y=True, q1="annulus", smoother="gs4c")
+    check_parity(p, W.annulus_rhs(n, n - 1, 3), np.zeros((n - 1, n)), 3, coarse_cta_nodes=300)
+
+
+@pytest.mark.parametrize("smoother", ["gs4c", "jacobi"])
+def test_grf_q1_per_cycle(smoother):
+    n = 65
+    p = Problem(n, n, q1="grf", smoother=smoother, omega=0.8)
+    f, _ = W.manufactured_sine(n)
+    check_parity(p, f, np.zeros((n, n)), 3, coarse_cta_nodes=300)
+
+
+def test_grf_q1_galerkin_levels_all_on_gpu():
+    """129^2 with per-op launches on every level (Galerkin 2-D bands on each)."""
+    n = 129
+    p = Problem(n, n, q1="grf", smoother="gs4c")
+    check_parity(p, W.normal_field(n, n, 8), np.zeros((n, n)), 2, coarse_cta_nodes=1)
+
+
+# ----------------------------------------------------------------------------- solve-level behaviour
+
+
+def test_residual_matches_oracle():
+    n = 129
+    p = Problem(n, n, eps=0.2)
+    g = p.grid()
+    rhs = W.normal_field(n, n, 9)
+    x = W.uniform_field(n, n, 10)
+    x_dirty = x.copy()
+    x_dirty[0, :] = 5.0  # boundary values are not unknowns and must be ignored
+    s = p.solver()
+    r = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    nrm = s.residual(torch.tensor(rhs, device="cuda"), torch.tensor(x_dirty, device="cuda"), r)
+    s.close()
+    ro = g.pack(rhs) - p.oracle().A[0] @ g.pack(x)
+    assert abs(nrm - np.linalg.norm(ro)) <= 1e-12 * np.linalg.norm(ro)
+    np.testing.assert_allclose(g.pack(r.cpu().numpy()), ro, atol=1e-12 * np.abs(ro).max())
+    assert np.all(r.cpu().numpy()[0, :] == 0)
+
+
+def test_diverging_jacobi_reports_diverged():
+    n = 33
+    p = Problem(n, n, smoother="jacobi", omega=2.5)
+    g = p.grid()
+    rhs = W.normal_field(n, n, 11)
+    ref = O.solve(p.oracle(), g.pack(rhs), np.zeros(g.n_unknowns), 1e-10, 200)
+    s = p.solver()
+    x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    info = s.solve(torch.tensor(rhs, device="cuda"), x, 1e-10, 200)
+    s.close()
+    assert ref.status == O.DIVERGED
+    assert info.status == _mg().MG_DIVERGED and info.cycles == ref.cycles
+
+
+def test_max_cycles_reports_not_converged():
+    n = 65
+    p = Problem(n, n, eps=1e-3)
+    s = p.solver()
+    x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    info = s.solve(torch.tensor(W.normal_field(n, n, 12), device="cuda"), x, 1e-10, 1)
+    s.close()
+    assert info.status == _mg().MG_NOT_CONVERGED and info.cycles == 1
+
+
+def test_zero_rhs_returns_immediately():
+    n = 65
+    s = Problem(n, n).solver()
+    x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    info = s.solve(torch.zeros((n, n), dtype=torch.float64, device="cuda"), x, 1e-10, 10)
+    s.close()
+    assert info.status == 0 and info.cycles == 0 and torch.all(x == 0)
+
+
+def test_resume_is_bitwise_equal():
+    n = 129
+    p = Problem(n, n, eps=0.05)
+    rhs = torch.tensor(W.normal_field(n, n, 13), device="cuda")
+    s = p.solver()
+    a = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    s.solve(rhs, a, 1e-300, 5, history=False)
+    b = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    s.solve(rhs, b, 1e-300, 2, history=False)
+    s.solve(rhs, b, 1e-300, 3, history=False)
+    s.close()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("eps", [1.0, 0.1, 0.01])
+def test_fp64_cycles_to_tolerance_match_oracle(eps):
+    n = 129
+    p = Problem(n, n, eps=eps)
+    g = p.grid()
+    rhs = W.aniso_rhs(n, 2)
+    ref = O.solve(p.oracle(), g.pack(rhs), np.zeros(g.n_unknowns), 1e-10, 2000)
+    s = p.solver()
+    x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    info = s.solve(torch.tensor(rhs, device="cuda"), x, 1e-10, 2000)
+    s.close()
+    assert info.status == 0 and abs(info.cycles - ref.cycles) <= 1
+    m = min(len(ref.history), len(info.history))
+    np.testing.assert_allclose(info.history[:m], ref.history[:m], rtol=1e-8, atol=HIST_ATOL * ref.history[0])
+    assert np.abs(g.pack(x.cpu().numpy()) - ref.x).max() <= 1e-9 * np.abs(ref.x).max()
+
+
+# ----------------------------------------------------------------------------- mixed precision
+
+
+@pytest.mark.parametrize("eps", [1.0, 0.1])
+def test_mixed_precision_reaches_tolerance(eps):
+    """Mixed form: the oracle's FP64 residual of the GPU solution is <= tol * r0
+    (plus FP64 evaluation noise), and it needs at most 2 more cycles than FP64."""
+    n = 257
+    p = Problem(n, n, eps=eps)
+    g = p.grid()
+    h = p.oracle()
+    rhs = W.aniso_rhs(n, 2)
+    ref = O.solve(h, g.pack(rhs), np.zeros(g.n_unknowns), 1e-10, 500)
+    s = p.solver(precision="mixed")
+    x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    info = s.solve(torch.tensor(rhs, device="cuda"), x, 1e-10, 500)
+    s.close()
+    assert info.status == 0
+    assert info.cycles <= ref.cycles + 2
+    r = O.residual_norm(h, g.pack(rhs), g.pack(x.cpu().numpy()))
+    assert r <= 1.05e-10 * ref.history[0]
+    diff = np.abs(g.pack(x.cpu().numpy()) - ref.x).max() / np.abs(ref.x).max()
+    assert diff < 1e-7, diff
+
+
+def test_mixed_first_cycle_close_to_oracle_mixed():
+    """One mixed outer step against the oracle's mixed step (FP32 inner cycle):
+    equal up to FP32 rounding of the correction."""
+    n = 129
+    p = Problem(n, n, eps=0.3)
+    g = p.grid()
+    h = p.oracle()
+    rhs = W.aniso_rhs(n, 2)
+    ref = O.solve_mixed(h, g.pack(rhs), np.zeros(g.n_unknowns), 1e-300, 2)
+    s = p.solver(precision="mixed")
+    x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    s.solve(torch.tensor(rhs, device="cuda"), x, 1e-300, 2, history=False)
+    s.close()
+    diff = np.abs(g.pack(x.cpu().numpy()) - ref.x).max() / np.abs(ref.x).max()
+    assert diff < 1e-5, diff
