@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--max-cycles", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eps", type=float, default=None, help="run one eps of the workload only (profiling)")
     return ap.parse_args()
 
 
@@ -49,7 +50,7 @@ def main():
     from paper_0805_3041_amd import mg
 
     n = 1025
-    eps_list = list(W.ANISO_EPS)
+    eps_list = list(W.ANISO_EPS) if args.eps is None else [args.eps]
     rhs = torch.tensor(W.aniso_rhs(n, 2), device="cuda")
     x0 = torch.tensor(W.aniso_x0(n, args.x0, 1), device="cuda")
     unknowns = (n - 2) ** 2

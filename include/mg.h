@@ -62,6 +62,7 @@ enum { MG_COEF_CONST5 = 0, MG_COEF_CELL9 = 1 };
 enum { MG_CYCLE_F = 0, MG_CYCLE_V = 1 };
 enum { MG_SMOOTH_JACOBI = 0, MG_SMOOTH_RBGS = 1, MG_SMOOTH_GS4C = 2 };
 enum { MG_PREC_FP64 = 0, MG_PREC_MIXED = 1 };
+enum { MG_TILES_FUSED = 0, MG_TILES_PER_OP = 1 };
 
 /* Grid: stored node counts and domain lengths.  A Dirichlet direction has
  * n = 2^k m + 1 nodes (h = l / (n - 1)); the periodic direction has n = 2^k m
@@ -91,7 +92,12 @@ typedef struct {
  * uses omega = 1).  precision MG_PREC_MIXED runs every cycle in FP32 inside an
  * FP64 defect-correction loop (x, rhs stay FP64 at the boundary).
  * coarse_cta_nodes: levels with at most this many stored nodes run inside one
- * persistent workgroup (0 = library default).  stream: hipStream_t. */
+ * persistent workgroup (0 = the largest levels whose sub-hierarchy fits in
+ * LDS).  tile_mode: MG_TILES_FUSED (default) runs each large-level visit as two
+ * LDS-tiled passes (smoothing fused with restriction / with prolongation);
+ * MG_TILES_PER_OP launches one kernel per smoothing sweep, restriction and
+ * prolongation (same results, bit for bit).  tile_x, tile_y: output tile of
+ * the fused passes (even, 0 = chosen per level).  stream: hipStream_t. */
 typedef struct {
   int32_t cycle;
   int32_t smoother;
@@ -99,6 +105,8 @@ typedef struct {
   double omega;
   int32_t precision;
   int32_t coarse_cta_nodes;
+  int32_t tile_mode;
+  int32_t tile_x, tile_y;
   void* stream;
 } mg_options;
 

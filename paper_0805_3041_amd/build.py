@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmg.so")
-SOURCES = ["mg_kernels.hip", "mg_api.hip"]
+SOURCES = ["mg_kernels.hip", "mg_fused.hip", "mg_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -22,6 +22,9 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
+    # no FMA contraction: a node gets bit-identical values from every kernel
+    # that can update it (tile passes, per-op kernels, coarse interpreter)
+    "-ffp-contract=off",
     "-shared",
     "-Wall",
     "-Wno-unused-result",

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "mg.h"
+#include "mg_fused.h"
 #include "mg_kernels.h"
 
 using namespace mg;
@@ -25,9 +26,7 @@ namespace {
 
 thread_local std::string g_thread_err;
 
-constexpr int DEFAULT_CTA_NODES = 17000;  // levels up to 129 x 129 run in one workgroup
-
-enum HostOpType { H_COLOR = 0, H_JACOBI, H_COPY, H_DR, H_PROLONG, H_COARSE, H_SUB };
+enum HostOpType { H_COLOR = 0, H_JACOBI, H_COPY, H_DR, H_PROLONG, H_COARSE, H_SUB, H_PRE, H_POST };
 
 struct HostOp {
   int type, level, arg;
@@ -76,6 +75,11 @@ struct mg_handle_s {
   double* dchol = nullptr;
   double** dcholp = nullptr;
 
+  // fused tile passes per level
+  std::vector<TileGeom> gpre, gpost;
+  bool norm_fused = false;   // FP64: the finest post-pass applies the stopping test
+  bool mixed_fused = false;  // mixed: the finest post-pass adds e into the FP64 iterate
+
   // cycle program
   std::vector<HostOp> prog;
   DOp* dprog = nullptr;
@@ -84,6 +88,10 @@ struct mg_handle_s {
   int nsub = 0;
 
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  // one cycle and eight cycles captured as graphs (kernel nodes only)
+  hipStream_t cap = nullptr;
+  hipGraphExec_t g1 = nullptr, g8 = nullptr;
 
   bool mixed() const { return opts.precision == MG_PREC_MIXED; }
 
@@ -124,12 +132,22 @@ bool can_coarsen(int nx, int ny, int py) {
 
 // ----------------------------------------------------------------------- cycle program
 
+// Bytes of LDS that levels l..L-1 need inside the coarse-level kernel.
+size_t sub_footprint(mg_handle h, int l) {
+  const size_t elem = h->mixed() ? sizeof(float) : sizeof(double);
+  const size_t narr = h->ncol == 0 ? 3 : 2;
+  size_t n = 0;
+  for (int k = l; k < h->nlev; ++k) n += (size_t)h->shp[k].nx * h->shp[k].ny;
+  return n * narr * elem;
+}
+
 struct Gen {
   mg_handle h;
-  int threshold;
+  int threshold;  // 0: the largest levels whose sub-hierarchy fits in LDS
   bool small(int l) const {
     const LevelShape& s = h->shp[l];
-    return (long)s.nx * s.ny <= threshold;
+    if (threshold > 0) return (long)s.nx * s.ny <= threshold;
+    return sub_footprint(h, l) <= SUB_LDS_BUDGET;
   }
   void smooth(std::vector<Abs>& out, int l, int steps) const {
     if (h->ncol == 0) {
@@ -176,15 +194,24 @@ struct Gen {
       out.push_back({H_SUB, l, kind, (int)subs.size() - 1});
       return;
     }
+    const bool fused = h->opts.tile_mode == MG_TILES_FUSED;
     std::vector<Abs> tmp;
-    smooth(tmp, l, h->opts.nu_pre);
-    for (const Abs& a : tmp) out.push_back({a.type, a.level, a.arg, -1});
-    out.push_back({H_DR, l, 0, -1});
+    if (fused) {
+      out.push_back({H_PRE, l, 0, -1});
+    } else {
+      smooth(tmp, l, h->opts.nu_pre);
+      for (const Abs& a : tmp) out.push_back({a.type, a.level, a.arg, -1});
+      out.push_back({H_DR, l, 0, -1});
+    }
     if (kind == MG_CYCLE_F) {
       host(out, subs, l + 1, MG_CYCLE_F);
       host(out, subs, l + 1, MG_CYCLE_V);
     } else {
       host(out, subs, l + 1, MG_CYCLE_V);
+    }
+    if (fused) {
+      out.push_back({H_POST, l, POST_PLAIN, -1});
+      return;
     }
     out.push_back({H_PROLONG, l, 0, -1});
     tmp.clear();
@@ -193,11 +220,56 @@ struct Gen {
   }
 };
 
+// Halo of a fused pass: one node per colour sweep (or Jacobi step), plus 2
+// for the defect and its restriction (pre) or 1 for the residual (post).
+int sweeps(mg_handle h, int steps) { return h->ncol == 0 ? steps : steps * h->ncol; }
+
+TileGeom choose_tile(mg_handle h, int l, int H, bool post) {
+  const LevelShape& s = h->shp[l];
+  const size_t elem = h->mixed() ? sizeof(float) : sizeof(double);
+  const int narr = h->ncol == 0 ? 3 : 2;
+  auto bytes = [&](int TX, int TY) {
+    const size_t W = TX + 2 * H, R = TY + 2 * H;
+    size_t n = W * R * narr;
+    if (post) n += ((W >> 1) + 2) * ((R >> 1) + 2);
+    return n * elem;
+  };
+  const bool fixed = h->opts.tile_x > 0 && h->opts.tile_y > 0;
+  int TX = h->opts.tile_x > 0 ? h->opts.tile_x : 64;
+  int TY = h->opts.tile_y > 0 ? h->opts.tile_y : 32;
+  auto ntiles = [&](int tx, int ty) { return (long)((s.nx + tx - 1) / tx) * ((s.ny + ty - 1) / ty); };
+  if (!fixed) {
+    while (ntiles(TX, TY) < 256 && TY > 8) TY >>= 1;
+    while (ntiles(TX, TY) < 256 && TX > 16) TX >>= 1;
+  }
+  while (bytes(TX, TY) > FUSED_LDS_MAX && TY > 2) TY >>= 1;
+  while (bytes(TX, TY) > FUSED_LDS_MAX && TX > 2) TX >>= 1;
+  return tile_geom(s.nx, s.ny, TX, TY, H);
+}
+
 mg_status build_program(mg_handle h) {
-  Gen g{h, h->opts.coarse_cta_nodes > 0 ? h->opts.coarse_cta_nodes : DEFAULT_CTA_NODES};
+  Gen g{h, h->opts.coarse_cta_nodes};
   std::vector<std::vector<Abs>> subs;
   h->prog.clear();
   g.host(h->prog, subs, 0, h->opts.cycle);
+  h->gpre.assign(h->nlev, TileGeom{});
+  h->gpost.assign(h->nlev, TileGeom{});
+  h->norm_fused = h->mixed_fused = false;
+  if (!h->prog.empty() && h->prog.back().type == H_POST && h->prog.back().level == 0) {
+    if (h->mixed()) {
+      h->prog.back().arg = POST_MIXED;
+      h->mixed_fused = true;
+    } else {
+      h->prog.back().arg = POST_NORM;
+      h->norm_fused = true;
+    }
+  }
+  for (const HostOp& op : h->prog) {
+    if (op.type == H_PRE) h->gpre[op.level] = choose_tile(h, op.level, sweeps(h, h->opts.nu_pre) + 2, false);
+    if (op.type == H_POST)
+      h->gpost[op.level] =
+          choose_tile(h, op.level, sweeps(h, h->opts.nu_post) + (op.arg == POST_NORM ? 1 : 0), true);
+  }
   std::vector<DOp> flat;
   std::vector<int> beg, cnt;
   for (const auto& s : subs) {
@@ -228,11 +300,12 @@ mg_status build_program(mg_handle h) {
   return MG_OK;
 }
 
+int stencil_kind(mg_handle h) { return h->kind == MG_COEF_CONST5 ? ST5 : ST9; }
+
 template <typename T>
-hipError_t run_op(mg_handle h, const HostOp& op, Level<T>* dL, T omega) {
+hipError_t run_op(mg_handle h, const HostOp& op, Level<T>* dL, T omega, hipStream_t st) {
   const int l = op.level;
   const LevelShape& s = h->shp[l];
-  hipStream_t st = h->stream;
   switch (op.type) {
     case H_COLOR: return launch_colour<T>(dL + l, s, op.arg, h->ncol, 1, st);
     case H_JACOBI: return launch_jacobi<T>(dL + l, s, op.arg, omega, 1, st);
@@ -240,25 +313,59 @@ hipError_t run_op(mg_handle h, const HostOp& op, Level<T>* dL, T omega) {
     case H_DR: return launch_dr<T>(dL + l, dL + l + 1, h->shp[l + 1], 1, st);
     case H_PROLONG: return launch_prolong<T>(dL + l, dL + l + 1, s, 1, st);
     case H_COARSE: return launch_coarse<T>(dL + l, h->dcholp, h->ncu, 1, st);
-    case H_SUB:
+    case H_PRE:
+      return launch_pre<T>(dL + l, dL + l + 1, h->gpre[l], h->opts.nu_pre, h->ncol, omega, stencil_kind(h), 1, st);
+    case H_POST:
+      return launch_post<T>(dL + l, dL + l + 1, h->gpost[l], h->opts.nu_post, h->ncol, omega, op.arg, h->dL64,
+                            stencil_kind(h), 1, st);
+    case H_SUB: {
+      const size_t bytes = sub_footprint(h, l);
+      if (bytes <= SUB_LDS_BUDGET)
+        return launch_subcycle_lds<T>(dL, h->nlev, l, h->dprog, h->dbeg + op.sub, h->dcnt + op.sub, h->dcholp,
+                                      h->ncu, omega, h->ncol, h->ncol == 0 ? 3 : 2, stencil_kind(h), bytes, 1, st);
       return launch_subcycle<T>(dL, h->nlev, h->dprog, h->dbeg + op.sub, h->dcnt + op.sub, h->dcholp, h->ncu, omega,
                                 h->ncol, 1, st);
+    }
   }
   return hipErrorInvalidValue;
 }
 
-// One cycle plus its stopping test.
-hipError_t enqueue_cycle(mg_handle h) {
+// One cycle plus its stopping test, on stream st.
+hipError_t enqueue_cycle(mg_handle h, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (!h->mixed()) {
     for (const HostOp& op : h->prog)
-      if ((e = run_op<double>(h, op, h->dL64, h->opts.omega)) != hipSuccess) return e;
-    return launch_resnorm<double>(h->dL64, h->shp[0], NORM_CHECK, nullptr, nullptr, 0, 1, h->stream);
+      if ((e = run_op<double>(h, op, h->dL64, h->opts.omega, st)) != hipSuccess) return e;
+    if (h->norm_fused) return hipSuccess;
+    return launch_resnorm<double>(h->dL64, h->shp[0], NORM_CHECK, nullptr, nullptr, 0, 1, st);
   }
   for (const HostOp& op : h->prog)
-    if ((e = run_op<float>(h, op, h->dL32, (float)h->opts.omega)) != hipSuccess) return e;
-  if ((e = launch_outer_update(h->dL64, h->dL32, h->shp[0], 1, h->stream)) != hipSuccess) return e;
-  return launch_resnorm<double>(h->dL64, h->shp[0], NORM_CHECK, nullptr, h->L32[0].b, h->L32[0].pitch, 1, h->stream);
+    if ((e = run_op<float>(h, op, h->dL32, (float)h->opts.omega, st)) != hipSuccess) return e;
+  if (!h->mixed_fused && (e = launch_outer_update(h->dL64, h->dL32, h->shp[0], 1, st)) != hipSuccess) return e;
+  return launch_resnorm<double>(h->dL64, h->shp[0], NORM_CHECK, nullptr, h->L32[0].b, h->L32[0].pitch, 1, st);
+}
+
+// Captures one cycle and eight cycles as graphs on a private stream (a graph
+// can then be launched on any stream, the null stream included).
+mg_status build_graphs(mg_handle h) {
+  HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  for (int k : {1, 8}) {
+    hipGraph_t graph = nullptr;
+    HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < k && e == hipSuccess; ++c) e = enqueue_cycle(h, h->cap);
+    hipError_t e2 = hipStreamEndCapture(h->cap, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(h, MG_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return fail(h, MG_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(e3));
+    (k == 1 ? h->g1 : h->g8) = ex;
+  }
+  return MG_OK;
 }
 
 // ----------------------------------------------------------------------- setup helpers
@@ -288,6 +395,9 @@ mg_status check_opts(const mg_options* o, int kind) {
   if (o->smoother == MG_SMOOTH_JACOBI && !finite_pos(o->omega)) return fail(nullptr, MG_EINVAL, "omega must be > 0");
   if (o->precision != MG_PREC_FP64 && o->precision != MG_PREC_MIXED) return fail(nullptr, MG_EINVAL, "bad precision");
   if (o->coarse_cta_nodes < 0) return fail(nullptr, MG_EINVAL, "coarse_cta_nodes must be >= 0");
+  if (o->tile_mode != MG_TILES_FUSED && o->tile_mode != MG_TILES_PER_OP) return fail(nullptr, MG_EINVAL, "bad tile_mode");
+  if (o->tile_x < 0 || o->tile_y < 0 || (o->tile_x & 1) || (o->tile_y & 1) || o->tile_x > 512 || o->tile_y > 512)
+    return fail(nullptr, MG_EINVAL, "tile_x and tile_y must be even, in [0, 512]");
   return MG_OK;
 }
 
@@ -311,6 +421,11 @@ mg_status sync_check(mg_handle h) {
 void release(mg_handle h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->g1) (void)hipGraphExecDestroy(h->g1);
+  if (h->g8) (void)hipGraphExecDestroy(h->g8);
+  h->g1 = h->g8 = nullptr;
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  h->cap = nullptr;
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
   if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -343,6 +458,7 @@ mg_status setup_impl(mg_handle h, const mg_grid* grid, const mg_coeffs* coeffs, 
     return fail(h, MG_EINVAL, "grid " + std::to_string(nx) + "x" + std::to_string(ny) + " supports at most " +
                                   std::to_string(maxlev) + " levels");
   h->nlev = levels ? levels : maxlev;
+  if (h->nlev > MAX_LEVELS) return fail(h, MG_EUNSUPPORTED, "more than " + std::to_string(MAX_LEVELS) + " levels");
   for (int l = 0; l < h->nlev; ++l) {
     h->shp.push_back({nx, ny, py, py ? ny : ny - 2});
     h->hx.push_back(grid->lx / (nx - 1));
@@ -363,7 +479,6 @@ mg_status setup_impl(mg_handle h, const mg_grid* grid, const mg_coeffs* coeffs, 
   HIPCHK(h, h->dalloc(&h->dstate, sizeof(SolveState)));
   HIPCHK(h, h->dalloc(&h->dstate_res, sizeof(SolveState)));
   HIPCHK(h, h->dalloc(&h->dLres, sizeof(Level<double>)));
-  HIPCHK(h, h->dalloc(&h->dpartial, MAX_NORM_BLOCKS * sizeof(double)));
   h->hist_cap = 4097;
   HIPCHK(h, h->dalloc(&h->dhist, h->hist_cap * sizeof(double)));
 
@@ -384,7 +499,6 @@ mg_status setup_impl(mg_handle h, const mg_grid* grid, const mg_coeffs* coeffs, 
 
   // level buffers
   const bool mixed = h->mixed();
-  const bool jac = h->ncol == 0;
   h->L64.resize(h->nlev);
   h->L32.resize(mixed ? h->nlev : 0);
   for (int l = 0; l < h->nlev; ++l) {
@@ -392,14 +506,14 @@ mg_status setup_impl(mg_handle h, const mg_grid* grid, const mg_coeffs* coeffs, 
     if (l == 0) {
       // finest FP64 level: x and b are the caller's arrays (pitch nx)
       h->L64[0] = make_level<double>(s, s.nx, h->dstate);
-      if (jac && !mixed) HIPCHK(h, h->dalloc(&h->L64[0].t, (size_t)s.nx * s.ny * sizeof(double)));
+      if (!mixed) HIPCHK(h, h->dalloc(&h->L64[0].t, (size_t)s.nx * s.ny * sizeof(double)));
     } else if (!mixed) {
       const int p = round_up(s.nx, 16);
       Level<double>& L = h->L64[l];
       L = make_level<double>(s, p, h->dstate);
       HIPCHK(h, h->dalloc(&L.x, (size_t)p * s.ny * sizeof(double)));
       HIPCHK(h, h->dalloc(&L.b, (size_t)p * s.ny * sizeof(double)));
-      if (jac) HIPCHK(h, h->dalloc(&L.t, (size_t)p * s.ny * sizeof(double)));
+      HIPCHK(h, h->dalloc(&L.t, (size_t)p * s.ny * sizeof(double)));
     }
     if (mixed) {
       const int p = round_up(s.nx, 32);
@@ -407,7 +521,7 @@ mg_status setup_impl(mg_handle h, const mg_grid* grid, const mg_coeffs* coeffs, 
       L = make_level<float>(s, p, h->dstate);
       HIPCHK(h, h->dalloc(&L.x, (size_t)p * s.ny * sizeof(float)));
       HIPCHK(h, h->dalloc(&L.b, (size_t)p * s.ny * sizeof(float)));
-      if (jac) HIPCHK(h, h->dalloc(&L.t, (size_t)p * s.ny * sizeof(float)));
+      HIPCHK(h, h->dalloc(&L.t, (size_t)p * s.ny * sizeof(float)));
     }
   }
 
@@ -495,9 +609,18 @@ mg_status setup_impl(mg_handle h, const mg_grid* grid, const mg_coeffs* coeffs, 
     HIPCHK(h,
            hipMemcpyAsync(h->dL32, h->L32.data(), h->nlev * sizeof(Level<float>), hipMemcpyHostToDevice, h->stream));
   }
+  HIPCHK(h, mixed ? prepare_subcycle_lds<float>() : prepare_subcycle_lds<double>());
+  HIPCHK(h, mixed ? prepare_fused<float>() : prepare_fused<double>());
   mg_status s = build_program(h);
   if (s != MG_OK) return s;
-  return sync_check(h);
+  // partial sums of a norm reduction: one per workgroup of the norm kernel or
+  // of the finest post-pass when it carries the stopping test
+  size_t nparts = MAX_NORM_BLOCKS;
+  if (h->norm_fused) nparts = std::max(nparts, (size_t)h->gpost[0].ntx * h->gpost[0].nty);
+  HIPCHK(h, h->dalloc(&h->dpartial, nparts * sizeof(double)));
+  s = sync_check(h);
+  if (s != MG_OK) return s;
+  return build_graphs(h);
 }
 
 mg_status grow_history(mg_handle h, int need) {
@@ -607,7 +730,8 @@ mg_status mg_solve(mg_handle h, const double* rhs, double* x, double tol, int32_
   int batch = 1;
   while (true) {
     const int nb = std::min(batch, max_cycles - queued);
-    for (int k = 0; k < nb; ++k) HIPCHK(h, enqueue_cycle(h));
+    for (int k = 0; k + 8 <= nb; k += 8) HIPCHK(h, hipGraphLaunch(h->g8, st));
+    for (int k = 0; k < nb % 8; ++k) HIPCHK(h, hipGraphLaunch(h->g1, st));
     queued += nb;
     HIPCHK(h, hipMemcpyAsync(&cur, h->dstate, sizeof(SolveState), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));

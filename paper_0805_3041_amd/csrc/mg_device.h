@@ -11,6 +11,15 @@
 
 namespace mg {
 
+// Pointer into LDS.  Written with the explicit address space so that every
+// access compiles to ds_read/ds_write rather than flat instructions.
+#define MG_LDS __attribute__((address_space(3)))
+
+template <typename T>
+__device__ __forceinline__ MG_LDS T* lds_cast(void* p) {
+  return (MG_LDS T*)(p);
+}
+
 // Per-problem solve state, in device memory.  Written only by the last
 // workgroup of a residual-norm kernel; read by every cycle kernel, which
 // returns at once when `done` is set.
@@ -72,72 +81,223 @@ __device__ __forceinline__ int row_hi(const Level<T>& L) { return L.py ? L.ny - 
 template <typename T>
 __device__ __forceinline__ const T* bandp(const Level<T>& L, int k) { return L.band + (size_t)k * L.bstride; }
 
-// Value of x at stored node (i, j); with MASK a Dirichlet boundary node reads
-// as 0 whatever is stored there (used where x comes from the caller).
-template <bool MASK, typename T>
-__device__ __forceinline__ T xval(const Level<T>& L, const T* __restrict__ x, int i, int j) {
-  if (MASK && (i == 0 || i == L.nx - 1 || (!L.py && (j == 0 || j == L.ny - 1)))) return (T)0;
-  return x[(size_t)j * L.pitch + i];
+// ---------------------------------------------------------------- x access
+// The arithmetic below reads x through an accessor: at(di, dj) is the value
+// at node (i + di, j + dj) of the node being updated (rows already wrapped).
+
+// Global array, rows jm, j, jp given by pointers already offset to column i.
+template <typename T>
+struct GX {
+  const T* rm;
+  const T* r0;
+  const T* rp;
+  __device__ __forceinline__ T at(int di, int dj) const { return dj < 0 ? rm[di] : (dj > 0 ? rp[di] : r0[di]); }
+};
+
+// Same, but a Dirichlet boundary node reads as 0 whatever is stored there
+// (used where x comes from the caller).
+template <typename T>
+struct GXMasked {
+  GX<T> g;
+  int i, j, nx, ny, py;
+  __device__ __forceinline__ T at(int di, int dj) const {
+    const int ii = i + di;
+    const int jj = j + dj;
+    if (ii == 0 || ii == nx - 1 || (!py && (jj == 0 || jj == ny - 1))) return (T)0;
+    return g.at(di, dj);
+  }
+};
+
+// Division by a small positive divisor fixed for a whole loop (a < 2^22):
+// float reciprocal, then a one-step correction.
+struct FDiv {
+  int d;
+  float inv;
+  __device__ __forceinline__ explicit FDiv(int dd) : d(dd), inv(1.0f / (float)dd) {}
+  __device__ __forceinline__ int q(int a) const {
+    int r = (int)((float)a * inv);
+    if (r * d > a) --r;
+    else if ((r + 1) * d <= a) ++r;
+    return r;
+  }
+};
+
+// LDS rows jm, j, jp, already offset to column i.
+template <typename T>
+struct LX3 {
+  const MG_LDS T* rm;
+  const MG_LDS T* r0;
+  const MG_LDS T* rp;
+  __device__ __forceinline__ T at(int di, int dj) const { return dj < 0 ? rm[di] : (dj > 0 ? rp[di] : r0[di]); }
+};
+
+// LDS tile with row pitch W; p points at the node itself.
+template <typename T>
+struct LXW {
+  const MG_LDS T* p;
+  int W;
+  __device__ __forceinline__ T at(int di, int dj) const { return p[dj * W + di]; }
+};
+
+template <typename T>
+__device__ __forceinline__ GX<T> gx(const T* x, int pitch, int i, int j, int jm, int jp) {
+  return GX<T>{x + (size_t)jm * pitch + i, x + (size_t)j * pitch + i, x + (size_t)jp * pitch + i};
 }
 
-// Sum over the neighbours q != p of a_pq x_q at interior node (i, j) of level L.
-// Rows jm, jp are j's wrapped neighbours.
-template <bool MASK = false, typename T>
-__device__ __forceinline__ T offdiag_sum(const Level<T>& L, const T* __restrict__ x, int i, int j, int jm, int jp) {
-  if (L.kind == ST5) {
-    const T xw = xval<MASK>(L, x, i - 1, j), xe = xval<MASK>(L, x, i + 1, j);
-    const T xs = xval<MASK>(L, x, i, jm), xn = xval<MASK>(L, x, i, jp);
-    return -(L.cx * (xw + xe) + L.cy * (xs + xn));
+// ---------------------------------------------------------------- arithmetic
+// Every kernel computes a node's value with these functions.  A node's x
+// neighbourhood and (9-point) coefficients are first gathered into registers
+// (so a thread can issue the loads of several nodes before using any), then
+// combined by the value functions below, always in the same order.
+
+// x around node p: c = p, then the 4 edge and 4 corner neighbours.
+template <typename T>
+struct Nbr {
+  T c, w, e, s, n, sw, se, nw, ne;
+};
+
+// a_pq of node p for its 9 couplings (symmetric band storage resolved).
+template <typename T>
+struct Cf {
+  T C, Ep, Ew, Np, Ns, NEp, NEsw, NWp, NWse;
+};
+
+// Stencil kind known at compile time (ST5, ST9) or read from the level (KDYN).
+constexpr int KDYN = -1;
+template <int K, typename T>
+__device__ __forceinline__ bool is5(const Level<T>& L) {
+  return K == ST5 ? true : (K == ST9 ? false : L.kind == ST5);
+}
+
+// Nodes a thread updates back to back in one sweep: all their loads are
+// issued before the first value is computed (nodes of one sweep never read
+// each other).  Fewer for 9-point operators, which need more registers.
+__host__ __device__ constexpr int nbatch(int K) { return K == ST5 ? 4 : 2; }
+
+template <int K = KDYN, typename T, typename X>
+__device__ __forceinline__ Nbr<T> gather(const Level<T>& L, const X& x, bool centre) {
+  Nbr<T> v{};
+  if (centre) v.c = x.at(0, 0);
+  v.w = x.at(-1, 0);
+  v.e = x.at(1, 0);
+  v.s = x.at(0, -1);
+  v.n = x.at(0, 1);
+  if (!is5<K>(L)) {
+    v.sw = x.at(-1, -1);
+    v.se = x.at(1, -1);
+    v.nw = x.at(-1, 1);
+    v.ne = x.at(1, 1);
   }
-  const int BP = L.bpitch;
-  const T* E = bandp(L, 1);
-  const T* N = bandp(L, 2);
-  const T* NE = bandp(L, 3);
-  const T* NW = bandp(L, 4);
-  const size_t rp = (size_t)j * BP, rs = (size_t)jm * BP;
-  T s = E[rp + i] * xval<MASK>(L, x, i + 1, j) + E[rp + i - 1] * xval<MASK>(L, x, i - 1, j);
-  s += N[rp + i] * xval<MASK>(L, x, i, jp) + N[rs + i] * xval<MASK>(L, x, i, jm);
-  s += NE[rp + i] * xval<MASK>(L, x, i + 1, jp) + NE[rs + i - 1] * xval<MASK>(L, x, i - 1, jm);
-  s += NW[rp + i] * xval<MASK>(L, x, i - 1, jp) + NW[rs + i + 1] * xval<MASK>(L, x, i + 1, jm);
+  return v;
+}
+
+// Coefficients at interior node (i, j); jm is j's wrapped lower row.
+template <int K = KDYN, typename T>
+__device__ __forceinline__ Cf<T> coefs(const Level<T>& L, int i, int j, int jm) {
+  Cf<T> c{};
+  if (is5<K>(L)) return c;
+  const size_t rp = (size_t)j * L.bpitch, rs = (size_t)jm * L.bpitch;
+  c.C = bandp(L, 0)[rp + i];
+  c.Ep = bandp(L, 1)[rp + i];
+  c.Ew = bandp(L, 1)[rp + i - 1];
+  c.Np = bandp(L, 2)[rp + i];
+  c.Ns = bandp(L, 2)[rs + i];
+  c.NEp = bandp(L, 3)[rp + i];
+  c.NEsw = bandp(L, 3)[rs + i - 1];
+  c.NWp = bandp(L, 4)[rp + i];
+  c.NWse = bandp(L, 4)[rs + i + 1];
+  return c;
+}
+
+// Sum over the neighbours q != p of a_pq x_q.
+template <int K = KDYN, typename T>
+__device__ __forceinline__ T offd(const Level<T>& L, const Cf<T>& a, const Nbr<T>& v) {
+  if (is5<K>(L)) return -(L.cx * (v.w + v.e) + L.cy * (v.s + v.n));
+  T s = a.Ep * v.e + a.Ew * v.w;
+  s += a.Np * v.n + a.Ns * v.s;
+  s += a.NEp * v.ne + a.NEsw * v.sw;
+  s += a.NWp * v.nw + a.NWse * v.se;
   return s;
 }
 
-template <typename T>
-__device__ __forceinline__ T diag_at(const Level<T>& L, int i, int j) {
-  if (L.kind == ST5) return L.dg;
-  return bandp(L, 0)[(size_t)j * L.bpitch + i];
+// Gauss-Seidel value: (b_p - sum_{q != p} a_pq x_q) / a_pp.
+template <int K = KDYN, typename T>
+__device__ __forceinline__ T gs_v(const Level<T>& L, const Cf<T>& a, const Nbr<T>& v, T bp) {
+  const T rhs = bp - offd<K>(L, a, v);
+  if (is5<K>(L)) return rhs * L.inv_dg;
+  return rhs / a.C;
 }
 
-// Gauss-Seidel value of node (i, j): (b_p - sum_{q != p} a_pq x_q) / a_pp.
-template <typename T>
-__device__ __forceinline__ T gs_value(const Level<T>& L, const T* __restrict__ x, const T* __restrict__ b,
-                                      int i, int j, int jm, int jp) {
-  const T off = offdiag_sum(L, x, i, j, jm, jp);
-  const T rhs = b[(size_t)j * L.pitch + i] - off;
-  if (L.kind == ST5) return rhs * L.inv_dg;
-  return rhs / diag_at(L, i, j);
-}
-
-// Defect b_p - (A x)_p at interior node (i, j).
-template <bool MASK = false, typename T>
-__device__ __forceinline__ T defect_at(const Level<T>& L, const T* __restrict__ x, const T* __restrict__ b,
-                                       int i, int j, int jm, int jp) {
-  const size_t p = (size_t)j * L.pitch + i;
-  return b[p] - (diag_at(L, i, j) * x[p] + offdiag_sum<MASK>(L, x, i, j, jm, jp));
+// Defect b_p - (A x)_p.
+template <int K = KDYN, typename T>
+__device__ __forceinline__ T defect_v(const Level<T>& L, const Cf<T>& a, const Nbr<T>& v, T bp) {
+  const T dg = is5<K>(L) ? L.dg : a.C;
+  return bp - (dg * v.c + offd<K>(L, a, v));
 }
 
 // Damped Jacobi value: x_p + omega (b - A x)_p / a_pp.
+template <int K = KDYN, typename T>
+__device__ __forceinline__ T jac_v(const Level<T>& L, const Cf<T>& a, const Nbr<T>& v, T bp, T omega) {
+  const T d = defect_v<K>(L, a, v, bp);
+  if (is5<K>(L)) return v.c + omega * d * L.inv_dg;
+  return v.c + omega * d / a.C;
+}
+
+// Accessor forms (gather, then the value functions above).
+template <int K = KDYN, typename T, typename X>
+__device__ __forceinline__ T gs_val(const Level<T>& L, const X& x, T bp, int i, int j, int jm) {
+  return gs_v<K>(L, coefs<K>(L, i, j, jm), gather<K>(L, x, false), bp);
+}
+
+template <int K = KDYN, typename T, typename X>
+__device__ __forceinline__ T defect_val(const Level<T>& L, const X& x, T bp, int i, int j, int jm) {
+  return defect_v<K>(L, coefs<K>(L, i, j, jm), gather<K>(L, x, true), bp);
+}
+
+template <int K = KDYN, typename T, typename X>
+__device__ __forceinline__ T jac_val(const Level<T>& L, const X& x, T bp, int i, int j, int jm, T omega) {
+  return jac_v<K>(L, coefs<K>(L, i, j, jm), gather<K>(L, x, true), bp, omega);
+}
+
+// Full weighting of a 3x3 block of fine defects d[row][col] (row 0 = south):
+// (1/16) [1 2 1; 2 4 2; 1 2 1].
+template <typename T>
+__device__ __forceinline__ T fw_combine(T s0, T s1, T s2) {  // s_r = row r's (1/4, 1/2, 1/4) combination
+  return (T)0.25 * (s0 + s2) + (T)0.5 * s1;
+}
+template <typename T>
+__device__ __forceinline__ T fw_row(T dw, T dc, T de) {
+  return (T)0.25 * (dw + de) + (T)0.5 * dc;
+}
+
+// Convenience wrappers over a global array.
+template <typename T>
+__device__ __forceinline__ T gs_value(const Level<T>& L, const T* __restrict__ x, const T* __restrict__ b,
+                                      int i, int j, int jm, int jp) {
+  return gs_val(L, gx(x, L.pitch, i, j, jm, jp), b[(size_t)j * L.pitch + i], i, j, jm);
+}
+
+template <typename T>
+__device__ __forceinline__ T defect_at(const Level<T>& L, const T* __restrict__ x, const T* __restrict__ b,
+                                       int i, int j, int jm, int jp) {
+  return defect_val(L, gx(x, L.pitch, i, j, jm, jp), b[(size_t)j * L.pitch + i], i, j, jm);
+}
+
+template <typename T>
+__device__ __forceinline__ T defect_masked(const Level<T>& L, const T* __restrict__ x, const T* __restrict__ b,
+                                           int i, int j, int jm, int jp) {
+  GXMasked<T> m{gx(x, L.pitch, i, j, jm, jp), i, j, L.nx, L.ny, L.py};
+  return defect_val(L, m, b[(size_t)j * L.pitch + i], i, j, jm);
+}
+
 template <typename T>
 __device__ __forceinline__ T jacobi_value(const Level<T>& L, const T* __restrict__ x, const T* __restrict__ b,
                                           int i, int j, int jm, int jp, T omega) {
-  const T d = defect_at(L, x, b, i, j, jm, jp);
-  const size_t p = (size_t)j * L.pitch + i;
-  if (L.kind == ST5) return x[p] + omega * d * L.inv_dg;
-  return x[p] + omega * d / diag_at(L, i, j);
+  return jac_val(L, gx(x, L.pitch, i, j, jm, jp), b[(size_t)j * L.pitch + i], i, j, jm, omega);
 }
 
-// Full-weighting restriction of the fine defect at coarse node (I, J):
-// (1/16) [1 2 1; 2 4 2; 1 2 1] centred on fine node (2I, 2J).
+// Full-weighting restriction of the fine defect at coarse node (I, J),
+// centred on fine node (2I, 2J).
 template <typename T>
 __device__ __forceinline__ T restrict_defect(const Level<T>& F, const T* __restrict__ x, const T* __restrict__ b,
                                              int I, int J) {
@@ -155,25 +315,34 @@ __device__ __forceinline__ T restrict_defect(const Level<T>& F, const T* __restr
     const T dw = defect_at(F, x, b, i0 - 1, j, jjm, jjp);
     const T dc = defect_at(F, x, b, i0, j, jjm, jjp);
     const T de = defect_at(F, x, b, i0 + 1, j, jjm, jjp);
-    acc[r] = (T)0.25 * (dw + de) + (T)0.5 * dc;
+    acc[r] = fw_row(dw, dc, de);
   }
-  return (T)0.25 * (acc[0] + acc[2]) + (T)0.5 * acc[1];
+  return fw_combine(acc[0], acc[1], acc[2]);
+}
+
+// Bilinear interpolation from the coarse values around fine node (i, j):
+// a00 = e(I, J), a10 = e(I+1, J), a01 = e(I, J+1), a11 = e(I+1, J+1) with
+// I = i >> 1, J = j >> 1; ox, oy = i & 1, j & 1.
+template <typename T>
+__device__ __forceinline__ T prolong_combine(T a00, T a10, T a01, T a11, int ox, int oy) {
+  if (!oy) {
+    if (!ox) return a00;
+    return (T)0.5 * (a00 + a10);
+  }
+  if (!ox) return (T)0.5 * (a00 + a01);
+  return (T)0.25 * ((a00 + a10) + (a01 + a11));
 }
 
 // Bilinear interpolation of the coarse correction at fine node (i, j).
 template <typename T>
 __device__ __forceinline__ T prolong_value(const T* __restrict__ xc, int pitchc, int nyc, int py, int i, int j) {
   const int I = i >> 1, J = j >> 1;
-  const bool ox = i & 1, oy = j & 1;
-  const int J1 = (oy && py && J + 1 == nyc) ? 0 : J + 1;
+  const int ox = i & 1, oy = j & 1;
   const T* r0 = xc + (size_t)J * pitchc;
-  if (!oy) {
-    if (!ox) return r0[I];
-    return (T)0.5 * (r0[I] + r0[I + 1]);
-  }
+  if (!oy) return prolong_combine(r0[I], ox ? r0[I + 1] : (T)0, (T)0, (T)0, ox, 0);
+  const int J1 = (py && J + 1 == nyc) ? 0 : J + 1;
   const T* r1 = xc + (size_t)J1 * pitchc;
-  if (!ox) return (T)0.5 * (r0[I] + r1[I]);
-  return (T)0.25 * ((r0[I] + r0[I + 1]) + (r1[I] + r1[I + 1]));
+  return prolong_combine(r0[I], ox ? r0[I + 1] : (T)0, r1[I], ox ? r1[I + 1] : (T)0, ox, 1);
 }
 
 }  // namespace mg

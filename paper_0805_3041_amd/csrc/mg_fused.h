@@ -1,0 +1,34 @@
+// Host-visible launchers of the fused, LDS-tiled level passes (mg_fused.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mg_kernels.h"
+
+namespace mg {
+
+constexpr size_t FUSED_LDS_MAX = 150 * 1024;
+
+enum PostMode { POST_PLAIN = 0, POST_NORM = 1, POST_MIXED = 2 };
+
+// Output tile TX x TY (both even), halo H, and the tile grid of a level.
+struct TileGeom {
+  int TX, TY, H, ntx, nty;
+};
+
+TileGeom tile_geom(int nx, int ny, int TX, int TY, int H);
+
+template <typename T>
+size_t pre_lds_bytes(const TileGeom& g, int ncol);
+template <typename T>
+size_t post_lds_bytes(const TileGeom& g, int ncol);
+template <typename T>
+hipError_t prepare_fused();
+template <typename T>
+hipError_t launch_pre(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g, int nsteps, int ncol, T omega,
+                      int kind, int nslots, hipStream_t st);
+template <typename T>
+hipError_t launch_post(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g, int nsteps, int ncol, T omega,
+                       int mode, const Level<double>* X64s, int kind, int nslots, hipStream_t st);
+
+}  // namespace mg

@@ -11,6 +11,9 @@ constexpr int MAX_COARSE_UNKNOWNS = 1024;  // coarsest grid solved by a dense Ch
 constexpr int SUB_NT = 1024;               // threads of the single-workgroup coarse-level kernel
 constexpr int MAX_NORM_BLOCKS = 1024;      // workgroups of a residual-norm reduction
 constexpr double DIVERGENCE_FACTOR = 1.0e6;
+constexpr int MAX_LEVELS = 24;
+constexpr int MAX_SUB_OPS = 1024;  // ops of a coarse-level program kept in LDS
+constexpr size_t SUB_LDS_BUDGET = 140 * 1024;  // dynamic LDS of the coarse-level kernel (160 KB per CU)
 
 enum NormMode { NORM_INIT = 0, NORM_CHECK = 1, NORM_RESID = 2 };
 
@@ -37,6 +40,16 @@ hipError_t launch_subcycle(const Level<T>* levs, int nlev, const DOp* prog, cons
 template <typename T>
 hipError_t launch_resnorm(const Level<T>* Ls, const LevelShape& s, int mode, T* rout, float* r32, int p32, int nslots,
                           hipStream_t st);
+
+template <typename T>
+hipError_t prepare_subcycle_lds();
+template <typename T>
+hipError_t launch_subcycle_lds(const Level<T>* levs, int nlev, int top, const DOp* prog, const int* beg,
+                               const int* cnt, const double* const* chol, int ncu, T omega, int ncol, int narr,
+                               int kind, size_t lds_bytes, int nslots, hipStream_t st);
+
+template <typename T>
+hipError_t launch_norm_finish(const Level<T>* Ls, int nblocks, int mode, int nslots, hipStream_t st);
 
 int norm_blocks(const LevelShape& s);
 

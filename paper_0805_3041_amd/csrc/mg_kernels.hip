@@ -189,34 +189,276 @@ __global__ void __launch_bounds__(NT) k_coarse(const Level<T>* __restrict__ Ls, 
   body_coarse(L, chol[blockIdx.z], n, g, threadIdx.x, NT);
 }
 
-// Single-workgroup interpreter: runs ops [beg[slot], beg[slot] + cnt[slot]) of
-// `prog` on the level array of its slot (levs + slot * nlev), one barrier
-// between ops.  Used for every level small enough that a launch per op would
-// cost more than the op itself.
+// --------------------------------------------------------------------------- op bodies on LDS levels
+// Levels held in LDS as dense [ny][nx] arrays (row pitch nx).  Threads map to
+// (column, row group) with power-of-two column groups and 32-bit offsets, so
+// the loops need no division; the node arithmetic is the shared one.
+
+__device__ __forceinline__ int ceil_log2(int v) { return v <= 1 ? 0 : 32 - __clz(v - 1); }
+
 template <typename T>
-__global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict__ levs, int nlev,
+__device__ __forceinline__ LX3<T> lgx(const MG_LDS T* x, int nx, int i, int j, int jm, int jp) {
+  return LX3<T>{x + jm * nx + i, x + j * nx + i, x + jp * nx + i};
+}
+
+template <typename T, int K>
+__device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, int c, int ncol, int tid) {
+  constexpr int NB = nbatch(K);
+  const int nx = L.nx, ny = L.ny, py = L.py;
+  const int lo = py ? 0 : 1, hi = py ? ny - 1 : ny - 2;
+  const int kl = ceil_log2((nx - 1) >> 1);
+  const int k = tid & ((1 << kl) - 1);
+  const int rg = SUB_NT >> kl;
+  int j = lo + (tid >> kl), jstep = rg;
+  int first_fixed = -1;
+  if (ncol == 4) {
+    const int j0 = lo + (((lo & 1) != (c >> 1)) ? 1 : 0);
+    j = j0 + 2 * (tid >> kl);
+    jstep = 2 * rg;
+    first_fixed = (c & 1) ? 1 : 2;
+  }
+  for (; j <= hi; j += NB * jstep) {
+    int pos[NB], ii[NB], jj[NB], jms[NB];
+    bool ok[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int ju = j + u * jstep;
+      const int first = first_fixed > 0 ? first_fixed : 1 + ((((1 + ju) & 1) != c) ? 1 : 0);
+      const int i = first + 2 * k;
+      ok[u] = ju <= hi && i <= nx - 2;
+      ii[u] = i;
+      jj[u] = ju;
+      jms[u] = wrap_dn(ju, ny, py);
+      pos[u] = ju * nx + i;
+    }
+    Nbr<T> v[NB];
+    Cf<T> a[NB];
+    T bp[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      if (!ok[u]) continue;
+      v[u] = gather<K>(L, lgx(x, nx, ii[u], jj[u], jms[u], wrap_up(jj[u], ny, py)), false);
+      bp[u] = b[pos[u]];
+      a[u] = coefs<K>(L, ii[u], jj[u], jms[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (ok[u]) x[pos[u]] = gs_v<K>(L, a[u], v[u], bp[u]);
+  }
+}
+
+template <typename T, int K>
+__device__ void lds_jacobi(const Level<T>& L, const MG_LDS T* src, MG_LDS T* dst, const MG_LDS T* b, T omega,
+                           int tid) {
+  constexpr int NB = nbatch(K);
+  const int nx = L.nx, ny = L.ny, py = L.py;
+  const int lo = py ? 0 : 1, hi = py ? ny - 1 : ny - 2;
+  const int kl = ceil_log2(nx - 2);
+  const int i = 1 + (tid & ((1 << kl) - 1));
+  if (i > nx - 2) return;
+  const int jstep = SUB_NT >> kl;
+  for (int j = lo + (tid >> kl); j <= hi; j += NB * jstep) {
+    Nbr<T> v[NB];
+    Cf<T> a[NB];
+    T bp[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int ju = j + u * jstep;
+      if (ju > hi) continue;
+      const int jm = wrap_dn(ju, ny, py);
+      v[u] = gather<K>(L, lgx(src, nx, i, ju, jm, wrap_up(ju, ny, py)), true);
+      bp[u] = b[ju * nx + i];
+      a[u] = coefs<K>(L, i, ju, jm);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int ju = j + u * jstep;
+      if (ju <= hi) dst[ju * nx + i] = jac_v<K>(L, a[u], v[u], bp[u], omega);
+    }
+  }
+}
+
+template <typename T>
+__device__ void lds_copy(const Level<T>& L, MG_LDS T* x, const MG_LDS T* t, int tid) {
+  const int nx = L.nx, ny = L.ny, py = L.py;
+  const int lo = py ? 0 : 1, hi = py ? ny - 1 : ny - 2;
+  const int kl = ceil_log2(nx - 2);
+  const int i = 1 + (tid & ((1 << kl) - 1));
+  if (i > nx - 2) return;
+  for (int j = lo + (tid >> kl); j <= hi; j += SUB_NT >> kl) x[j * nx + i] = t[j * nx + i];
+}
+
+template <typename T, int K>
+__device__ void lds_dr(const Level<T>& F, const MG_LDS T* xf, const MG_LDS T* bf, const Level<T>& C, MG_LDS T* xc,
+                       MG_LDS T* bc, int tid) {
+  const int nx = F.nx, ny = F.ny, py = F.py;
+  const int lo = C.py ? 0 : 1, hi = C.py ? C.ny - 1 : C.ny - 2;
+  const int kl = ceil_log2(C.nx - 2);
+  const int I = 1 + (tid & ((1 << kl) - 1));
+  if (I > C.nx - 2) return;
+  for (int J = lo + (tid >> kl); J <= hi; J += SUB_NT >> kl) {
+    const int i0 = 2 * I, j0 = 2 * J;
+    const int rows[3] = {wrap_dn(j0, ny, py), j0, wrap_up(j0, ny, py)};
+    T acc[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int j = rows[r];
+      const int jm = wrap_dn(j, ny, py), jp = wrap_up(j, ny, py);
+      const int q = j * nx;
+      const T dw = defect_val<K>(F, lgx(xf, nx, i0 - 1, j, jm, jp), bf[q + i0 - 1], i0 - 1, j, jm);
+      const T dc = defect_val<K>(F, lgx(xf, nx, i0, j, jm, jp), bf[q + i0], i0, j, jm);
+      const T de = defect_val<K>(F, lgx(xf, nx, i0 + 1, j, jm, jp), bf[q + i0 + 1], i0 + 1, j, jm);
+      acc[r] = fw_row(dw, dc, de);
+    }
+    const int pc = J * C.nx + I;
+    bc[pc] = fw_combine(acc[0], acc[1], acc[2]);
+    xc[pc] = (T)0;
+  }
+}
+
+template <typename T>
+__device__ void lds_prolong(const Level<T>& F, MG_LDS T* xf, const Level<T>& C, const MG_LDS T* xc, int tid) {
+  const int nx = F.nx, ny = F.ny, py = F.py;
+  const int lo = py ? 0 : 1, hi = py ? ny - 1 : ny - 2;
+  const int kl = ceil_log2(nx - 2);
+  const int i = 1 + (tid & ((1 << kl) - 1));
+  if (i > nx - 2) return;
+  const int I = i >> 1, ox = i & 1;
+  for (int j = lo + (tid >> kl); j <= hi; j += SUB_NT >> kl) {
+    const int J = j >> 1, oy = j & 1;
+    const MG_LDS T* r0 = xc + J * C.nx + I;
+    T v;
+    if (!oy) {
+      v = prolong_combine(r0[0], ox ? r0[1] : (T)0, (T)0, (T)0, ox, 0);
+    } else {
+      const int J1 = (py && J + 1 == C.ny) ? 0 : J + 1;
+      const MG_LDS T* r1 = xc + J1 * C.nx + I;
+      v = prolong_combine(r0[0], ox ? r0[1] : (T)0, r1[0], ox ? r1[1] : (T)0, ox, 1);
+    }
+    xf[j * nx + i] += v;
+  }
+}
+
+// Single-workgroup interpreter: runs ops [beg[slot], beg[slot] + cnt[slot]) of
+// `prog` on the levels of its slot (levs + slot * nlev), one barrier between
+// ops.  Used for every level small enough that a launch per op would cost
+// more than the op itself.  The op list and the level descriptors are first
+// copied to LDS so that no op waits on a global load to learn what to do.
+// IN_LDS: every level from `top` down also lives in LDS (x, b and, for
+// Jacobi, t as dense [ny][nx] arrays): the top level's x and b are read once
+// and x written back at exit; coarser levels never leave LDS.  Bands
+// (9-point operators) are read from global memory.
+__device__ __forceinline__ int pack_op(const DOp& o) { return o.type | (o.level << 4) | (o.arg << 12); }
+
+template <typename T, bool IN_LDS, int K>
+__global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict__ levs, int nlev, int top,
                                                      const DOp* __restrict__ prog, const int* __restrict__ beg,
-                                                     const int* __restrict__ cnt, const double* const* __restrict__ chol,
-                                                     int ncu, T omega, int ncol) {
+                                                     const int* __restrict__ cnt,
+                                                     const double* const* __restrict__ chol, int ncu, T omega,
+                                                     int ncol, int narr) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  MG_LDS T* lds = lds_cast<T>(smem_raw);
   __shared__ double g[MAX_COARSE_UNKNOWNS];
+  __shared__ int offs[MAX_LEVELS + 1];
+  __shared__ int sops[MAX_SUB_OPS];
   const int slot = blockIdx.z;
   const Level<T>* Ls = levs + (size_t)slot * nlev;
   if (Ls[0].st->done) return;
-  const int b0 = beg[slot], nops = cnt[slot];
   const int tid = threadIdx.x;
-  for (int k = 0; k < nops; ++k) {
-    const DOp op = prog[b0 + k];
-    const Level<T> L = Ls[op.level];
-    switch (op.type) {
-      case OP_COLOR: body_colour(L, op.arg, ncol, tid, SUB_NT); break;
-      case OP_JACOBI: body_jacobi(L, op.arg, omega, tid, SUB_NT); break;
-      case OP_COPY: body_copy(L, tid, SUB_NT); break;
-      case OP_DR: body_dr(L, Ls[op.level + 1], tid, SUB_NT); break;
-      case OP_PROLONG: body_prolong(L, Ls[op.level + 1], tid, SUB_NT); break;
-      case OP_COARSE: body_coarse(L, chol[slot], ncu, g, tid, SUB_NT); break;
-      default: break;
+  const int b0 = beg[slot], nops = cnt[slot];
+  const bool ops_in_lds = nops <= MAX_SUB_OPS;
+  if (ops_in_lds)
+    for (int k = tid; k < nops; k += SUB_NT) sops[k] = pack_op(prog[b0 + k]);
+  if (IN_LDS && tid == 0) {
+    int o = 0;
+    for (int l = top; l < nlev; ++l) {
+      offs[l] = o;
+      o += narr * Ls[l].nx * Ls[l].ny;
+    }
+    offs[nlev] = o;
+  }
+  __syncthreads();
+  if (IN_LDS) {
+    const int total = offs[nlev];
+    for (int k = tid; k < total; k += SUB_NT) lds[k] = (T)0;
+    __syncthreads();
+    const Level<T> G = Ls[top];
+    const int lo = row_lo(G), nr = row_hi(G) - lo + 1, ni = G.nx - 2, n = nr * ni;
+    MG_LDS T* xl = lds + offs[top];
+    MG_LDS T* bl = xl + G.nx * G.ny;
+    for (int idx = tid; idx < n; idx += SUB_NT) {
+      const int r = idx / ni;
+      const int i = idx - r * ni + 1, j = lo + r;
+      xl[j * G.nx + i] = G.x[(size_t)j * G.pitch + i];
+      bl[j * G.nx + i] = G.b[(size_t)j * G.pitch + i];
     }
     __syncthreads();
+  }
+  for (int k = 0; k < nops; ++k) {
+    // op and level descriptor through the scalar cache (uniform index)
+    int type, l, arg;
+    if (ops_in_lds) {
+      const int w = __builtin_amdgcn_readfirstlane(sops[k]);
+      type = w & 15;
+      l = (w >> 4) & 255;
+      arg = w >> 12;
+    } else {
+      const DOp o = prog[b0 + k];
+      type = o.type;
+      l = o.level;
+      arg = o.arg;
+    }
+    Level<T> L = Ls[l];
+    if (IN_LDS) {
+      const int nl = L.nx * L.ny;
+      L.x = (T*)(lds + offs[l]);  // generic view, used by the coarsest solve only
+      L.b = L.x + nl;
+      L.t = L.b + nl;
+      L.pitch = L.nx;
+    }
+    if (IN_LDS) {
+      MG_LDS T* xl = lds + offs[l];
+      MG_LDS T* bl = xl + L.nx * L.ny;
+      MG_LDS T* tl = bl + L.nx * L.ny;
+      switch (type) {
+        case OP_COLOR: lds_colour<T, K>(L, xl, bl, arg, ncol, tid); break;
+        case OP_JACOBI: lds_jacobi<T, K>(L, arg == 0 ? xl : tl, arg == 0 ? tl : xl, bl, omega, tid); break;
+        case OP_COPY: lds_copy(L, xl, tl, tid); break;
+        case OP_DR:
+        case OP_PROLONG: {
+          const Level<T> C = Ls[l + 1];
+          MG_LDS T* xc = lds + offs[l + 1];
+          if (type == OP_DR)
+            lds_dr<T, K>(L, xl, bl, C, xc, xc + C.nx * C.ny, tid);
+          else
+            lds_prolong(L, xl, C, xc, tid);
+          break;
+        }
+        case OP_COARSE: body_coarse(L, chol[slot], ncu, g, tid, SUB_NT); break;
+        default: break;
+      }
+    } else {
+      switch (type) {
+        case OP_COLOR: body_colour(L, arg, ncol, tid, SUB_NT); break;
+        case OP_JACOBI: body_jacobi(L, arg, omega, tid, SUB_NT); break;
+        case OP_COPY: body_copy(L, tid, SUB_NT); break;
+        case OP_DR: body_dr(L, Ls[l + 1], tid, SUB_NT); break;
+        case OP_PROLONG: body_prolong(L, Ls[l + 1], tid, SUB_NT); break;
+        case OP_COARSE: body_coarse(L, chol[slot], ncu, g, tid, SUB_NT); break;
+        default: break;
+      }
+    }
+    __syncthreads();
+  }
+  if (IN_LDS) {
+    const Level<T> G = Ls[top];
+    const int lo = row_lo(G), nr = row_hi(G) - lo + 1, ni = G.nx - 2, n = nr * ni;
+    const MG_LDS T* xl = lds + offs[top];
+    for (int idx = tid; idx < n; idx += SUB_NT) {
+      const int r = idx / ni;
+      const int i = idx - r * ni + 1, j = lo + r;
+      G.x[(size_t)j * G.pitch + i] = xl[j * G.nx + i];
+    }
   }
 }
 
@@ -236,47 +478,41 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
-// Finishes a norm reduction: the last workgroup to arrive sums the partials
-// in index order and applies the stopping test.
-__device__ void finish_norm(SolveState* st, double part, int nblocks, int mode) {
-  __shared__ int is_last;
-  if (threadIdx.x == 0) {
-    st->partial[blockIdx.x] = part;
-    __threadfence();
-    const unsigned prev = atomicAdd(&st->counter, 1u);
-    is_last = (prev == (unsigned)nblocks - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    volatile double* pp = st->partial;
-    for (int k = 0; k < nblocks; ++k) s += pp[k];
-    const double nrm = sqrt(s);
-    st->counter = 0u;
-    st->prev = st->last;
-    st->last = nrm;
-    if (mode == NORM_INIT) {
-      st->r0 = nrm;
-      st->cycles = 0;
-      if (st->hist_cap > 0) st->history[0] = nrm;
-      st->done = (nrm == 0.0) ? 1 : 0;
-    } else if (mode == NORM_CHECK) {
-      const int c = st->cycles + 1;
-      st->cycles = c;
-      if (c < st->hist_cap) st->history[c] = nrm;
-      if (nrm <= st->tol * st->r0)
-        st->done = 1;
-      else if (!(nrm <= DIVERGENCE_FACTOR * st->r0))  // also catches NaN
-        st->done = 2;
-    }
-    __threadfence();
+// Stopping test from the partial sums of a norm reduction (one workgroup per
+// problem slot, launched after the kernel that wrote the partials).  Thread
+// t sums partials t, t + NT, ... in order, then a fixed tree: the result does
+// not depend on scheduling.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_norm_finish(const Level<T>* __restrict__ Ls, int nblocks, int mode) {
+  __shared__ double sh[NT / 64];
+  SolveState* st = Ls[blockIdx.z].st;
+  if (mode == NORM_CHECK && st->done) return;
+  double v = 0.0;
+  for (int k = threadIdx.x; k < nblocks; k += NT) v += st->partial[k];
+  const double s = block_sum(v, sh);
+  if (threadIdx.x != 0) return;
+  const double nrm = sqrt(s);
+  st->prev = st->last;
+  st->last = nrm;
+  if (mode == NORM_INIT) {
+    st->r0 = nrm;
+    st->cycles = 0;
+    if (st->hist_cap > 0) st->history[0] = nrm;
+    st->done = (nrm == 0.0) ? 1 : 0;
+  } else if (mode == NORM_CHECK) {
+    const int c = st->cycles + 1;
+    st->cycles = c;
+    if (c < st->hist_cap) st->history[c] = nrm;
+    if (nrm <= st->tol * st->r0)
+      st->done = 1;
+    else if (!(nrm <= DIVERGENCE_FACTOR * st->r0))  // also catches NaN
+      st->done = 2;
   }
 }
 
-// r = b - A x on level L (FP64 accumulation of the norm), boundary x read as 0
-// when mask_boundary.  Optional outputs: r64 (pitch L.pitch) and r32 (pitch p32).
+// r = b - A x on level L (FP64 accumulation), boundary x read as 0.
+// Optional outputs r (pitch L.pitch) and r32 (pitch p32).  Writes one partial
+// sum of squares per workgroup; k_norm_finish completes the norm.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_resnorm(const Level<T>* __restrict__ Ls, int mode, T* __restrict__ rout,
                                                 float* __restrict__ r32, int p32) {
@@ -292,13 +528,13 @@ __global__ void __launch_bounds__(NT) k_resnorm(const Level<T>* __restrict__ Ls,
     const int i = idx - r * ni + 1;
     const int j = lo + r;
     const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
-    const T d = defect_at<true>(L, L.x, L.b, i, j, jm, jp);
+    const T d = defect_masked(L, L.x, L.b, i, j, jm, jp);
     if (rout) rout[(size_t)j * L.pitch + i] = d;
     if (r32) r32[(size_t)j * p32 + i] = (float)d;
     acc += (double)d * (double)d;
   }
   const double part = block_sum(acc, sh);
-  finish_norm(st, part, gridDim.x, mode);
+  if (threadIdx.x == 0) st->partial[blockIdx.x] = part;
 }
 
 // Mixed precision outer update: x (FP64) += e (FP32), e = 0.
@@ -619,8 +855,33 @@ hipError_t launch_coarse(const Level<T>* Ls, const double* const* chol, int n, i
 template <typename T>
 hipError_t launch_subcycle(const Level<T>* levs, int nlev, const DOp* prog, const int* beg, const int* cnt,
                            const double* const* chol, int ncu, T omega, int ncol, int nslots, hipStream_t st) {
-  hipLaunchKernelGGL(k_subcycle<T>, dim3(1, 1, nslots), dim3(SUB_NT), 0, st, levs, nlev, prog, beg, cnt, chol, ncu,
-                     omega, ncol);
+  hipLaunchKernelGGL((k_subcycle<T, false, KDYN>), dim3(1, 1, nslots), dim3(SUB_NT), 0, st, levs, nlev, 0, prog, beg,
+                     cnt, chol, ncu, omega, ncol, 0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t prepare_subcycle_lds() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_subcycle<T, true, ST5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)SUB_LDS_BUDGET);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_subcycle<T, true, ST9>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)SUB_LDS_BUDGET);
+}
+
+template <typename T>
+hipError_t launch_subcycle_lds(const Level<T>* levs, int nlev, int top, const DOp* prog, const int* beg,
+                               const int* cnt, const double* const* chol, int ncu, T omega, int ncol, int narr,
+                               int kind, size_t lds_bytes, int nslots, hipStream_t st) {
+  auto k = kind == ST5 ? k_subcycle<T, true, ST5> : k_subcycle<T, true, ST9>;
+  hipLaunchKernelGGL(k, dim3(1, 1, nslots), dim3(SUB_NT), lds_bytes, st, levs, nlev, top, prog, beg, cnt, chol, ncu,
+                     omega, ncol, narr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_norm_finish(const Level<T>* Ls, int nblocks, int mode, int nslots, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm_finish<T>, dim3(1, 1, nslots), dim3(NT), 0, st, Ls, nblocks, mode);
   return hipGetLastError();
 }
 
@@ -635,8 +896,11 @@ int norm_blocks(const LevelShape& s) {
 template <typename T>
 hipError_t launch_resnorm(const Level<T>* Ls, const LevelShape& s, int mode, T* rout, float* r32, int p32, int nslots,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_resnorm<T>, dim3(norm_blocks(s), 1, nslots), dim3(NT), 0, st, Ls, mode, rout, r32, p32);
-  return hipGetLastError();
+  const int nb = norm_blocks(s);
+  hipLaunchKernelGGL(k_resnorm<T>, dim3(nb, 1, nslots), dim3(NT), 0, st, Ls, mode, rout, r32, p32);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_norm_finish<T>(Ls, nb, mode, nslots, st);
 }
 
 hipError_t launch_outer_update(const Level<double>* L64, const Level<float>* L32, const LevelShape& s, int nslots,
@@ -719,7 +983,11 @@ hipError_t launch_coeff_grad(const double* u, const double* lam, double* g, int 
   template hipError_t launch_coarse<T>(const Level<T>*, const double* const*, int, int, hipStream_t);             \
   template hipError_t launch_subcycle<T>(const Level<T>*, int, const DOp*, const int*, const int*,                \
                                          const double* const*, int, T, int, int, hipStream_t);                     \
-  template hipError_t launch_resnorm<T>(const Level<T>*, const LevelShape&, int, T*, float*, int, int, hipStream_t);
+  template hipError_t launch_resnorm<T>(const Level<T>*, const LevelShape&, int, T*, float*, int, int, hipStream_t); \
+  template hipError_t prepare_subcycle_lds<T>();                                                                   \
+  template hipError_t launch_norm_finish<T>(const Level<T>*, int, int, int, hipStream_t);                          \
+  template hipError_t launch_subcycle_lds<T>(const Level<T>*, int, int, const DOp*, const int*, const int*,        \
+                                             const double* const*, int, T, int, int, int, size_t, int, hipStream_t);
 
 MG_INSTANTIATE(double)
 MG_INSTANTIATE(float)

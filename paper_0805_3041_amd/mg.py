@@ -23,6 +23,7 @@ MG_COEF_CONST5, MG_COEF_CELL9 = 0, 1
 MG_CYCLE_F, MG_CYCLE_V = 0, 1
 MG_SMOOTH_JACOBI, MG_SMOOTH_RBGS, MG_SMOOTH_GS4C = 0, 1, 2
 MG_PREC_FP64, MG_PREC_MIXED = 0, 1
+MG_TILES_FUSED, MG_TILES_PER_OP = 0, 1
 
 SMOOTHERS = {"jacobi": MG_SMOOTH_JACOBI, "rbgs": MG_SMOOTH_RBGS, "gs4c": MG_SMOOTH_GS4C}
 CYCLES = {"F": MG_CYCLE_F, "V": MG_CYCLE_V}
@@ -47,7 +48,8 @@ class mg_coeffs(ctypes.Structure):
 class mg_options(ctypes.Structure):
     _fields_ = [("cycle", ctypes.c_int32), ("smoother", ctypes.c_int32), ("nu_pre", ctypes.c_int32),
                 ("nu_post", ctypes.c_int32), ("omega", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("coarse_cta_nodes", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("coarse_cta_nodes", ctypes.c_int32), ("tile_mode", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("tile_y", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class mg_info(ctypes.Structure):
@@ -122,6 +124,8 @@ def _check_f64(t: torch.Tensor, shape, name):
 
 def _stream_ptr(stream):
     if stream is None:
+        if not torch.cuda.is_available():
+            return ctypes.c_void_p(None)
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
 
@@ -200,10 +204,14 @@ def mg_level_shape(h, l: int):
     return nx.value, ny.value
 
 
+TILE_MODES = {"fused": MG_TILES_FUSED, "per_op": MG_TILES_PER_OP}
+
+
 def make_options(cycle="F", smoother="rbgs", nu_pre=2, nu_post=2, omega=0.8, precision="fp64",
-                 coarse_cta_nodes=0, stream=None) -> mg_options:
+                 coarse_cta_nodes=0, tile_mode="fused", tile_x=0, tile_y=0, stream=None) -> mg_options:
     return mg_options(CYCLES[cycle], SMOOTHERS[smoother], int(nu_pre), int(nu_post), float(omega),
-                      PRECISIONS[precision], int(coarse_cta_nodes), _stream_ptr(stream))
+                      PRECISIONS[precision], int(coarse_cta_nodes), TILE_MODES[tile_mode], int(tile_x), int(tile_y),
+                      _stream_ptr(stream))
 
 
 class Solver:

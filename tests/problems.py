@@ -52,13 +52,13 @@ class Problem:
             return O.hierarchy_q1(g, kx, ky, opts, self.levels, separable=True)
         return O.hierarchy_q1(g, kx, ky, opts, self.levels)
 
-    def solver(self, precision="fp64", coarse_cta_nodes=0):
+    def solver(self, precision="fp64", coarse_cta_nodes=0, **extra):
         import torch
         from paper_0805_3041_amd import mg
         c = self.coefficients()
         kw = dict(periodic_y=self.periodic_y, levels=self.levels, cycle=self.cycle, smoother=self.smoother,
                   nu_pre=self.nu_pre, nu_post=self.nu_post, omega=self.omega, precision=precision,
-                  coarse_cta_nodes=coarse_cta_nodes)
+                  coarse_cta_nodes=coarse_cta_nodes, **extra)
         if c is None:
             return mg.Solver(self.nx, self.ny, eps_x=self.eps, eps_y=1.0, **kw)
         kx, ky, oned = c

@@ -45,7 +45,7 @@ def test_status_strings(mg):
 
 
 def _setup(mg, grid, coeffs, levels=0, **opt):
-    opts = mg.mg_options(mg.MG_CYCLE_F, mg.MG_SMOOTH_RBGS, 2, 2, 0.8, mg.MG_PREC_FP64, 0, None)
+    opts = mg.make_options()
     for k, v in opt.items():
         setattr(opts, k, v)
     h = ctypes.c_void_p()
@@ -69,6 +69,9 @@ def _setup(mg, grid, coeffs, levels=0, **opt):
     dict(opt=dict(precision=5)),
     dict(opt=dict(smoother=0, omega=float("inf"))),
     dict(opt=dict(coarse_cta_nodes=-5)),
+    dict(opt=dict(tile_mode=2)),
+    dict(opt=dict(tile_x=7)),
+    dict(opt=dict(tile_y=-2)),
     dict(levels=-1),
     dict(cell9_null=True),
     dict(cell9_rbgs=True, status=-4),

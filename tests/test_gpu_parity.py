@@ -306,3 +306,66 @@ def test_mixed_first_cycle_close_to_oracle_mixed():
     s.close()
     diff = np.abs(g.pack(x.cpu().numpy()) - ref.x).max() / np.abs(ref.x).max()
     assert diff < 1e-5, diff
+
+
+# ----------------------------------------------------------------------------- fused tiles
+
+
+FUSED_CASES = [
+    dict(p=dict(nx=129, ny=129, eps=0.01, smoother="rbgs"), cta=300),
+    dict(p=dict(nx=257, ny=257, eps=0.1, smoother="rbgs", nu_pre=1, nu_post=3), cta=300),
+    dict(p=dict(nx=257, ny=257, eps=1.0, smoother="rbgs", nu_pre=4, nu_post=4), cta=300),
+    dict(p=dict(nx=65, ny=64, periodic_y=True, eps=0.5, smoother="rbgs"), cta=100),
+    dict(p=dict(nx=97, ny=49, eps=0.3, smoother="rbgs"), cta=100),
+    dict(p=dict(nx=129, ny=128, periodic_y=True, q1="annulus", smoother="gs4c"), cta=300),
+    dict(p=dict(nx=129, ny=129, q1="grf", smoother="gs4c"), cta=300),
+    dict(p=dict(nx=129, ny=129, q1="grf", smoother="jacobi", nu_pre=3, nu_post=1), cta=300),
+    dict(p=dict(nx=65, ny=65, smoother="jacobi"), cta=1),
+    dict(p=dict(nx=129, ny=129, eps=0.2, smoother="rbgs", cycle="V"), cta=100, tile=(16, 4)),
+    dict(p=dict(nx=129, ny=129, eps=0.2, smoother="gs4c"), cta=100, tile=(128, 32)),
+    dict(p=dict(nx=257, ny=257, eps=0.05, smoother="rbgs"), cta=100, tile=(32, 8)),
+]
+
+
+@pytest.mark.parametrize("case", FUSED_CASES, ids=[str(i) for i in range(len(FUSED_CASES))])
+def test_fused_tiles_equal_per_op_bitwise(case):
+    """The LDS-tiled passes give the per-op kernels' iterate bit for bit, and
+    both match the oracle."""
+    p = Problem(**case["p"])
+    rhs = W.normal_field(p.nx, p.ny, 21, p.periodic_y)
+    x0 = W.uniform_field(p.nx, p.ny, 22, p.periodic_y)
+    tx, ty = case.get("tile", (0, 0))
+    a = p.solver(coarse_cta_nodes=case["cta"], tile_mode="per_op")
+    b = p.solver(coarse_cta_nodes=case["cta"], tile_mode="fused", tile_x=tx, tile_y=ty)
+    try:
+        xa = gpu_iterates(a, rhs, x0, 2)
+        xb = gpu_iterates(b, rhs, x0, 2)
+    finally:
+        a.close()
+        b.close()
+    for u, v in zip(xa, xb):
+        assert np.array_equal(u, v)
+    g = p.grid()
+    xo = oracle_iterates(p.oracle(), g, rhs, x0, 2)
+    for u, v in zip(xb, xo):
+        assert np.abs(g.pack(u) - v).max() <= PARITY * np.abs(v).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_solve_matches_per_op_solve(precision):
+    """Whole solves (stopping test fused into the finest post-pass) agree with the per-op path."""
+    n = 257
+    p = Problem(n, n, eps=0.05)
+    rhs = torch.tensor(W.aniso_rhs(n, 2), device="cuda")
+    out = []
+    for mode in ("per_op", "fused"):
+        s = p.solver(precision=precision, tile_mode=mode)
+        x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        info = s.solve(rhs, x, 1e-10, 1000)
+        s.close()
+        out.append((info, x.cpu().numpy()))
+    (ia, xa), (ib, xb) = out
+    assert ia.status == ib.status == 0 and ia.cycles == ib.cycles
+    assert np.array_equal(xa, xb)
+    # same iterates; the norms are summed in a different order (tiles vs rows)
+    np.testing.assert_allclose(ia.history, ib.history, rtol=1e-14, atol=0)
