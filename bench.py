@@ -2,11 +2,17 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload aniso1025]
 
-A step solves every problem of the workload to a 1e-10 relative residual
-(||b - A x_k|| <= 1e-10 ||b - A x_0||) from the stated start vector; inputs are
-resident in device memory before the timed region.  `value` is unknowns solved
-per second over the timed steps in the headline precision; the other
-precision's figure is reported beside it.  Prints one JSON line.
+Workload aniso1025: -(eps u_xx + u_yy) = f on the unit square, 1025 x 1025
+nodes, zero Dirichlet, 5-point finite differences, f = N(0, 1) (seed 2),
+x0 = 0, red-black Gauss-Seidel 2/2, F-cycle over 10 levels down to 3 x 3.
+One step solves the four problems eps in {1, 1e-1, 1e-2, 1e-3} to a 1e-10
+relative residual (||b - A x_k|| <= 1e-10 ||b - A x_0||), inputs resident in
+device memory.  `value` = unknowns solved per second in the headline
+precision (FP32 cycles inside FP64 defect correction); the FP64 form is
+timed beside it.  `roofline` reports the finest-level post-pass (the
+heaviest HBM pass of a cycle) timed with HIP events on the solver's stream;
+`cpu_baseline` times the CPU oracle on a bounded sample of the same
+workload.  Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -14,6 +20,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -21,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 TOL = 1e-10
+HBM_PEAK_GBS = 8000.0
 
 
 def parse():
@@ -33,15 +41,78 @@ def parse():
     ap.add_argument("--x0", default="zero", choices=["zero", "uniform"])
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--max-cycles", type=int, default=20000)
+    ap.add_argument("--eps", type=float, default=None, help="one eps of the workload only (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--eps", type=float, default=None, help="run one eps of the workload only (profiling)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device copy of 512 MiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+# Algorithmic bytes per stored fine node of the finest-level fused passes
+# (5-point operator): reads and writes the pass cannot avoid.
+#   FP64 pre-pass : read x, b; write smoothed x; write coarse b and x (1/4 node each)
+#   FP64 post-pass: read smoothed x, b, coarse x (1/4); write x
+#   FP32 pre-pass : same with 4-byte values
+#   FP32 post-pass (mixed, finest level): read e, r, coarse e (1/4); read and
+#                   write the FP64 iterate; write e = 0
+BYTES_PER_NODE = {
+    ("fp64", 0): 8 + 8 + 8 + 2 + 2,
+    ("fp64", 1): 8 + 8 + 2 + 8,
+    ("mixed", 0): 4 + 4 + 4 + 1 + 1,
+    ("mixed", 1): 4 + 4 + 1 + 8 + 8 + 4,
+}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(n, eps_list, cycles_per_eps, nu, seconds):
+    """The oracle (FP64, scipy.sparse, one thread) runs F-cycles of the
+    workload's hardest problem for about `seconds`; its time per cycle times
+    the cycles the workload needs gives its unknowns/s."""
+    import numpy as np
+
+    from oracle import mg_oracle as O
+    import workloads as W
+
+    g = O.Grid(n, n)
+    eps = min(eps_list)
+    h = O.hierarchy_5pt(g, eps, 1.0, O.Options(smoother="rbgs", nu_pre=nu, nu_post=nu))
+    b = g.pack(W.aniso_rhs(n, 2))
+    x = np.zeros(g.n_unknowns)
+    done = 0
+    t0 = time.perf_counter()
+    while done < 2 or time.perf_counter() - t0 < seconds:
+        x = O.mg_cycle(h, 0, x, b, "F")
+        done += 1
+    t = (time.perf_counter() - t0) / done
+    total_cycles = sum(cycles_per_eps)
+    unknowns = (n - 2) ** 2 * len(eps_list)
+    return {
+        "value": unknowns / (t * total_cycles),
+        "unit": "unknowns/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{done} FP64 F-cycles of the eps={eps:g} problem at {n}x{n} ({t:.3f} s per cycle), "
+                  f"scaled to the {total_cycles} cycles the workload needs",
+        "host_cpu": cpu_model(),
+        "host_threads_available": os.cpu_count(),
+    }
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}), flush=True)
+        print(json.dumps({"error": "this build runs on one GPU only: collectives and multi-GPU sharding are not "
+                                   "built; run with --gpus 1"}), flush=True)
         sys.exit(2)
     import numpy as np
     import torch
@@ -55,41 +126,64 @@ def main():
     x0 = torch.tensor(W.aniso_x0(n, args.x0, 1), device="cuda")
     unknowns = (n - 2) ** 2
 
-    def run(precision, steps, warmup):
-        solvers = [mg.Solver(n, n, eps_x=e, smoother="rbgs", nu_pre=args.nu, nu_post=args.nu,
-                             precision=precision) for e in eps_list]
-        xs = [x0.clone() for _ in eps_list]
-        infos = []
+    def make(precision):
+        return [mg.Solver(n, n, eps_x=e, smoother="rbgs", nu_pre=args.nu, nu_post=args.nu, precision=precision)
+                for e in eps_list]
+
+    def run(solvers, steps, warmup):
+        xs = [x0.clone() for _ in solvers]
         for _ in range(warmup):
             for s, x in zip(solvers, xs):
                 x.copy_(x0)
                 s.solve(rhs, x, TOL, args.max_cycles, history=False)
         torch.cuda.synchronize()
-        dev_s = 0.0
+        infos = []
         t0 = time.perf_counter()
         for _ in range(steps):
             infos = []
             for s, x in zip(solvers, xs):
                 x.copy_(x0)
-                info = s.solve(rhs, x, TOL, args.max_cycles, history=False)
-                infos.append(info)
-                dev_s += info.seconds
+                infos.append(s.solve(rhs, x, TOL, args.max_cycles, history=False))
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        for s in solvers:
-            s.close()
-        return wall, dev_s, infos
+        return time.perf_counter() - t0, infos
 
     head = args.precision
     other = "fp64" if head == "mixed" else "mixed"
-    wall_h, dev_h, infos_h = run(head, args.steps, args.warmup)
-    wall_o, dev_o, infos_o = run(other, max(1, args.steps // 2), 1)
+    solvers = make(head)
+    wall_h, infos_h = run(solvers, args.steps, args.warmup)
+    for i in infos_h:
+        if i.status != mg.MG_OK:
+            raise SystemExit(f"solve did not converge: {mg.status_string(i.status)} rel_res {i.rel_res:.3e}")
+
+    # roofline: finest-level post-pass of the headline precision, HIP events on the solver's stream
+    scratch = x0.clone()
+    s0 = solvers[0]
+    times = {which: s0.profile_pass(rhs, scratch, 0, which, reps=100) for which in (0, 1)}
+    dom = 1 if times[1] >= times[0] else 0
+    nodes = n * n
+    alg_bytes = BYTES_PER_NODE[(head, dom)] * nodes
+    achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
+    for s in solvers:
+        s.close()
+
+    solvers_o = make(other)
     steps_o = max(1, args.steps // 2)
+    wall_o, infos_o = run(solvers_o, steps_o, 1)
+    for s in solvers_o:
+        s.close()
+
+    if args.calibrate_copy:
+        a = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
+        bcp = torch.empty_like(a)
+        bcp.copy_(a)
+        torch.cuda.synchronize()
+
     total = unknowns * len(eps_list)
-    value = total * args.steps / wall_h
+    kernel_name = {("mixed", 1): "k_post<float, ST5, FINE>", ("mixed", 0): "k_pre<float, ST5, FINE>",
+                   ("fp64", 1): "k_post<double, ST5, FINE>", ("fp64", 0): "k_pre<double, ST5, FINE>"}[(head, dom)]
     out = {
         "metric": "unknowns/s to 1e-10 rel. residual",
-        "value": value,
+        "value": total * args.steps / wall_h,
         "unit": "unknowns/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -100,17 +194,25 @@ def main():
         "vs_baseline": None,
         "dtype": "f32-inner/f64-outer" if head == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "aniso1025: -(eps u_xx + u_yy) = N(0,1), 1025x1025, eps in {1,1e-1,1e-2,1e-3}, "
-                               f"red-black GS {args.nu}/{args.nu}, F-cycle, x0={args.x0}",
+        "config": {"workload": f"aniso1025: -(eps u_xx + u_yy) = N(0,1) on 1025x1025 nodes, eps in "
+                               f"{{{','.join(f'{e:g}' for e in eps_list)}}}, 5-point FD, red-black GS "
+                               f"{args.nu}/{args.nu}, F-cycle to 3x3, x0={args.x0}, tol 1e-10",
                    "precision": head},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": kernel_name, "avg_us": times[dom], "bytes_per_launch": alg_bytes,
+                     "bytes_per_node": BYTES_PER_NODE[(head, dom)], "nodes": nodes,
+                     "other_pass_us": times[1 - dom]},
         "cycles": {f"{e:g}": i.cycles for e, i in zip(eps_list, infos_h)},
         "rel_res": {f"{e:g}": i.rel_res for e, i in zip(eps_list, infos_h)},
+        "us_per_cycle": {f"{e:g}": 1e6 * i.seconds / max(1, i.cycles) for e, i in zip(eps_list, infos_h)},
         f"value_{other}": total * steps_o / wall_o,
         f"cycles_{other}": {f"{e:g}": i.cycles for e, i in zip(eps_list, infos_o)},
-        "speedup_mixed_over_fp64": (wall_o / steps_o) / (wall_h / args.steps) if head == "mixed"
-        else (wall_h / args.steps) / (wall_o / steps_o),
-        "us_per_cycle": {f"{e:g}": 1e6 * i.seconds / max(1, i.cycles) for e, i in zip(eps_list, infos_h)},
+        "speedup_mixed_over_fp64": ((wall_o / steps_o) / (wall_h / args.steps)) if head == "mixed"
+        else ((wall_h / args.steps) / (wall_o / steps_o)),
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, eps_list, [i.cycles for i in infos_h], args.nu, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -146,6 +146,16 @@ mg_status mg_residual(mg_handle h, const double* rhs, const double* x, double* r
  * arrays [ny][nx]; dL_dk: device cell array [ncy][ncx]. */
 mg_status mg_coeff_grad(mg_handle h, const double* u, const double* lam, double* dL_dk);
 
+/* Measurement helper (for benchmarks, not part of a solve): runs the fused
+ * pre-pass (which = 0) or post-pass (which = 1) of `level` once, then `reps`
+ * more times between two HIP events on the handle's stream, and returns the
+ * average device time per launch in *avg_us.  rhs and x are the finest-level
+ * arrays as for mg_solve; x is used as scratch and its content is
+ * overwritten.  MG_EUNSUPPORTED if that level has no fused pass (it runs in
+ * the single-workgroup coarse kernel or tile_mode is MG_TILES_PER_OP). */
+mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t level, int32_t which, int32_t reps,
+                          double* avg_us);
+
 /* Batched: nprob independent 5-point problems (MG_COEF_CONST5 only) with
  * their own grids (square or not, all coarsening to the same coarsest shape)
  * and their own eps_x, eps_y.  grids, coeffs: host arrays of nprob entries.

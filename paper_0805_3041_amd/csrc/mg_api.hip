@@ -314,10 +314,11 @@ hipError_t run_op(mg_handle h, const HostOp& op, Level<T>* dL, T omega, hipStrea
     case H_PROLONG: return launch_prolong<T>(dL + l, dL + l + 1, s, 1, st);
     case H_COARSE: return launch_coarse<T>(dL + l, h->dcholp, h->ncu, 1, st);
     case H_PRE:
-      return launch_pre<T>(dL + l, dL + l + 1, h->gpre[l], h->opts.nu_pre, h->ncol, omega, stencil_kind(h), 1, st);
+      return launch_pre<T>(dL + l, dL + l + 1, h->gpre[l], h->opts.nu_pre, h->ncol, omega, stencil_kind(h), l == 0, 1,
+                           st);
     case H_POST:
       return launch_post<T>(dL + l, dL + l + 1, h->gpost[l], h->opts.nu_post, h->ncol, omega, op.arg, h->dL64,
-                            stencil_kind(h), 1, st);
+                            stencil_kind(h), l == 0, 1, st);
     case H_SUB: {
       const size_t bytes = sub_footprint(h, l);
       if (bytes <= SUB_LDS_BUDGET)
@@ -787,6 +788,54 @@ mg_status mg_residual(mg_handle h, const double* rhs, const double* x, double* r
   HIPCHK(h, hipMemcpyAsync(&cur, h->dstate_res, sizeof(SolveState), hipMemcpyDeviceToHost, st));
   HIPCHK(h, hipStreamSynchronize(st));
   *norm2 = cur.last;
+  return MG_OK;
+}
+
+mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t level, int32_t which, int32_t reps,
+                          double* avg_us) {
+  if (!h) return fail(nullptr, MG_EINVAL, "handle is NULL");
+  if (!rhs || !x || !avg_us) return fail(h, MG_EINVAL, "rhs, x and avg_us must not be NULL");
+  if (which != 0 && which != 1) return fail(h, MG_EINVAL, "which must be 0 (pre-pass) or 1 (post-pass)");
+  if (reps < 1 || reps > 100000) return fail(h, MG_EINVAL, "reps must be in [1, 100000]");
+  if (level < 0 || level >= h->nlev) return fail(h, MG_EINVAL, "level out of range");
+  const HostOp* found = nullptr;
+  for (const HostOp& op : h->prog)
+    if (op.type == (which == 0 ? H_PRE : H_POST) && op.level == level) found = &op;
+  if (!found) return fail(h, MG_EUNSUPPORTED, "no fused pass of that kind runs on this level");
+  hipStream_t st = h->stream;
+  h->L64[0].x = x;
+  h->L64[0].b = const_cast<double*>(rhs);
+  HIPCHK(h, hipMemcpyAsync(h->dL64, h->L64.data(), sizeof(Level<double>), hipMemcpyHostToDevice, st));
+  SolveState init{};
+  init.tol = 1.0;
+  init.history = h->dhist;
+  init.hist_cap = h->hist_cap;
+  init.partial = h->dpartial;
+  HIPCHK(h, hipMemcpyAsync(h->dstate, &init, sizeof(SolveState), hipMemcpyHostToDevice, st));
+  const int l = level;
+  const int kind = stencil_kind(h);
+  auto launch = [&]() -> hipError_t {
+    if (h->mixed()) {
+      if (which == 0)
+        return launch_pre<float>(h->dL32 + l, h->dL32 + l + 1, h->gpre[l], h->opts.nu_pre, h->ncol,
+                                 (float)h->opts.omega, kind, l == 0, 1, st);
+      return launch_post<float>(h->dL32 + l, h->dL32 + l + 1, h->gpost[l], h->opts.nu_post, h->ncol,
+                                (float)h->opts.omega, found->arg, h->dL64, kind, l == 0, 1, st, false);
+    }
+    if (which == 0)
+      return launch_pre<double>(h->dL64 + l, h->dL64 + l + 1, h->gpre[l], h->opts.nu_pre, h->ncol, h->opts.omega,
+                                kind, l == 0, 1, st);
+    return launch_post<double>(h->dL64 + l, h->dL64 + l + 1, h->gpost[l], h->opts.nu_post, h->ncol, h->opts.omega,
+                               found->arg, h->dL64, kind, l == 0, 1, st, false);
+  };
+  HIPCHK(h, launch());
+  HIPCHK(h, hipEventRecord(h->ev0, st));
+  for (int r = 0; r < reps; ++r) HIPCHK(h, launch());
+  HIPCHK(h, hipEventRecord(h->ev1, st));
+  HIPCHK(h, hipEventSynchronize(h->ev1));
+  float ms = 0.f;
+  HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  *avg_us = 1e3 * ms / reps;
   return MG_OK;
 }
 

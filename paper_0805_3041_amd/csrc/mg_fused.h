@@ -26,9 +26,10 @@ template <typename T>
 hipError_t prepare_fused();
 template <typename T>
 hipError_t launch_pre(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g, int nsteps, int ncol, T omega,
-                      int kind, int nslots, hipStream_t st);
+                      int kind, bool fine, int nslots, hipStream_t st);
 template <typename T>
 hipError_t launch_post(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g, int nsteps, int ncol, T omega,
-                       int mode, const Level<double>* X64s, int kind, int nslots, hipStream_t st);
+                       int mode, const Level<double>* X64s, int kind, bool fine, int nslots, hipStream_t st,
+                       bool with_finish = true);
 
 }  // namespace mg

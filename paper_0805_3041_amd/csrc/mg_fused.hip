@@ -22,7 +22,7 @@
 
 namespace mg {
 
-constexpr int FT = 256;  // threads per tile workgroup
+constexpr int FT = 512;  // threads per tile workgroup
 
 struct TileMap {
   int i0, j0, H, nx, ny, py;
@@ -239,7 +239,9 @@ __device__ __forceinline__ double wg_sum(double v, double* sh) {
 
 // ------------------------------------------------------------------ pre-pass
 
-template <typename T, int K>
+// FINE: instantiation used on the finest level only (a separate symbol, so
+// profiles and timings of the finest pass are not mixed with coarser ones).
+template <typename T, int K, bool FINE>
 __global__ void __launch_bounds__(FT) k_pre(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs, int TX,
                                             int TY, int H, int ntx, int nty, int nsteps, int ncol, T omega) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -311,7 +313,7 @@ __global__ void __launch_bounds__(FT) k_pre(const Level<T>* __restrict__ Fs, con
 
 // mode: POST_PLAIN, POST_NORM (finest level: stopping test of the new
 // iterate), POST_MIXED (finest FP32 level: x64 += e, e = 0).
-template <typename T, int K>
+template <typename T, int K, bool FINE>
 __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs, int TX,
                                              int TY, int H, int ntx, int nty, int nsteps, int ncol, T omega, int mode,
                                              const Level<double>* __restrict__ X64s) {
@@ -421,8 +423,10 @@ size_t post_lds_bytes(const TileGeom& g, int ncol) {
 
 template <typename T>
 hipError_t prepare_fused() {
-  const void* ks[4] = {(const void*)k_pre<T, ST5>, (const void*)k_pre<T, ST9>, (const void*)k_post<T, ST5>,
-                       (const void*)k_post<T, ST9>};
+  const void* ks[8] = {(const void*)k_pre<T, ST5, false>,  (const void*)k_pre<T, ST9, false>,
+                       (const void*)k_post<T, ST5, false>, (const void*)k_post<T, ST9, false>,
+                       (const void*)k_pre<T, ST5, true>,   (const void*)k_pre<T, ST9, true>,
+                       (const void*)k_post<T, ST5, true>,  (const void*)k_post<T, ST9, true>};
   for (const void* k : ks) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)FUSED_LDS_MAX);
     if (e != hipSuccess) return e;
@@ -432,8 +436,9 @@ hipError_t prepare_fused() {
 
 template <typename T>
 hipError_t launch_pre(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g, int nsteps, int ncol, T omega,
-                      int kind, int nslots, hipStream_t st) {
-  auto k = kind == ST5 ? k_pre<T, ST5> : k_pre<T, ST9>;
+                      int kind, bool fine, int nslots, hipStream_t st) {
+  auto k = kind == ST5 ? (fine ? k_pre<T, ST5, true> : k_pre<T, ST5, false>)
+                       : (fine ? k_pre<T, ST9, true> : k_pre<T, ST9, false>);
   hipLaunchKernelGGL(k, dim3(g.ntx * g.nty, 1, nslots), dim3(FT), pre_lds_bytes<T>(g, ncol), st, Fs, Cs, g.TX, g.TY,
                      g.H, g.ntx, g.nty, nsteps, ncol, omega);
   return hipGetLastError();
@@ -441,12 +446,14 @@ hipError_t launch_pre(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g,
 
 template <typename T>
 hipError_t launch_post(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g, int nsteps, int ncol, T omega,
-                       int mode, const Level<double>* X64s, int kind, int nslots, hipStream_t st) {
-  auto k = kind == ST5 ? k_post<T, ST5> : k_post<T, ST9>;
+                       int mode, const Level<double>* X64s, int kind, bool fine, int nslots, hipStream_t st,
+                       bool with_finish) {
+  auto k = kind == ST5 ? (fine ? k_post<T, ST5, true> : k_post<T, ST5, false>)
+                       : (fine ? k_post<T, ST9, true> : k_post<T, ST9, false>);
   hipLaunchKernelGGL(k, dim3(g.ntx * g.nty, 1, nslots), dim3(FT), post_lds_bytes<T>(g, ncol), st, Fs, Cs, g.TX, g.TY,
                      g.H, g.ntx, g.nty, nsteps, ncol, omega, mode, X64s);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || mode != POST_NORM) return e;
+  if (e != hipSuccess || mode != POST_NORM || !with_finish) return e;
   return launch_norm_finish<T>(Fs, g.ntx * g.nty, NORM_CHECK, nslots, st);
 }
 
@@ -454,10 +461,10 @@ hipError_t launch_post(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g
   template size_t pre_lds_bytes<T>(const TileGeom&, int);                                                          \
   template size_t post_lds_bytes<T>(const TileGeom&, int);                                                         \
   template hipError_t prepare_fused<T>();                                                                          \
-  template hipError_t launch_pre<T>(const Level<T>*, const Level<T>*, const TileGeom&, int, int, T, int, int,     \
+  template hipError_t launch_pre<T>(const Level<T>*, const Level<T>*, const TileGeom&, int, int, T, int, bool, int, \
                                     hipStream_t);                                                                  \
   template hipError_t launch_post<T>(const Level<T>*, const Level<T>*, const TileGeom&, int, int, T, int,         \
-                                     const Level<double>*, int, int, hipStream_t);
+                                     const Level<double>*, int, bool, int, hipStream_t, bool);
 
 MG_FUSED_INSTANTIATE(double)
 MG_FUSED_INSTANTIATE(float)

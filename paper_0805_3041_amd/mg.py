@@ -31,7 +31,7 @@ PRECISIONS = {"fp64": MG_PREC_FP64, "mixed": MG_PREC_MIXED}
 
 EXPORTED = (
     "mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
-    "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_shape", "mg_num_levels",
+    "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_shape", "mg_num_levels", "mg_profile_pass",
 )
 
 
@@ -87,8 +87,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_last_error.restype = ctypes.c_char_p
     lib.mg_level_shape.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
     lib.mg_num_levels.argtypes = [ctypes.c_void_p]
+    lib.mg_profile_pass.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, P(ctypes.c_double)]
     for name in ("mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
-                 "mg_destroy", "mg_level_shape"):
+                 "mg_destroy", "mg_level_shape", "mg_profile_pass"):
         getattr(lib, name).restype = ctypes.c_int
     lib.mg_num_levels.restype = ctypes.c_int32
     _lib = lib
@@ -187,6 +189,15 @@ def mg_coeff_grad(h, u: torch.Tensor, lam: torch.Tensor, out: torch.Tensor) -> t
     return out
 
 
+def mg_profile_pass(h, rhs: torch.Tensor, x: torch.Tensor, level: int, which: int, reps: int) -> float:
+    lib = load_library()
+    us = ctypes.c_double()
+    s = lib.mg_profile_pass(h, _ptr(rhs), _ptr(x), int(level), int(which), int(reps), ctypes.byref(us))
+    if s != MG_OK:
+        raise MGError(s, last_error(h))
+    return us.value
+
+
 def mg_destroy(h) -> None:
     if h is not None and h.value:
         load_library().mg_destroy(h)
@@ -255,6 +266,10 @@ class Solver:
         ncy = self.ny if self.periodic_y else self.ny - 1
         out = torch.empty((ncy, self.nx - 1), dtype=torch.float64, device=u.device)
         return mg_coeff_grad(self.h, u, lam, out)
+
+    def profile_pass(self, rhs: torch.Tensor, x: torch.Tensor, level: int, which: int, reps: int = 50) -> float:
+        """Average device time (us) of one fused pre-pass (which=0) or post-pass (1) on `level`."""
+        return mg_profile_pass(self.h, rhs, x, level, which, reps)
 
     def close(self) -> None:
         if getattr(self, "h", None) is not None:
