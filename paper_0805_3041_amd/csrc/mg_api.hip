@@ -1,19 +1,27 @@
-// Host side of libmg: argument checks, level hierarchy, cycle programs, the
-// solve loop and the C ABI declared in include/mg.h.
+// Host side of libmg: argument checks, level hierarchies, cycle programs, the
+// solve loops and the C ABI declared in include/mg.h.
 //
 // The cycle is compiled once, at setup, into a flat list of ops by walking
-// the recursive algorithm MG(l, u, g) ("The Multigrid Technique"): smoothing
-// ops, defect restriction, the recursive coarse calls (an F-cycle gives the
-// coarse problem one F-cycle then one V-cycle), prolongation with omega_l = 1
-// and the exact coarsest solve.  Levels with few nodes are not expanded into
-// launches: their whole sub-cycle is one launch of a single-workgroup kernel
-// that interprets the same op list.  The solve loop queues cycles in batches
-// and reads the device-side stopping state once per batch.
+// the recursive algorithm MG(l, u, g) ("The Multigrid Technique"): smoothing,
+// defect restriction, the recursive coarse calls (an F-cycle gives the coarse
+// problem one F-cycle then one V-cycle), prolongation with omega_l = 1 and the
+// exact coarsest solve.  Large levels run as fused LDS-tiled passes; small
+// levels run their whole sub-cycle in one launch of a single-workgroup
+// kernel.  The cycle is captured as a HIP graph; the solve loop replays it in
+// batches and reads the device-side stopping state once per batch.
+//
+// A handle holds one or more groups.  A group is a set of problems with the
+// same grid (the batched solver groups its problems by grid); all of a
+// group's problems go through the same launches, one problem per blockIdx.z,
+// each masked once its own stopping test is met.  The groups of a batched
+// handle are captured as parallel branches of one graph.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "mg.h"
@@ -25,6 +33,8 @@ using namespace mg;
 namespace {
 
 thread_local std::string g_thread_err;
+
+constexpr int MAX_BATCH = 4096;
 
 enum HostOpType { H_COLOR = 0, H_JACOBI, H_COPY, H_DR, H_PROLONG, H_COARSE, H_SUB, H_PRE, H_POST };
 
@@ -41,53 +51,65 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-}  // namespace
-
-struct mg_handle_s {
-  // configuration
+// Problems of one grid.  Level descriptors are kept twice on the device:
+// level-major [level][slot] for per-op and tile kernels (blockIdx.z = slot)
+// and problem-major [slot][level] for the coarse-level kernel.
+struct Group {
+  int ns = 1;
+  std::vector<int> probs;  // problem index of each slot
   mg_grid grid{};
-  int kind = MG_COEF_CONST5;
-  double eps_x = 1.0, eps_y = 1.0;
-  int oned = 0;
-  mg_options opts{};
-  int nlev = 0;
-  int ncol = 0;  // 0 Jacobi, 2 red-black, 4 four-colour
-  int ncu = 0;   // unknowns of the coarsest grid
+  int nlev = 0, ncu = 0;
   std::vector<LevelShape> shp;
   std::vector<double> hx, hy;
-  hipStream_t stream = nullptr;
-  std::string err;
-
-  // device memory
-  std::vector<void*> allocs;
-  std::vector<Level<double>> L64;
+  std::vector<Level<double>> L64;  // [level * ns + slot]
   std::vector<Level<float>> L32;
   Level<double>* dL64 = nullptr;
   Level<float>* dL32 = nullptr;
+  Level<double>* dP64 = nullptr;
+  Level<float>* dP32 = nullptr;
   std::vector<double*> band64;
   std::vector<float*> band32;
-  SolveState* dstate = nullptr;
-  SolveState* dstate_res = nullptr;  // mg_residual's own state
-  Level<double>* dLres = nullptr;     // mg_residual's finest-level descriptor
-  double* dhist = nullptr;
-  int hist_cap = 0;
-  double* dpartial = nullptr;
-  double* dchol = nullptr;
-  double** dcholp = nullptr;
-
-  // fused tile passes per level
+  double** dcholp = nullptr;  // Cholesky factor of each slot's coarsest operator
   std::vector<TileGeom> gpre, gpost;
   bool norm_fused = false;   // FP64: the finest post-pass applies the stopping test
   bool mixed_fused = false;  // mixed: the finest post-pass adds e into the FP64 iterate
-
-  // cycle program
   std::vector<HostOp> prog;
   DOp* dprog = nullptr;
-  int* dbeg = nullptr;
+  int* dbeg = nullptr;  // [sub * ns + slot]
   int* dcnt = nullptr;
   int nsub = 0;
+  hipStream_t branch = nullptr;  // capture branch of this group
 
+  Level<double>& l64(int l, int s) { return L64[(size_t)l * ns + s]; }
+  Level<float>& l32(int l, int s) { return L32[(size_t)l * ns + s]; }
+  const Level<double>& l64(int l, int s) const { return L64[(size_t)l * ns + s]; }
+};
+
+}  // namespace
+
+struct mg_handle_s {
+  bool batched = false;
+  int nprob = 1;
+  int kind = MG_COEF_CONST5;
+  int oned = 0;
+  mg_options opts{};
+  int ncol = 0;                      // 0 Jacobi, 2 red-black, 4 four-colour
+  std::vector<double> eps_x, eps_y;  // per problem (5-point)
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  std::vector<Group> groups;
+
+  // device memory
+  std::vector<void*> allocs;
+  SolveState* dstate = nullptr;      // [nprob]
+  SolveState* dstate_res = nullptr;  // mg_residual's own state
+  Level<double>* dLres = nullptr;    // mg_residual's finest-level descriptor
+  std::vector<double*> dhist;        // per problem
+  int hist_cap = 0;
+  std::vector<double*> dpartial;     // per problem
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> fork;      // capture fork/join events
 
   // one cycle and eight cycles captured as graphs (kernel nodes only)
   hipStream_t cap = nullptr;
@@ -130,24 +152,27 @@ bool can_coarsen(int nx, int ny, int py) {
   return okx && oky;
 }
 
+int stencil_kind(mg_handle h) { return h->kind == MG_COEF_CONST5 ? ST5 : ST9; }
+
 // ----------------------------------------------------------------------- cycle program
 
 // Bytes of LDS that levels l..L-1 need inside the coarse-level kernel.
-size_t sub_footprint(mg_handle h, int l) {
+size_t sub_footprint(mg_handle h, const Group& G, int l) {
   const size_t elem = h->mixed() ? sizeof(float) : sizeof(double);
   const size_t narr = h->ncol == 0 ? 3 : 2;
   size_t n = 0;
-  for (int k = l; k < h->nlev; ++k) n += (size_t)h->shp[k].nx * h->shp[k].ny;
+  for (int k = l; k < G.nlev; ++k) n += (size_t)G.shp[k].nx * G.shp[k].ny;
   return n * narr * elem;
 }
 
 struct Gen {
   mg_handle h;
+  const Group& G;
   int threshold;  // 0: the largest levels whose sub-hierarchy fits in LDS
   bool small(int l) const {
-    const LevelShape& s = h->shp[l];
+    const LevelShape& s = G.shp[l];
     if (threshold > 0) return (long)s.nx * s.ny <= threshold;
-    return sub_footprint(h, l) <= SUB_LDS_BUDGET;
+    return sub_footprint(h, G, l) <= SUB_LDS_BUDGET;
   }
   void smooth(std::vector<Abs>& out, int l, int steps) const {
     if (h->ncol == 0) {
@@ -164,7 +189,7 @@ struct Gen {
   }
   // Fully expanded op list of one cycle of `kind` starting on level l.
   void expand(std::vector<Abs>& out, int l, int kind) const {
-    if (l == h->nlev - 1) {
+    if (l == G.nlev - 1) {
       if (out.empty() || out.back().type != H_COARSE) out.push_back({H_COARSE, l, 0});
       return;
     }
@@ -181,7 +206,7 @@ struct Gen {
   }
   // Host program: ops on large levels, one H_SUB per maximal small-level call.
   void host(std::vector<HostOp>& out, std::vector<std::vector<Abs>>& subs, int l, int kind) const {
-    if (small(l) || l == h->nlev - 1) {
+    if (small(l) || l == G.nlev - 1) {
       std::vector<Abs> body;
       expand(body, l, kind);
       if (!out.empty() && out.back().type == H_SUB && out.back().level == l) {
@@ -224,8 +249,8 @@ struct Gen {
 // for the defect and its restriction (pre) or 1 for the residual (post).
 int sweeps(mg_handle h, int steps) { return h->ncol == 0 ? steps : steps * h->ncol; }
 
-TileGeom choose_tile(mg_handle h, int l, int H, bool post) {
-  const LevelShape& s = h->shp[l];
+TileGeom choose_tile(mg_handle h, const Group& G, int l, int H, bool post) {
+  const LevelShape& s = G.shp[l];
   const size_t elem = h->mixed() ? sizeof(float) : sizeof(double);
   const int narr = h->ncol == 0 ? 3 : 2;
   auto bytes = [&](int TX, int TY) {
@@ -237,7 +262,8 @@ TileGeom choose_tile(mg_handle h, int l, int H, bool post) {
   const bool fixed = h->opts.tile_x > 0 && h->opts.tile_y > 0;
   int TX = h->opts.tile_x > 0 ? h->opts.tile_x : 64;
   int TY = h->opts.tile_y > 0 ? h->opts.tile_y : 32;
-  auto ntiles = [&](int tx, int ty) { return (long)((s.nx + tx - 1) / tx) * ((s.ny + ty - 1) / ty); };
+  // tiles over all of the group's problems
+  auto ntiles = [&](int tx, int ty) { return (long)G.ns * ((s.nx + tx - 1) / tx) * ((s.ny + ty - 1) / ty); };
   if (!fixed) {
     while (ntiles(TX, TY) < 256 && TY > 8) TY >>= 1;
     while (ntiles(TX, TY) < 256 && TX > 16) TX >>= 1;
@@ -247,34 +273,37 @@ TileGeom choose_tile(mg_handle h, int l, int H, bool post) {
   return tile_geom(s.nx, s.ny, TX, TY, H);
 }
 
-mg_status build_program(mg_handle h) {
-  Gen g{h, h->opts.coarse_cta_nodes};
+mg_status build_program(mg_handle h, Group& G) {
+  Gen g{h, G, h->opts.coarse_cta_nodes};
   std::vector<std::vector<Abs>> subs;
-  h->prog.clear();
-  g.host(h->prog, subs, 0, h->opts.cycle);
-  h->gpre.assign(h->nlev, TileGeom{});
-  h->gpost.assign(h->nlev, TileGeom{});
-  h->norm_fused = h->mixed_fused = false;
-  if (!h->prog.empty() && h->prog.back().type == H_POST && h->prog.back().level == 0) {
+  G.prog.clear();
+  g.host(G.prog, subs, 0, h->opts.cycle);
+  G.gpre.assign(G.nlev, TileGeom{});
+  G.gpost.assign(G.nlev, TileGeom{});
+  G.norm_fused = G.mixed_fused = false;
+  if (!G.prog.empty() && G.prog.back().type == H_POST && G.prog.back().level == 0) {
     if (h->mixed()) {
-      h->prog.back().arg = POST_MIXED;
-      h->mixed_fused = true;
+      G.prog.back().arg = POST_MIXED;
+      G.mixed_fused = true;
     } else {
-      h->prog.back().arg = POST_NORM;
-      h->norm_fused = true;
+      G.prog.back().arg = POST_NORM;
+      G.norm_fused = true;
     }
   }
-  for (const HostOp& op : h->prog) {
-    if (op.type == H_PRE) h->gpre[op.level] = choose_tile(h, op.level, sweeps(h, h->opts.nu_pre) + 2, false);
+  for (const HostOp& op : G.prog) {
+    if (op.type == H_PRE) G.gpre[op.level] = choose_tile(h, G, op.level, sweeps(h, h->opts.nu_pre) + 2, false);
     if (op.type == H_POST)
-      h->gpost[op.level] =
-          choose_tile(h, op.level, sweeps(h, h->opts.nu_post) + (op.arg == POST_NORM ? 1 : 0), true);
+      G.gpost[op.level] =
+          choose_tile(h, G, op.level, sweeps(h, h->opts.nu_post) + (op.arg == POST_NORM ? 1 : 0), true);
   }
   std::vector<DOp> flat;
   std::vector<int> beg, cnt;
   for (const auto& s : subs) {
-    beg.push_back((int)flat.size());
-    cnt.push_back((int)s.size());
+    const int b = (int)flat.size();
+    for (int k = 0; k < G.ns; ++k) {  // every slot of a group runs the same program
+      beg.push_back(b);
+      cnt.push_back((int)s.size());
+    }
     for (const Abs& a : s) {
       int t = OP_COLOR;
       switch (a.type) {
@@ -288,73 +317,93 @@ mg_status build_program(mg_handle h) {
       flat.push_back({t, a.level, a.arg, 0});
     }
   }
-  h->nsub = (int)subs.size();
+  G.nsub = (int)subs.size();
   if (!flat.empty()) {
-    HIPCHK(h, h->dalloc(&h->dprog, flat.size() * sizeof(DOp)));
-    HIPCHK(h, hipMemcpyAsync(h->dprog, flat.data(), flat.size() * sizeof(DOp), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, h->dalloc(&h->dbeg, beg.size() * sizeof(int)));
-    HIPCHK(h, h->dalloc(&h->dcnt, cnt.size() * sizeof(int)));
-    HIPCHK(h, hipMemcpyAsync(h->dbeg, beg.data(), beg.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->dcnt, cnt.data(), cnt.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, h->dalloc(&G.dprog, flat.size() * sizeof(DOp)));
+    HIPCHK(h, hipMemcpyAsync(G.dprog, flat.data(), flat.size() * sizeof(DOp), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, h->dalloc(&G.dbeg, beg.size() * sizeof(int)));
+    HIPCHK(h, h->dalloc(&G.dcnt, cnt.size() * sizeof(int)));
+    HIPCHK(h, hipMemcpyAsync(G.dbeg, beg.data(), beg.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(G.dcnt, cnt.data(), cnt.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));  // the host vectors are about to go
   }
   return MG_OK;
 }
 
-int stencil_kind(mg_handle h) { return h->kind == MG_COEF_CONST5 ? ST5 : ST9; }
-
 template <typename T>
-hipError_t run_op(mg_handle h, const HostOp& op, Level<T>* dL, T omega, hipStream_t st) {
-  const int l = op.level;
-  const LevelShape& s = h->shp[l];
+hipError_t run_op(mg_handle h, const Group& G, const HostOp& op, Level<T>* dL, Level<T>* dP, T omega,
+                  hipStream_t st) {
+  const int l = op.level, ns = G.ns;
+  const LevelShape& s = G.shp[l];
+  Level<T>* Ls = dL + (size_t)l * ns;
+  Level<T>* Cs = dL + (size_t)(l + 1) * ns;
   switch (op.type) {
-    case H_COLOR: return launch_colour<T>(dL + l, s, op.arg, h->ncol, 1, st);
-    case H_JACOBI: return launch_jacobi<T>(dL + l, s, op.arg, omega, 1, st);
-    case H_COPY: return launch_copy<T>(dL + l, s, 1, st);
-    case H_DR: return launch_dr<T>(dL + l, dL + l + 1, h->shp[l + 1], 1, st);
-    case H_PROLONG: return launch_prolong<T>(dL + l, dL + l + 1, s, 1, st);
-    case H_COARSE: return launch_coarse<T>(dL + l, h->dcholp, h->ncu, 1, st);
+    case H_COLOR: return launch_colour<T>(Ls, s, op.arg, h->ncol, ns, st);
+    case H_JACOBI: return launch_jacobi<T>(Ls, s, op.arg, omega, ns, st);
+    case H_COPY: return launch_copy<T>(Ls, s, ns, st);
+    case H_DR: return launch_dr<T>(Ls, Cs, G.shp[l + 1], ns, st);
+    case H_PROLONG: return launch_prolong<T>(Ls, Cs, s, ns, st);
+    case H_COARSE: return launch_coarse<T>(Ls, G.dcholp, G.ncu, ns, st);
     case H_PRE:
-      return launch_pre<T>(dL + l, dL + l + 1, h->gpre[l], h->opts.nu_pre, h->ncol, omega, stencil_kind(h), l == 0, 1,
-                           st);
+      return launch_pre<T>(Ls, Cs, G.gpre[l], h->opts.nu_pre, h->ncol, omega, stencil_kind(h), l == 0, ns, st);
     case H_POST:
-      return launch_post<T>(dL + l, dL + l + 1, h->gpost[l], h->opts.nu_post, h->ncol, omega, op.arg, h->dL64,
-                            stencil_kind(h), l == 0, 1, st);
+      return launch_post<T>(Ls, Cs, G.gpost[l], h->opts.nu_post, h->ncol, omega, op.arg, G.dL64, stencil_kind(h),
+                            l == 0, ns, st);
     case H_SUB: {
-      const size_t bytes = sub_footprint(h, l);
+      const size_t bytes = sub_footprint(h, G, l);
+      const int* beg = G.dbeg + (size_t)op.sub * ns;
+      const int* cnt = G.dcnt + (size_t)op.sub * ns;
       if (bytes <= SUB_LDS_BUDGET)
-        return launch_subcycle_lds<T>(dL, h->nlev, l, h->dprog, h->dbeg + op.sub, h->dcnt + op.sub, h->dcholp,
-                                      h->ncu, omega, h->ncol, h->ncol == 0 ? 3 : 2, stencil_kind(h), bytes, 1, st);
-      return launch_subcycle<T>(dL, h->nlev, h->dprog, h->dbeg + op.sub, h->dcnt + op.sub, h->dcholp, h->ncu, omega,
-                                h->ncol, 1, st);
+        return launch_subcycle_lds<T>(dP, G.nlev, l, G.dprog, beg, cnt, G.dcholp, G.ncu, omega, h->ncol,
+                                      h->ncol == 0 ? 3 : 2, stencil_kind(h), bytes, ns, st);
+      return launch_subcycle<T>(dP, G.nlev, G.dprog, beg, cnt, G.dcholp, G.ncu, omega, h->ncol, ns, st);
     }
   }
   return hipErrorInvalidValue;
 }
 
-// One cycle plus its stopping test, on stream st.
-hipError_t enqueue_cycle(mg_handle h, hipStream_t st) {
+// One cycle of a group plus its stopping test, on stream st.
+hipError_t enqueue_cycle(mg_handle h, const Group& G, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (!h->mixed()) {
-    for (const HostOp& op : h->prog)
-      if ((e = run_op<double>(h, op, h->dL64, h->opts.omega, st)) != hipSuccess) return e;
-    if (h->norm_fused) return hipSuccess;
-    return launch_resnorm<double>(h->dL64, h->shp[0], NORM_CHECK, nullptr, nullptr, 0, 1, st);
+    for (const HostOp& op : G.prog)
+      if ((e = run_op<double>(h, G, op, G.dL64, G.dP64, h->opts.omega, st)) != hipSuccess) return e;
+    if (G.norm_fused) return hipSuccess;
+    return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, nullptr, G.ns, st);
   }
-  for (const HostOp& op : h->prog)
-    if ((e = run_op<float>(h, op, h->dL32, (float)h->opts.omega, st)) != hipSuccess) return e;
-  if (!h->mixed_fused && (e = launch_outer_update(h->dL64, h->dL32, h->shp[0], 1, st)) != hipSuccess) return e;
-  return launch_resnorm<double>(h->dL64, h->shp[0], NORM_CHECK, nullptr, h->L32[0].b, h->L32[0].pitch, 1, st);
+  for (const HostOp& op : G.prog)
+    if ((e = run_op<float>(h, G, op, G.dL32, G.dP32, (float)h->opts.omega, st)) != hipSuccess) return e;
+  if (!G.mixed_fused && (e = launch_outer_update(G.dL64, G.dL32, G.shp[0], G.ns, st)) != hipSuccess) return e;
+  return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, G.dL32, G.ns, st);
 }
 
 // Captures one cycle and eight cycles as graphs on a private stream (a graph
-// can then be launched on any stream, the null stream included).
+// can then be launched on any stream, the null stream included).  The groups
+// of a batched handle become parallel branches (fork/join through events).
 mg_status build_graphs(mg_handle h) {
   HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  const int ng = (int)h->groups.size();
+  h->fork.assign(2 * ng, nullptr);
+  for (auto& ev : h->fork) HIPCHK(h, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  for (int g = 1; g < ng; ++g) HIPCHK(h, hipStreamCreateWithFlags(&h->groups[g].branch, hipStreamNonBlocking));
+  h->groups[0].branch = h->cap;
   for (int k : {1, 8}) {
     hipGraph_t graph = nullptr;
     HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int c = 0; c < k && e == hipSuccess; ++c) e = enqueue_cycle(h, h->cap);
+    for (int c = 0; c < k && e == hipSuccess; ++c) {
+      if (ng == 1) {
+        e = enqueue_cycle(h, h->groups[0], h->cap);
+        continue;
+      }
+      e = hipEventRecord(h->fork[0], h->cap);
+      for (int g = 1; g < ng && e == hipSuccess; ++g) e = hipStreamWaitEvent(h->groups[g].branch, h->fork[0], 0);
+      for (int g = 0; g < ng && e == hipSuccess; ++g) e = enqueue_cycle(h, h->groups[g], h->groups[g].branch);
+      for (int g = 1; g < ng && e == hipSuccess; ++g) {
+        e = hipEventRecord(h->fork[ng + g], h->groups[g].branch);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->cap, h->fork[ng + g], 0);
+      }
+    }
     hipError_t e2 = hipStreamEndCapture(h->cap, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -375,7 +424,7 @@ mg_status check_grid(const mg_grid* g) {
   if (!g) return fail(nullptr, MG_EINVAL, "grid is NULL");
   if (g->periodic_x) return fail(nullptr, MG_EUNSUPPORTED, "periodic x is not supported (only y may be periodic)");
   if (!(finite_pos(g->lx) && finite_pos(g->ly))) return fail(nullptr, MG_EINVAL, "lx and ly must be finite and > 0");
-  if (g->nx < 3 || (g->nx - 1) < 2) return fail(nullptr, MG_EINVAL, "nx must be >= 3");
+  if (g->nx < 3) return fail(nullptr, MG_EINVAL, "nx must be >= 3");
   if (g->periodic_y) {
     if (g->ny < 4 || (g->ny & 1)) return fail(nullptr, MG_EINVAL, "periodic ny must be even and >= 4");
   } else if (g->ny < 3) {
@@ -425,8 +474,13 @@ void release(mg_handle h) {
   if (h->g1) (void)hipGraphExecDestroy(h->g1);
   if (h->g8) (void)hipGraphExecDestroy(h->g8);
   h->g1 = h->g8 = nullptr;
+  for (size_t g = 1; g < h->groups.size(); ++g)
+    if (h->groups[g].branch) (void)hipStreamDestroy(h->groups[g].branch);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   h->cap = nullptr;
+  for (auto& ev : h->fork)
+    if (ev) (void)hipEventDestroy(ev);
+  h->fork.clear();
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
   if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -434,58 +488,210 @@ void release(mg_handle h) {
   h->ev0 = h->ev1 = nullptr;
 }
 
-mg_status setup_impl(mg_handle h, const mg_grid* grid, const mg_coeffs* coeffs, int32_t levels) {
-  h->grid = *grid;
-  h->kind = coeffs->kind;
-  h->eps_x = coeffs->eps_x;
-  h->eps_y = coeffs->eps_y;
-  h->oned = coeffs->kx_1d_along_x ? 1 : 0;
-  h->ncol = h->opts.smoother == MG_SMOOTH_JACOBI ? 0 : (h->opts.smoother == MG_SMOOTH_RBGS ? 2 : 4);
-  h->stream = static_cast<hipStream_t>(h->opts.stream);
-  const int py = grid->periodic_y ? 1 : 0;
-
-  // level shapes (finest first)
-  int nx = grid->nx, ny = grid->ny;
-  int maxlev = 1;
-  {
-    int a = nx, b = ny;
-    while (can_coarsen(a, b, py)) {
-      a = (a - 1) / 2 + 1;
-      b = py ? b / 2 : (b - 1) / 2 + 1;
-      ++maxlev;
-    }
+int max_levels(int nx, int ny, int py) {
+  int m = 1;
+  while (can_coarsen(nx, ny, py)) {
+    nx = (nx - 1) / 2 + 1;
+    ny = py ? ny / 2 : (ny - 1) / 2 + 1;
+    ++m;
   }
+  return m;
+}
+
+// Shapes, buffers, operators, coarsest factors and descriptors of a group.
+// Problem p = G.probs[s] uses h->eps_x[p], h->eps_y[p] (5-point) or the
+// coefficient arrays in coeffs (9-point, single-problem handles only).
+mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t levels) {
+  const mg_grid& grid = G.grid;
+  const int py = grid.periodic_y ? 1 : 0;
+  const int maxlev = max_levels(grid.nx, grid.ny, py);
   if (levels < 0 || levels > maxlev)
-    return fail(h, MG_EINVAL, "grid " + std::to_string(nx) + "x" + std::to_string(ny) + " supports at most " +
-                                  std::to_string(maxlev) + " levels");
-  h->nlev = levels ? levels : maxlev;
-  if (h->nlev > MAX_LEVELS) return fail(h, MG_EUNSUPPORTED, "more than " + std::to_string(MAX_LEVELS) + " levels");
-  for (int l = 0; l < h->nlev; ++l) {
-    h->shp.push_back({nx, ny, py, py ? ny : ny - 2});
-    h->hx.push_back(grid->lx / (nx - 1));
-    h->hy.push_back(py ? grid->ly / ny : grid->ly / (ny - 1));
+    return fail(h, MG_EINVAL, "grid " + std::to_string(grid.nx) + "x" + std::to_string(grid.ny) +
+                                  " supports at most " + std::to_string(maxlev) + " levels");
+  G.nlev = levels ? levels : maxlev;
+  if (G.nlev > MAX_LEVELS) return fail(h, MG_EUNSUPPORTED, "more than " + std::to_string(MAX_LEVELS) + " levels");
+  int nx = grid.nx, ny = grid.ny;
+  for (int l = 0; l < G.nlev; ++l) {
+    G.shp.push_back({nx, ny, py, py ? ny : ny - 2});
+    G.hx.push_back(grid.lx / (nx - 1));
+    G.hy.push_back(py ? grid.ly / ny : grid.ly / (ny - 1));
     nx = (nx - 1) / 2 + 1;
     ny = py ? ny / 2 : (ny - 1) / 2 + 1;
   }
-  const LevelShape& sc = h->shp.back();
-  h->ncu = (sc.nx - 2) * sc.nrows;
-  if (h->ncu > MAX_COARSE_UNKNOWNS)
-    return fail(h, MG_EUNSUPPORTED, "coarsest grid has " + std::to_string(h->ncu) + " unknowns (max " +
+  const LevelShape sc = G.shp.back();
+  G.ncu = (sc.nx - 2) * sc.nrows;
+  if (G.ncu > MAX_COARSE_UNKNOWNS)
+    return fail(h, MG_EUNSUPPORTED, "coarsest grid has " + std::to_string(G.ncu) + " unknowns (max " +
                                         std::to_string(MAX_COARSE_UNKNOWNS) + "); use a grid that coarsens further");
+  const int ns = G.ns;
+  const bool mixed = h->mixed();
 
+  // level buffers
+  G.L64.assign((size_t)G.nlev * ns, Level<double>{});
+  G.L32.assign(mixed ? (size_t)G.nlev * ns : 0, Level<float>{});
+  for (int s = 0; s < ns; ++s) {
+    SolveState* st = h->dstate + G.probs[s];
+    for (int l = 0; l < G.nlev; ++l) {
+      const LevelShape& sh = G.shp[l];
+      if (l == 0) {
+        // finest FP64 level: x and b are the caller's arrays (pitch nx)
+        G.l64(0, s) = make_level<double>(sh, sh.nx, st);
+        if (!mixed) HIPCHK(h, h->dalloc(&G.l64(0, s).t, (size_t)sh.nx * sh.ny * sizeof(double)));
+      } else {
+        const int p = round_up(sh.nx, 16);
+        Level<double>& L = G.l64(l, s);
+        L = make_level<double>(sh, p, st);
+        if (!mixed) {
+          HIPCHK(h, h->dalloc(&L.x, (size_t)p * sh.ny * sizeof(double)));
+          HIPCHK(h, h->dalloc(&L.b, (size_t)p * sh.ny * sizeof(double)));
+          HIPCHK(h, h->dalloc(&L.t, (size_t)p * sh.ny * sizeof(double)));
+        }
+      }
+      if (mixed) {
+        const int p = round_up(sh.nx, 32);
+        Level<float>& L = G.l32(l, s);
+        L = make_level<float>(sh, p, st);
+        HIPCHK(h, h->dalloc(&L.x, (size_t)p * sh.ny * sizeof(float)));
+        HIPCHK(h, h->dalloc(&L.b, (size_t)p * sh.ny * sizeof(float)));
+        HIPCHK(h, h->dalloc(&L.t, (size_t)p * sh.ny * sizeof(float)));
+      }
+    }
+  }
+
+  // operators
+  if (h->kind == MG_COEF_CONST5) {
+    for (int s = 0; s < ns; ++s) {
+      const int p = G.probs[s];
+      for (int l = 0; l < G.nlev; ++l) {
+        const double cx = h->eps_x[p] / (G.hx[l] * G.hx[l]);
+        const double cy = h->eps_y[p] / (G.hy[l] * G.hy[l]);
+        const double dg = 2.0 * (cx + cy);
+        Level<double>& L = G.l64(l, s);
+        L.kind = ST5;
+        L.cx = cx;
+        L.cy = cy;
+        L.dg = dg;
+        L.inv_dg = 1.0 / dg;
+        if (mixed) {
+          Level<float>& M = G.l32(l, s);
+          M.kind = ST5;
+          M.cx = (float)cx;
+          M.cy = (float)cy;
+          M.dg = (float)dg;
+          M.inv_dg = (float)(1.0 / dg);
+        }
+      }
+    }
+  } else {
+    const int ncx = grid.nx - 1;
+    G.band64.resize(G.nlev);
+    G.band32.resize(G.nlev);
+    for (int l = 0; l < G.nlev; ++l) {
+      const LevelShape& sh = G.shp[l];
+      const int bp = round_up(sh.nx, 16);
+      const int brows = h->oned ? 1 : sh.ny;
+      const int bstride = bp * brows;
+      HIPCHK(h, h->dalloc(&G.band64[l], (size_t)5 * bstride * sizeof(double)));
+      if (l == 0) {
+        HIPCHK(h, launch_q1_bands(G.band64[0], bstride, h->oned ? 0 : bp, brows, sh.nx, sh.ny, sh.py, coeffs->kx,
+                                  coeffs->ky, h->oned ? 0 : ncx, G.hx[0], G.hy[0], h->stream));
+      } else {
+        const LevelShape& f = G.shp[l - 1];
+        const int fbp = round_up(f.nx, 16);
+        const int fbstride = fbp * (h->oned ? 1 : f.ny);
+        HIPCHK(h, launch_rap(G.band64[l], bstride, h->oned ? 0 : bp, brows, sh.nx, sh.ny, G.band64[l - 1], fbstride,
+                             h->oned ? 0 : fbp, f.nx, f.ny, sh.py, h->stream));
+      }
+      Level<double>& L = G.l64(l, 0);
+      L.kind = ST9;
+      L.band = G.band64[l];
+      L.bpitch = h->oned ? 0 : bp;
+      L.bstride = bstride;
+      if (mixed) {
+        HIPCHK(h, h->dalloc(&G.band32[l], (size_t)5 * bstride * sizeof(float)));
+        HIPCHK(h, launch_to_float(G.band64[l], G.band32[l], (long)5 * bstride, h->stream));
+        Level<float>& M = G.l32(l, 0);
+        M.kind = ST9;
+        M.band = G.band32[l];
+        M.bpitch = L.bpitch;
+        M.bstride = bstride;
+      }
+    }
+  }
+
+  // coarsest operator of each slot: dense matrix and Cholesky factor (FP64)
+  {
+    const int n = G.ncu;
+    std::vector<double*> chol(ns, nullptr);
+    int* dinfo = nullptr;
+    HIPCHK(h, h->dalloc(&dinfo, (size_t)ns * sizeof(int)));
+    for (int s = 0; s < ns; ++s) {
+      const Level<double>& L = G.l64(G.nlev - 1, s);
+      HIPCHK(h, h->dalloc(&chol[s], (size_t)n * n * sizeof(double)));
+      HIPCHK(h, launch_dense_coarse(chol[s], n, sc.nx, sc.ny, sc.py, L.kind, L.cx, L.cy, L.dg, L.band, L.bstride,
+                                    L.bpitch, h->stream));
+      HIPCHK(h, launch_cholesky(chol[s], n, dinfo + s, h->stream));
+    }
+    std::vector<int> info(ns, 0);
+    HIPCHK(h, hipMemcpyAsync(info.data(), dinfo, (size_t)ns * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, h->dalloc(&G.dcholp, (size_t)ns * sizeof(double*)));
+    HIPCHK(h, hipMemcpyAsync(G.dcholp, chol.data(), (size_t)ns * sizeof(double*), hipMemcpyHostToDevice, h->stream));
+    mg_status st = sync_check(h);
+    if (st != MG_OK) return st;
+    for (int s = 0; s < ns; ++s)
+      if (info[s]) return fail(h, MG_EINVAL, "coarsest operator is not positive definite");
+  }
+
+  // descriptors: level-major and problem-major copies
+  const size_t nd = (size_t)G.nlev * ns;
+  HIPCHK(h, h->dalloc(&G.dL64, nd * sizeof(Level<double>)));
+  HIPCHK(h, h->dalloc(&G.dP64, nd * sizeof(Level<double>)));
+  if (mixed) {
+    HIPCHK(h, h->dalloc(&G.dL32, nd * sizeof(Level<float>)));
+    HIPCHK(h, h->dalloc(&G.dP32, nd * sizeof(Level<float>)));
+  }
+  return build_program(h, G);
+}
+
+// Uploads both descriptor layouts of a group (after the finest level's caller
+// arrays changed) and waits for the copies.
+mg_status upload_descriptors(mg_handle h, Group& G) {
+  const size_t nd = (size_t)G.nlev * G.ns;
+  hipStream_t st = h->stream;
+  std::vector<Level<double>> p64(nd);
+  for (int s = 0; s < G.ns; ++s)
+    for (int l = 0; l < G.nlev; ++l) p64[(size_t)s * G.nlev + l] = G.l64(l, s);
+  HIPCHK(h, hipMemcpyAsync(G.dL64, G.L64.data(), nd * sizeof(Level<double>), hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(G.dP64, p64.data(), nd * sizeof(Level<double>), hipMemcpyHostToDevice, st));
+  std::vector<Level<float>> p32;
+  if (h->mixed()) {
+    p32.resize(nd);
+    for (int s = 0; s < G.ns; ++s)
+      for (int l = 0; l < G.nlev; ++l) p32[(size_t)s * G.nlev + l] = G.l32(l, s);
+    HIPCHK(h, hipMemcpyAsync(G.dL32, G.L32.data(), nd * sizeof(Level<float>), hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(G.dP32, p32.data(), nd * sizeof(Level<float>), hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(h, hipStreamSynchronize(st));
+  return MG_OK;
+}
+
+// Common part of mg_setup and mg_setup_batched after the groups are formed.
+mg_status setup_handle(mg_handle h, const mg_coeffs* coeffs, int32_t levels) {
+  h->ncol = h->opts.smoother == MG_SMOOTH_JACOBI ? 0 : (h->opts.smoother == MG_SMOOTH_RBGS ? 2 : 4);
+  h->stream = static_cast<hipStream_t>(h->opts.stream);
   HIPCHK(h, hipEventCreate(&h->ev0));
   HIPCHK(h, hipEventCreate(&h->ev1));
-
-  // solve state
-  HIPCHK(h, h->dalloc(&h->dstate, sizeof(SolveState)));
+  HIPCHK(h, h->dalloc(&h->dstate, (size_t)h->nprob * sizeof(SolveState)));
   HIPCHK(h, h->dalloc(&h->dstate_res, sizeof(SolveState)));
   HIPCHK(h, h->dalloc(&h->dLres, sizeof(Level<double>)));
   h->hist_cap = 4097;
-  HIPCHK(h, h->dalloc(&h->dhist, h->hist_cap * sizeof(double)));
+  h->dhist.assign(h->nprob, nullptr);
+  for (int p = 0; p < h->nprob; ++p) HIPCHK(h, h->dalloc(&h->dhist[p], (size_t)h->hist_cap * sizeof(double)));
 
   // coefficient checks (read-only device pass)
-  const int ncx = grid->nx - 1, ncy = py ? grid->ny : grid->ny - 1;
   if (h->kind == MG_COEF_CELL9) {
+    const mg_grid& grid = h->groups[0].grid;
+    const int ncx = grid.nx - 1, ncy = grid.periodic_y ? grid.ny : grid.ny - 1;
     int* dcount = nullptr;
     HIPCHK(h, h->dalloc(&dcount, sizeof(int)));
     const long nc = h->oned ? ncx : (long)ncx * ncy;
@@ -497,140 +703,130 @@ mg_status setup_impl(mg_handle h, const mg_grid* grid, const mg_coeffs* coeffs, 
     if (s != MG_OK) return s;
     if (bad) return fail(h, MG_EINVAL, std::to_string(bad) + " coefficient values are not finite and > 0");
   }
-
-  // level buffers
-  const bool mixed = h->mixed();
-  h->L64.resize(h->nlev);
-  h->L32.resize(mixed ? h->nlev : 0);
-  for (int l = 0; l < h->nlev; ++l) {
-    const LevelShape& s = h->shp[l];
-    if (l == 0) {
-      // finest FP64 level: x and b are the caller's arrays (pitch nx)
-      h->L64[0] = make_level<double>(s, s.nx, h->dstate);
-      if (!mixed) HIPCHK(h, h->dalloc(&h->L64[0].t, (size_t)s.nx * s.ny * sizeof(double)));
-    } else if (!mixed) {
-      const int p = round_up(s.nx, 16);
-      Level<double>& L = h->L64[l];
-      L = make_level<double>(s, p, h->dstate);
-      HIPCHK(h, h->dalloc(&L.x, (size_t)p * s.ny * sizeof(double)));
-      HIPCHK(h, h->dalloc(&L.b, (size_t)p * s.ny * sizeof(double)));
-      HIPCHK(h, h->dalloc(&L.t, (size_t)p * s.ny * sizeof(double)));
-    }
-    if (mixed) {
-      const int p = round_up(s.nx, 32);
-      Level<float>& L = h->L32[l];
-      L = make_level<float>(s, p, h->dstate);
-      HIPCHK(h, h->dalloc(&L.x, (size_t)p * s.ny * sizeof(float)));
-      HIPCHK(h, h->dalloc(&L.b, (size_t)p * s.ny * sizeof(float)));
-      HIPCHK(h, h->dalloc(&L.t, (size_t)p * s.ny * sizeof(float)));
-    }
-  }
-
-  // operators
-  if (h->kind == MG_COEF_CONST5) {
-    for (int l = 0; l < h->nlev; ++l) {
-      const double cx = h->eps_x / (h->hx[l] * h->hx[l]);
-      const double cy = h->eps_y / (h->hy[l] * h->hy[l]);
-      const double dg = 2.0 * (cx + cy);
-      Level<double>& L = h->L64[l];
-      L.kind = ST5;
-      L.cx = cx;
-      L.cy = cy;
-      L.dg = dg;
-      L.inv_dg = 1.0 / dg;
-      if (mixed) {
-        Level<float>& M = h->L32[l];
-        M.kind = ST5;
-        M.cx = (float)cx;
-        M.cy = (float)cy;
-        M.dg = (float)dg;
-        M.inv_dg = (float)(1.0 / dg);
-      }
-    }
-  } else {
-    h->band64.resize(h->nlev);
-    h->band32.resize(h->nlev);
-    for (int l = 0; l < h->nlev; ++l) {
-      const LevelShape& s = h->shp[l];
-      const int bp = round_up(s.nx, 16);
-      const int brows = h->oned ? 1 : s.ny;
-      const int bstride = bp * brows;
-      HIPCHK(h, h->dalloc(&h->band64[l], (size_t)5 * bstride * sizeof(double)));
-      if (l == 0) {
-        HIPCHK(h, launch_q1_bands(h->band64[0], bstride, h->oned ? 0 : bp, brows, s.nx, s.ny, s.py, coeffs->kx,
-                                  coeffs->ky, h->oned ? 0 : ncx, h->hx[0], h->hy[0], h->stream));
-      } else {
-        const LevelShape& f = h->shp[l - 1];
-        const int fbp = round_up(f.nx, 16);
-        const int fbstride = fbp * (h->oned ? 1 : f.ny);
-        HIPCHK(h, launch_rap(h->band64[l], bstride, h->oned ? 0 : bp, brows, s.nx, s.ny, h->band64[l - 1], fbstride,
-                             h->oned ? 0 : fbp, f.nx, f.ny, s.py, h->stream));
-      }
-      Level<double>& L = h->L64[l];
-      L.kind = ST9;
-      L.band = h->band64[l];
-      L.bpitch = h->oned ? 0 : bp;
-      L.bstride = bstride;
-      if (mixed) {
-        HIPCHK(h, h->dalloc(&h->band32[l], (size_t)5 * bstride * sizeof(float)));
-        HIPCHK(h, launch_to_float(h->band64[l], h->band32[l], (long)5 * bstride, h->stream));
-        Level<float>& M = h->L32[l];
-        M.kind = ST9;
-        M.band = h->band32[l];
-        M.bpitch = L.bpitch;
-        M.bstride = bstride;
-      }
-    }
-  }
-
-  // coarsest operator: dense matrix and Cholesky factor (FP64)
-  {
-    const int n = h->ncu;
-    const Level<double>& L = h->L64[h->nlev - 1];
-    HIPCHK(h, h->dalloc(&h->dchol, (size_t)n * n * sizeof(double)));
-    HIPCHK(h, launch_dense_coarse(h->dchol, n, sc.nx, sc.ny, sc.py, L.kind, L.cx, L.cy, L.dg, L.band, L.bstride,
-                                  L.bpitch, h->stream));
-    int* dinfo = nullptr;
-    HIPCHK(h, h->dalloc(&dinfo, sizeof(int)));
-    HIPCHK(h, launch_cholesky(h->dchol, n, dinfo, h->stream));
-    int info = 0;
-    HIPCHK(h, hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    mg_status s = sync_check(h);
+  HIPCHK(h, h->mixed() ? prepare_subcycle_lds<float>() : prepare_subcycle_lds<double>());
+  HIPCHK(h, h->mixed() ? prepare_fused<float>() : prepare_fused<double>());
+  for (Group& G : h->groups) {
+    mg_status s = setup_group(h, G, coeffs, levels);
     if (s != MG_OK) return s;
-    if (info) return fail(h, MG_EINVAL, "coarsest operator is not positive definite");
-    HIPCHK(h, h->dalloc(&h->dcholp, sizeof(double*)));
-    HIPCHK(h, hipMemcpyAsync(h->dcholp, &h->dchol, sizeof(double*), hipMemcpyHostToDevice, h->stream));
   }
-
-  // descriptors
-  HIPCHK(h, h->dalloc(&h->dL64, h->nlev * sizeof(Level<double>)));
-  HIPCHK(h, hipMemcpyAsync(h->dL64, h->L64.data(), h->nlev * sizeof(Level<double>), hipMemcpyHostToDevice, h->stream));
-  if (mixed) {
-    HIPCHK(h, h->dalloc(&h->dL32, h->nlev * sizeof(Level<float>)));
-    HIPCHK(h,
-           hipMemcpyAsync(h->dL32, h->L32.data(), h->nlev * sizeof(Level<float>), hipMemcpyHostToDevice, h->stream));
-  }
-  HIPCHK(h, mixed ? prepare_subcycle_lds<float>() : prepare_subcycle_lds<double>());
-  HIPCHK(h, mixed ? prepare_fused<float>() : prepare_fused<double>());
-  mg_status s = build_program(h);
-  if (s != MG_OK) return s;
   // partial sums of a norm reduction: one per workgroup of the norm kernel or
   // of the finest post-pass when it carries the stopping test
-  size_t nparts = MAX_NORM_BLOCKS;
-  if (h->norm_fused) nparts = std::max(nparts, (size_t)h->gpost[0].ntx * h->gpost[0].nty);
-  HIPCHK(h, h->dalloc(&h->dpartial, nparts * sizeof(double)));
-  s = sync_check(h);
+  h->dpartial.assign(h->nprob, nullptr);
+  for (const Group& G : h->groups) {
+    size_t nparts = MAX_NORM_BLOCKS;
+    if (G.norm_fused) nparts = std::max(nparts, (size_t)G.gpost[0].ntx * G.gpost[0].nty);
+    for (int s = 0; s < G.ns; ++s) HIPCHK(h, h->dalloc(&h->dpartial[G.probs[s]], nparts * sizeof(double)));
+  }
+  for (Group& G : h->groups) {
+    mg_status s = upload_descriptors(h, G);
+    if (s != MG_OK) return s;
+  }
+  mg_status s = sync_check(h);
   if (s != MG_OK) return s;
   return build_graphs(h);
 }
 
 mg_status grow_history(mg_handle h, int need) {
   if (need <= h->hist_cap) return MG_OK;
-  double* p = nullptr;
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  HIPCHK(h, h->dalloc(&p, (size_t)need * sizeof(double)));
-  h->dhist = p;  // the old buffer stays owned by the handle until mg_destroy
+  for (int p = 0; p < h->nprob; ++p) {
+    double* q = nullptr;
+    HIPCHK(h, h->dalloc(&q, (size_t)need * sizeof(double)));
+    h->dhist[p] = q;  // the old buffer stays owned by the handle until mg_destroy
+  }
   h->hist_cap = need;
+  return MG_OK;
+}
+
+// Points every problem's finest level at the caller's arrays, zeroes their
+// Dirichlet boundaries, resets the stopping states and measures r0 (events
+// start before the r0 measurement).
+mg_status begin_solve(mg_handle h, const double* const* rhs, double* const* x, double tol) {
+  hipStream_t st = h->stream;
+  std::vector<SolveState> init(h->nprob);
+  for (int p = 0; p < h->nprob; ++p) {
+    init[p] = SolveState{};
+    init[p].tol = tol;
+    init[p].history = h->dhist[p];
+    init[p].hist_cap = h->hist_cap;
+    init[p].partial = h->dpartial[p];
+  }
+  HIPCHK(h, hipMemcpyAsync(h->dstate, init.data(), (size_t)h->nprob * sizeof(SolveState), hipMemcpyHostToDevice, st));
+  for (Group& G : h->groups) {
+    for (int s = 0; s < G.ns; ++s) {
+      const int p = G.probs[s];
+      G.l64(0, s).x = x[p];
+      G.l64(0, s).b = const_cast<double*>(rhs[p]);
+      const LevelShape& s0 = G.shp[0];
+      HIPCHK(h, launch_zero_boundary(x[p], s0.nx, s0.ny, s0.nx, s0.py, st));
+    }
+    mg_status s = upload_descriptors(h, G);  // also waits for the state upload above
+    if (s != MG_OK) return s;
+  }
+  HIPCHK(h, hipEventRecord(h->ev0, st));
+  for (Group& G : h->groups)
+    HIPCHK(h, launch_resnorm<double>(G.dL64, G.shp[0], NORM_INIT, nullptr, h->mixed() ? G.dL32 : nullptr, G.ns, st));
+  return MG_OK;
+}
+
+// Replays the cycle graph until every problem stopped or max_cycles cycles
+// were queued; reads the stopping states once per batch into `cur`.
+mg_status run_cycles(mg_handle h, int max_cycles, double tol, std::vector<SolveState>& cur) {
+  hipStream_t st = h->stream;
+  cur.assign(h->nprob, SolveState{});
+  int queued = 0, batch = 1;
+  while (true) {
+    const int nb = std::min(batch, max_cycles - queued);
+    for (int k = 0; k + 8 <= nb; k += 8) HIPCHK(h, hipGraphLaunch(h->g8, st));
+    for (int k = 0; k < nb % 8; ++k) HIPCHK(h, hipGraphLaunch(h->g1, st));
+    queued += nb;
+    HIPCHK(h, hipMemcpyAsync(cur.data(), h->dstate, (size_t)h->nprob * sizeof(SolveState), hipMemcpyDeviceToHost,
+                             st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    if (queued >= max_cycles) break;
+    // predict the cycles still needed from the slowest running problem's latest factor
+    int need = 0;
+    bool running = false;
+    for (const SolveState& s : cur) {
+      if (s.done) continue;
+      running = true;
+      const double rho = s.prev > 0 ? s.last / s.prev : 0.0;
+      const double goal = tol * s.r0;
+      int n = std::min(2 * batch, 64);
+      if (rho > 0.0 && rho < 1.0 && s.last > goal)
+        n = (int)std::min(4096.0, std::max(1.0, std::ceil(std::log(goal / s.last) / std::log(rho))));
+      need = std::max(need, n);
+    }
+    if (!running) break;
+    batch = std::max(1, need);
+  }
+  return MG_OK;
+}
+
+void fill_info(const SolveState& s, float ms, mg_info* info) {
+  info->cycles = s.cycles;
+  info->res0 = s.r0;
+  info->res = s.last;
+  info->rel_res = s.r0 > 0 ? s.last / s.r0 : 0.0;
+  info->rho_last = s.prev > 0 ? s.last / s.prev : 0.0;
+  info->rho_mean = (s.cycles > 0 && s.r0 > 0 && s.last > 0) ? std::pow(s.last / s.r0, 1.0 / s.cycles) : 0.0;
+  info->seconds = ms * 1e-3;
+}
+
+mg_status status_of(const SolveState& s) {
+  return s.done == 1 ? MG_OK : (s.done == 2 ? MG_DIVERGED : MG_NOT_CONVERGED);
+}
+
+mg_status single_only(mg_handle h) {
+  if (!h) return fail(nullptr, MG_EINVAL, "handle is NULL");
+  if (h->batched) return fail(h, MG_EUNSUPPORTED, "handle was made by mg_setup_batched");
+  return MG_OK;
+}
+
+mg_status finish_solve(mg_handle h, float* ms) {
+  HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+  HIPCHK(h, hipEventSynchronize(h->ev1));
+  HIPCHK(h, hipEventElapsedTime(ms, h->ev0, h->ev1));
   return MG_OK;
 }
 
@@ -655,13 +851,14 @@ const char* mg_status_string(mg_status s) {
 
 const char* mg_last_error(mg_handle h) { return h ? h->err.c_str() : g_thread_err.c_str(); }
 
-int32_t mg_num_levels(mg_handle h) { return h ? h->nlev : 0; }
+int32_t mg_num_levels(mg_handle h) { return h && !h->groups.empty() ? h->groups[0].nlev : 0; }
 
 mg_status mg_level_shape(mg_handle h, int32_t l, int32_t* nx, int32_t* ny) {
   if (!h || !nx || !ny) return fail(h, MG_EINVAL, "NULL argument");
-  if (l < 0 || l >= h->nlev) return fail(h, MG_EINVAL, "level out of range");
-  *nx = h->shp[l].nx;
-  *ny = h->shp[l].ny;
+  const Group& G = h->groups[0];
+  if (l < 0 || l >= G.nlev) return fail(h, MG_EINVAL, "level out of range");
+  *nx = G.shp[l].nx;
+  *ny = G.shp[l].ny;
   return MG_OK;
 }
 
@@ -687,7 +884,78 @@ mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, int32_t levels,
 
   mg_handle h = new mg_handle_s();
   h->opts = *opts;
-  s = setup_impl(h, grid, coeffs, levels);
+  h->kind = coeffs->kind;
+  h->oned = coeffs->kx_1d_along_x ? 1 : 0;
+  h->nprob = 1;
+  h->eps_x.assign(1, coeffs->eps_x);
+  h->eps_y.assign(1, coeffs->eps_y);
+  h->groups.resize(1);
+  h->groups[0].grid = *grid;
+  h->groups[0].ns = 1;
+  h->groups[0].probs = {0};
+  s = setup_handle(h, coeffs, levels);
+  if (s != MG_OK) {
+    g_thread_err = h->err;
+    release(h);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return MG_OK;
+}
+
+mg_status mg_setup_batched(const mg_grid* grids, const mg_coeffs* coeffs, int32_t nprob, const mg_options* opts,
+                           mg_handle* out) {
+  g_thread_err.clear();
+  if (!out) return fail(nullptr, MG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!grids || !coeffs) return fail(nullptr, MG_EINVAL, "grids and coeffs must be host arrays");
+  if (nprob < 1 || nprob > MAX_BATCH)
+    return fail(nullptr, MG_EINVAL, "nprob must be in [1, " + std::to_string(MAX_BATCH) + "]");
+  for (int p = 0; p < nprob; ++p) {
+    mg_status s = check_grid(grids + p);
+    if (s != MG_OK) return fail(nullptr, s, "problem " + std::to_string(p) + ": " + g_thread_err);
+    if (coeffs[p].kind != MG_COEF_CONST5)
+      return fail(nullptr, MG_EUNSUPPORTED, "batched solves take MG_COEF_CONST5 problems only");
+    if (!(finite_pos(coeffs[p].eps_x) && finite_pos(coeffs[p].eps_y)))
+      return fail(nullptr, MG_EINVAL, "problem " + std::to_string(p) + ": eps_x and eps_y must be finite and > 0");
+  }
+  mg_status s = check_opts(opts, MG_COEF_CONST5);
+  if (s != MG_OK) return s;
+
+  mg_handle h = new mg_handle_s();
+  h->batched = true;
+  h->opts = *opts;
+  h->kind = MG_COEF_CONST5;
+  h->nprob = nprob;
+  h->eps_x.resize(nprob);
+  h->eps_y.resize(nprob);
+  // one group per distinct grid, largest grids first
+  std::map<std::tuple<int, int, int, double, double>, int> key;
+  std::vector<int> order(nprob);
+  for (int p = 0; p < nprob; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (long)grids[a].nx * grids[a].ny > (long)grids[b].nx * grids[b].ny;
+  });
+  for (int p : order) {
+    h->eps_x[p] = coeffs[p].eps_x;
+    h->eps_y[p] = coeffs[p].eps_y;
+    const auto k = std::make_tuple(grids[p].nx, grids[p].ny, grids[p].periodic_y, grids[p].lx, grids[p].ly);
+    auto it = key.find(k);
+    int g;
+    if (it == key.end()) {
+      g = (int)h->groups.size();
+      key[k] = g;
+      h->groups.emplace_back();
+      h->groups[g].grid = grids[p];
+      h->groups[g].ns = 0;
+    } else {
+      g = it->second;
+    }
+    h->groups[g].ns++;
+    h->groups[g].probs.push_back(p);
+  }
+  s = setup_handle(h, nullptr, 0);
   if (s != MG_OK) {
     g_thread_err = h->err;
     release(h);
@@ -699,91 +967,81 @@ mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, int32_t levels,
 }
 
 mg_status mg_solve(mg_handle h, const double* rhs, double* x, double tol, int32_t max_cycles, mg_info* info) {
-  if (!h) return fail(nullptr, MG_EINVAL, "handle is NULL");
-  if (h->kind < 0) return fail(h, MG_EUNSUPPORTED, "handle was made by mg_setup_batched");
+  mg_status s = single_only(h);
+  if (s != MG_OK) return s;
   if (!rhs || !x) return fail(h, MG_EINVAL, "rhs and x must be device arrays");
+  if (!(std::isfinite(tol) && tol > 0.0)) return fail(h, MG_EINVAL, "tol must be finite and > 0");
+  if (max_cycles < 1) return fail(h, MG_EINVAL, "max_cycles must be >= 1");
+  s = grow_history(h, max_cycles + 1);
+  if (s != MG_OK) return s;
+  const double* rr[1] = {rhs};
+  double* xx[1] = {x};
+  s = begin_solve(h, rr, xx, tol);
+  if (s != MG_OK) return s;
+  std::vector<SolveState> cur;
+  s = run_cycles(h, max_cycles, tol, cur);
+  if (s != MG_OK) return s;
+  float ms = 0.f;
+  s = finish_solve(h, &ms);
+  if (s != MG_OK) return s;
+  if (info) {
+    fill_info(cur[0], ms, info);
+    if (info->history)
+      HIPCHK(h, hipMemcpy(info->history, h->dhist[0], (size_t)(cur[0].cycles + 1) * sizeof(double),
+                          hipMemcpyDeviceToHost));
+  }
+  return status_of(cur[0]);
+}
+
+mg_status mg_solve_batched(mg_handle h, const double* const* rhs, double* const* x, double tol, int32_t max_cycles,
+                           mg_info* info) {
+  if (!h) return fail(nullptr, MG_EINVAL, "handle is NULL");
+  if (!h->batched) return fail(h, MG_EUNSUPPORTED, "handle was made by mg_setup");
+  if (!rhs || !x) return fail(h, MG_EINVAL, "rhs and x must be host arrays of device pointers");
+  for (int p = 0; p < h->nprob; ++p)
+    if (!rhs[p] || !x[p]) return fail(h, MG_EINVAL, "problem " + std::to_string(p) + ": NULL array");
   if (!(std::isfinite(tol) && tol > 0.0)) return fail(h, MG_EINVAL, "tol must be finite and > 0");
   if (max_cycles < 1) return fail(h, MG_EINVAL, "max_cycles must be >= 1");
   mg_status s = grow_history(h, max_cycles + 1);
   if (s != MG_OK) return s;
-
-  const LevelShape& s0 = h->shp[0];
-  hipStream_t st = h->stream;
-  h->L64[0].x = x;
-  h->L64[0].b = const_cast<double*>(rhs);
-  HIPCHK(h, hipMemcpyAsync(h->dL64, h->L64.data(), sizeof(Level<double>), hipMemcpyHostToDevice, st));
-  SolveState init{};
-  init.tol = tol;
-  init.history = h->dhist;
-  init.hist_cap = h->hist_cap;
-  init.partial = h->dpartial;
-  HIPCHK(h, hipMemcpyAsync(h->dstate, &init, sizeof(SolveState), hipMemcpyHostToDevice, st));
-  HIPCHK(h, launch_zero_boundary(x, s0.nx, s0.ny, s0.nx, s0.py, st));
-  HIPCHK(h, hipEventRecord(h->ev0, st));
-  if (h->mixed()) {
-    HIPCHK(h, launch_resnorm<double>(h->dL64, s0, NORM_INIT, nullptr, h->L32[0].b, h->L32[0].pitch, 1, st));
-  } else {
-    HIPCHK(h, launch_resnorm<double>(h->dL64, s0, NORM_INIT, nullptr, nullptr, 0, 1, st));
-  }
-
-  SolveState cur{};
-  int queued = 0;
-  int batch = 1;
-  while (true) {
-    const int nb = std::min(batch, max_cycles - queued);
-    for (int k = 0; k + 8 <= nb; k += 8) HIPCHK(h, hipGraphLaunch(h->g8, st));
-    for (int k = 0; k < nb % 8; ++k) HIPCHK(h, hipGraphLaunch(h->g1, st));
-    queued += nb;
-    HIPCHK(h, hipMemcpyAsync(&cur, h->dstate, sizeof(SolveState), hipMemcpyDeviceToHost, st));
-    HIPCHK(h, hipStreamSynchronize(st));
-    if (cur.done || queued >= max_cycles) break;
-    // predict the cycles still needed from the latest convergence factor
-    const double rho = cur.prev > 0 ? cur.last / cur.prev : 0.0;
-    const double goal = tol * cur.r0;
-    int next = std::min(2 * batch, 64);
-    if (rho > 0.0 && rho < 1.0 && cur.last > goal) {
-      const double need = std::ceil(std::log(goal / cur.last) / std::log(rho));
-      next = (int)std::min(4096.0, std::max(1.0, need));
-    }
-    batch = next;
-  }
-  HIPCHK(h, hipEventRecord(h->ev1, st));
-  HIPCHK(h, hipEventSynchronize(h->ev1));
+  s = begin_solve(h, rhs, x, tol);
+  if (s != MG_OK) return s;
+  std::vector<SolveState> cur;
+  s = run_cycles(h, max_cycles, tol, cur);
+  if (s != MG_OK) return s;
   float ms = 0.f;
-  HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
-
-  mg_status status = cur.done == 1 ? MG_OK : (cur.done == 2 ? MG_DIVERGED : MG_NOT_CONVERGED);
-  if (info) {
-    info->cycles = cur.cycles;
-    info->res0 = cur.r0;
-    info->res = cur.last;
-    info->rel_res = cur.r0 > 0 ? cur.last / cur.r0 : 0.0;
-    info->rho_last = cur.prev > 0 ? cur.last / cur.prev : 0.0;
-    info->rho_mean = (cur.cycles > 0 && cur.r0 > 0 && cur.last > 0) ? std::pow(cur.last / cur.r0, 1.0 / cur.cycles) : 0.0;
-    info->seconds = ms * 1e-3;
-    if (info->history) {
-      HIPCHK(h, hipMemcpy(info->history, h->dhist, (size_t)(cur.cycles + 1) * sizeof(double), hipMemcpyDeviceToHost));
+  s = finish_solve(h, &ms);
+  if (s != MG_OK) return s;
+  mg_status worst = MG_OK;
+  for (int p = 0; p < h->nprob; ++p) {
+    if (info) {
+      fill_info(cur[p], ms, info + p);
+      if (info[p].history)
+        HIPCHK(h, hipMemcpy(info[p].history, h->dhist[p], (size_t)(cur[p].cycles + 1) * sizeof(double),
+                            hipMemcpyDeviceToHost));
     }
+    worst = std::max(worst, status_of(cur[p]));
   }
-  return status;
+  return worst;
 }
 
 mg_status mg_residual(mg_handle h, const double* rhs, const double* x, double* r, double* norm2) {
-  if (!h) return fail(nullptr, MG_EINVAL, "handle is NULL");
-  if (h->kind < 0) return fail(h, MG_EUNSUPPORTED, "handle was made by mg_setup_batched");
+  mg_status s = single_only(h);
+  if (s != MG_OK) return s;
   if (!rhs || !x || !norm2) return fail(h, MG_EINVAL, "rhs, x and norm2 must not be NULL");
   hipStream_t st = h->stream;
-  const LevelShape& s0 = h->shp[0];
-  Level<double> L = h->L64[0];
+  const Group& G = h->groups[0];
+  const LevelShape& s0 = G.shp[0];
+  Level<double> L = G.L64[0];
   L.x = const_cast<double*>(x);
   L.b = const_cast<double*>(rhs);
   L.st = h->dstate_res;
   SolveState init{};
-  init.partial = h->dpartial;
+  init.partial = h->dpartial[0];
   HIPCHK(h, hipMemcpyAsync(h->dstate_res, &init, sizeof(SolveState), hipMemcpyHostToDevice, st));
   HIPCHK(h, hipMemcpyAsync(h->dLres, &L, sizeof(Level<double>), hipMemcpyHostToDevice, st));
   if (r) HIPCHK(h, hipMemsetAsync(r, 0, (size_t)s0.nx * s0.ny * sizeof(double), st));
-  HIPCHK(h, launch_resnorm<double>(h->dLres, s0, NORM_RESID, r, nullptr, 0, 1, st));
+  HIPCHK(h, launch_resnorm<double>(h->dLres, s0, NORM_RESID, r, nullptr, 1, st));
   SolveState cur{};
   HIPCHK(h, hipMemcpyAsync(&cur, h->dstate_res, sizeof(SolveState), hipMemcpyDeviceToHost, st));
   HIPCHK(h, hipStreamSynchronize(st));
@@ -793,40 +1051,37 @@ mg_status mg_residual(mg_handle h, const double* rhs, const double* x, double* r
 
 mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t level, int32_t which, int32_t reps,
                           double* avg_us) {
-  if (!h) return fail(nullptr, MG_EINVAL, "handle is NULL");
+  mg_status s = single_only(h);
+  if (s != MG_OK) return s;
   if (!rhs || !x || !avg_us) return fail(h, MG_EINVAL, "rhs, x and avg_us must not be NULL");
   if (which != 0 && which != 1) return fail(h, MG_EINVAL, "which must be 0 (pre-pass) or 1 (post-pass)");
   if (reps < 1 || reps > 100000) return fail(h, MG_EINVAL, "reps must be in [1, 100000]");
-  if (level < 0 || level >= h->nlev) return fail(h, MG_EINVAL, "level out of range");
+  Group& G = h->groups[0];
+  if (level < 0 || level >= G.nlev) return fail(h, MG_EINVAL, "level out of range");
   const HostOp* found = nullptr;
-  for (const HostOp& op : h->prog)
+  for (const HostOp& op : G.prog)
     if (op.type == (which == 0 ? H_PRE : H_POST) && op.level == level) found = &op;
   if (!found) return fail(h, MG_EUNSUPPORTED, "no fused pass of that kind runs on this level");
   hipStream_t st = h->stream;
-  h->L64[0].x = x;
-  h->L64[0].b = const_cast<double*>(rhs);
-  HIPCHK(h, hipMemcpyAsync(h->dL64, h->L64.data(), sizeof(Level<double>), hipMemcpyHostToDevice, st));
-  SolveState init{};
-  init.tol = 1.0;
-  init.history = h->dhist;
-  init.hist_cap = h->hist_cap;
-  init.partial = h->dpartial;
-  HIPCHK(h, hipMemcpyAsync(h->dstate, &init, sizeof(SolveState), hipMemcpyHostToDevice, st));
+  const double* rr[1] = {rhs};
+  double* xx[1] = {x};
+  s = begin_solve(h, rr, xx, 1e-300);  // descriptors, zero boundary, a running state
+  if (s != MG_OK) return s;
   const int l = level;
   const int kind = stencil_kind(h);
   auto launch = [&]() -> hipError_t {
     if (h->mixed()) {
       if (which == 0)
-        return launch_pre<float>(h->dL32 + l, h->dL32 + l + 1, h->gpre[l], h->opts.nu_pre, h->ncol,
+        return launch_pre<float>(G.dL32 + l, G.dL32 + l + 1, G.gpre[l], h->opts.nu_pre, h->ncol,
                                  (float)h->opts.omega, kind, l == 0, 1, st);
-      return launch_post<float>(h->dL32 + l, h->dL32 + l + 1, h->gpost[l], h->opts.nu_post, h->ncol,
-                                (float)h->opts.omega, found->arg, h->dL64, kind, l == 0, 1, st, false);
+      return launch_post<float>(G.dL32 + l, G.dL32 + l + 1, G.gpost[l], h->opts.nu_post, h->ncol,
+                                (float)h->opts.omega, found->arg, G.dL64, kind, l == 0, 1, st, false);
     }
     if (which == 0)
-      return launch_pre<double>(h->dL64 + l, h->dL64 + l + 1, h->gpre[l], h->opts.nu_pre, h->ncol, h->opts.omega,
+      return launch_pre<double>(G.dL64 + l, G.dL64 + l + 1, G.gpre[l], h->opts.nu_pre, h->ncol, h->opts.omega,
                                 kind, l == 0, 1, st);
-    return launch_post<double>(h->dL64 + l, h->dL64 + l + 1, h->gpost[l], h->opts.nu_post, h->ncol, h->opts.omega,
-                               found->arg, h->dL64, kind, l == 0, 1, st, false);
+    return launch_post<double>(G.dL64 + l, G.dL64 + l + 1, G.gpost[l], h->opts.nu_post, h->ncol, h->opts.omega,
+                               found->arg, G.dL64, kind, l == 0, 1, st, false);
   };
   HIPCHK(h, launch());
   HIPCHK(h, hipEventRecord(h->ev0, st));
@@ -840,33 +1095,15 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
 }
 
 mg_status mg_coeff_grad(mg_handle h, const double* u, const double* lam, double* dL_dk) {
-  if (!h) return fail(nullptr, MG_EINVAL, "handle is NULL");
+  mg_status s = single_only(h);
+  if (s != MG_OK) return s;
   if (h->kind != MG_COEF_CELL9) return fail(h, MG_EUNSUPPORTED, "coefficient gradient needs MG_COEF_CELL9");
   if (!u || !lam || !dL_dk) return fail(h, MG_EINVAL, "u, lam and dL_dk must be device arrays");
-  const LevelShape& s = h->shp[0];
-  HIPCHK(h, launch_coeff_grad(u, lam, dL_dk, s.nx, s.ny, s.py, h->hx[0], h->hy[0], h->stream));
+  const Group& G = h->groups[0];
+  const LevelShape& s0 = G.shp[0];
+  HIPCHK(h, launch_coeff_grad(u, lam, dL_dk, s0.nx, s0.ny, s0.py, G.hx[0], G.hy[0], h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   return MG_OK;
-}
-
-mg_status mg_setup_batched(const mg_grid* grids, const mg_coeffs* coeffs, int32_t nprob, const mg_options* opts,
-                           mg_handle* out) {
-  (void)grids;
-  (void)coeffs;
-  (void)nprob;
-  (void)opts;
-  if (out) *out = nullptr;
-  return fail(nullptr, MG_EUNSUPPORTED, "batched solves are not built yet");
-}
-
-mg_status mg_solve_batched(mg_handle h, const double* const* rhs, double* const* x, double tol, int32_t max_cycles,
-                           mg_info* info) {
-  (void)rhs;
-  (void)x;
-  (void)tol;
-  (void)max_cycles;
-  (void)info;
-  return fail(h, MG_EUNSUPPORTED, "batched solves are not built yet");
 }
 
 mg_status mg_destroy(mg_handle h) {

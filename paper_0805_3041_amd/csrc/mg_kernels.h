@@ -38,8 +38,8 @@ template <typename T>
 hipError_t launch_subcycle(const Level<T>* levs, int nlev, const DOp* prog, const int* beg, const int* cnt,
                            const double* const* chol, int ncu, T omega, int ncol, int nslots, hipStream_t st);
 template <typename T>
-hipError_t launch_resnorm(const Level<T>* Ls, const LevelShape& s, int mode, T* rout, float* r32, int p32, int nslots,
-                          hipStream_t st);
+hipError_t launch_resnorm(const Level<T>* Ls, const LevelShape& s, int mode, T* rout, const Level<float>* R32s,
+                          int nslots, hipStream_t st);
 
 template <typename T>
 hipError_t prepare_subcycle_lds();

@@ -511,15 +511,19 @@ __global__ void __launch_bounds__(NT) k_norm_finish(const Level<T>* __restrict__
 }
 
 // r = b - A x on level L (FP64 accumulation), boundary x read as 0.
-// Optional outputs r (pitch L.pitch) and r32 (pitch p32).  Writes one partial
-// sum of squares per workgroup; k_norm_finish completes the norm.
+// Optional outputs: r (pitch L.pitch) and, for the mixed-precision outer
+// step, (float) r into the FP32 finest level's b of the same slot (R32s).
+// Writes one partial sum of squares per workgroup; k_norm_finish completes
+// the norm.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_resnorm(const Level<T>* __restrict__ Ls, int mode, T* __restrict__ rout,
-                                                float* __restrict__ r32, int p32) {
+                                                const Level<float>* __restrict__ R32s) {
   __shared__ double sh[NT / 64];
   const Level<T> L = Ls[blockIdx.z];
   SolveState* st = L.st;
   if (mode == NORM_CHECK && st->done) return;
+  float* r32 = R32s ? R32s[blockIdx.z].b : nullptr;
+  const int p32 = R32s ? R32s[blockIdx.z].pitch : 0;
   const int lo = row_lo(L), nr = row_hi(L) - lo + 1, ni = L.nx - 2;
   const int n = nr * ni;
   double acc = 0.0;
@@ -894,10 +898,10 @@ int norm_blocks(const LevelShape& s) {
 }
 
 template <typename T>
-hipError_t launch_resnorm(const Level<T>* Ls, const LevelShape& s, int mode, T* rout, float* r32, int p32, int nslots,
-                          hipStream_t st) {
+hipError_t launch_resnorm(const Level<T>* Ls, const LevelShape& s, int mode, T* rout, const Level<float>* R32s,
+                          int nslots, hipStream_t st) {
   const int nb = norm_blocks(s);
-  hipLaunchKernelGGL(k_resnorm<T>, dim3(nb, 1, nslots), dim3(NT), 0, st, Ls, mode, rout, r32, p32);
+  hipLaunchKernelGGL(k_resnorm<T>, dim3(nb, 1, nslots), dim3(NT), 0, st, Ls, mode, rout, R32s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_norm_finish<T>(Ls, nb, mode, nslots, st);
@@ -983,7 +987,8 @@ hipError_t launch_coeff_grad(const double* u, const double* lam, double* g, int 
   template hipError_t launch_coarse<T>(const Level<T>*, const double* const*, int, int, hipStream_t);             \
   template hipError_t launch_subcycle<T>(const Level<T>*, int, const DOp*, const int*, const int*,                \
                                          const double* const*, int, T, int, int, hipStream_t);                     \
-  template hipError_t launch_resnorm<T>(const Level<T>*, const LevelShape&, int, T*, float*, int, int, hipStream_t); \
+  template hipError_t launch_resnorm<T>(const Level<T>*, const LevelShape&, int, T*, const Level<float>*, int,     \
+                                        hipStream_t);                                                               \
   template hipError_t prepare_subcycle_lds<T>();                                                                   \
   template hipError_t launch_norm_finish<T>(const Level<T>*, int, int, int, hipStream_t);                          \
   template hipError_t launch_subcycle_lds<T>(const Level<T>*, int, int, const DOp*, const int*, const int*,        \

@@ -198,6 +198,47 @@ def mg_profile_pass(h, rhs: torch.Tensor, x: torch.Tensor, level: int, which: in
     return us.value
 
 
+def mg_setup_batched(grids, coeffs, opts: mg_options):
+    lib = load_library()
+    n = len(grids)
+    ga = (mg_grid * n)(*grids)
+    ca = (mg_coeffs * n)(*coeffs)
+    h = ctypes.c_void_p()
+    s = lib.mg_setup_batched(ga, ca, n, ctypes.byref(opts), ctypes.byref(h))
+    if s != MG_OK:
+        raise MGError(s, last_error(None))
+    return h
+
+
+def mg_solve_batched(h, rhs: list, x: list, tol: float, max_cycles: int, history: bool = False):
+    lib = load_library()
+    n = len(rhs)
+    ra = (ctypes.c_void_p * n)(*[t.data_ptr() for t in rhs])
+    xa = (ctypes.c_void_p * n)(*[t.data_ptr() for t in x])
+    infos = (mg_info * n)()
+    hists = []
+    if history:
+        for k in range(n):
+            hh = np.zeros(max_cycles + 1, dtype=np.float64)
+            infos[k].history = hh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            hists.append(hh)
+    s = lib.mg_solve_batched(h, ra, xa, float(tol), int(max_cycles), infos)
+    if s < 0:
+        raise MGError(s, last_error(h))
+    out = []
+    for k in range(n):
+        i = infos[k]
+        if not np.isfinite(i.rel_res) or i.rel_res > 1e6:
+            st = MG_DIVERGED
+        elif i.rel_res <= tol:
+            st = MG_OK
+        else:
+            st = MG_NOT_CONVERGED
+        out.append(SolveInfo(st, i.cycles, i.res0, i.res, i.rel_res, i.rho_last, i.rho_mean, i.seconds,
+                             hists[k][: i.cycles + 1].copy() if history else np.zeros(0)))
+    return s, out
+
+
 def mg_destroy(h) -> None:
     if h is not None and h.value:
         load_library().mg_destroy(h)
@@ -270,6 +311,43 @@ class Solver:
     def profile_pass(self, rhs: torch.Tensor, x: torch.Tensor, level: int, which: int, reps: int = 50) -> float:
         """Average device time (us) of one fused pre-pass (which=0) or post-pass (1) on `level`."""
         return mg_profile_pass(self.h, rhs, x, level, which, reps)
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None:
+            mg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchedSolver:
+    """Many independent 5-point problems solved by one sequence of launches
+    (mg_setup_batched).  grids: list of (nx, ny) or (nx, ny, periodic_y);
+    eps: list of eps_x (eps_y = 1) or (eps_x, eps_y)."""
+
+    def __init__(self, grids, eps, **opt):
+        gs, cs = [], []
+        for g, e in zip(grids, eps):
+            nx, ny = g[0], g[1]
+            py = g[2] if len(g) > 2 else False
+            gs.append(mg_grid(nx, ny, 0, 1 if py else 0, 1.0, 1.0))
+            ex, ey = (e, 1.0) if not isinstance(e, (tuple, list)) else e
+            cs.append(mg_coeffs(MG_COEF_CONST5, float(ex), float(ey), None, None, 0))
+        self.shapes = [(g.ny, g.nx) for g in gs]
+        self.opts = make_options(**opt)
+        self.h = mg_setup_batched(gs, cs, self.opts)
+
+    def solve(self, rhs: list, x: list, tol: float = 1e-10, max_cycles: int = 100, history: bool = False):
+        """Returns (worst status, [SolveInfo per problem]); each info.status is
+        MG_OK if that problem met the tolerance."""
+        for r, xx, shp in zip(rhs, x, self.shapes):
+            _check_f64(r, shp, "rhs")
+            _check_f64(xx, shp, "x")
+        return mg_solve_batched(self.h, rhs, x, tol, max_cycles, history)
 
     def close(self) -> None:
         if getattr(self, "h", None) is not None:

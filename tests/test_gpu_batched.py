@@ -1,0 +1,129 @@
+"""Batched solves (mg_setup_batched / mg_solve_batched): every problem's
+iterates equal its own single-problem solve bit for bit and the oracle to
+1e-12 per cycle; statuses and cycle counts match."""
+
+import numpy as np
+import pytest
+
+from oracle import mg_oracle as O
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _mg():
+    from paper_0805_3041_amd import mg
+    return mg
+
+
+SIZES = [33, 65, 129, 65, 33, 129, 257, 65]
+EPS = [1.0, 0.3, 0.05, 1e-2, 1e-3, 0.7, 0.2, 1.0]
+
+
+def _inputs(sizes):
+    return [W.normal_field(n, n, 1000 + i) for i, n in enumerate(sizes)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_iterates_equal_single_solves(precision):
+    mg = _mg()
+    rhs = _inputs(SIZES)
+    B = mg.BatchedSolver([(n, n) for n in SIZES], EPS, smoother="rbgs", precision=precision)
+    rt = [torch.tensor(r, device="cuda") for r in rhs]
+    xb = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for n in SIZES]
+    outs = []
+    for _ in range(3):
+        B.solve(rt, xb, 1e-300, 1)
+        outs.append([x.cpu().numpy().copy() for x in xb])
+    B.close()
+    for i, (n, e) in enumerate(zip(SIZES, EPS)):
+        s = mg.Solver(n, n, eps_x=e, smoother="rbgs", precision=precision)
+        x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        for c in range(3):
+            s.solve(rt[i], x, 1e-300, 1, history=False)
+            assert np.array_equal(x.cpu().numpy(), outs[c][i]), (i, c)
+        s.close()
+
+
+def test_batched_matches_oracle_per_cycle():
+    rhs = _inputs(SIZES)
+    mg = _mg()
+    B = mg.BatchedSolver([(n, n) for n in SIZES], EPS, smoother="rbgs")
+    rt = [torch.tensor(r, device="cuda") for r in rhs]
+    xb = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for n in SIZES]
+    got = []
+    for _ in range(2):
+        B.solve(rt, xb, 1e-300, 1)
+        got.append([x.cpu().numpy().copy() for x in xb])
+    B.close()
+    for i, (n, e) in enumerate(zip(SIZES, EPS)):
+        g = O.Grid(n, n)
+        h = O.hierarchy_5pt(g, e, 1.0, O.Options(smoother="rbgs"))
+        x = np.zeros(g.n_unknowns)
+        for c in range(2):
+            x = O.mg_cycle(h, 0, x, g.pack(rhs[i]), "F")
+            err = np.abs(g.pack(got[c][i]) - x).max() / np.abs(x).max()
+            assert err <= 1e-12, (i, c, err)
+
+
+def test_batched_to_tolerance_statuses_and_cycles():
+    mg = _mg()
+    rhs = _inputs(SIZES)
+    B = mg.BatchedSolver([(n, n) for n in SIZES], EPS, smoother="rbgs")
+    rt = [torch.tensor(r, device="cuda") for r in rhs]
+    xb = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for n in SIZES]
+    worst, infos = B.solve(rt, xb, 1e-10, 5000, history=True)
+    B.close()
+    assert worst == mg.MG_OK
+    for i, (n, e) in enumerate(zip(SIZES, EPS)):
+        s = mg.Solver(n, n, eps_x=e, smoother="rbgs")
+        x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        info = s.solve(rt[i], x, 1e-10, 5000)
+        s.close()
+        assert info.status == mg.MG_OK and infos[i].status == mg.MG_OK
+        assert infos[i].cycles == info.cycles, (i, infos[i].cycles, info.cycles)
+        assert torch.equal(x, xb[i])
+        np.testing.assert_array_equal(infos[i].history, info.history)
+
+
+def test_batched_max_cycles_and_masking():
+    """With max_cycles = 3 the fast problems converge and stop while slow ones report
+    MG_NOT_CONVERGED after exactly 3 cycles."""
+    mg = _mg()
+    sizes, eps = [65, 65], [1.0, 1e-3]
+    rhs = _inputs(sizes)
+    B = mg.BatchedSolver([(n, n) for n in sizes], eps, smoother="rbgs")
+    rt = [torch.tensor(r, device="cuda") for r in rhs]
+    xb = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for n in sizes]
+    worst, infos = B.solve(rt, xb, 1e-3, 3)
+    B.close()
+    assert worst == mg.MG_NOT_CONVERGED
+    assert infos[0].status == mg.MG_OK and infos[0].cycles <= 3
+    assert infos[1].status == mg.MG_NOT_CONVERGED and infos[1].cycles == 3
+
+
+@pytest.mark.slow
+def test_batch256_sample_problems_match_oracle():
+    """The full 256-problem batch (sizes from {129, 257, 513, 1025}, eps log-uniform):
+    two cycles; a sample of problems of every size checked against the oracle."""
+    mg = _mg()
+    sizes, eps = W.batch_problems(256, 4)
+    B = mg.BatchedSolver([(n, n) for n in sizes], eps, smoother="rbgs")
+    rt = [torch.tensor(W.batch_rhs(n, i), device="cuda") for i, n in enumerate(sizes)]
+    xb = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for n in sizes]
+    B.solve(rt, xb, 1e-300, 2)
+    B.close()
+    picked = {}
+    for i, n in enumerate(sizes):
+        picked.setdefault(n, i)
+    for n, i in sorted(picked.items()):
+        if n > 513:
+            continue  # the oracle's 1025^2 cycles are covered by the single-problem full-size test
+        g = O.Grid(n, n)
+        h = O.hierarchy_5pt(g, eps[i], 1.0, O.Options(smoother="rbgs"))
+        x = np.zeros(g.n_unknowns)
+        for _ in range(2):
+            x = O.mg_cycle(h, 0, x, g.pack(W.batch_rhs(n, i)), "F")
+        err = np.abs(g.pack(xb[i].cpu().numpy()) - x).max() / np.abs(x).max()
+        assert err <= 1e-12, (n, i, err)
