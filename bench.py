@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="aniso1025", choices=["aniso1025"])
+    ap.add_argument("--workload", default="aniso1025", choices=["aniso1025", "annulus4097"])
     ap.add_argument("--nu", type=int, default=2)
     ap.add_argument("--x0", default="zero", choices=["zero", "uniform"])
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
@@ -108,12 +108,127 @@ def cpu_baseline(n, eps_list, cycles_per_eps, nu, seconds):
     }
 
 
+def annulus(args):
+    """Workload annulus4097: r in [0.5, 1], theta periodic, mapped to the unit
+    square (Q1, kx = 4 pi r, ky = 1/(4 pi r) per radial cell), 4097 radial x
+    4096 angular nodes (16,773,120 unknowns), f = N(0, 1) (seed 3), x0 = 0,
+    four-colour Gauss-Seidel 2/2, F-cycle over 11 levels down to 5 x 4."""
+    import torch
+
+    import workloads as W
+    from paper_0805_3041_amd import mg
+
+    nx, ny = 4097, 4096
+    kx, ky = W.annulus_cell_coefficients(nx)
+    kxt, kyt = torch.tensor(kx, device="cuda"), torch.tensor(ky, device="cuda")
+    rhs = torch.tensor(W.annulus_rhs(nx, ny, 3), device="cuda")
+    unknowns = (nx - 2) * ny
+
+    def make(precision):
+        return mg.Solver(nx, ny, periodic_y=True, kx=kxt, ky=kyt, kx_1d_along_x=True, smoother="gs4c",
+                         nu_pre=args.nu, nu_post=args.nu, precision=precision)
+
+    def run(s, steps, warmup):
+        x = torch.zeros_like(rhs)
+        for _ in range(warmup):
+            x.zero_()
+            s.solve(rhs, x, TOL, args.max_cycles, history=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = None
+        for _ in range(steps):
+            x.zero_()
+            info = s.solve(rhs, x, TOL, args.max_cycles, history=False)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, info, x
+
+    head = args.precision
+    other = "fp64" if head == "mixed" else "mixed"
+    s = make(head)
+    wall_h, info_h, x = run(s, args.steps, args.warmup)
+    if info_h.status != mg.MG_OK:
+        raise SystemExit(f"solve did not converge: {mg.status_string(info_h.status)} rel_res {info_h.rel_res:.3e}")
+    scratch = torch.zeros_like(rhs)
+    times = {which: s.profile_pass(rhs, scratch, 0, which, reps=20) for which in (0, 1)}
+    s.close()
+    dom = 1 if times[1] >= times[0] else 0
+    alg_bytes = BYTES_PER_NODE[(head, dom)] * nx * ny
+    achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
+    s = make(other)
+    steps_o = max(1, args.steps // 2)
+    wall_o, info_o, _ = run(s, steps_o, 1)
+    s.close()
+    kernel_name = {("mixed", 1): "k_post<float, ST9, FINE>", ("mixed", 0): "k_pre<float, ST9, FINE>",
+                   ("fp64", 1): "k_post<double, ST9, FINE>", ("fp64", 0): "k_pre<double, ST9, FINE>"}[(head, dom)]
+    out = {
+        "metric": "unknowns/s to 1e-10 rel. residual",
+        "value": unknowns * args.steps / wall_h,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall_h / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-inner/f64-outer" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "annulus4097: polar annulus r in [0.5,1], theta periodic, mapped to the unit square, "
+                               "Q1 with kx=4 pi r, ky=1/(4 pi r), 4097x4096 nodes, f = N(0,1), four-colour GS "
+                               f"{args.nu}/{args.nu}, F-cycle to 5x4, x0=0, tol 1e-10", "precision": head},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel_name,
+                     "avg_us": times[dom], "bytes_per_launch": alg_bytes, "bytes_per_node": BYTES_PER_NODE[(head, dom)],
+                     "nodes": nx * ny, "other_pass_us": times[1 - dom]},
+        "cycles": info_h.cycles,
+        "rel_res": info_h.rel_res,
+        "us_per_cycle": 1e6 * info_h.seconds / max(1, info_h.cycles),
+        f"value_{other}": unknowns * steps_o / wall_o,
+        f"cycles_{other}": info_o.cycles,
+        "speedup_mixed_over_fp64": ((wall_o / steps_o) / (wall_h / args.steps)) if head == "mixed"
+        else ((wall_h / args.steps) / (wall_o / steps_o)),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_annulus(info_h.cycles, args.nu, args.cpu_seconds, unknowns)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_annulus(cycles, nu, seconds, unknowns_full):
+    """Oracle F-cycles on the 1025 x 1024 annulus for about `seconds`; its cost
+    per unknown-cycle, scaled to the full grid and the cycles the full solve
+    needs (the cycle's work is linear in the number of unknowns)."""
+    import numpy as np
+
+    from oracle import mg_oracle as O
+    import workloads as W
+
+    n = 1025
+    g = O.Grid(n, n - 1, periodic_y=True)
+    kx, ky = W.annulus_cell_coefficients(n)
+    h = O.hierarchy_q1(g, kx, ky, O.Options(smoother="gs4c", nu_pre=nu, nu_post=nu), separable=True)
+    b = g.pack(W.annulus_rhs(n, n - 1, 3))
+    x = np.zeros(g.n_unknowns)
+    done = 0
+    t0 = time.perf_counter()
+    while done < 2 or time.perf_counter() - t0 < seconds:
+        x = O.mg_cycle(h, 0, x, b, "F")
+        done += 1
+    t = (time.perf_counter() - t0) / done
+    per_unknown_cycle = t / g.n_unknowns
+    return {"value": 1.0 / (per_unknown_cycle * cycles), "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} FP64 F-cycles on the 1025x1024 annulus ({t:.2f} s per cycle), scaled linearly to "
+                      f"4097x4096 and the {cycles} cycles of the full solve",
+            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: collectives and multi-GPU sharding are not "
                                    "built; run with --gpus 1"}), flush=True)
         sys.exit(2)
+    if args.workload == "annulus4097":
+        return annulus(args)
     import numpy as np
     import torch
 

@@ -296,6 +296,31 @@ def assemble_q1_separable(g: Grid, kx_of_x: np.ndarray, ky_of_x: np.ndarray) -> 
     return (sp.kron(My, Kx) + sp.kron(Ky, Mx)).tocsr()
 
 
+def q1_row(g: Grid, kx: np.ndarray, ky: np.ndarray, i: int, j: int) -> dict:
+    """Row of the Q1 matrix at unknown node (i, j): {(jq, iq): a_pq} over the
+    unknown nodes q that share a cell with it, from the element matrices of
+    its (up to 4) cells.  kx, ky: [ncy][ncx] cell arrays.  For checking single
+    rows of grids too large to assemble."""
+    Ex, Ey = q1_element_matrices(g.hx, g.hy)
+    out: dict = {}
+    for cj in (j - 1, j):
+        if g.periodic_y:
+            cj %= g.ncy
+        elif cj < 0 or cj >= g.ncy:
+            continue
+        for ci in (i - 1, i):
+            if ci < 0 or ci >= g.ncx:
+                continue
+            E = kx[cj, ci] * Ex + ky[cj, ci] * Ey
+            nodes = _cell_nodes(g, ci, cj)
+            p = nodes.index((j % g.ny if g.periodic_y else j, i))
+            for q, (jq, iq) in enumerate(nodes):
+                if iq < 1 or iq > g.nx - 2 or (not g.periodic_y and (jq < 1 or jq > g.ny - 2)):
+                    continue
+                out[(jq, iq)] = out.get((jq, iq), 0.0) + E[p, q]
+    return out
+
+
 def restriction(gf: Grid) -> sp.csr_matrix:
     """Full weighting R = (1/16)[1 2 1; 2 4 2; 1 2 1] from ``gf`` to ``gf.coarse()``
     on the unknowns (the restriction R_l^{l-1} of the multigrid algorithm)."""

@@ -128,6 +128,23 @@ def test_q1_brute_force_dense_assembly():
     np.testing.assert_allclose(A, A.T, atol=1e-12 * np.abs(A).max())
 
 
+def test_q1_row_equals_assembled_rows():
+    """Single-row assembly (used to sample very large grids) equals rows of the assembled matrix."""
+    for g in (O.Grid(9, 8, periodic_y=True), O.Grid(9, 9)):
+        rng = np.random.default_rng(12)
+        kx = rng.uniform(0.5, 2, (g.ncy, g.ncx))
+        ky = rng.uniform(0.5, 2, (g.ncy, g.ncx))
+        A = O.assemble_q1(g, kx, ky).toarray()
+        idx = O._unknown_index(g)
+        for j in g.uy:
+            for i in g.ux:
+                row = O.q1_row(g, kx, ky, i, j)
+                dense = np.zeros(g.n_unknowns)
+                for (jq, iq), v in row.items():
+                    dense[idx[jq, iq]] += v
+                np.testing.assert_allclose(dense, A[idx[j, i]], atol=1e-12 * np.abs(A).max())
+
+
 def test_q1_separable_equals_elementwise():
     g = O.Grid(9, 8, periodic_y=True)
     kx, ky = W.annulus_cell_coefficients(9)
