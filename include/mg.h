@@ -62,7 +62,7 @@ enum { MG_COEF_CONST5 = 0, MG_COEF_CELL9 = 1 };
 enum { MG_CYCLE_F = 0, MG_CYCLE_V = 1 };
 enum { MG_SMOOTH_JACOBI = 0, MG_SMOOTH_RBGS = 1, MG_SMOOTH_GS4C = 2 };
 enum { MG_PREC_FP64 = 0, MG_PREC_MIXED = 1 };
-enum { MG_TILES_FUSED = 0, MG_TILES_PER_OP = 1 };
+enum { MG_TILES_FUSED = 0, MG_TILES_PER_OP = 1, MG_TILES_NARROW = 2, MG_TILES_WIDE = 3 };
 
 /* Grid: stored node counts and domain lengths.  A Dirichlet direction has
  * n = 2^k m + 1 nodes (h = l / (n - 1)); the periodic direction has n = 2^k m
@@ -94,10 +94,15 @@ typedef struct {
  * coarse_cta_nodes: levels with at most this many stored nodes run inside one
  * persistent workgroup (0 = the largest levels whose sub-hierarchy fits in
  * LDS).  tile_mode: MG_TILES_FUSED (default) runs each large-level visit as two
- * LDS-tiled passes (smoothing fused with restriction / with prolongation);
- * MG_TILES_PER_OP launches one kernel per smoothing sweep, restriction and
- * prolongation (same results, bit for bit).  tile_x, tile_y: output tile of
- * the fused passes (even, 0 = chosen per level).  stream: hipStream_t. */
+ * LDS-tiled passes (smoothing fused with restriction / with prolongation),
+ * with 128-column "wide" tiles on levels large enough to fill the GPU with
+ * them and small tiles elsewhere; MG_TILES_NARROW uses small tiles only,
+ * MG_TILES_WIDE wide tiles on every fused level; MG_TILES_PER_OP launches
+ * one kernel per smoothing sweep, restriction and prolongation.  All modes
+ * give the same results, bit for bit.  tile_x, tile_y: output tile of the
+ * fused passes (even, 0 = chosen per level); a nonzero tile_x selects small
+ * tiles of that width, tile_y alone sets the height of wide tiles.
+ * stream: hipStream_t. */
 typedef struct {
   int32_t cycle;
   int32_t smoother;

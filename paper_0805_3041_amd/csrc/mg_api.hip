@@ -219,7 +219,7 @@ struct Gen {
       out.push_back({H_SUB, l, kind, (int)subs.size() - 1});
       return;
     }
-    const bool fused = h->opts.tile_mode == MG_TILES_FUSED;
+    const bool fused = h->opts.tile_mode != MG_TILES_PER_OP;
     std::vector<Abs> tmp;
     if (fused) {
       out.push_back({H_PRE, l, 0, -1});
@@ -255,7 +255,7 @@ TileGeom choose_tile(mg_handle h, const Group& G, int l, int H, bool post) {
   const int narr = h->ncol == 0 ? 3 : 2;
   auto bytes = [&](int TX, int TY) {
     const size_t W = TX + 2 * H, R = TY + 2 * H;
-    size_t n = W * R * narr;
+    size_t n = W * R * narr + NBANDS * W;  // + LDS copy of 1-D bands
     if (post) n += ((W >> 1) + 2) * ((R >> 1) + 2);
     return n * elem;
   };
@@ -264,6 +264,25 @@ TileGeom choose_tile(mg_handle h, const Group& G, int l, int H, bool post) {
   int TY = h->opts.tile_y > 0 ? h->opts.tile_y : 32;
   // tiles over all of the group's problems
   auto ntiles = [&](int tx, int ty) { return (long)G.ns * ((s.nx + tx - 1) / tx) * ((s.ny + ty - 1) / ty); };
+  // wide tiles (fixed region width, output width WW - 2H) wherever they
+  // still give the chip enough workgroups; at most WIDE_LDS_TARGET of LDS so
+  // that two workgroups share a CU
+  const int mode = h->opts.tile_mode;
+  if (mode != MG_TILES_NARROW && h->opts.tile_x == 0 && H <= 24) {
+    const int WW = wide_width(), TXw = WW - 2 * H;
+    auto wbytes = [&](int ty) {
+      const size_t R = ty + 2 * H;
+      size_t n = R * narr * WW + NBANDS * WW;
+      if (post) n += (size_t)(WW / 2 + 2) * ((R >> 1) + 2);
+      return n * elem;
+    };
+    const bool force = mode == MG_TILES_WIDE;
+    int TYw = h->opts.tile_y > 0 ? h->opts.tile_y : 32;
+    if (h->opts.tile_y == 0)
+      while (TYw > (force ? 2 : 16) && ((!force && ntiles(TXw, TYw) < 256) || wbytes(TYw) > WIDE_LDS_TARGET))
+        TYw -= 2;
+    if ((force || ntiles(TXw, TYw) >= 256) && wbytes(TYw) <= FUSED_LDS_MAX) return wide_geom(s.nx, s.ny, TYw, H);
+  }
   if (!fixed) {
     while (ntiles(TX, TY) < 256 && TY > 8) TY >>= 1;
     while (ntiles(TX, TY) < 256 && TX > 16) TX >>= 1;
@@ -345,10 +364,11 @@ hipError_t run_op(mg_handle h, const Group& G, const HostOp& op, Level<T>* dL, L
     case H_PROLONG: return launch_prolong<T>(Ls, Cs, s, ns, st);
     case H_COARSE: return launch_coarse<T>(Ls, G.dcholp, G.ncu, ns, st);
     case H_PRE:
-      return launch_pre<T>(Ls, Cs, G.gpre[l], h->opts.nu_pre, h->ncol, omega, stencil_kind(h), l == 0, ns, st);
+      return launch_pre<T>(Ls, Cs, G.gpre[l], h->opts.nu_pre, h->ncol, omega, stencil_kind(h), h->oned, l == 0, ns,
+                           st);
     case H_POST:
       return launch_post<T>(Ls, Cs, G.gpost[l], h->opts.nu_post, h->ncol, omega, op.arg, G.dL64, stencil_kind(h),
-                            l == 0, ns, st);
+                            h->oned, l == 0, ns, st);
     case H_SUB: {
       const size_t bytes = sub_footprint(h, G, l);
       const int* beg = G.dbeg + (size_t)op.sub * ns;
@@ -445,7 +465,7 @@ mg_status check_opts(const mg_options* o, int kind) {
   if (o->smoother == MG_SMOOTH_JACOBI && !finite_pos(o->omega)) return fail(nullptr, MG_EINVAL, "omega must be > 0");
   if (o->precision != MG_PREC_FP64 && o->precision != MG_PREC_MIXED) return fail(nullptr, MG_EINVAL, "bad precision");
   if (o->coarse_cta_nodes < 0) return fail(nullptr, MG_EINVAL, "coarse_cta_nodes must be >= 0");
-  if (o->tile_mode != MG_TILES_FUSED && o->tile_mode != MG_TILES_PER_OP) return fail(nullptr, MG_EINVAL, "bad tile_mode");
+  if (o->tile_mode < MG_TILES_FUSED || o->tile_mode > MG_TILES_WIDE) return fail(nullptr, MG_EINVAL, "bad tile_mode");
   if (o->tile_x < 0 || o->tile_y < 0 || (o->tile_x & 1) || (o->tile_y & 1) || o->tile_x > 512 || o->tile_y > 512)
     return fail(nullptr, MG_EINVAL, "tile_x and tile_y must be even, in [0, 512]");
   return MG_OK;
@@ -591,7 +611,7 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
       const int bp = round_up(sh.nx, 16);
       const int brows = h->oned ? 1 : sh.ny;
       const int bstride = bp * brows;
-      HIPCHK(h, h->dalloc(&G.band64[l], (size_t)5 * bstride * sizeof(double)));
+      HIPCHK(h, h->dalloc(&G.band64[l], (size_t)NBANDS * bstride * sizeof(double)));
       if (l == 0) {
         HIPCHK(h, launch_q1_bands(G.band64[0], bstride, h->oned ? 0 : bp, brows, sh.nx, sh.ny, sh.py, coeffs->kx,
                                   coeffs->ky, h->oned ? 0 : ncx, G.hx[0], G.hy[0], h->stream));
@@ -602,14 +622,15 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
         HIPCHK(h, launch_rap(G.band64[l], bstride, h->oned ? 0 : bp, brows, sh.nx, sh.ny, G.band64[l - 1], fbstride,
                              h->oned ? 0 : fbp, f.nx, f.ny, sh.py, h->stream));
       }
+      HIPCHK(h, launch_inv_diag(G.band64[l], bstride, h->stream));
       Level<double>& L = G.l64(l, 0);
       L.kind = ST9;
       L.band = G.band64[l];
       L.bpitch = h->oned ? 0 : bp;
       L.bstride = bstride;
       if (mixed) {
-        HIPCHK(h, h->dalloc(&G.band32[l], (size_t)5 * bstride * sizeof(float)));
-        HIPCHK(h, launch_to_float(G.band64[l], G.band32[l], (long)5 * bstride, h->stream));
+        HIPCHK(h, h->dalloc(&G.band32[l], (size_t)NBANDS * bstride * sizeof(float)));
+        HIPCHK(h, launch_to_float(G.band64[l], G.band32[l], (long)NBANDS * bstride, h->stream));
         Level<float>& M = G.l32(l, 0);
         M.kind = ST9;
         M.band = G.band32[l];
@@ -1073,15 +1094,15 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
     if (h->mixed()) {
       if (which == 0)
         return launch_pre<float>(G.dL32 + l, G.dL32 + l + 1, G.gpre[l], h->opts.nu_pre, h->ncol,
-                                 (float)h->opts.omega, kind, l == 0, 1, st);
+                                 (float)h->opts.omega, kind, h->oned, l == 0, 1, st);
       return launch_post<float>(G.dL32 + l, G.dL32 + l + 1, G.gpost[l], h->opts.nu_post, h->ncol,
-                                (float)h->opts.omega, found->arg, G.dL64, kind, l == 0, 1, st, false);
+                                (float)h->opts.omega, found->arg, G.dL64, kind, h->oned, l == 0, 1, st, false);
     }
     if (which == 0)
       return launch_pre<double>(G.dL64 + l, G.dL64 + l + 1, G.gpre[l], h->opts.nu_pre, h->ncol, h->opts.omega,
-                                kind, l == 0, 1, st);
+                                kind, h->oned, l == 0, 1, st);
     return launch_post<double>(G.dL64 + l, G.dL64 + l + 1, G.gpost[l], h->opts.nu_post, h->ncol, h->opts.omega,
-                               found->arg, G.dL64, kind, l == 0, 1, st, false);
+                               found->arg, G.dL64, kind, h->oned, l == 0, 1, st, false);
   };
   HIPCHK(h, launch());
   HIPCHK(h, hipEventRecord(h->ev0, st));

@@ -49,7 +49,7 @@ struct Level {
   int kind;               // ST5 or ST9
   T cx, cy, dg;           // ST5: A x = dg x_p - cx (x_w + x_e) - cy (x_s + x_n)
   T inv_dg;               // ST5: 1 / dg
-  const T* band;          // ST9: bands C, E, N, NE, NW, each `bstride` apart
+  const T* band;          // ST9: bands C, E, N, NE, NW, D = 1/C, each `bstride` apart
   int bpitch;             // ST9: band row pitch (0: one row for every j)
   int bstride;
   SolveState* st;         // owning problem's state
@@ -156,11 +156,16 @@ struct Nbr {
   T c, w, e, s, n, sw, se, nw, ne;
 };
 
-// a_pq of node p for its 9 couplings (symmetric band storage resolved).
+// a_pq of node p for its 9 couplings (symmetric band storage resolved) and
+// D = 1 / a_pp.
 template <typename T>
 struct Cf {
-  T C, Ep, Ew, Np, Ns, NEp, NEsw, NWp, NWse;
+  T C, Ep, Ew, Np, Ns, NEp, NEsw, NWp, NWse, D;
 };
+
+// Band index of the inverse diagonal.
+constexpr int BAND_D = 5;
+constexpr int NBANDS = 6;
 
 // Stencil kind known at compile time (ST5, ST9) or read from the level (KDYN).
 constexpr int KDYN = -1;
@@ -206,41 +211,48 @@ __device__ __forceinline__ Cf<T> coefs(const Level<T>& L, int i, int j, int jm) 
   c.NEsw = bandp(L, 3)[rs + i - 1];
   c.NWp = bandp(L, 4)[rp + i];
   c.NWse = bandp(L, 4)[rs + i + 1];
+  c.D = bandp(L, BAND_D)[rp + i];
   return c;
 }
 
-// Sum over the neighbours q != p of a_pq x_q.
+// Sum over the neighbours q != p of a_pq x_q, as one chain of fused
+// multiply-adds in a fixed order.
 template <int K = KDYN, typename T>
 __device__ __forceinline__ T offd(const Level<T>& L, const Cf<T>& a, const Nbr<T>& v) {
-  if (is5<K>(L)) return -(L.cx * (v.w + v.e) + L.cy * (v.s + v.n));
-  T s = a.Ep * v.e + a.Ew * v.w;
-  s += a.Np * v.n + a.Ns * v.s;
-  s += a.NEp * v.ne + a.NEsw * v.sw;
-  s += a.NWp * v.nw + a.NWse * v.se;
+  if (is5<K>(L)) return -fma(L.cx, v.w + v.e, L.cy * (v.s + v.n));
+  T s = a.Ep * v.e;
+  s = fma(a.Ew, v.w, s);
+  s = fma(a.Np, v.n, s);
+  s = fma(a.Ns, v.s, s);
+  s = fma(a.NEp, v.ne, s);
+  s = fma(a.NEsw, v.sw, s);
+  s = fma(a.NWp, v.nw, s);
+  s = fma(a.NWse, v.se, s);
   return s;
+}
+
+template <int K = KDYN, typename T>
+__device__ __forceinline__ T inv_diag(const Level<T>& L, const Cf<T>& a) {
+  return is5<K>(L) ? L.inv_dg : a.D;
 }
 
 // Gauss-Seidel value: (b_p - sum_{q != p} a_pq x_q) / a_pp.
 template <int K = KDYN, typename T>
 __device__ __forceinline__ T gs_v(const Level<T>& L, const Cf<T>& a, const Nbr<T>& v, T bp) {
-  const T rhs = bp - offd<K>(L, a, v);
-  if (is5<K>(L)) return rhs * L.inv_dg;
-  return rhs / a.C;
+  return (bp - offd<K>(L, a, v)) * inv_diag<K>(L, a);
 }
 
 // Defect b_p - (A x)_p.
 template <int K = KDYN, typename T>
 __device__ __forceinline__ T defect_v(const Level<T>& L, const Cf<T>& a, const Nbr<T>& v, T bp) {
   const T dg = is5<K>(L) ? L.dg : a.C;
-  return bp - (dg * v.c + offd<K>(L, a, v));
+  return bp - fma(dg, v.c, offd<K>(L, a, v));
 }
 
 // Damped Jacobi value: x_p + omega (b - A x)_p / a_pp.
 template <int K = KDYN, typename T>
 __device__ __forceinline__ T jac_v(const Level<T>& L, const Cf<T>& a, const Nbr<T>& v, T bp, T omega) {
-  const T d = defect_v<K>(L, a, v, bp);
-  if (is5<K>(L)) return v.c + omega * d * L.inv_dg;
-  return v.c + omega * d / a.C;
+  return fma(omega * defect_v<K>(L, a, v, bp), inv_diag<K>(L, a), v.c);
 }
 
 // Accessor forms (gather, then the value functions above).
@@ -325,12 +337,10 @@ __device__ __forceinline__ T restrict_defect(const Level<T>& F, const T* __restr
 // I = i >> 1, J = j >> 1; ox, oy = i & 1, j & 1.
 template <typename T>
 __device__ __forceinline__ T prolong_combine(T a00, T a10, T a01, T a11, int ox, int oy) {
-  if (!oy) {
-    if (!ox) return a00;
-    return (T)0.5 * (a00 + a10);
-  }
-  if (!ox) return (T)0.5 * (a00 + a01);
-  return (T)0.25 * ((a00 + a10) + (a01 + a11));
+  // selects rather than branches: neighbouring lanes differ in ox
+  const T s0 = ox ? (T)0.5 * (a00 + a10) : a00;
+  const T s1 = ox ? (T)0.5 * (a01 + a11) : a01;
+  return oy ? (T)0.5 * (s0 + s1) : s0;
 }
 
 // Bilinear interpolation of the coarse correction at fine node (i, j).

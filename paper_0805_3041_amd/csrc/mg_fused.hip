@@ -18,6 +18,13 @@
 // per node is the shared device function of mg_device.h.  Reading x and
 // writing the result to different buffers keeps workgroups from seeing a
 // neighbour's already-updated nodes in their halo.
+//
+// Cost model: the passes are bound by instruction issue, not by HBM, so the
+// per-node work is kept small: a tile whose region lies inside the grid's
+// unknowns (all but the tiles along a Dirichlet edge) runs a sweep body with
+// no boundary tests; node positions advance incrementally instead of being
+// divided out of a flat index; 9-point operators whose coefficients vary
+// along x only keep the tile's columns of their bands in LDS.
 #include "mg_fused.h"
 
 namespace mg {
@@ -28,10 +35,18 @@ struct TileMap {
   int i0, j0, H, nx, ny, py;
   __device__ __forceinline__ int gi(int li) const { return i0 - H + li; }
   __device__ __forceinline__ int gj(int lj) const { return j0 - H + lj; }  // not wrapped
-  __device__ __forceinline__ int wrapj(int j) const { return py ? ((j % ny) + ny) % ny : j; }
   __device__ __forceinline__ bool unknown(int i, int j) const {
-    if (i < 1 || i > nx - 2) return false;
-    return py ? true : (j >= 1 && j <= ny - 2);
+    const bool in_i = (unsigned)(i - 1) < (unsigned)(nx - 2);
+    return py ? in_i : (in_i && (unsigned)(j - 1) < (unsigned)(ny - 2));
+  }
+  // stored row of global row j (periodic y wraps; a region may overhang
+  // by more than one period on small coarse levels)
+  __device__ __forceinline__ int wrapj(int j) const {
+    if (py) {
+      while (j < 0) j += ny;
+      while (j >= ny) j -= ny;
+    }
+    return j;
   }
 };
 
@@ -48,49 +63,104 @@ __device__ __forceinline__ void tile_coords(int ntx, int nty, int& tx, int& ty) 
   tx = t - ty * ntx;
 }
 
-// One Gauss-Seidel colour sweep over the region shrunk by s.
-template <typename T, int K>
-__device__ void tile_colour(const Level<T>& L, const TileMap& m, MG_LDS T* x, const MG_LDS T* b, int W, int R, int s,
-                            int c, int ncol) {
-  constexpr int NB = nbatch(K);
-  const int lo = s, hiW = W - s, hiR = R - s;
-  int nk, nr, lj0, rstep, li0 = 0;
-  if (ncol == 2) {
-    nk = (hiW - lo + 1) >> 1;
-    nr = hiR - lo;
-    lj0 = lo;
-    rstep = 1;
+// Row-major walk over an index space with nk columns: a thread visits
+// idx, idx + FT, idx + 2 FT, ... and keeps (row r, column k) up to date
+// with adds instead of a division per step.
+struct Walk {
+  int r, k, dq, dk, nk;
+  __device__ __forceinline__ Walk(int idx, int nk_) : nk(nk_) {
+    const FDiv d(nk_);
+    r = d.q(idx);
+    k = idx - r * nk_;
+    dq = d.q(FT);
+    dk = FT - dq * nk_;
+  }
+  __device__ __forceinline__ void next() {
+    k += dk;
+    r += dq;
+    if (k >= nk) {
+      k -= nk;
+      ++r;
+    }
+  }
+};
+
+// Coefficients of the node at tile column li (global gi, wrapped row gjw).
+// B1: the bands vary along x only and the tile's W columns of each band sit
+// in LDS (band k at bl + k W), giving the same values as coefs().
+template <typename T, int K, bool B1>
+__device__ __forceinline__ Cf<T> tcoef(const Level<T>& L, const MG_LDS T* bl, int W, int li, int gi, int gjw) {
+  if constexpr (K == ST5) {
+    return Cf<T>{};
+  } else if constexpr (B1) {
+    const MG_LDS T* p = bl + li;
+    Cf<T> c;
+    c.C = p[0];
+    c.Ep = p[W];
+    c.Ew = p[W - 1];
+    c.Np = p[2 * W];
+    c.Ns = c.Np;
+    c.NEp = p[3 * W];
+    c.NEsw = p[3 * W - 1];
+    c.NWp = p[4 * W];
+    c.NWse = p[4 * W + 1];
+    c.D = p[BAND_D * W];
+    return c;
   } else {
-    lj0 = lo + (((m.gj(lo) & 1) != (c >> 1)) ? 1 : 0);
-    li0 = lo + (((m.gi(lo) & 1) != (c & 1)) ? 1 : 0);
-    nr = lj0 < hiR ? (hiR - lj0 + 1) >> 1 : 0;
+    return coefs<K>(L, gi, gjw, wrap_dn(gjw, L.ny, L.py));
+  }
+}
+
+// Row of a tile that does not need boundary tests (EDGE false): the global
+// row, wrapped once for periodic y (the region is at most one period tall).
+__device__ __forceinline__ int wrap_once(int j, int ny, int py) {
+  if (!py) return j;
+  return j < 0 ? j + ny : (j >= ny ? j - ny : j);
+}
+
+// One Gauss-Seidel colour sweep over the region shrunk by s.
+// NCOL 4: colour c holds i = c & 1, j = c >> 1 (mod 2); NCOL 2: colour c
+// holds (i + j) mod 2 == c.  Parities are those of global indices.
+template <typename T, int K, int NCOL, bool B1, bool EDGE>
+__device__ void sweep_colour(const Level<T>& L, const TileMap& m, MG_LDS T* x, const MG_LDS T* b,
+                             const MG_LDS T* bl, int W, int R, int s, int c) {
+  constexpr int NB = nbatch(K);
+  const int hiW = W - s, hiR = R - s;
+  int li0 = s, lj0 = s, rs = 1, nk, nr, par = 0;
+  if constexpr (NCOL == 4) {
+    li0 = s + ((m.gi(s) ^ c) & 1);
+    lj0 = s + ((m.gj(s) ^ (c >> 1)) & 1);
     nk = li0 < hiW ? (hiW - li0 + 1) >> 1 : 0;
-    rstep = 2;
+    nr = lj0 < hiR ? (hiR - lj0 + 1) >> 1 : 0;
+    rs = 2;
+  } else {
+    nk = (hiW - s + 1) >> 1;
+    nr = hiR - s;
+    par = (m.gi(s) + m.gj(s) + c) & 1;  // column offset of the colour in row r: (par + r) & 1
   }
   const int n = nr * nk;
   if (n <= 0) return;
-  const FDiv dk(nk);
+  Walk w(threadIdx.x, nk);
   for (int base = threadIdx.x; base < n; base += FT * NB) {
-    int pos[NB], gi[NB], gjw[NB];
+    int pos[NB], li[NB], gi[NB], gjw[NB];
     bool ok[NB];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int idx = base + u * FT;
-      ok[u] = false;
-      pos[u] = gi[u] = gjw[u] = 0;
-      if (idx < n) {
-        const int r = dk.q(idx);
-        const int k = idx - r * nk;
-        const int lj = lj0 + rstep * r;
+      const int lj = lj0 + rs * w.r;
+      int l = li0 + 2 * w.k;
+      if constexpr (NCOL == 2) l += (par + w.r) & 1;
+      ok[u] = base + u * FT < n && l < hiW;
+      w.next();
+      li[u] = l;
+      pos[u] = lj * W + l;
+      gi[u] = m.gi(l);
+      gjw[u] = 0;
+      if constexpr (EDGE) {
         const int gj = m.gj(lj);
-        const int li = ncol == 2 ? lo + 2 * k + ((((m.gi(lo) + gj) & 1) != c) ? 1 : 0) : li0 + 2 * k;
-        const int g = m.gi(li);
-        if (li < hiW && m.unknown(g, gj)) {
-          ok[u] = true;
-          pos[u] = lj * W + li;
-          gi[u] = g;
-          gjw[u] = m.wrapj(gj);
-        }
+        ok[u] = ok[u] && m.unknown(gi[u], gj);
+        if (ok[u] && K == ST9 && !B1) gjw[u] = m.wrapj(gj);
+      } else if constexpr (K == ST9 && !B1) {
+        gjw[u] = wrap_once(m.gj(lj), m.ny, m.py);
       }
     }
     Nbr<T> v[NB];
@@ -101,7 +171,7 @@ __device__ void tile_colour(const Level<T>& L, const TileMap& m, MG_LDS T* x, co
       if (!ok[u]) continue;
       v[u] = gather<K>(L, LXW<T>{x + pos[u], W}, false);
       bp[u] = b[pos[u]];
-      a[u] = coefs<K>(L, gi[u], gjw[u], wrap_dn(gjw[u], L.ny, L.py));
+      a[u] = tcoef<T, K, B1>(L, bl, W, li[u], gi[u], gjw[u]);
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u)
@@ -109,32 +179,36 @@ __device__ void tile_colour(const Level<T>& L, const TileMap& m, MG_LDS T* x, co
   }
 }
 
-// Region nodes (shrunk by s) that are unknowns, NB per thread per round:
-// f(pos, gi, gj_wrapped) is called for the loads, g(...) for the stores.
-template <typename T, int K>
-__device__ void tile_jacobi(const Level<T>& L, const TileMap& m, const MG_LDS T* src, MG_LDS T* dst,
-                            const MG_LDS T* b, int W, int R, int s, T omega) {
+// Every node of the region shrunk by s, NB nodes per thread per round
+// (their loads issued before any store).  JACOBI: damped Jacobi step
+// src -> dst.  Otherwise the defect b - A src, written in place into b (a
+// node's defect reads only its own b), 0 at nodes that are not unknowns.
+template <typename T, int K, bool B1, bool EDGE, bool JACOBI>
+__device__ void sweep_region(const Level<T>& L, const TileMap& m, const MG_LDS T* src, MG_LDS T* dst,
+                             MG_LDS T* b, const MG_LDS T* bl, int W, int R, int s, T omega) {
   constexpr int NB = nbatch(K);
   const int cols = W - 2 * s, n = (R - 2 * s) * cols;
-  const FDiv dc(cols);
+  if (n <= 0) return;
+  Walk w(threadIdx.x, cols);
   for (int base = threadIdx.x; base < n; base += FT * NB) {
-    int pos[NB], gi[NB], gjw[NB];
-    bool ok[NB];
+    int pos[NB], li[NB], gi[NB], gjw[NB];
+    bool ok[NB], in[NB];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int idx = base + u * FT;
-      ok[u] = false;
-      pos[u] = gi[u] = gjw[u] = 0;
-      if (idx < n) {
-        const int r = dc.q(idx);
-        const int lj = s + r, li = s + idx - r * cols;
-        const int gj = m.gj(lj), g = m.gi(li);
-        if (m.unknown(g, gj)) {
-          ok[u] = true;
-          pos[u] = lj * W + li;
-          gi[u] = g;
-          gjw[u] = m.wrapj(gj);
-        }
+      const int lj = s + w.r, l = s + w.k;
+      in[u] = base + u * FT < n;
+      ok[u] = in[u];
+      w.next();
+      li[u] = l;
+      pos[u] = lj * W + l;
+      gi[u] = m.gi(l);
+      gjw[u] = 0;
+      if constexpr (EDGE) {
+        const int gj = m.gj(lj);
+        ok[u] = ok[u] && m.unknown(gi[u], gj);
+        if (ok[u] && K == ST9 && !B1) gjw[u] = m.wrapj(gj);
+      } else if constexpr (K == ST9 && !B1) {
+        gjw[u] = wrap_once(m.gj(lj), m.ny, m.py);
       }
     }
     Nbr<T> v[NB];
@@ -145,84 +219,72 @@ __device__ void tile_jacobi(const Level<T>& L, const TileMap& m, const MG_LDS T*
       if (!ok[u]) continue;
       v[u] = gather<K>(L, LXW<T>{src + pos[u], W}, true);
       bp[u] = b[pos[u]];
-      a[u] = coefs<K>(L, gi[u], gjw[u], wrap_dn(gjw[u], L.ny, L.py));
+      a[u] = tcoef<T, K, B1>(L, bl, W, li[u], gi[u], gjw[u]);
     }
 #pragma unroll
-    for (int u = 0; u < NB; ++u)
-      if (ok[u]) dst[pos[u]] = jac_v<K>(L, a[u], v[u], bp[u], omega);
-  }
-}
-
-// Defect b - A x on the region shrunk by s, written in place into b (a
-// node's defect reads only its own b); 0 at non-unknowns.
-template <typename T, int K>
-__device__ void tile_defect(const Level<T>& L, const TileMap& m, const MG_LDS T* x, MG_LDS T* b, int W, int R,
-                            int s) {
-  constexpr int NB = nbatch(K);
-  const int cols = W - 2 * s, n = (R - 2 * s) * cols;
-  const FDiv dc(cols);
-  for (int base = threadIdx.x; base < n; base += FT * NB) {
-    int pos[NB], gi[NB], gjw[NB];
-    bool ok[NB], in[NB];
-#pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int idx = base + u * FT;
-      ok[u] = in[u] = false;
-      pos[u] = gi[u] = gjw[u] = 0;
-      if (idx < n) {
-        in[u] = true;
-        const int r = dc.q(idx);
-        const int lj = s + r, li = s + idx - r * cols;
-        const int gj = m.gj(lj), g = m.gi(li);
-        pos[u] = lj * W + li;
-        if (m.unknown(g, gj)) {
-          ok[u] = true;
-          gi[u] = g;
-          gjw[u] = m.wrapj(gj);
-        }
+      if constexpr (JACOBI) {
+        if (ok[u]) dst[pos[u]] = jac_v<K>(L, a[u], v[u], bp[u], omega);
+      } else {
+        if (in[u]) b[pos[u]] = ok[u] ? defect_v<K>(L, a[u], v[u], bp[u]) : (T)0;
       }
     }
-    Nbr<T> v[NB];
-    Cf<T> a[NB];
-    T bp[NB];
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      if (!ok[u]) continue;
-      v[u] = gather<K>(L, LXW<T>{x + pos[u], W}, true);
-      bp[u] = b[pos[u]];
-      a[u] = coefs<K>(L, gi[u], gjw[u], wrap_dn(gjw[u], L.ny, L.py));
-    }
-#pragma unroll
-    for (int u = 0; u < NB; ++u)
-      if (in[u]) b[pos[u]] = ok[u] ? defect_v<K>(L, a[u], v[u], bp[u]) : (T)0;
   }
 }
 
 // nsteps smoothing steps on the region; returns the LDS array holding the
 // result (x, or t after an odd number of Jacobi steps).
-template <typename T, int K>
-__device__ MG_LDS T* tile_smooth(const Level<T>& L, const TileMap& m, MG_LDS T* x, MG_LDS T* t, const MG_LDS T* b,
-                                 int W, int R, int nsteps, int ncol, T omega) {
+template <typename T, int K, int NCOL, bool B1, bool EDGE>
+__device__ MG_LDS T* tile_smooth(const Level<T>& L, const TileMap& m, MG_LDS T* x, MG_LDS T* t, MG_LDS T* b,
+                                 const MG_LDS T* bl, int W, int R, int nsteps, T omega) {
   int s = 1;
-  if (ncol == 0) {
+  if constexpr (NCOL == 0) {
     MG_LDS T* src = x;
     MG_LDS T* dst = t;
     for (int k = 0; k < nsteps; ++k, ++s) {
-      tile_jacobi<T, K>(L, m, src, dst, b, W, R, s, omega);
+      sweep_region<T, K, B1, EDGE, true>(L, m, src, dst, b, bl, W, R, s, omega);
       __syncthreads();
       MG_LDS T* tmp = src;
       src = dst;
       dst = tmp;
     }
     return src;
-  }
-  for (int k = 0; k < nsteps; ++k) {
-    for (int c = 0; c < ncol; ++c, ++s) {
-      tile_colour<T, K>(L, m, x, b, W, R, s, c, ncol);
-      __syncthreads();
+  } else {
+    for (int k = 0; k < nsteps; ++k) {
+      for (int c = 0; c < NCOL; ++c, ++s) {
+        sweep_colour<T, K, NCOL, B1, EDGE>(L, m, x, b, bl, W, R, s, c);
+        __syncthreads();
+      }
     }
+    return x;
   }
-  return x;
+}
+
+// False when every node of the region shrunk by 1 is an unknown and (for
+// 9-point operators read from 2-D global bands on a periodic level) the
+// region is at most one period tall, so a sweep body needs no boundary
+// tests.  Uniform over the workgroup.
+template <typename T, int K, bool B1>
+__device__ __forceinline__ bool tile_edge(const Level<T>& F, const TileMap& m, int W, int R) {
+  const bool in_i = m.gi(1) >= 1 && m.gi(W - 2) <= F.nx - 2;
+  bool in_j;
+  if (F.py)
+    in_j = (K == ST9 && !B1) ? R <= F.ny : true;
+  else
+    in_j = m.gj(1) >= 1 && m.gj(R - 2) <= F.ny - 2;
+  return !(in_i && in_j);
+}
+
+// The tile's W columns of the NBANDS bands of a level whose bands vary
+// along x only.  Columns outside the grid are clamped (no unknown reads
+// them: an unknown's columns i-1 .. i+1 lie inside).
+template <typename T>
+__device__ void load_bands(const Level<T>& F, const TileMap& m, MG_LDS T* dst, int W) {
+  for (int idx = threadIdx.x; idx < NBANDS * W; idx += FT) {
+    const int k = idx / W, li = idx - k * W;
+    const int g = min(max(m.gi(li), 0), F.nx - 1);
+    dst[idx] = bandp(F, k)[g];
+  }
 }
 
 __device__ __forceinline__ double wg_sum(double v, double* sh) {
@@ -237,13 +299,25 @@ __device__ __forceinline__ double wg_sum(double v, double* sh) {
   return s;
 }
 
+constexpr int LB = 4;  // region nodes a thread loads from global memory per round
+
 // ------------------------------------------------------------------ pre-pass
+
+template <typename T, int K, int NCOL, bool B1, bool EDGE>
+__device__ __forceinline__ MG_LDS T* pre_body(const Level<T>& F, const TileMap& m, MG_LDS T* x, MG_LDS T* t,
+                                              MG_LDS T* b, const MG_LDS T* bl, int W, int R, int H, int nsteps,
+                                              T omega) {
+  MG_LDS T* xs = tile_smooth<T, K, NCOL, B1, EDGE>(F, m, x, t, b, bl, W, R, nsteps, omega);
+  // defect on the region shrunk by H - 1 (in place into b)
+  sweep_region<T, K, B1, EDGE, false>(F, m, xs, nullptr, b, bl, W, R, H - 1, omega);
+  return xs;
+}
 
 // FINE: instantiation used on the finest level only (a separate symbol, so
 // profiles and timings of the finest pass are not mixed with coarser ones).
-template <typename T, int K, bool FINE>
+template <typename T, int K, bool FINE, int NCOL, bool B1>
 __global__ void __launch_bounds__(FT) k_pre(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs, int TX,
-                                            int TY, int H, int ntx, int nty, int nsteps, int ncol, T omega) {
+                                            int TY, int H, int ntx, int nty, int nsteps, T omega) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Level<T> F = Fs[blockIdx.z];
   if (F.st->done) return;
@@ -254,36 +328,54 @@ __global__ void __launch_bounds__(FT) k_pre(const Level<T>* __restrict__ Fs, con
   MG_LDS T* x = lds_cast<T>(smem_raw);
   MG_LDS T* b = x + W * R;
   MG_LDS T* t = b + W * R;  // Jacobi only
+  MG_LDS T* bl = b + W * R * (NCOL == 0 ? 2 : 1);
   const TileMap m{tx * TX, ty * TY, H, F.nx, F.ny, F.py};
+  if constexpr (B1) load_bands(F, m, bl, W);
 
-  const FDiv dW(W);
-  for (int idx = threadIdx.x; idx < W * R; idx += FT) {
-    const int lj = dW.q(idx), li = idx - lj * W;
-    const int gi = m.gi(li), gj = m.gj(lj);
-    T xv = (T)0, bv = (T)0;
-    if (m.unknown(gi, gj)) {
-      const size_t p = (size_t)m.wrapj(gj) * F.pitch + gi;
-      xv = F.x[p];
-      bv = F.b[p];
+  {
+    Walk w(threadIdx.x, W);
+    const int n = W * R;
+    for (int base = threadIdx.x; base < n; base += FT * LB) {
+      T xv[LB], bv[LB];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) {
+        const int gi = m.gi(w.k), gj = m.gj(w.r);
+        w.next();
+        xv[u] = bv[u] = (T)0;
+        if (base + u * FT < n && m.unknown(gi, gj)) {
+          const size_t p = (size_t)m.wrapj(gj) * F.pitch + gi;
+          xv[u] = F.x[p];
+          bv[u] = F.b[p];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < LB; ++u) {
+        const int idx = base + u * FT;
+        if (idx < n) {
+          x[idx] = xv[u];
+          b[idx] = bv[u];
+          if constexpr (NCOL == 0) t[idx] = (T)0;
+        }
+      }
     }
-    x[idx] = xv;
-    b[idx] = bv;
-    if (ncol == 0) t[idx] = (T)0;
   }
   __syncthreads();
 
-  MG_LDS T* xs = tile_smooth<T, K>(F, m, x, t, b, W, R, nsteps, ncol, omega);
-
-  // defect on the region shrunk by H - 1 (in place into b)
-  tile_defect<T, K>(F, m, xs, b, W, R, H - 1);
+  MG_LDS T* xs;
+  if (tile_edge<T, K, B1>(F, m, W, R))
+    xs = pre_body<T, K, NCOL, B1, true>(F, m, x, t, b, bl, W, R, H, nsteps, omega);
+  else
+    xs = pre_body<T, K, NCOL, B1, false>(F, m, x, t, b, bl, W, R, H, nsteps, omega);
   __syncthreads();
 
   // full weighting at the coarse nodes of the tile; zero coarse start
   {
     const int ca = TX >> 1, n = ca * (TY >> 1);
     const int lo = C.py ? 0 : 1, hi = C.py ? C.ny - 1 : C.ny - 2;
+    Walk w(threadIdx.x, ca);
     for (int idx = threadIdx.x; idx < n; idx += FT) {
-      const int rb = idx / ca, a = idx - rb * ca;
+      const int a = w.k, rb = w.r;
+      w.next();
       const int I = (m.i0 >> 1) + a, J = (m.j0 >> 1) + rb;
       if (I < 1 || I > C.nx - 2 || J < lo || J > hi) continue;
       const int li = H + 2 * a, lj = H + 2 * rb;
@@ -299,9 +391,10 @@ __global__ void __launch_bounds__(FT) k_pre(const Level<T>* __restrict__ Fs, con
   // smoothed iterate of the output nodes -> ping-pong buffer
   {
     const int n = TX * TY;
+    Walk w(threadIdx.x, TX);
     for (int idx = threadIdx.x; idx < n; idx += FT) {
-      const int r = idx / TX;
-      const int lj = H + r, li = H + idx - r * TX;
+      const int lj = H + w.r, li = H + w.k;
+      w.next();
       const int gj = m.gj(lj), gi = m.gi(li);
       if (!m.unknown(gi, gj) || gj >= F.ny) continue;
       F.t[(size_t)gj * F.pitch + gi] = xs[lj * W + li];
@@ -313,9 +406,9 @@ __global__ void __launch_bounds__(FT) k_pre(const Level<T>* __restrict__ Fs, con
 
 // mode: POST_PLAIN, POST_NORM (finest level: stopping test of the new
 // iterate), POST_MIXED (finest FP32 level: x64 += e, e = 0).
-template <typename T, int K, bool FINE>
+template <typename T, int K, bool FINE, int NCOL, bool B1>
 __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs, int TX,
-                                             int TY, int H, int ntx, int nty, int nsteps, int ncol, T omega, int mode,
+                                             int TY, int H, int ntx, int nty, int nsteps, T omega, int mode,
                                              const Level<double>* __restrict__ X64s) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double sh[FT / 64];
@@ -334,46 +427,84 @@ __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, co
   // coarse correction covering the region
   const int cI0 = m.gi(0) >> 1, cJ0 = m.gj(0) >> 1;
   const int CW = (W >> 1) + 2, CR = (R >> 1) + 2;
-  MG_LDS T* ec = t + (ncol == 0 ? W * R : 0);
+  MG_LDS T* ec = t + (NCOL == 0 ? W * R : 0);
+  MG_LDS T* bl = ec + CW * CR;
+  if constexpr (B1) load_bands(F, m, bl, W);
   {
     const int clo = C.py ? 0 : 1, chi = C.py ? C.ny - 1 : C.ny - 2;
-    for (int idx = threadIdx.x; idx < CW * CR; idx += FT) {
-      const int r = idx / CW, c = idx - r * CW;
-      const int I = cI0 + c;
-      int J = cJ0 + r;
-      T v = (T)0;
-      if (C.py) J = ((J % C.ny) + C.ny) % C.ny;
-      if (I >= 1 && I <= C.nx - 2 && J >= clo && J <= chi) v = C.x[(size_t)J * C.pitch + I];
-      ec[idx] = v;
+    const int n = CW * CR;
+    Walk w(threadIdx.x, CW);
+    for (int base = threadIdx.x; base < n; base += FT * LB) {
+      T v[LB];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) {
+        const int I = cI0 + w.k;
+        int J = cJ0 + w.r;
+        w.next();
+        v[u] = (T)0;
+        if (C.py) {
+          while (J < 0) J += C.ny;
+          while (J >= C.ny) J -= C.ny;
+        }
+        if (base + u * FT < n && I >= 1 && I <= C.nx - 2 && J >= clo && J <= chi) v[u] = C.x[(size_t)J * C.pitch + I];
+      }
+#pragma unroll
+      for (int u = 0; u < LB; ++u)
+        if (base + u * FT < n) ec[base + u * FT] = v[u];
     }
   }
   __syncthreads();
-  const FDiv dW(W);
-  for (int idx = threadIdx.x; idx < W * R; idx += FT) {
-    const int lj = dW.q(idx), li = idx - lj * W;
-    const int gi = m.gi(li), gj = m.gj(lj);
-    T xv = (T)0, bv = (T)0;
-    if (m.unknown(gi, gj)) {
-      const size_t p = (size_t)m.wrapj(gj) * F.pitch + gi;
-      const int I = gi >> 1, J = gj >> 1;
-      const MG_LDS T* r0 = ec + (J - cJ0) * CW + (I - cI0);
-      const MG_LDS T* r1 = r0 + CW;
-      xv = F.t[p] + prolong_combine(r0[0], r0[1], r1[0], r1[1], gi & 1, gj & 1);
-      bv = F.b[p];
+  {
+    Walk w(threadIdx.x, W);
+    const int n = W * R;
+    for (int base = threadIdx.x; base < n; base += FT * LB) {
+      T tv[LB], bv[LB];
+      int gi[LB], gj[LB];
+      bool ok[LB];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) {
+        gi[u] = m.gi(w.k);
+        gj[u] = m.gj(w.r);
+        w.next();
+        tv[u] = bv[u] = (T)0;
+        ok[u] = base + u * FT < n && m.unknown(gi[u], gj[u]);
+        if (ok[u]) {
+          const size_t p = (size_t)m.wrapj(gj[u]) * F.pitch + gi[u];
+          tv[u] = F.t[p];
+          bv[u] = F.b[p];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < LB; ++u) {
+        const int idx = base + u * FT;
+        if (idx >= n) continue;
+        T xv = (T)0;
+        if (ok[u]) {
+          const int I = gi[u] >> 1, J = gj[u] >> 1;
+          const MG_LDS T* r0 = ec + (J - cJ0) * CW + (I - cI0);
+          const MG_LDS T* r1 = r0 + CW;
+          xv = tv[u] + prolong_combine(r0[0], r0[1], r1[0], r1[1], gi[u] & 1, gj[u] & 1);
+        }
+        x[idx] = xv;
+        b[idx] = bv[u];
+        if constexpr (NCOL == 0) t[idx] = (T)0;
+      }
     }
-    x[idx] = xv;
-    b[idx] = bv;
-    if (ncol == 0) t[idx] = (T)0;
   }
   __syncthreads();
 
-  MG_LDS T* xs = tile_smooth<T, K>(F, m, x, t, b, W, R, nsteps, ncol, omega);
+  MG_LDS T* xs;
+  if (tile_edge<T, K, B1>(F, m, W, R))
+    xs = tile_smooth<T, K, NCOL, B1, true>(F, m, x, t, b, bl, W, R, nsteps, omega);
+  else
+    xs = tile_smooth<T, K, NCOL, B1, false>(F, m, x, t, b, bl, W, R, nsteps, omega);
 
   double acc = 0.0;
   const int n = TX * TY;
+  Walk w(threadIdx.x, TX);
   for (int idx = threadIdx.x; idx < n; idx += FT) {
-    const int r = idx / TX;
-    const int lj = H + r, li = H + idx - r * TX;
+    const int lj = H + w.r, li = H + w.k;
+    w.next();
     const int gj = m.gj(lj), gi = m.gi(li);
     if (!m.unknown(gi, gj) || gj >= F.ny) continue;
     const size_t p = (size_t)gj * F.pitch + gi;
@@ -385,12 +516,541 @@ __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, co
     } else {
       F.x[p] = xs[q];
       if (mode == POST_NORM) {
-        const T d = defect_val<K>(F, LXW<T>{xs + q, W}, b[q], gi, gj, wrap_dn(gj, F.ny, F.py));
+        const T d = defect_v<K>(F, tcoef<T, K, B1>(F, bl, W, li, gi, gj), gather<K>(F, LXW<T>{xs + q, W}, true), b[q]);
         acc += (double)d * (double)d;
       }
     }
   }
   if (mode == POST_NORM) {
+    const double part = wg_sum(acc, sh);
+    if (threadIdx.x == 0) st->partial[blockIdx.x] = part;
+  }
+}
+
+// ------------------------------------------------------------------ wide tiles
+//
+// Variant for large levels.  The region is WW = 128 columns wide (output
+// width TX = WW - 2H) and each LDS row holds the arrays side by side, every
+// array split by column parity:
+//   [x even | x odd | b even | b odd (| t even | t odd)],  WH = 64 per half.
+// A colour sweep updates one column parity, so lane l owns the column of
+// half-index A = A0 + l (unit stride in LDS, no bank conflicts) for the
+// whole sweep and each wave takes whole rows (row indices are uniform).
+// All stencil reads of a node then sit at compile-time offsets from one
+// address, and per-column quantities (bands that vary along x only, the
+// column's boundary test) are computed once per sweep instead of per node.
+
+constexpr int WW = 128;
+constexpr int WH = WW / 2;
+constexpr int NWAVE = FT / 64;
+constexpr int UL = 4;  // rows whose global loads a wave issues before its first wait
+
+template <int NCOL>
+constexpr int wide_narr() {
+  return NCOL == 0 ? 3 : 2;
+}
+
+struct WMap {
+  int i0, j0, H, nx, ny, py;
+  __device__ __forceinline__ int gi(int li) const { return i0 - H + li; }
+  __device__ __forceinline__ int gj(int lj) const { return j0 - H + lj; }
+  __device__ __forceinline__ bool col_ok(int li) const { return (unsigned)(gi(li) - 1) < (unsigned)(nx - 2); }
+  __device__ __forceinline__ bool row_ok(int lj) const {
+    return py ? true : (unsigned)(gj(lj) - 1) < (unsigned)(ny - 2);
+  }
+  __device__ __forceinline__ int wrapj(int j) const {
+    if (py) {
+      while (j < 0) j += ny;
+      while (j >= ny) j -= ny;
+    }
+    return j;
+  }
+};
+
+// Offset of column li inside an array's row (parity split).
+__device__ __forceinline__ int wcol(int li) { return (li & 1) * WH + (li >> 1); }
+
+// x around a node of column parity Q: p points at row lj - 1, half-index A
+// of the array (p = array + (lj - 1) P + A).  The node's own column is at
+// `own`, its west and east neighbours in the other half at ow, ow + 1.
+template <typename T, int K, int P, int Q, bool CENTRE>
+__device__ __forceinline__ Nbr<T> wgather(const MG_LDS T* p) {
+  constexpr int own = Q ? WH : 0, ow = Q ? 0 : WH - 1;
+  Nbr<T> v{};
+  v.s = p[own];
+  v.w = p[P + ow];
+  v.e = p[P + ow + 1];
+  if (CENTRE) v.c = p[P + own];
+  v.n = p[2 * P + own];
+  if (K != ST5) {
+    v.sw = p[ow];
+    v.se = p[ow + 1];
+    v.nw = p[2 * P + ow];
+    v.ne = p[2 * P + ow + 1];
+  }
+  return v;
+}
+
+// Coefficients of column half-index A (parity Q) from the LDS copy of
+// bands that vary along x only (band k at bl + k WW, parity split).
+template <typename T, int Q>
+__device__ __forceinline__ Cf<T> wcoef_cols(const MG_LDS T* bl, int A) {
+  constexpr int own = Q ? WH : 0, oth = Q ? 0 : WH;
+  const MG_LDS T* p = bl + A;
+  Cf<T> c;
+  c.C = p[own];
+  c.Ep = p[WW + own];
+  c.Ew = p[WW + oth - 1 + Q];
+  c.Np = p[2 * WW + own];
+  c.Ns = c.Np;
+  c.NEp = p[3 * WW + own];
+  c.NEsw = p[3 * WW + oth - 1 + Q];
+  c.NWp = p[4 * WW + own];
+  c.NWse = p[4 * WW + oth + Q];
+  c.D = p[BAND_D * WW + own];
+  return c;
+}
+
+// Coefficients of node (gi, row lj) for a sweep: hoisted column values
+// (B1), the level's global bands (2-D), or none (5-point).
+template <typename T, int K, bool B1>
+__device__ __forceinline__ Cf<T> wcoef(const Level<T>& L, const WMap& m, const Cf<T>& col, int gi, int lj) {
+  if constexpr (K == ST5 || B1) {
+    return col;
+  } else {
+    const int gjw = m.wrapj(m.gj(lj));
+    return coefs<K>(L, gi, gjw, wrap_dn(gjw, L.ny, L.py));
+  }
+}
+
+// Wave index as a scalar: row loops then run on the scalar unit.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Gauss-Seidel update of the column-parity-Q nodes of a colour on the rows
+// lj0 + rstep (wave + NWAVE k) < hiR, two rows per round.  Loads are issued
+// for every lane (addresses stay inside the region's rows); only lanes whose
+// column is an unknown of the colour store.
+template <typename T, int K, int NCOL, bool B1, int Q>
+__device__ void wcolour_rows(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG_LDS T* bl, int hiR, int lj0,
+                             int rstep, int A, bool lane_ok, int gi) {
+  constexpr int P = wide_narr<NCOL>() * WW;
+  constexpr int own = Q ? WH : 0;
+  Cf<T> col{};
+  if constexpr (K == ST9 && B1) {
+    if (lane_ok) col = wcoef_cols<T, Q>(bl, A);
+  }
+  const int step = rstep * NWAVE;
+  auto node = [&](int lj) -> T {
+    const Nbr<T> v = wgather<T, K, P, Q, false>(lds + (lj - 1) * P + A);
+    return gs_v<K>(L, wcoef<T, K, B1>(L, m, col, gi, lj), v, lds[lj * P + WW + own + A]);
+  };
+  int lj = lj0 + rstep * wave_id();
+  for (; lj + step < hiR; lj += 2 * step) {
+    const int lj2 = lj + step;
+    const bool r1 = m.row_ok(lj), r2 = m.row_ok(lj2);
+    if (r1 && r2) {
+      const T x1 = node(lj), x2 = node(lj2);
+      if (lane_ok) {
+        lds[lj * P + own + A] = x1;
+        lds[lj2 * P + own + A] = x2;
+      }
+    } else if (r1 || r2) {
+      const int l = r1 ? lj : lj2;
+      const T x1 = node(l);
+      if (lane_ok) lds[l * P + own + A] = x1;
+    }
+  }
+  if (lj < hiR && m.row_ok(lj)) {
+    const T x1 = node(lj);
+    if (lane_ok) lds[lj * P + own + A] = x1;
+  }
+}
+
+// One Gauss-Seidel colour sweep over the region shrunk by s (colours as in
+// sweep_colour; i0, j0 are even, so local and global parities agree up to H).
+template <typename T, int K, int NCOL, bool B1>
+__device__ void wsweep_colour(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG_LDS T* bl, int R, int s,
+                              int c) {
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  int q, lj0, rstep;
+  if constexpr (NCOL == 4) {
+    const int qr = ((c >> 1) + m.H) & 1;
+    lj0 = s + ((s ^ qr) & 1);
+    rstep = 2;
+    q = ((c & 1) + m.H) & 1;
+  } else {
+    // the wave's rows s + wave + NWAVE k share the parity of s + wave
+    lj0 = s;
+    rstep = 1;
+    q = (c + s + wave) & 1;
+  }
+  const int li = s + ((s ^ q) & 1) + 2 * lane;
+  const bool lane_ok = li < WW - s && m.col_ok(li);
+  // a lane outside the unknowns still loads (its results are not stored):
+  // give it an interior column for global band reads
+  const int gi = lane_ok ? m.gi(li) : 1;
+  if (q)
+    wcolour_rows<T, K, NCOL, B1, 1>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi);
+  else
+    wcolour_rows<T, K, NCOL, B1, 0>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi);
+}
+
+// Every node of the region shrunk by s, both column parities per lane and
+// row.  DST == 1: defect b - A src in place into b (0 at region nodes that
+// are not unknowns).  Otherwise damped Jacobi src -> dst.  Array indices:
+// 0 x, 1 b, 2 t.
+template <typename T, int K, int NCOL, bool B1, int SRC, int DST>
+__device__ void wsweep_region(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG_LDS T* bl, int R, int s,
+                              T omega) {
+  constexpr int P = wide_narr<NCOL>() * WW;
+  const int lane = threadIdx.x & 63;
+  const int li0 = 2 * (((s + 1) >> 1) + lane), li1 = 2 * ((s >> 1) + lane) + 1;
+  const int A0 = li0 >> 1, A1 = li1 >> 1;
+  const bool in0 = li0 < WW - s, in1 = li1 < WW - s;
+  const bool ok0 = in0 && m.col_ok(li0), ok1 = in1 && m.col_ok(li1);
+  const int g0 = ok0 ? m.gi(li0) : 1, g1 = ok1 ? m.gi(li1) : 1;  // interior column for lanes that only load
+  Cf<T> c0{}, c1{};
+  if constexpr (K == ST9 && B1) {
+    if (ok0) c0 = wcoef_cols<T, 0>(bl, A0);
+    if (ok1) c1 = wcoef_cols<T, 1>(bl, A1);
+  }
+  for (int lj = s + wave_id(); lj < R - s; lj += NWAVE) {
+    MG_LDS T* row = lds + lj * P;
+    if (!m.row_ok(lj)) {
+      if constexpr (DST == 1) {
+        if (in0) row[WW + A0] = (T)0;
+        if (in1) row[WW + WH + A1] = (T)0;
+      }
+      continue;
+    }
+    const MG_LDS T* src = lds + SRC * WW + (lj - 1) * P;
+    const Nbr<T> v0 = wgather<T, K, P, 0, true>(src + A0);
+    const Nbr<T> v1 = wgather<T, K, P, 1, true>(src + A1);
+    const T b0 = row[WW + A0], b1 = row[WW + WH + A1];
+    const Cf<T> a0 = wcoef<T, K, B1>(L, m, c0, g0, lj), a1 = wcoef<T, K, B1>(L, m, c1, g1, lj);
+    if constexpr (DST == 1) {
+      const T d0 = defect_v<K>(L, a0, v0, b0), d1 = defect_v<K>(L, a1, v1, b1);
+      if (in0) row[WW + A0] = ok0 ? d0 : (T)0;
+      if (in1) row[WW + WH + A1] = ok1 ? d1 : (T)0;
+    } else {
+      const T y0 = jac_v<K>(L, a0, v0, b0, omega), y1 = jac_v<K>(L, a1, v1, b1, omega);
+      if (ok0) row[DST * WW + A0] = y0;
+      if (ok1) row[DST * WW + WH + A1] = y1;
+    }
+  }
+}
+
+// nsteps smoothing steps; returns the array index (0 x, 2 t) of the result.
+template <typename T, int K, int NCOL, bool B1>
+__device__ int wsmooth(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG_LDS T* bl, int R, int nsteps,
+                       T omega) {
+  if constexpr (NCOL == 0) {
+    for (int k = 0; k < nsteps; ++k) {
+      if (k & 1)
+        wsweep_region<T, K, NCOL, B1, 2, 0>(L, m, lds, bl, R, k + 1, omega);
+      else
+        wsweep_region<T, K, NCOL, B1, 0, 2>(L, m, lds, bl, R, k + 1, omega);
+      __syncthreads();
+    }
+    return (nsteps & 1) ? 2 : 0;
+  } else {
+    int s = 1;
+    for (int k = 0; k < nsteps; ++k)
+      for (int c = 0; c < NCOL; ++c, ++s) {
+        wsweep_colour<T, K, NCOL, B1>(L, m, lds, bl, R, s, c);
+        __syncthreads();
+      }
+    return 0;
+  }
+}
+
+template <typename T>
+__device__ void wload_bands(const Level<T>& F, const WMap& m, MG_LDS T* bl) {
+  for (int idx = threadIdx.x; idx < NBANDS * WW; idx += FT) {
+    const int k = idx / WW, li = idx - k * WW;
+    const int g = min(max(m.gi(li), 0), F.nx - 1);
+    bl[k * WW + wcol(li)] = bandp(F, k)[g];
+  }
+}
+
+template <typename T, int K, bool FINE, int NCOL, bool B1>
+__global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs,
+                                              int TY, int H, int ntx, int nty, int nsteps, T omega) {
+  constexpr int P = wide_narr<NCOL>() * WW;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const Level<T> F = Fs[blockIdx.z];
+  if (F.st->done) return;
+  const Level<T> C = Cs[blockIdx.z];
+  int tx, ty;
+  tile_coords(ntx, nty, tx, ty);
+  const int TX = WW - 2 * H, R = TY + 2 * H;
+  MG_LDS T* lds = lds_cast<T>(smem_raw);
+  MG_LDS T* bl = lds + R * P;
+  const WMap m{tx * TX, ty * TY, H, F.nx, F.ny, F.py};
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  if constexpr (B1) wload_bands(F, m, bl);
+
+  {
+    const int la = lane, lb = lane + 64;
+    const int ca = wcol(la), cb = wcol(lb);
+    const bool oka = m.col_ok(la), okb = m.col_ok(lb);
+    const int ga = m.gi(la), gb = m.gi(lb);
+    for (int lj0 = wave; lj0 < R; lj0 += NWAVE * UL) {
+      T xa[UL], xb[UL], ba[UL], bb[UL];
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int lj = lj0 + u * NWAVE;
+        xa[u] = xb[u] = ba[u] = bb[u] = (T)0;
+        if (lj < R && m.row_ok(lj)) {
+          const size_t row = (size_t)m.wrapj(m.gj(lj)) * F.pitch;
+          if (oka) {
+            xa[u] = F.x[row + ga];
+            ba[u] = F.b[row + ga];
+          }
+          if (okb) {
+            xb[u] = F.x[row + gb];
+            bb[u] = F.b[row + gb];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int lj = lj0 + u * NWAVE;
+        if (lj >= R) break;
+        MG_LDS T* r = lds + lj * P;
+        r[ca] = xa[u];
+        r[cb] = xb[u];
+        r[WW + ca] = ba[u];
+        r[WW + cb] = bb[u];
+        if constexpr (NCOL == 0) {
+          r[2 * WW + ca] = (T)0;
+          r[2 * WW + cb] = (T)0;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  const int xsrc = wsmooth<T, K, NCOL, B1>(F, m, lds, bl, R, nsteps, omega);
+  if (xsrc == 0)
+    wsweep_region<T, K, NCOL, B1, 0, 1>(F, m, lds, bl, R, H - 1, omega);
+  else
+    wsweep_region<T, K, NCOL, B1, 2, 1>(F, m, lds, bl, R, H - 1, omega);
+  __syncthreads();
+
+  // full weighting at the coarse nodes of the tile; zero coarse start
+  {
+    const int ca = TX >> 1, nrb = TY >> 1;
+    const int li = H + 2 * lane, A = li >> 1;
+    const int I = (m.i0 >> 1) + lane;
+    const bool iok = lane < ca && I >= 1 && I <= C.nx - 2;
+    const int lo = C.py ? 0 : 1, hi = C.py ? C.ny - 1 : C.ny - 2;
+    for (int rb = wave; rb < nrb; rb += NWAVE) {
+      const int J = (m.j0 >> 1) + rb;
+      if (!iok || J < lo || J > hi) continue;
+      const MG_LDS T* p = lds + WW + (H + 2 * rb - 1) * P + A;
+      const Nbr<T> d = (H & 1) ? wgather<T, ST9, P, 1, true>(p) : wgather<T, ST9, P, 0, true>(p);
+      const T g = fw_combine(fw_row(d.sw, d.s, d.se), fw_row(d.w, d.c, d.e), fw_row(d.nw, d.n, d.ne));
+      const size_t q = (size_t)J * C.pitch + I;
+      C.b[q] = g;
+      C.x[q] = (T)0;
+    }
+  }
+  // smoothed iterate of the output nodes -> ping-pong buffer
+  {
+    const int la = H + lane, lb = H + lane + 64;
+    const bool oka = m.col_ok(la), okb = lb < H + TX && m.col_ok(lb);
+    const int ga = m.gi(la), gb = m.gi(lb);
+    for (int lj = H + wave; lj < H + TY; lj += NWAVE) {
+      const int gj = m.gj(lj);
+      if (!m.row_ok(lj) || gj >= F.ny) continue;
+      const MG_LDS T* r = lds + lj * P + xsrc * WW;
+      T* row = F.t + (size_t)gj * F.pitch;
+      if (oka) row[ga] = r[wcol(la)];
+      if (okb) row[gb] = r[wcol(lb)];
+    }
+  }
+}
+
+// Residual norm contribution of the output nodes of column parity Q.
+template <typename T, int K, bool B1, int P, int Q>
+__device__ double wnorm_part(const Level<T>& F, const WMap& m, const MG_LDS T* lds, const MG_LDS T* bl, int xsrc,
+                             int TX, int TY) {
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int H = m.H;
+  const int li = H + ((H ^ Q) & 1) + 2 * lane;
+  if (!(li < H + TX && m.col_ok(li))) return 0.0;
+  const int A = li >> 1, gi = m.gi(li);
+  Cf<T> col{};
+  if constexpr (K == ST9 && B1) col = wcoef_cols<T, Q>(bl, A);
+  constexpr int own = Q ? WH : 0;
+  double acc = 0.0;
+  for (int lj = H + wave; lj < H + TY; lj += NWAVE) {
+    if (!m.row_ok(lj) || m.gj(lj) >= F.ny) continue;
+    const Nbr<T> v = wgather<T, K, P, Q, true>(lds + xsrc * WW + (lj - 1) * P + A);
+    const T d = defect_v<K>(F, wcoef<T, K, B1>(F, m, col, gi, lj), v, lds[lj * P + WW + own + A]);
+    acc += (double)d * (double)d;
+  }
+  return acc;
+}
+
+template <typename T, int K, bool FINE, int NCOL, bool B1>
+__global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs,
+                                               int TY, int H, int ntx, int nty, int nsteps, T omega, int mode,
+                                               const Level<double>* __restrict__ X64s) {
+  constexpr int P = wide_narr<NCOL>() * WW;
+  constexpr int CW = WH + 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double sh[FT / 64];
+  const Level<T> F = Fs[blockIdx.z];
+  SolveState* st = F.st;
+  if (st->done) return;
+  const Level<T> C = Cs[blockIdx.z];
+  int tx, ty;
+  tile_coords(ntx, nty, tx, ty);
+  const int TX = WW - 2 * H, R = TY + 2 * H;
+  const int CR = (R >> 1) + 2;
+  MG_LDS T* lds = lds_cast<T>(smem_raw);
+  MG_LDS T* ec = lds + R * P;
+  MG_LDS T* bl = ec + CW * CR;
+  const WMap m{tx * TX, ty * TY, H, F.nx, F.ny, F.py};
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  if constexpr (B1) wload_bands(F, m, bl);
+
+  // coarse correction covering the region
+  const int cI0 = m.gi(0) >> 1, cJ0 = m.gj(0) >> 1;
+  {
+    const int clo = C.py ? 0 : 1, chi = C.py ? C.ny - 1 : C.ny - 2;
+    const int Ia = cI0 + lane, Ib = cI0 + lane + 64;
+    const bool oka = Ia >= 1 && Ia <= C.nx - 2, okb = lane + 64 < CW && Ib >= 1 && Ib <= C.nx - 2;
+    for (int r0 = wave; r0 < CR; r0 += NWAVE * UL) {
+      T va[UL], vb[UL];
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        int J = cJ0 + r0 + u * NWAVE;
+        if (C.py) {
+          while (J < 0) J += C.ny;
+          while (J >= C.ny) J -= C.ny;
+        }
+        va[u] = vb[u] = (T)0;
+        if (r0 + u * NWAVE < CR && J >= clo && J <= chi) {
+          const T* row = C.x + (size_t)J * C.pitch;
+          if (oka) va[u] = row[Ia];
+          if (okb) vb[u] = row[Ib];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int r = r0 + u * NWAVE;
+        if (r >= CR) break;
+        ec[r * CW + lane] = va[u];
+        if (lane + 64 < CW) ec[r * CW + lane + 64] = vb[u];
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int la = lane, lb = lane + 64;
+    const int ca = wcol(la), cb = wcol(lb);
+    const bool oka = m.col_ok(la), okb = m.col_ok(lb);
+    const int ga = m.gi(la), gb = m.gi(lb);
+    const int ea = (ga >> 1) - cI0, eb = (gb >> 1) - cI0;
+    for (int lj0 = wave; lj0 < R; lj0 += NWAVE * UL) {
+      T ta[UL], tb[UL], ba[UL], bb[UL];
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int lj = lj0 + u * NWAVE;
+        ta[u] = tb[u] = ba[u] = bb[u] = (T)0;
+        if (lj < R && m.row_ok(lj)) {
+          const size_t row = (size_t)m.wrapj(m.gj(lj)) * F.pitch;
+          if (oka) {
+            ta[u] = F.t[row + ga];
+            ba[u] = F.b[row + ga];
+          }
+          if (okb) {
+            tb[u] = F.t[row + gb];
+            bb[u] = F.b[row + gb];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int lj = lj0 + u * NWAVE;
+        if (lj >= R) break;
+        const int gj = m.gj(lj);
+        T xa = (T)0, xb = (T)0;
+        if (m.row_ok(lj)) {
+          const MG_LDS T* e0 = ec + ((gj >> 1) - cJ0) * CW;
+          const MG_LDS T* e1 = e0 + CW;
+          const int oy = gj & 1;
+          if (oka) xa = ta[u] + prolong_combine(e0[ea], e0[ea + 1], e1[ea], e1[ea + 1], ga & 1, oy);
+          if (okb) xb = tb[u] + prolong_combine(e0[eb], e0[eb + 1], e1[eb], e1[eb + 1], gb & 1, oy);
+        }
+        MG_LDS T* r = lds + lj * P;
+        r[ca] = xa;
+        r[cb] = xb;
+        r[WW + ca] = ba[u];
+        r[WW + cb] = bb[u];
+        if constexpr (NCOL == 0) {
+          r[2 * WW + ca] = (T)0;
+          r[2 * WW + cb] = (T)0;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  const int xsrc = wsmooth<T, K, NCOL, B1>(F, m, lds, bl, R, nsteps, omega);
+
+  {
+    const int la = H + lane, lb = H + lane + 64;
+    const bool oka = m.col_ok(la), okb = lb < H + TX && m.col_ok(lb);
+    const int ga = m.gi(la), gb = m.gi(lb);
+    if (mode == POST_MIXED) {
+      const Level<double>& X = X64s[blockIdx.z];
+      for (int lj0 = H + wave; lj0 < H + TY; lj0 += NWAVE * UL) {
+        double xa[UL], xb[UL];
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+          const int lj = lj0 + u * NWAVE, gj = m.gj(lj);
+          xa[u] = xb[u] = 0.0;
+          if (lj < H + TY && m.row_ok(lj) && gj < F.ny) {
+            const double* xrow = X.x + (size_t)gj * X.pitch;
+            if (oka) xa[u] = xrow[ga];
+            if (okb) xb[u] = xrow[gb];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+          const int lj = lj0 + u * NWAVE, gj = m.gj(lj);
+          if (!(lj < H + TY && m.row_ok(lj) && gj < F.ny)) continue;
+          const MG_LDS T* r = lds + lj * P + xsrc * WW;
+          double* xrow = X.x + (size_t)gj * X.pitch;
+          T* row = F.x + (size_t)gj * F.pitch;
+          if (oka) {
+            xrow[ga] = xa[u] + (double)r[wcol(la)];
+            row[ga] = (T)0;
+          }
+          if (okb) {
+            xrow[gb] = xb[u] + (double)r[wcol(lb)];
+            row[gb] = (T)0;
+          }
+        }
+      }
+    } else {
+      for (int lj = H + wave; lj < H + TY; lj += NWAVE) {
+        const int gj = m.gj(lj);
+        if (!m.row_ok(lj) || gj >= F.ny) continue;
+        const MG_LDS T* r = lds + lj * P + xsrc * WW;
+        T* row = F.x + (size_t)gj * F.pitch;
+        if (oka) row[ga] = r[wcol(la)];
+        if (okb) row[gb] = r[wcol(lb)];
+      }
+    }
+  }
+  if (mode == POST_NORM) {
+    double acc = wnorm_part<T, K, B1, P, 0>(F, m, lds, bl, xsrc, TX, TY);
+    acc += wnorm_part<T, K, B1, P, 1>(F, m, lds, bl, xsrc, TX, TY);
     const double part = wg_sum(acc, sh);
     if (threadIdx.x == 0) st->partial[blockIdx.x] = part;
   }
@@ -405,53 +1065,172 @@ TileGeom tile_geom(int nx, int ny, int TX, int TY, int H) {
   g.H = H;
   g.ntx = (nx + TX - 1) / TX;
   g.nty = (ny + TY - 1) / TY;
+  g.wide = 0;
   return g;
 }
 
+TileGeom wide_geom(int nx, int ny, int TY, int H) {
+  TileGeom g = tile_geom(nx, ny, WW - 2 * H, TY, H);
+  g.wide = 1;
+  return g;
+}
+
+int wide_width() { return WW; }
+
 template <typename T>
 size_t pre_lds_bytes(const TileGeom& g, int ncol) {
+  const size_t narr = ncol == 0 ? 3 : 2;
+  if (g.wide) return ((g.TY + 2 * g.H) * narr * WW + NBANDS * WW) * sizeof(T);
   const size_t W = g.TX + 2 * g.H, R = g.TY + 2 * g.H;
-  return W * R * (ncol == 0 ? 3 : 2) * sizeof(T);
+  return (W * R * narr + NBANDS * W) * sizeof(T);
 }
 
 template <typename T>
 size_t post_lds_bytes(const TileGeom& g, int ncol) {
+  const size_t narr = ncol == 0 ? 3 : 2;
+  if (g.wide) {
+    const size_t R = g.TY + 2 * g.H;
+    return (R * narr * WW + (WH + 2) * ((R >> 1) + 2) + NBANDS * WW) * sizeof(T);
+  }
   const size_t W = g.TX + 2 * g.H, R = g.TY + 2 * g.H;
   const size_t CW = (W >> 1) + 2, CR = (R >> 1) + 2;
-  return (W * R * (ncol == 0 ? 3 : 2) + CW * CR) * sizeof(T);
+  return (W * R * narr + CW * CR + NBANDS * W) * sizeof(T);
+}
+
+// Kernel variants by stencil, finest level, smoother (Jacobi, red-black,
+// four-colour), 1-D bands and tile shape.  Red-black is not defined for
+// 9-point operators and 1-D bands only exist for them: those variants are
+// nullptr.
+template <typename T>
+using PreFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, int, T);
+template <typename T>
+using PostFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, int, T, int, const Level<double>*);
+template <typename T>
+using PreWFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, T);
+template <typename T>
+using PostWFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, T, int, const Level<double>*);
+
+// f(NCOL, B1) -> kernel for the valid (stencil, smoother, bands) triples.
+#define MG_VARIANT(K, ncol, b1, F)                                                        \
+  do {                                                                                    \
+    if constexpr (K == ST5) {                                                             \
+      if (b1) return nullptr;                                                             \
+      if (ncol == 0) return F(0, false);                                                  \
+      if (ncol == 2) return F(2, false);                                                  \
+      if (ncol == 4) return F(4, false);                                                  \
+    } else {                                                                              \
+      if (ncol == 0) return b1 ? F(0, true) : F(0, false);                                \
+      if (ncol == 4) return b1 ? F(4, true) : F(4, false);                                \
+    }                                                                                     \
+    return nullptr;                                                                       \
+  } while (0)
+
+template <typename T, int K, bool FINE>
+PreFn<T> pre_fn(int ncol, bool b1) {
+#define MG_F(NC, B) k_pre<T, K, FINE, NC, B>
+  MG_VARIANT(K, ncol, b1, MG_F);
+#undef MG_F
+}
+
+template <typename T, int K, bool FINE>
+PostFn<T> post_fn(int ncol, bool b1) {
+#define MG_F(NC, B) k_post<T, K, FINE, NC, B>
+  MG_VARIANT(K, ncol, b1, MG_F);
+#undef MG_F
+}
+
+template <typename T, int K, bool FINE>
+PreWFn<T> pre_w_fn(int ncol, bool b1) {
+#define MG_F(NC, B) k_pre_w<T, K, FINE, NC, B>
+  MG_VARIANT(K, ncol, b1, MG_F);
+#undef MG_F
+}
+
+template <typename T, int K, bool FINE>
+PostWFn<T> post_w_fn(int ncol, bool b1) {
+#define MG_F(NC, B) k_post_w<T, K, FINE, NC, B>
+  MG_VARIANT(K, ncol, b1, MG_F);
+#undef MG_F
+}
+
+#undef MG_VARIANT
+
+template <typename T>
+PreFn<T> pick_pre(int kind, bool oned, bool fine, int ncol) {
+  if (kind == ST5) return fine ? pre_fn<T, ST5, true>(ncol, false) : pre_fn<T, ST5, false>(ncol, false);
+  return fine ? pre_fn<T, ST9, true>(ncol, oned) : pre_fn<T, ST9, false>(ncol, oned);
+}
+
+template <typename T>
+PostFn<T> pick_post(int kind, bool oned, bool fine, int ncol) {
+  if (kind == ST5) return fine ? post_fn<T, ST5, true>(ncol, false) : post_fn<T, ST5, false>(ncol, false);
+  return fine ? post_fn<T, ST9, true>(ncol, oned) : post_fn<T, ST9, false>(ncol, oned);
+}
+
+template <typename T>
+PreWFn<T> pick_pre_w(int kind, bool oned, bool fine, int ncol) {
+  if (kind == ST5) return fine ? pre_w_fn<T, ST5, true>(ncol, false) : pre_w_fn<T, ST5, false>(ncol, false);
+  return fine ? pre_w_fn<T, ST9, true>(ncol, oned) : pre_w_fn<T, ST9, false>(ncol, oned);
+}
+
+template <typename T>
+PostWFn<T> pick_post_w(int kind, bool oned, bool fine, int ncol) {
+  if (kind == ST5) return fine ? post_w_fn<T, ST5, true>(ncol, false) : post_w_fn<T, ST5, false>(ncol, false);
+  return fine ? post_w_fn<T, ST9, true>(ncol, oned) : post_w_fn<T, ST9, false>(ncol, oned);
 }
 
 template <typename T>
 hipError_t prepare_fused() {
-  const void* ks[8] = {(const void*)k_pre<T, ST5, false>,  (const void*)k_pre<T, ST9, false>,
-                       (const void*)k_post<T, ST5, false>, (const void*)k_post<T, ST9, false>,
-                       (const void*)k_pre<T, ST5, true>,   (const void*)k_pre<T, ST9, true>,
-                       (const void*)k_post<T, ST5, true>,  (const void*)k_post<T, ST9, true>};
-  for (const void* k : ks) {
-    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)FUSED_LDS_MAX);
-    if (e != hipSuccess) return e;
-  }
+  for (int kind : {(int)ST5, (int)ST9})
+    for (int oned = 0; oned < 2; ++oned)
+      for (int fine = 0; fine < 2; ++fine)
+        for (int ncol : {0, 2, 4}) {
+          const void* ks[4] = {(const void*)pick_pre<T>(kind, oned, fine, ncol),
+                               (const void*)pick_post<T>(kind, oned, fine, ncol),
+                               (const void*)pick_pre_w<T>(kind, oned, fine, ncol),
+                               (const void*)pick_post_w<T>(kind, oned, fine, ncol)};
+          for (const void* k : ks) {
+            if (!k) continue;
+            hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)FUSED_LDS_MAX);
+            if (e != hipSuccess) return e;
+          }
+        }
   return hipSuccess;
 }
 
 template <typename T>
 hipError_t launch_pre(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g, int nsteps, int ncol, T omega,
-                      int kind, bool fine, int nslots, hipStream_t st) {
-  auto k = kind == ST5 ? (fine ? k_pre<T, ST5, true> : k_pre<T, ST5, false>)
-                       : (fine ? k_pre<T, ST9, true> : k_pre<T, ST9, false>);
-  hipLaunchKernelGGL(k, dim3(g.ntx * g.nty, 1, nslots), dim3(FT), pre_lds_bytes<T>(g, ncol), st, Fs, Cs, g.TX, g.TY,
-                     g.H, g.ntx, g.nty, nsteps, ncol, omega);
+                      int kind, bool oned, bool fine, int nslots, hipStream_t st) {
+  const dim3 grid(g.ntx * g.nty, 1, nslots);
+  const size_t lds = pre_lds_bytes<T>(g, ncol);
+  if (g.wide) {
+    PreWFn<T> k = pick_pre_w<T>(kind, oned, fine, ncol);
+    if (!k || g.TX != WW - 2 * g.H) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TY, g.H, g.ntx, g.nty, nsteps, omega);
+  } else {
+    PreFn<T> k = pick_pre<T>(kind, oned, fine, ncol);
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TX, g.TY, g.H, g.ntx, g.nty, nsteps, omega);
+  }
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_post(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g, int nsteps, int ncol, T omega,
-                       int mode, const Level<double>* X64s, int kind, bool fine, int nslots, hipStream_t st,
-                       bool with_finish) {
-  auto k = kind == ST5 ? (fine ? k_post<T, ST5, true> : k_post<T, ST5, false>)
-                       : (fine ? k_post<T, ST9, true> : k_post<T, ST9, false>);
-  hipLaunchKernelGGL(k, dim3(g.ntx * g.nty, 1, nslots), dim3(FT), post_lds_bytes<T>(g, ncol), st, Fs, Cs, g.TX, g.TY,
-                     g.H, g.ntx, g.nty, nsteps, ncol, omega, mode, X64s);
+                       int mode, const Level<double>* X64s, int kind, bool oned, bool fine, int nslots,
+                       hipStream_t st, bool with_finish) {
+  const dim3 grid(g.ntx * g.nty, 1, nslots);
+  const size_t lds = post_lds_bytes<T>(g, ncol);
+  if (g.wide) {
+    PostWFn<T> k = pick_post_w<T>(kind, oned, fine, ncol);
+    if (!k || g.TX != WW - 2 * g.H) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TY, g.H, g.ntx, g.nty, nsteps, omega, mode, X64s);
+  } else {
+    PostFn<T> k = pick_post<T>(kind, oned, fine, ncol);
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TX, g.TY, g.H, g.ntx, g.nty, nsteps, omega, mode,
+                       X64s);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || mode != POST_NORM || !with_finish) return e;
   return launch_norm_finish<T>(Fs, g.ntx * g.nty, NORM_CHECK, nslots, st);
@@ -461,10 +1240,10 @@ hipError_t launch_post(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g
   template size_t pre_lds_bytes<T>(const TileGeom&, int);                                                          \
   template size_t post_lds_bytes<T>(const TileGeom&, int);                                                         \
   template hipError_t prepare_fused<T>();                                                                          \
-  template hipError_t launch_pre<T>(const Level<T>*, const Level<T>*, const TileGeom&, int, int, T, int, bool, int, \
-                                    hipStream_t);                                                                  \
+  template hipError_t launch_pre<T>(const Level<T>*, const Level<T>*, const TileGeom&, int, int, T, int, bool,     \
+                                    bool, int, hipStream_t);                                                       \
   template hipError_t launch_post<T>(const Level<T>*, const Level<T>*, const TileGeom&, int, int, T, int,         \
-                                     const Level<double>*, int, bool, int, hipStream_t, bool);
+                                     const Level<double>*, int, bool, bool, int, hipStream_t, bool);
 
 MG_FUSED_INSTANTIATE(double)
 MG_FUSED_INSTANTIATE(float)

@@ -66,6 +66,8 @@ hipError_t launch_cholesky(double* A, int n, int* info, hipStream_t st);
 hipError_t launch_count_bad(const double* v, long n, int* count, hipStream_t st);
 hipError_t launch_count_nonfinite(const double* v, int nx, int ny, int pitch, int py, int* count, hipStream_t st);
 hipError_t launch_to_float(const double* s, float* d, long n, hipStream_t st);
+// band D (index BAND_D) = 1 / band C of a level's band storage
+hipError_t launch_inv_diag(double* band, int bstride, hipStream_t st);
 hipError_t launch_coeff_grad(const double* u, const double* lam, double* g, int nx, int ny, int py, double hx,
                              double hy, hipStream_t st);
 

@@ -784,6 +784,12 @@ __global__ void k_convert(const S* __restrict__ s, D* __restrict__ d, long n) {
   for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) d[k] = (D)s[k];
 }
 
+// Inverse-diagonal band D = 1 / C (0 where C is 0: entries no unknown reads).
+__global__ void k_inv_diag(const double* __restrict__ c, double* __restrict__ d, long n) {
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+    d[k] = c[k] != 0.0 ? 1.0 / c[k] : 0.0;
+}
+
 // dL/dk for each cell: -lam_e^T K u_e with K = Ex + Ey the unit-coefficient
 // element matrix (local node order 2 b + a, a along x).
 __global__ void k_coeff_grad(const double* __restrict__ u, const double* __restrict__ lam, double* __restrict__ g,
@@ -968,6 +974,15 @@ hipError_t launch_to_float(const double* s, float* d, long n, hipStream_t st) {
   if (b > 8192) b = 8192;
   if (b < 1) b = 1;
   hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)b), dim3(NT), 0, st, s, d, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_inv_diag(double* band, int bstride, hipStream_t st) {
+  long b = (bstride + NT - 1) / NT;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_inv_diag, dim3((unsigned)b), dim3(NT), 0, st, band, band + (size_t)BAND_D * bstride,
+                     (long)bstride);
   return hipGetLastError();
 }
 

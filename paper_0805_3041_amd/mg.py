@@ -23,7 +23,7 @@ MG_COEF_CONST5, MG_COEF_CELL9 = 0, 1
 MG_CYCLE_F, MG_CYCLE_V = 0, 1
 MG_SMOOTH_JACOBI, MG_SMOOTH_RBGS, MG_SMOOTH_GS4C = 0, 1, 2
 MG_PREC_FP64, MG_PREC_MIXED = 0, 1
-MG_TILES_FUSED, MG_TILES_PER_OP = 0, 1
+MG_TILES_FUSED, MG_TILES_PER_OP, MG_TILES_NARROW, MG_TILES_WIDE = 0, 1, 2, 3
 
 SMOOTHERS = {"jacobi": MG_SMOOTH_JACOBI, "rbgs": MG_SMOOTH_RBGS, "gs4c": MG_SMOOTH_GS4C}
 CYCLES = {"F": MG_CYCLE_F, "V": MG_CYCLE_V}
@@ -256,7 +256,8 @@ def mg_level_shape(h, l: int):
     return nx.value, ny.value
 
 
-TILE_MODES = {"fused": MG_TILES_FUSED, "per_op": MG_TILES_PER_OP}
+TILE_MODES = {"fused": MG_TILES_FUSED, "per_op": MG_TILES_PER_OP, "narrow": MG_TILES_NARROW,
+              "wide": MG_TILES_WIDE}
 
 
 def make_options(cycle="F", smoother="rbgs", nu_pre=2, nu_post=2, omega=0.8, precision="fp64",

@@ -69,7 +69,7 @@ def _setup(mg, grid, coeffs, levels=0, **opt):
     dict(opt=dict(precision=5)),
     dict(opt=dict(smoother=0, omega=float("inf"))),
     dict(opt=dict(coarse_cta_nodes=-5)),
-    dict(opt=dict(tile_mode=2)),
+    dict(opt=dict(tile_mode=4)),
     dict(opt=dict(tile_x=7)),
     dict(opt=dict(tile_y=-2)),
     dict(levels=-1),

@@ -324,19 +324,28 @@ FUSED_CASES = [
     dict(p=dict(nx=129, ny=129, eps=0.2, smoother="rbgs", cycle="V"), cta=100, tile=(16, 4)),
     dict(p=dict(nx=129, ny=129, eps=0.2, smoother="gs4c"), cta=100, tile=(128, 32)),
     dict(p=dict(nx=257, ny=257, eps=0.05, smoother="rbgs"), cta=100, tile=(32, 8)),
+    dict(p=dict(nx=289, ny=161, eps=0.3, smoother="rbgs"), cta=100, wide_ty=6),
+    dict(p=dict(nx=257, ny=256, periodic_y=True, q1="annulus", smoother="gs4c"), cta=300, wide_ty=10),
+    dict(p=dict(nx=257, ny=256, periodic_y=True, q1="annulus", smoother="jacobi", nu_pre=2, nu_post=3), cta=300),
 ]
 
 
+@pytest.mark.parametrize("mode", ["narrow", "wide"])
 @pytest.mark.parametrize("case", FUSED_CASES, ids=[str(i) for i in range(len(FUSED_CASES))])
-def test_fused_tiles_equal_per_op_bitwise(case):
-    """The LDS-tiled passes give the per-op kernels' iterate bit for bit, and
-    both match the oracle."""
+def test_fused_tiles_equal_per_op_bitwise(case, mode):
+    """The LDS-tiled passes (small tiles, and 128-column wide tiles forced on
+    every fused level) give the per-op kernels' iterate bit for bit, and both
+    match the oracle."""
     p = Problem(**case["p"])
     rhs = W.normal_field(p.nx, p.ny, 21, p.periodic_y)
     x0 = W.uniform_field(p.nx, p.ny, 22, p.periodic_y)
     tx, ty = case.get("tile", (0, 0))
+    if mode == "wide":
+        if tx:
+            pytest.skip("explicit small-tile width")
+        ty = case.get("wide_ty", 0)
     a = p.solver(coarse_cta_nodes=case["cta"], tile_mode="per_op")
-    b = p.solver(coarse_cta_nodes=case["cta"], tile_mode="fused", tile_x=tx, tile_y=ty)
+    b = p.solver(coarse_cta_nodes=case["cta"], tile_mode=mode, tile_x=tx, tile_y=ty)
     try:
         xa = gpu_iterates(a, rhs, x0, 2)
         xb = gpu_iterates(b, rhs, x0, 2)
@@ -358,14 +367,15 @@ def test_fused_solve_matches_per_op_solve(precision):
     p = Problem(n, n, eps=0.05)
     rhs = torch.tensor(W.aniso_rhs(n, 2), device="cuda")
     out = []
-    for mode in ("per_op", "fused"):
+    for mode in ("per_op", "fused", "wide"):
         s = p.solver(precision=precision, tile_mode=mode)
         x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
         info = s.solve(rhs, x, 1e-10, 1000)
         s.close()
         out.append((info, x.cpu().numpy()))
-    (ia, xa), (ib, xb) = out
-    assert ia.status == ib.status == 0 and ia.cycles == ib.cycles
-    assert np.array_equal(xa, xb)
-    # same iterates; the norms are summed in a different order (tiles vs rows)
-    np.testing.assert_allclose(ia.history, ib.history, rtol=1e-14, atol=0)
+    (ia, xa) = out[0]
+    for ib, xb in out[1:]:
+        assert ia.status == ib.status == 0 and ia.cycles == ib.cycles
+        assert np.array_equal(xa, xb)
+        # same iterates; the norms are summed in a different order (tiles vs rows)
+        np.testing.assert_allclose(ia.history, ib.history, rtol=1e-14, atol=0)
