@@ -46,7 +46,134 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 512 MiB (HBM counter calibration)")
+    ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
+                    help="print a markdown summary of a rocprofv3 --stats kernel_stats.csv and exit")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the HBM traffic summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "this bench with --calibrate-copy, and exit")
+    ap.add_argument("--command", default="", help="command line recorded in a summary")
     return ap.parse_args()
+
+
+COPY_BYTES = 512 << 20
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def calibrate_copy():
+    """One device-to-device copy of COPY_BYTES: the reference a counter-based
+    byte count is scaled by."""
+    import torch
+
+    a = torch.zeros(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def source_digest() -> str:
+    """sha256 over the kernel sources: a stored counter measurement is only
+    reported while the kernels it was taken on are unchanged."""
+    import hashlib
+
+    d = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_0805_3041_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                d.update(name.encode() + b"\0" + f.read())
+    return d.hexdigest()
+
+
+def stored_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from profiles/<workload>_traffic.md, or
+    None when absent or taken on other kernel sources."""
+    path = os.path.join(PROFILES, f"{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    digest, found = None, None
+    for line in open(path):
+        line = line.strip().strip("`")
+        if line.startswith("source_sha256:"):
+            digest = line.split(":", 1)[1].strip()
+        if line.startswith("traffic_bytes_per_launch[") and kernel in line:
+            found = float(line.rsplit(":", 1)[1])
+    if digest != source_digest():
+        return None
+    return found
+
+
+def _csv_rows(path):
+    import csv
+
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def stats_summary(path: str, command: str) -> str:
+    rows = _csv_rows(path)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = ["# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+           f"Total kernel time: {tot / 1e6:.3f} ms", "",
+           "| calls | total ms | avg us | min us | max us | % | kernel |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:25]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        out.append(f"| {int(r['Calls'])} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                   f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} | `{name}` |")
+    return "\n".join(out) + "\n"
+
+
+def _per_dispatch(path, counter):
+    """{dispatch id: (kernel name, counter value summed over its rows)}."""
+    acc = {}
+    for r in _csv_rows(path):
+        if r["Counter_Name"] != counter:
+            continue
+        key = r["Dispatch_Id"]
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        v = acc.get(key, (name, 0.0))[1] + float(r["Counter_Value"])
+        acc[key] = (name, v)
+    return acc
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, command: str) -> str:
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the finest-level fused
+    passes, each scaled by what the same counter reads for the COPY_BYTES
+    device copy."""
+    fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _per_dispatch(write_csv, "WRITE_SIZE")
+
+    def copy_kib(acc):
+        vals = [v for n, v in acc.values() if "copy" in n.lower() or "Copy" in n]
+        return max(vals) if vals else None
+
+    cf, cw = copy_kib(fetch), copy_kib(write)
+    exp_kib = COPY_BYTES / 1024
+    out = ["# HBM traffic of the finest-level fused passes (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
+           f"Command: `{command}`", "",
+           f"Calibration: a {COPY_BYTES >> 20} MiB device copy reads FETCH_SIZE {cf:.0f} KiB and writes "
+           f"WRITE_SIZE {cw:.0f} KiB (expected {exp_kib:.0f} KiB each); scale factors "
+           f"{exp_kib / cf:.4f} (read), {exp_kib / cw:.4f} (write).", "",
+           "| kernel | dispatches | FETCH_SIZE KiB / dispatch | WRITE_SIZE KiB / dispatch | scaled bytes / launch |",
+           "|---|---|---|---|---|"]
+    per_kernel = {}
+    for acc, which in ((fetch, 0), (write, 1)):
+        for n, v in acc.values():
+            if "k_pre" in n or "k_post" in n:
+                if ", true," not in n:
+                    continue
+                per_kernel.setdefault(n, ([], []))[which].append(v)
+    lines = []
+    for n, (fv, wv) in sorted(per_kernel.items()):
+        if not fv or not wv:
+            continue
+        f_avg, w_avg = sum(fv) / len(fv), sum(wv) / len(wv)
+        bytes_ = (f_avg * exp_kib / cf + w_avg * exp_kib / cw) * 1024
+        out.append(f"| `{n}` | {len(fv)} | {f_avg:.0f} | {w_avg:.0f} | {bytes_:.4g} |")
+        lines.append(f"traffic_bytes_per_launch[{n}]: {bytes_:.6g}")
+    out += ["", *lines, f"source_sha256: {source_digest()}", ""]
+    return "\n".join(out)
 
 
 # Algorithmic bytes per stored fine node of the finest-level fused passes
@@ -150,16 +277,18 @@ def annulus(args):
         raise SystemExit(f"solve did not converge: {mg.status_string(info_h.status)} rel_res {info_h.rel_res:.3e}")
     scratch = torch.zeros_like(rhs)
     times = {which: s.profile_pass(rhs, scratch, 0, which, reps=20) for which in (0, 1)}
-    s.close()
     dom = 1 if times[1] >= times[0] else 0
+    kernel_name = s.pass_kernel_name(0, dom)
+    s.close()
     alg_bytes = BYTES_PER_NODE[(head, dom)] * nx * ny
     achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
     s = make(other)
     steps_o = max(1, args.steps // 2)
     wall_o, info_o, _ = run(s, steps_o, 1)
     s.close()
-    kernel_name = {("mixed", 1): "k_post<float, ST9, FINE>", ("mixed", 0): "k_pre<float, ST9, FINE>",
-                   ("fp64", 1): "k_post<double, ST9, FINE>", ("fp64", 0): "k_pre<double, ST9, FINE>"}[(head, dom)]
+    if args.calibrate_copy:
+        calibrate_copy()
+    traffic = stored_traffic("annulus4097", kernel_name)
     out = {
         "metric": "unknowns/s to 1e-10 rel. residual",
         "value": unknowns * args.steps / wall_h,
@@ -177,7 +306,7 @@ def annulus(args):
                                "Q1 with kx=4 pi r, ky=1/(4 pi r), 4097x4096 nodes, f = N(0,1), four-colour GS "
                                f"{args.nu}/{args.nu}, F-cycle to 5x4, x0=0, tol 1e-10", "precision": head},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel_name,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel_name,
                      "avg_us": times[dom], "bytes_per_launch": alg_bytes, "bytes_per_node": BYTES_PER_NODE[(head, dom)],
                      "nodes": nx * ny, "other_pass_us": times[1 - dom]},
         "cycles": info_h.cycles,
@@ -223,6 +352,12 @@ def cpu_baseline_annulus(cycles, nu, seconds, unknowns_full):
 
 def main():
     args = parse()
+    if args.stats_summary:
+        sys.stdout.write(stats_summary(args.stats_summary, args.command))
+        return
+    if args.traffic_summary:
+        sys.stdout.write(traffic_summary(*args.traffic_summary, args.command))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: collectives and multi-GPU sharding are not "
                                    "built; run with --gpus 1"}), flush=True)
@@ -275,6 +410,7 @@ def main():
     s0 = solvers[0]
     times = {which: s0.profile_pass(rhs, scratch, 0, which, reps=100) for which in (0, 1)}
     dom = 1 if times[1] >= times[0] else 0
+    kernel_name = s0.pass_kernel_name(0, dom)
     nodes = n * n
     alg_bytes = BYTES_PER_NODE[(head, dom)] * nodes
     achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
@@ -288,14 +424,10 @@ def main():
         s.close()
 
     if args.calibrate_copy:
-        a = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
-        bcp = torch.empty_like(a)
-        bcp.copy_(a)
-        torch.cuda.synchronize()
+        calibrate_copy()
 
     total = unknowns * len(eps_list)
-    kernel_name = {("mixed", 1): "k_post<float, ST5, FINE>", ("mixed", 0): "k_pre<float, ST5, FINE>",
-                   ("fp64", 1): "k_post<double, ST5, FINE>", ("fp64", 0): "k_pre<double, ST5, FINE>"}[(head, dom)]
+    traffic = stored_traffic("aniso1025", kernel_name)
     out = {
         "metric": "unknowns/s to 1e-10 rel. residual",
         "value": total * args.steps / wall_h,
@@ -314,7 +446,7 @@ def main():
                                f"{args.nu}/{args.nu}, F-cycle to 3x3, x0={args.x0}, tol 1e-10",
                    "precision": head},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel_name, "avg_us": times[dom], "bytes_per_launch": alg_bytes,
                      "bytes_per_node": BYTES_PER_NODE[(head, dom)], "nodes": nodes,
                      "other_pass_us": times[1 - dom]},

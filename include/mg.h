@@ -161,6 +161,15 @@ mg_status mg_coeff_grad(mg_handle h, const double* u, const double* lam, double*
 mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t level, int32_t which, int32_t reps,
                           double* avg_us);
 
+/* Measurement helper: the launch shape of the fused pre-pass (which = 0) or
+ * post-pass (which = 1) of `level`, written to the host array out[8]:
+ * out[0] wide tiles (1) or small tiles (0), out[1] TX, out[2] TY, out[3]
+ * halo H, out[4] workgroups per problem, out[5] colours per smoothing step
+ * (0 Jacobi, 2, 4), out[6] stencil (0 5-point, 1 9-point), out[7] 1 if the
+ * 9-point bands vary along x only.  Same errors as mg_profile_pass; no
+ * device work. */
+mg_status mg_pass_info(mg_handle h, int32_t level, int32_t which, int32_t* out);
+
 /* Batched: nprob independent 5-point problems (MG_COEF_CONST5 only) with
  * their own grids (square or not, all coarsening to the same coarsest shape)
  * and their own eps_x, eps_y.  grids, coeffs: host arrays of nprob entries.

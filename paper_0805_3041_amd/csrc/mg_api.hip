@@ -1070,6 +1070,29 @@ mg_status mg_residual(mg_handle h, const double* rhs, const double* x, double* r
   return MG_OK;
 }
 
+mg_status mg_pass_info(mg_handle h, int32_t level, int32_t which, int32_t* out) {
+  mg_status s = single_only(h);
+  if (s != MG_OK) return s;
+  if (!out) return fail(h, MG_EINVAL, "out must not be NULL");
+  if (which != 0 && which != 1) return fail(h, MG_EINVAL, "which must be 0 (pre-pass) or 1 (post-pass)");
+  Group& G = h->groups[0];
+  if (level < 0 || level >= G.nlev) return fail(h, MG_EINVAL, "level out of range");
+  bool found = false;
+  for (const HostOp& op : G.prog)
+    if (op.type == (which == 0 ? H_PRE : H_POST) && op.level == level) found = true;
+  if (!found) return fail(h, MG_EUNSUPPORTED, "no fused pass of that kind runs on this level");
+  const TileGeom& g = which == 0 ? G.gpre[level] : G.gpost[level];
+  out[0] = g.wide;
+  out[1] = g.TX;
+  out[2] = g.TY;
+  out[3] = g.H;
+  out[4] = g.ntx * g.nty;
+  out[5] = h->ncol;
+  out[6] = stencil_kind(h);
+  out[7] = stencil_kind(h) == ST9 && h->oned ? 1 : 0;
+  return MG_OK;
+}
+
 mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t level, int32_t which, int32_t reps,
                           double* avg_us) {
   mg_status s = single_only(h);

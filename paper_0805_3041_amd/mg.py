@@ -32,6 +32,7 @@ PRECISIONS = {"fp64": MG_PREC_FP64, "mixed": MG_PREC_MIXED}
 EXPORTED = (
     "mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
     "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_shape", "mg_num_levels", "mg_profile_pass",
+    "mg_pass_info",
 )
 
 
@@ -89,8 +90,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_num_levels.argtypes = [ctypes.c_void_p]
     lib.mg_profile_pass.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, P(ctypes.c_double)]
+    lib.mg_pass_info.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32)]
     for name in ("mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
-                 "mg_destroy", "mg_level_shape", "mg_profile_pass"):
+                 "mg_destroy", "mg_level_shape", "mg_profile_pass", "mg_pass_info"):
         getattr(lib, name).restype = ctypes.c_int
     lib.mg_num_levels.restype = ctypes.c_int32
     _lib = lib
@@ -196,6 +198,18 @@ def mg_profile_pass(h, rhs: torch.Tensor, x: torch.Tensor, level: int, which: in
     if s != MG_OK:
         raise MGError(s, last_error(h))
     return us.value
+
+
+PASS_INFO_KEYS = ("wide", "tx", "ty", "halo", "workgroups", "colours", "stencil", "bands_1d")
+
+
+def mg_pass_info(h, level: int, which: int) -> dict:
+    lib = load_library()
+    out = (ctypes.c_int32 * 8)()
+    s = lib.mg_pass_info(h, int(level), int(which), out)
+    if s != MG_OK:
+        raise MGError(s, last_error(h))
+    return dict(zip(PASS_INFO_KEYS, list(out)))
 
 
 def mg_setup_batched(grids, coeffs, opts: mg_options):
@@ -312,6 +326,19 @@ class Solver:
     def profile_pass(self, rhs: torch.Tensor, x: torch.Tensor, level: int, which: int, reps: int = 50) -> float:
         """Average device time (us) of one fused pre-pass (which=0) or post-pass (1) on `level`."""
         return mg_profile_pass(self.h, rhs, x, level, which, reps)
+
+    def pass_info(self, level: int, which: int) -> dict:
+        """Launch shape of the fused pass (see mg_pass_info in include/mg.h)."""
+        return mg_pass_info(self.h, level, which)
+
+    def pass_kernel_name(self, level: int, which: int) -> str:
+        """Symbol (as profilers print it) of the kernel that runs the fused pass."""
+        i = self.pass_info(level, which)
+        t = "float" if self.opts.precision == MG_PREC_MIXED else "double"
+        base = ("k_pre" if which == 0 else "k_post") + ("_w" if i["wide"] else "")
+        flag = "true" if level == 0 else "false"
+        b1 = "true" if i["bands_1d"] else "false"
+        return f"mg::{base}<{t}, {i['stencil']}, {flag}, {i['colours']}, {b1}>"
 
     def close(self) -> None:
         if getattr(self, "h", None) is not None:
