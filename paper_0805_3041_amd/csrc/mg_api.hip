@@ -69,7 +69,7 @@ struct Group {
   Level<float>* dP32 = nullptr;
   std::vector<double*> band64;
   std::vector<float*> band32;
-  double** dcholp = nullptr;  // Cholesky factor of each slot's coarsest operator
+  double** dcholp = nullptr;  // inverse of each slot's coarsest operator
   std::vector<TileGeom> gpre, gpost;
   bool norm_fused = false;   // FP64: the finest post-pass applies the stopping test
   bool mixed_fused = false;  // mixed: the finest post-pass adds e into the FP64 iterate
@@ -389,12 +389,12 @@ hipError_t enqueue_cycle(mg_handle h, const Group& G, hipStream_t st) {
     for (const HostOp& op : G.prog)
       if ((e = run_op<double>(h, G, op, G.dL64, G.dP64, h->opts.omega, st)) != hipSuccess) return e;
     if (G.norm_fused) return hipSuccess;
-    return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, nullptr, G.ns, st);
+    return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, nullptr, stencil_kind(h), G.ns, st);
   }
   for (const HostOp& op : G.prog)
     if ((e = run_op<float>(h, G, op, G.dL32, G.dP32, (float)h->opts.omega, st)) != hipSuccess) return e;
   if (!G.mixed_fused && (e = launch_outer_update(G.dL64, G.dL32, G.shp[0], G.ns, st)) != hipSuccess) return e;
-  return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, G.dL32, G.ns, st);
+  return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, G.dL32, stencil_kind(h), G.ns, st);
 }
 
 // Captures one cycle and eight cycles as graphs on a private stream (a graph
@@ -640,23 +640,26 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
     }
   }
 
-  // coarsest operator of each slot: dense matrix and Cholesky factor (FP64)
+  // coarsest operator of each slot: dense matrix, Cholesky factor and the
+  // inverse the coarse solve applies (FP64)
   {
     const int n = G.ncu;
-    std::vector<double*> chol(ns, nullptr);
+    std::vector<double*> chol(ns, nullptr), inv(ns, nullptr);
     int* dinfo = nullptr;
     HIPCHK(h, h->dalloc(&dinfo, (size_t)ns * sizeof(int)));
     for (int s = 0; s < ns; ++s) {
       const Level<double>& L = G.l64(G.nlev - 1, s);
       HIPCHK(h, h->dalloc(&chol[s], (size_t)n * n * sizeof(double)));
+      HIPCHK(h, h->dalloc(&inv[s], (size_t)n * n * sizeof(double)));
       HIPCHK(h, launch_dense_coarse(chol[s], n, sc.nx, sc.ny, sc.py, L.kind, L.cx, L.cy, L.dg, L.band, L.bstride,
                                     L.bpitch, h->stream));
       HIPCHK(h, launch_cholesky(chol[s], n, dinfo + s, h->stream));
+      HIPCHK(h, launch_chol_inverse(chol[s], inv[s], n, h->stream));
     }
     std::vector<int> info(ns, 0);
     HIPCHK(h, hipMemcpyAsync(info.data(), dinfo, (size_t)ns * sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, h->dalloc(&G.dcholp, (size_t)ns * sizeof(double*)));
-    HIPCHK(h, hipMemcpyAsync(G.dcholp, chol.data(), (size_t)ns * sizeof(double*), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(G.dcholp, inv.data(), (size_t)ns * sizeof(double*), hipMemcpyHostToDevice, h->stream));
     mg_status st = sync_check(h);
     if (st != MG_OK) return st;
     for (int s = 0; s < ns; ++s)
@@ -786,7 +789,8 @@ mg_status begin_solve(mg_handle h, const double* const* rhs, double* const* x, d
   }
   HIPCHK(h, hipEventRecord(h->ev0, st));
   for (Group& G : h->groups)
-    HIPCHK(h, launch_resnorm<double>(G.dL64, G.shp[0], NORM_INIT, nullptr, h->mixed() ? G.dL32 : nullptr, G.ns, st));
+    HIPCHK(h, launch_resnorm<double>(G.dL64, G.shp[0], NORM_INIT, nullptr, h->mixed() ? G.dL32 : nullptr,
+                                     stencil_kind(h), G.ns, st));
   return MG_OK;
 }
 
@@ -1062,7 +1066,7 @@ mg_status mg_residual(mg_handle h, const double* rhs, const double* x, double* r
   HIPCHK(h, hipMemcpyAsync(h->dstate_res, &init, sizeof(SolveState), hipMemcpyHostToDevice, st));
   HIPCHK(h, hipMemcpyAsync(h->dLres, &L, sizeof(Level<double>), hipMemcpyHostToDevice, st));
   if (r) HIPCHK(h, hipMemsetAsync(r, 0, (size_t)s0.nx * s0.ny * sizeof(double), st));
-  HIPCHK(h, launch_resnorm<double>(h->dLres, s0, NORM_RESID, r, nullptr, 1, st));
+  HIPCHK(h, launch_resnorm<double>(h->dLres, s0, NORM_RESID, r, nullptr, stencil_kind(h), 1, st));
   SolveState cur{};
   HIPCHK(h, hipMemcpyAsync(&cur, h->dstate_res, sizeof(SolveState), hipMemcpyDeviceToHost, st));
   HIPCHK(h, hipStreamSynchronize(st));

@@ -39,7 +39,7 @@ hipError_t launch_subcycle(const Level<T>* levs, int nlev, const DOp* prog, cons
                            const double* const* chol, int ncu, T omega, int ncol, int nslots, hipStream_t st);
 template <typename T>
 hipError_t launch_resnorm(const Level<T>* Ls, const LevelShape& s, int mode, T* rout, const Level<float>* R32s,
-                          int nslots, hipStream_t st);
+                          int kind, int nslots, hipStream_t st);
 
 template <typename T>
 hipError_t prepare_subcycle_lds();
@@ -63,6 +63,8 @@ hipError_t launch_rap(double* cband, int cbstride, int cbpitch, int cnrows, int 
 hipError_t launch_dense_coarse(double* A, int n, int nx, int ny, int py, int kind, double cx, double cy, double dg,
                                const double* band, int bstride, int bpitch, hipStream_t st);
 hipError_t launch_cholesky(double* A, int n, int* info, hipStream_t st);
+// X = A^-1 (n x n) from the Cholesky factor of A
+hipError_t launch_chol_inverse(const double* Lf, double* X, int n, hipStream_t st);
 hipError_t launch_count_bad(const double* v, long n, int* count, hipStream_t st);
 hipError_t launch_count_nonfinite(const double* v, int nx, int ny, int pitch, int py, int* count, hipStream_t st);
 hipError_t launch_to_float(const double* s, float* d, long n, hipStream_t st);

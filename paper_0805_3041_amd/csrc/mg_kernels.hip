@@ -110,34 +110,26 @@ __device__ void body_prolong(const Level<T>& F, const Level<T>& C, int tid, int 
   }
 }
 
-// Exact solve with the Cholesky factor Lc (n x n, row-major, lower) of the
-// coarsest operator, unknowns numbered row by row.  One workgroup; `g` is
-// LDS scratch of n doubles.
+// Exact solve on the coarsest level: x = Ainv b with the inverse of the
+// coarsest operator (n x n, row-major, unknowns numbered row by row),
+// accumulated in FP64 in a fixed order.  One dot product per unknown, so no
+// barrier inside the op.
 template <typename T>
-__device__ void body_coarse(const Level<T>& L, const double* __restrict__ Lc, int n, double* g, int tid, int nth) {
+__device__ void body_coarse(const Level<T>& L, const double* __restrict__ Ainv, int n, int tid, int nth) {
   const int lo = row_lo(L), ni = L.nx - 2;
-  for (int k = tid; k < n; k += nth) {
-    const int r = k / ni;
-    g[k] = (double)L.b[(size_t)(lo + r) * L.pitch + (k - r * ni + 1)];
-  }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {  // forward: L y = g
-    if (tid == 0) g[k] = g[k] / Lc[(size_t)k * n + k];
-    __syncthreads();
-    const double gk = g[k];
-    for (int r = k + 1 + tid; r < n; r += nth) g[r] -= Lc[(size_t)r * n + k] * gk;
-    __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {  // backward: L^T x = y
-    if (tid == 0) g[k] = g[k] / Lc[(size_t)k * n + k];
-    __syncthreads();
-    const double gk = g[k];
-    for (int r = tid; r < k; r += nth) g[r] -= Lc[(size_t)k * n + r] * gk;
-    __syncthreads();
-  }
-  for (int k = tid; k < n; k += nth) {
-    const int r = k / ni;
-    L.x[(size_t)(lo + r) * L.pitch + (k - r * ni + 1)] = (T)g[k];
+  for (int r = tid; r < n; r += nth) {
+    const double* row = Ainv + (size_t)r * n;
+    double s = 0.0;
+    int i = 1, j = lo;
+    for (int k = 0; k < n; ++k) {
+      s = fma(row[k], (double)L.b[(size_t)j * L.pitch + i], s);
+      if (++i > ni) {
+        i = 1;
+        ++j;
+      }
+    }
+    const int rr = r / ni;
+    L.x[(size_t)(lo + rr) * L.pitch + (r - rr * ni + 1)] = (T)s;
   }
 }
 
@@ -183,10 +175,9 @@ __global__ void __launch_bounds__(NT) k_prolong(const Level<T>* __restrict__ Fs,
 template <typename T>
 __global__ void __launch_bounds__(NT) k_coarse(const Level<T>* __restrict__ Ls, const double* const* __restrict__ chol,
                                                int n) {
-  __shared__ double g[MAX_COARSE_UNKNOWNS];
   const Level<T> L = Ls[blockIdx.z];
   if (L.st->done) return;
-  body_coarse(L, chol[blockIdx.z], n, g, threadIdx.x, NT);
+  body_coarse(L, chol[blockIdx.z], n, threadIdx.x, NT);
 }
 
 // --------------------------------------------------------------------------- op bodies on LDS levels
@@ -358,7 +349,6 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
                                                      int ncol, int narr) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   MG_LDS T* lds = lds_cast<T>(smem_raw);
-  __shared__ double g[MAX_COARSE_UNKNOWNS];
   __shared__ int offs[MAX_LEVELS + 1];
   __shared__ int sops[MAX_SUB_OPS];
   const int slot = blockIdx.z;
@@ -434,7 +424,7 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
             lds_prolong(L, xl, C, xc, tid);
           break;
         }
-        case OP_COARSE: body_coarse(L, chol[slot], ncu, g, tid, SUB_NT); break;
+        case OP_COARSE: body_coarse(L, chol[slot], ncu, tid, SUB_NT); break;
         default: break;
       }
     } else {
@@ -444,7 +434,7 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
         case OP_COPY: body_copy(L, tid, SUB_NT); break;
         case OP_DR: body_dr(L, Ls[l + 1], tid, SUB_NT); break;
         case OP_PROLONG: body_prolong(L, Ls[l + 1], tid, SUB_NT); break;
-        case OP_COARSE: body_coarse(L, chol[slot], ncu, g, tid, SUB_NT); break;
+        case OP_COARSE: body_coarse(L, chol[slot], ncu, tid, SUB_NT); break;
         default: break;
       }
     }
@@ -515,27 +505,58 @@ __global__ void __launch_bounds__(NT) k_norm_finish(const Level<T>* __restrict__
 // step, (float) r into the FP32 finest level's b of the same slot (R32s).
 // Writes one partial sum of squares per workgroup; k_norm_finish completes
 // the norm.
-template <typename T>
+template <typename T, int K>
 __global__ void __launch_bounds__(NT) k_resnorm(const Level<T>* __restrict__ Ls, int mode, T* __restrict__ rout,
                                                 const Level<float>* __restrict__ R32s) {
+  constexpr int RU = 4;  // nodes of a row per thread per round (loads issued together)
   __shared__ double sh[NT / 64];
   const Level<T> L = Ls[blockIdx.z];
   SolveState* st = L.st;
   if (mode == NORM_CHECK && st->done) return;
   float* r32 = R32s ? R32s[blockIdx.z].b : nullptr;
   const int p32 = R32s ? R32s[blockIdx.z].pitch : 0;
-  const int lo = row_lo(L), nr = row_hi(L) - lo + 1, ni = L.nx - 2;
-  const int n = nr * ni;
+  const int lo = row_lo(L), hi = row_hi(L), ni = L.nx - 2;
   double acc = 0.0;
-  for (int idx = blockIdx.x * NT + threadIdx.x; idx < n; idx += gridDim.x * NT) {
-    const int r = idx / ni;
-    const int i = idx - r * ni + 1;
-    const int j = lo + r;
+  // workgroup per row (rows strided by gridDim.x), threads along the row;
+  // a Dirichlet boundary node reads as 0 whatever the caller stored there
+  for (int j = lo + blockIdx.x; j <= hi; j += gridDim.x) {
     const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
-    const T d = defect_masked(L, L.x, L.b, i, j, jm, jp);
-    if (rout) rout[(size_t)j * L.pitch + i] = d;
-    if (r32) r32[(size_t)j * p32 + i] = (float)d;
-    acc += (double)d * (double)d;
+    const bool sok = L.py || jm != 0, nok = L.py || jp != L.ny - 1;
+    const T* xm = L.x + (size_t)jm * L.pitch;
+    const T* x0 = L.x + (size_t)j * L.pitch;
+    const T* xp = L.x + (size_t)jp * L.pitch;
+    const T* b0 = L.b + (size_t)j * L.pitch;
+    for (int i0 = 1 + threadIdx.x; i0 <= ni; i0 += NT * RU) {
+      T d[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int i = i0 + u * NT;
+        d[u] = (T)0;
+        if (i > ni) continue;
+        const bool wok = i > 1, eok = i < ni;
+        Nbr<T> v{};
+        v.c = x0[i];
+        v.w = wok ? x0[i - 1] : (T)0;
+        v.e = eok ? x0[i + 1] : (T)0;
+        v.s = sok ? xm[i] : (T)0;
+        v.n = nok ? xp[i] : (T)0;
+        if (K == ST9) {
+          v.sw = sok && wok ? xm[i - 1] : (T)0;
+          v.se = sok && eok ? xm[i + 1] : (T)0;
+          v.nw = nok && wok ? xp[i - 1] : (T)0;
+          v.ne = nok && eok ? xp[i + 1] : (T)0;
+        }
+        d[u] = defect_v<K>(L, coefs<K>(L, i, j, jm), v, b0[i]);
+      }
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int i = i0 + u * NT;
+        if (i > ni) continue;
+        if (rout) rout[(size_t)j * L.pitch + i] = d[u];
+        if (r32) r32[(size_t)j * p32 + i] = (float)d[u];
+        acc += (double)d[u] * (double)d[u];
+      }
+    }
   }
   const double part = block_sum(acc, sh);
   if (threadIdx.x == 0) st->partial[blockIdx.x] = part;
@@ -756,6 +777,26 @@ __global__ void k_cholesky(double* A, int n, int* info) {
   if (tid == 0) info[0] = bad;
 }
 
+// Inverse of A = L L^T from its Cholesky factor (lower, row-major): one
+// thread per column c solves L y = e_c, L^T x = y and writes x as row c of
+// the (symmetric) inverse.  Setup only.
+__global__ void k_chol_inverse(const double* __restrict__ Lf, double* __restrict__ X, int n) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double* x = X + (size_t)c * n;
+  for (int k = 0; k < c; ++k) x[k] = 0.0;
+  for (int k = c; k < n; ++k) {
+    double s = k == c ? 1.0 : 0.0;
+    for (int j = c; j < k; ++j) s -= Lf[(size_t)k * n + j] * x[j];
+    x[k] = s / Lf[(size_t)k * n + k];
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double s = x[k];
+    for (int j = k + 1; j < n; ++j) s -= Lf[(size_t)j * n + k] * x[j];
+    x[k] = s / Lf[(size_t)k * n + k];
+  }
+}
+
 // Counts entries of v that are not finite or not > 0.
 __global__ void k_count_bad(const double* __restrict__ v, long n, int* count) {
   int bad = 0;
@@ -905,9 +946,10 @@ int norm_blocks(const LevelShape& s) {
 
 template <typename T>
 hipError_t launch_resnorm(const Level<T>* Ls, const LevelShape& s, int mode, T* rout, const Level<float>* R32s,
-                          int nslots, hipStream_t st) {
-  const int nb = norm_blocks(s);
-  hipLaunchKernelGGL(k_resnorm<T>, dim3(nb, 1, nslots), dim3(NT), 0, st, Ls, mode, rout, R32s);
+                          int kind, int nslots, hipStream_t st) {
+  const int nb = s.nrows < MAX_NORM_BLOCKS ? s.nrows : MAX_NORM_BLOCKS;
+  auto k = kind == ST5 ? k_resnorm<T, ST5> : k_resnorm<T, ST9>;
+  hipLaunchKernelGGL(k, dim3(nb, 1, nslots), dim3(NT), 0, st, Ls, mode, rout, R32s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_norm_finish<T>(Ls, nb, mode, nslots, st);
@@ -949,6 +991,11 @@ hipError_t launch_dense_coarse(double* A, int n, int nx, int ny, int py, int kin
 
 hipError_t launch_cholesky(double* A, int n, int* info, hipStream_t st) {
   hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, st, A, n, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_inverse(const double* Lf, double* X, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_chol_inverse, dim3((n + 63) / 64), dim3(64), 0, st, Lf, X, n);
   return hipGetLastError();
 }
 
@@ -1002,7 +1049,7 @@ hipError_t launch_coeff_grad(const double* u, const double* lam, double* g, int 
   template hipError_t launch_coarse<T>(const Level<T>*, const double* const*, int, int, hipStream_t);             \
   template hipError_t launch_subcycle<T>(const Level<T>*, int, const DOp*, const int*, const int*,                \
                                          const double* const*, int, T, int, int, hipStream_t);                     \
-  template hipError_t launch_resnorm<T>(const Level<T>*, const LevelShape&, int, T*, const Level<float>*, int,     \
+  template hipError_t launch_resnorm<T>(const Level<T>*, const LevelShape&, int, T*, const Level<float>*, int, int, \
                                         hipStream_t);                                                               \
   template hipError_t prepare_subcycle_lds<T>();                                                                   \
   template hipError_t launch_norm_finish<T>(const Level<T>*, int, int, int, hipStream_t);                          \
