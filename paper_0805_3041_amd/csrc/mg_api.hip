@@ -389,12 +389,13 @@ hipError_t enqueue_cycle(mg_handle h, const Group& G, hipStream_t st) {
     for (const HostOp& op : G.prog)
       if ((e = run_op<double>(h, G, op, G.dL64, G.dP64, h->opts.omega, st)) != hipSuccess) return e;
     if (G.norm_fused) return hipSuccess;
-    return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, nullptr, stencil_kind(h), G.ns, st);
+    return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, nullptr, stencil_kind(h), h->oned, G.ns,
+                                  st);
   }
   for (const HostOp& op : G.prog)
     if ((e = run_op<float>(h, G, op, G.dL32, G.dP32, (float)h->opts.omega, st)) != hipSuccess) return e;
   if (!G.mixed_fused && (e = launch_outer_update(G.dL64, G.dL32, G.shp[0], G.ns, st)) != hipSuccess) return e;
-  return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, G.dL32, stencil_kind(h), G.ns, st);
+  return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, G.dL32, stencil_kind(h), h->oned, G.ns, st);
 }
 
 // Captures one cycle and eight cycles as graphs on a private stream (a graph
@@ -790,7 +791,7 @@ mg_status begin_solve(mg_handle h, const double* const* rhs, double* const* x, d
   HIPCHK(h, hipEventRecord(h->ev0, st));
   for (Group& G : h->groups)
     HIPCHK(h, launch_resnorm<double>(G.dL64, G.shp[0], NORM_INIT, nullptr, h->mixed() ? G.dL32 : nullptr,
-                                     stencil_kind(h), G.ns, st));
+                                     stencil_kind(h), h->oned, G.ns, st));
   return MG_OK;
 }
 
@@ -1066,7 +1067,7 @@ mg_status mg_residual(mg_handle h, const double* rhs, const double* x, double* r
   HIPCHK(h, hipMemcpyAsync(h->dstate_res, &init, sizeof(SolveState), hipMemcpyHostToDevice, st));
   HIPCHK(h, hipMemcpyAsync(h->dLres, &L, sizeof(Level<double>), hipMemcpyHostToDevice, st));
   if (r) HIPCHK(h, hipMemsetAsync(r, 0, (size_t)s0.nx * s0.ny * sizeof(double), st));
-  HIPCHK(h, launch_resnorm<double>(h->dLres, s0, NORM_RESID, r, nullptr, stencil_kind(h), 1, st));
+  HIPCHK(h, launch_resnorm<double>(h->dLres, s0, NORM_RESID, r, nullptr, stencil_kind(h), h->oned, 1, st));
   SolveState cur{};
   HIPCHK(h, hipMemcpyAsync(&cur, h->dstate_res, sizeof(SolveState), hipMemcpyDeviceToHost, st));
   HIPCHK(h, hipStreamSynchronize(st));

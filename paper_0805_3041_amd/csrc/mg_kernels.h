@@ -39,7 +39,7 @@ hipError_t launch_subcycle(const Level<T>* levs, int nlev, const DOp* prog, cons
                            const double* const* chol, int ncu, T omega, int ncol, int nslots, hipStream_t st);
 template <typename T>
 hipError_t launch_resnorm(const Level<T>* Ls, const LevelShape& s, int mode, T* rout, const Level<float>* R32s,
-                          int kind, int nslots, hipStream_t st);
+                          int kind, bool oned, int nslots, hipStream_t st);
 
 template <typename T>
 hipError_t prepare_subcycle_lds();

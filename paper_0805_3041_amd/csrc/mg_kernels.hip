@@ -505,10 +505,10 @@ __global__ void __launch_bounds__(NT) k_norm_finish(const Level<T>* __restrict__
 // step, (float) r into the FP32 finest level's b of the same slot (R32s).
 // Writes one partial sum of squares per workgroup; k_norm_finish completes
 // the norm.
-template <typename T, int K>
+template <typename T, int K, bool B1>
 __global__ void __launch_bounds__(NT) k_resnorm(const Level<T>* __restrict__ Ls, int mode, T* __restrict__ rout,
-                                                const Level<float>* __restrict__ R32s) {
-  constexpr int RU = 4;  // nodes of a row per thread per round (loads issued together)
+                                                const Level<float>* __restrict__ R32s, int nbx, int rows_per_block) {
+  constexpr int RB = 4;  // rows whose loads a thread issues together
   __shared__ double sh[NT / 64];
   const Level<T> L = Ls[blockIdx.z];
   SolveState* st = L.st;
@@ -516,45 +516,64 @@ __global__ void __launch_bounds__(NT) k_resnorm(const Level<T>* __restrict__ Ls,
   float* r32 = R32s ? R32s[blockIdx.z].b : nullptr;
   const int p32 = R32s ? R32s[blockIdx.z].pitch : 0;
   const int lo = row_lo(L), hi = row_hi(L), ni = L.nx - 2;
+  // block = (column chunk, row group); thread = one column, marching up the
+  // group's rows with a 3x3 window of x in registers.  A Dirichlet boundary
+  // node reads as 0 whatever the caller stored there.
+  const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
+  const int i = 1 + bx * NT + threadIdx.x;
+  const bool act = i <= ni;
+  const int ic = act ? i : 1;  // in-range column for lanes past the row end (their results are dropped)
+  const bool wok = ic > 1, eok = ic < ni;
+  const int j0 = lo + by * rows_per_block, j1 = min(hi, j0 + rows_per_block - 1);
+  Cf<T> col{};
+  if (K == ST9 && B1) col = coefs<K>(L, ic, 0, 0);
+  auto load_row = [&](int r, T* w) {  // x at columns ic-1, ic, ic+1 of stored row r (wrapped)
+    const bool bnd = !L.py && (r == 0 || r == L.ny - 1);
+    const T* xr = L.x + (size_t)r * L.pitch;
+    w[0] = (!bnd && wok) ? xr[ic - 1] : (T)0;
+    w[1] = !bnd ? xr[ic] : (T)0;
+    w[2] = (!bnd && eok) ? xr[ic + 1] : (T)0;
+  };
   double acc = 0.0;
-  // workgroup per row (rows strided by gridDim.x), threads along the row;
-  // a Dirichlet boundary node reads as 0 whatever the caller stored there
-  for (int j = lo + blockIdx.x; j <= hi; j += gridDim.x) {
-    const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
-    const bool sok = L.py || jm != 0, nok = L.py || jp != L.ny - 1;
-    const T* xm = L.x + (size_t)jm * L.pitch;
-    const T* x0 = L.x + (size_t)j * L.pitch;
-    const T* xp = L.x + (size_t)jp * L.pitch;
-    const T* b0 = L.b + (size_t)j * L.pitch;
-    for (int i0 = 1 + threadIdx.x; i0 <= ni; i0 += NT * RU) {
-      T d[RU];
+  if (j0 <= j1) {
+    T ws[3], wc[3];
+    load_row(wrap_dn(j0, L.ny, L.py), ws);
+    load_row(j0, wc);
+    for (int j = j0; j <= j1; j += RB) {
+      T wn[RB][3], bp[RB];
 #pragma unroll
-      for (int u = 0; u < RU; ++u) {
-        const int i = i0 + u * NT;
-        d[u] = (T)0;
-        if (i > ni) continue;
-        const bool wok = i > 1, eok = i < ni;
-        Nbr<T> v{};
-        v.c = x0[i];
-        v.w = wok ? x0[i - 1] : (T)0;
-        v.e = eok ? x0[i + 1] : (T)0;
-        v.s = sok ? xm[i] : (T)0;
-        v.n = nok ? xp[i] : (T)0;
-        if (K == ST9) {
-          v.sw = sok && wok ? xm[i - 1] : (T)0;
-          v.se = sok && eok ? xm[i + 1] : (T)0;
-          v.nw = nok && wok ? xp[i - 1] : (T)0;
-          v.ne = nok && eok ? xp[i + 1] : (T)0;
-        }
-        d[u] = defect_v<K>(L, coefs<K>(L, i, j, jm), v, b0[i]);
+      for (int u = 0; u < RB; ++u) {
+        const int jj = j + u;
+        if (jj > j1) break;
+        load_row(wrap_up(jj, L.ny, L.py), wn[u]);
+        bp[u] = L.b[(size_t)jj * L.pitch + ic];
       }
 #pragma unroll
-      for (int u = 0; u < RU; ++u) {
-        const int i = i0 + u * NT;
-        if (i > ni) continue;
-        if (rout) rout[(size_t)j * L.pitch + i] = d[u];
-        if (r32) r32[(size_t)j * p32 + i] = (float)d[u];
-        acc += (double)d[u] * (double)d[u];
+      for (int u = 0; u < RB; ++u) {
+        const int jj = j + u;
+        if (jj > j1) break;
+        Nbr<T> v;
+        v.sw = ws[0];
+        v.s = ws[1];
+        v.se = ws[2];
+        v.w = wc[0];
+        v.c = wc[1];
+        v.e = wc[2];
+        v.nw = wn[u][0];
+        v.n = wn[u][1];
+        v.ne = wn[u][2];
+        const Cf<T> a = (K == ST9 && !B1) ? coefs<K>(L, ic, jj, wrap_dn(jj, L.ny, L.py)) : col;
+        const T d = defect_v<K>(L, a, v, bp[u]);
+        if (act) {
+          if (rout) rout[(size_t)jj * L.pitch + i] = d;
+          if (r32) r32[(size_t)jj * p32 + i] = (float)d;
+          acc += (double)d * (double)d;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          ws[c] = wc[c];
+          wc[c] = wn[u][c];
+        }
       }
     }
   }
@@ -946,10 +965,14 @@ int norm_blocks(const LevelShape& s) {
 
 template <typename T>
 hipError_t launch_resnorm(const Level<T>* Ls, const LevelShape& s, int mode, T* rout, const Level<float>* R32s,
-                          int kind, int nslots, hipStream_t st) {
-  const int nb = s.nrows < MAX_NORM_BLOCKS ? s.nrows : MAX_NORM_BLOCKS;
-  auto k = kind == ST5 ? k_resnorm<T, ST5> : k_resnorm<T, ST9>;
-  hipLaunchKernelGGL(k, dim3(nb, 1, nslots), dim3(NT), 0, st, Ls, mode, rout, R32s);
+                          int kind, bool oned, int nslots, hipStream_t st) {
+  const int nbx = (s.nx - 2 + NT - 1) / NT;
+  const int maxby = MAX_NORM_BLOCKS / nbx > 0 ? MAX_NORM_BLOCKS / nbx : 1;
+  const int rpb = (s.nrows + maxby - 1) / maxby;
+  const int nb = nbx * ((s.nrows + rpb - 1) / rpb);
+  if (nb > MAX_NORM_BLOCKS) return hipErrorInvalidValue;
+  auto k = kind == ST5 ? k_resnorm<T, ST5, false> : (oned ? k_resnorm<T, ST9, true> : k_resnorm<T, ST9, false>);
+  hipLaunchKernelGGL(k, dim3(nb, 1, nslots), dim3(NT), 0, st, Ls, mode, rout, R32s, nbx, rpb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_norm_finish<T>(Ls, nb, mode, nslots, st);
@@ -1049,8 +1072,8 @@ hipError_t launch_coeff_grad(const double* u, const double* lam, double* g, int 
   template hipError_t launch_coarse<T>(const Level<T>*, const double* const*, int, int, hipStream_t);             \
   template hipError_t launch_subcycle<T>(const Level<T>*, int, const DOp*, const int*, const int*,                \
                                          const double* const*, int, T, int, int, hipStream_t);                     \
-  template hipError_t launch_resnorm<T>(const Level<T>*, const LevelShape&, int, T*, const Level<float>*, int, int, \
-                                        hipStream_t);                                                               \
+  template hipError_t launch_resnorm<T>(const Level<T>*, const LevelShape&, int, T*, const Level<float>*, int, bool, \
+                                        int, hipStream_t);                                                          \
   template hipError_t prepare_subcycle_lds<T>();                                                                   \
   template hipError_t launch_norm_finish<T>(const Level<T>*, int, int, int, hipStream_t);                          \
   template hipError_t launch_subcycle_lds<T>(const Level<T>*, int, int, const DOp*, const int*, const int*,        \
