@@ -160,9 +160,10 @@ int stencil_kind(mg_handle h) { return h->kind == MG_COEF_CONST5 ? ST5 : ST9; }
 size_t sub_footprint(mg_handle h, const Group& G, int l) {
   const size_t elem = h->mixed() ? sizeof(float) : sizeof(double);
   const size_t narr = h->ncol == 0 ? 3 : 2;
+  const bool bands = stencil_kind(h) == ST9 && h->oned;  // 1-D bands staged in LDS too
   size_t n = 0;
-  for (int k = l; k < G.nlev; ++k) n += (size_t)G.shp[k].nx * G.shp[k].ny;
-  return n * narr * elem;
+  for (int k = l; k < G.nlev; ++k) n += (size_t)G.shp[k].nx * G.shp[k].ny * narr + (bands ? NBANDS * G.shp[k].nx : 0);
+  return n * elem;
 }
 
 struct Gen {
@@ -375,7 +376,7 @@ hipError_t run_op(mg_handle h, const Group& G, const HostOp& op, Level<T>* dL, L
       const int* cnt = G.dcnt + (size_t)op.sub * ns;
       if (bytes <= SUB_LDS_BUDGET)
         return launch_subcycle_lds<T>(dP, G.nlev, l, G.dprog, beg, cnt, G.dcholp, G.ncu, omega, h->ncol,
-                                      h->ncol == 0 ? 3 : 2, stencil_kind(h), bytes, ns, st);
+                                      h->ncol == 0 ? 3 : 2, stencil_kind(h), h->oned, bytes, ns, st);
       return launch_subcycle<T>(dP, G.nlev, G.dprog, beg, cnt, G.dcholp, G.ncu, omega, h->ncol, ns, st);
     }
   }

@@ -46,7 +46,7 @@ hipError_t prepare_subcycle_lds();
 template <typename T>
 hipError_t launch_subcycle_lds(const Level<T>* levs, int nlev, int top, const DOp* prog, const int* beg,
                                const int* cnt, const double* const* chol, int ncu, T omega, int ncol, int narr,
-                               int kind, size_t lds_bytes, int nslots, hipStream_t st);
+                               int kind, bool oned, size_t lds_bytes, int nslots, hipStream_t st);
 
 template <typename T>
 hipError_t launch_norm_finish(const Level<T>* Ls, int nblocks, int mode, int nslots, hipStream_t st);

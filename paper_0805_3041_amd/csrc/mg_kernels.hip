@@ -192,8 +192,34 @@ __device__ __forceinline__ LX3<T> lgx(const MG_LDS T* x, int nx, int i, int j, i
   return LX3<T>{x + jm * nx + i, x + j * nx + i, x + jp * nx + i};
 }
 
-template <typename T, int K>
-__device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, int c, int ncol, int tid) {
+// Coefficients of node (i, j) on an LDS-resident level: B1 (9-point bands
+// that vary along x only) from the level's LDS copy of its bands (band k at
+// bl + k nx, the same values as coefs()), otherwise coefs().
+template <typename T, int K, bool B1>
+__device__ __forceinline__ Cf<T> sub_coefs(const Level<T>& L, const MG_LDS T* bl, int i, int j, int jm) {
+  if constexpr (K == ST9 && B1) {
+    const int nx = L.nx;
+    const MG_LDS T* p = bl + i;
+    Cf<T> c;
+    c.C = p[0];
+    c.Ep = p[nx];
+    c.Ew = p[nx - 1];
+    c.Np = p[2 * nx];
+    c.Ns = c.Np;
+    c.NEp = p[3 * nx];
+    c.NEsw = p[3 * nx - 1];
+    c.NWp = p[4 * nx];
+    c.NWse = p[4 * nx + 1];
+    c.D = p[BAND_D * nx];
+    return c;
+  } else {
+    return coefs<K>(L, i, j, jm);
+  }
+}
+
+template <typename T, int K, bool B1>
+__device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int c, int ncol,
+                           int tid) {
   constexpr int NB = nbatch(K);
   const int nx = L.nx, ny = L.ny, py = L.py;
   const int lo = py ? 0 : 1, hi = py ? ny - 1 : ny - 2;
@@ -230,7 +256,7 @@ __device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, in
       if (!ok[u]) continue;
       v[u] = gather<K>(L, lgx(x, nx, ii[u], jj[u], jms[u], wrap_up(jj[u], ny, py)), false);
       bp[u] = b[pos[u]];
-      a[u] = coefs<K>(L, ii[u], jj[u], jms[u]);
+      a[u] = sub_coefs<T, K, B1>(L, bl, ii[u], jj[u], jms[u]);
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u)
@@ -238,9 +264,9 @@ __device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, in
   }
 }
 
-template <typename T, int K>
-__device__ void lds_jacobi(const Level<T>& L, const MG_LDS T* src, MG_LDS T* dst, const MG_LDS T* b, T omega,
-                           int tid) {
+template <typename T, int K, bool B1>
+__device__ void lds_jacobi(const Level<T>& L, const MG_LDS T* src, MG_LDS T* dst, const MG_LDS T* b,
+                           const MG_LDS T* bl, T omega, int tid) {
   constexpr int NB = nbatch(K);
   const int nx = L.nx, ny = L.ny, py = L.py;
   const int lo = py ? 0 : 1, hi = py ? ny - 1 : ny - 2;
@@ -259,7 +285,7 @@ __device__ void lds_jacobi(const Level<T>& L, const MG_LDS T* src, MG_LDS T* dst
       const int jm = wrap_dn(ju, ny, py);
       v[u] = gather<K>(L, lgx(src, nx, i, ju, jm, wrap_up(ju, ny, py)), true);
       bp[u] = b[ju * nx + i];
-      a[u] = coefs<K>(L, i, ju, jm);
+      a[u] = sub_coefs<T, K, B1>(L, bl, i, ju, jm);
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
@@ -279,9 +305,9 @@ __device__ void lds_copy(const Level<T>& L, MG_LDS T* x, const MG_LDS T* t, int 
   for (int j = lo + (tid >> kl); j <= hi; j += SUB_NT >> kl) x[j * nx + i] = t[j * nx + i];
 }
 
-template <typename T, int K>
-__device__ void lds_dr(const Level<T>& F, const MG_LDS T* xf, const MG_LDS T* bf, const Level<T>& C, MG_LDS T* xc,
-                       MG_LDS T* bc, int tid) {
+template <typename T, int K, bool B1>
+__device__ void lds_dr(const Level<T>& F, const MG_LDS T* xf, const MG_LDS T* bf, const MG_LDS T* bl,
+                       const Level<T>& C, MG_LDS T* xc, MG_LDS T* bc, int tid) {
   const int nx = F.nx, ny = F.ny, py = F.py;
   const int lo = C.py ? 0 : 1, hi = C.py ? C.ny - 1 : C.ny - 2;
   const int kl = ceil_log2(C.nx - 2);
@@ -296,9 +322,12 @@ __device__ void lds_dr(const Level<T>& F, const MG_LDS T* xf, const MG_LDS T* bf
       const int j = rows[r];
       const int jm = wrap_dn(j, ny, py), jp = wrap_up(j, ny, py);
       const int q = j * nx;
-      const T dw = defect_val<K>(F, lgx(xf, nx, i0 - 1, j, jm, jp), bf[q + i0 - 1], i0 - 1, j, jm);
-      const T dc = defect_val<K>(F, lgx(xf, nx, i0, j, jm, jp), bf[q + i0], i0, j, jm);
-      const T de = defect_val<K>(F, lgx(xf, nx, i0 + 1, j, jm, jp), bf[q + i0 + 1], i0 + 1, j, jm);
+      const T dw = defect_v<K>(F, sub_coefs<T, K, B1>(F, bl, i0 - 1, j, jm),
+                               gather<K>(F, lgx(xf, nx, i0 - 1, j, jm, jp), true), bf[q + i0 - 1]);
+      const T dc = defect_v<K>(F, sub_coefs<T, K, B1>(F, bl, i0, j, jm), gather<K>(F, lgx(xf, nx, i0, j, jm, jp), true),
+                               bf[q + i0]);
+      const T de = defect_v<K>(F, sub_coefs<T, K, B1>(F, bl, i0 + 1, j, jm),
+                               gather<K>(F, lgx(xf, nx, i0 + 1, j, jm, jp), true), bf[q + i0 + 1]);
       acc[r] = fw_row(dw, dc, de);
     }
     const int pc = J * C.nx + I;
@@ -341,7 +370,7 @@ __device__ void lds_prolong(const Level<T>& F, MG_LDS T* xf, const Level<T>& C, 
 // (9-point operators) are read from global memory.
 __device__ __forceinline__ int pack_op(const DOp& o) { return o.type | (o.level << 4) | (o.arg << 12); }
 
-template <typename T, bool IN_LDS, int K>
+template <typename T, bool IN_LDS, int K, bool B1 = false>
 __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict__ levs, int nlev, int top,
                                                      const DOp* __restrict__ prog, const int* __restrict__ beg,
                                                      const int* __restrict__ cnt,
@@ -350,6 +379,7 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
   extern __shared__ __align__(16) unsigned char smem_raw[];
   MG_LDS T* lds = lds_cast<T>(smem_raw);
   __shared__ int offs[MAX_LEVELS + 1];
+  __shared__ int boffs[MAX_LEVELS];  // B1: LDS offset of each level's bands
   __shared__ int sops[MAX_SUB_OPS];
   const int slot = blockIdx.z;
   const Level<T>* Ls = levs + (size_t)slot * nlev;
@@ -366,11 +396,25 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
       o += narr * Ls[l].nx * Ls[l].ny;
     }
     offs[nlev] = o;
+    if (B1)
+      for (int l = top; l < nlev; ++l) {
+        boffs[l] = o;
+        o += NBANDS * Ls[l].nx;
+      }
   }
   __syncthreads();
   if (IN_LDS) {
     const int total = offs[nlev];
     for (int k = tid; k < total; k += SUB_NT) lds[k] = (T)0;
+    if (B1)
+      for (int l = top; l < nlev; ++l) {
+        const Level<T>& Lb = Ls[l];
+        MG_LDS T* dst = lds + boffs[l];
+        for (int k = tid; k < NBANDS * Lb.nx; k += SUB_NT) {
+          const int band = k / Lb.nx, i = k - band * Lb.nx;
+          dst[k] = bandp(Lb, band)[i];
+        }
+      }
     __syncthreads();
     const Level<T> G = Ls[top];
     const int lo = row_lo(G), nr = row_hi(G) - lo + 1, ni = G.nx - 2, n = nr * ni;
@@ -410,16 +454,19 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
       MG_LDS T* xl = lds + offs[l];
       MG_LDS T* bl = xl + L.nx * L.ny;
       MG_LDS T* tl = bl + L.nx * L.ny;
+      const MG_LDS T* bands = B1 ? lds + boffs[l] : nullptr;
       switch (type) {
-        case OP_COLOR: lds_colour<T, K>(L, xl, bl, arg, ncol, tid); break;
-        case OP_JACOBI: lds_jacobi<T, K>(L, arg == 0 ? xl : tl, arg == 0 ? tl : xl, bl, omega, tid); break;
+        case OP_COLOR: lds_colour<T, K, B1>(L, xl, bl, bands, arg, ncol, tid); break;
+        case OP_JACOBI:
+          lds_jacobi<T, K, B1>(L, arg == 0 ? xl : tl, arg == 0 ? tl : xl, bl, bands, omega, tid);
+          break;
         case OP_COPY: lds_copy(L, xl, tl, tid); break;
         case OP_DR:
         case OP_PROLONG: {
           const Level<T> C = Ls[l + 1];
           MG_LDS T* xc = lds + offs[l + 1];
           if (type == OP_DR)
-            lds_dr<T, K>(L, xl, bl, C, xc, xc + C.nx * C.ny, tid);
+            lds_dr<T, K, B1>(L, xl, bl, bands, C, xc, xc + C.nx * C.ny, tid);
           else
             lds_prolong(L, xl, C, xc, tid);
           break;
@@ -932,18 +979,21 @@ hipError_t launch_subcycle(const Level<T>* levs, int nlev, const DOp* prog, cons
 
 template <typename T>
 hipError_t prepare_subcycle_lds() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_subcycle<T, true, ST5>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)SUB_LDS_BUDGET);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_subcycle<T, true, ST9>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)SUB_LDS_BUDGET);
+  const void* ks[3] = {(const void*)k_subcycle<T, true, ST5>, (const void*)k_subcycle<T, true, ST9>,
+                       (const void*)k_subcycle<T, true, ST9, true>};
+  for (const void* k : ks) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)SUB_LDS_BUDGET);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <typename T>
 hipError_t launch_subcycle_lds(const Level<T>* levs, int nlev, int top, const DOp* prog, const int* beg,
                                const int* cnt, const double* const* chol, int ncu, T omega, int ncol, int narr,
-                               int kind, size_t lds_bytes, int nslots, hipStream_t st) {
-  auto k = kind == ST5 ? k_subcycle<T, true, ST5> : k_subcycle<T, true, ST9>;
+                               int kind, bool oned, size_t lds_bytes, int nslots, hipStream_t st) {
+  auto k = kind == ST5 ? k_subcycle<T, true, ST5>
+                       : (oned ? k_subcycle<T, true, ST9, true> : k_subcycle<T, true, ST9, false>);
   hipLaunchKernelGGL(k, dim3(1, 1, nslots), dim3(SUB_NT), lds_bytes, st, levs, nlev, top, prog, beg, cnt, chol, ncu,
                      omega, ncol, narr);
   return hipGetLastError();
@@ -1077,7 +1127,8 @@ hipError_t launch_coeff_grad(const double* u, const double* lam, double* g, int 
   template hipError_t prepare_subcycle_lds<T>();                                                                   \
   template hipError_t launch_norm_finish<T>(const Level<T>*, int, int, int, hipStream_t);                          \
   template hipError_t launch_subcycle_lds<T>(const Level<T>*, int, int, const DOp*, const int*, const int*,        \
-                                             const double* const*, int, T, int, int, int, size_t, int, hipStream_t);
+                                             const double* const*, int, T, int, int, int, bool, size_t, int,      \
+                                             hipStream_t);
 
 MG_INSTANTIATE(double)
 MG_INSTANTIATE(float)
