@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="aniso1025", choices=["aniso1025", "annulus4097"])
+    ap.add_argument("--workload", default="aniso1025", choices=["aniso1025", "annulus4097", "batch256", "grf2049"])
     ap.add_argument("--nu", type=int, default=2)
     ap.add_argument("--x0", default="zero", choices=["zero", "uniform"])
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
@@ -350,6 +350,208 @@ def cpu_baseline_annulus(cycles, nu, seconds, unknowns_full):
             "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
 
 
+def _roofline_single(n, eps, head, nu):
+    """Roofline of the finest-level fused pass of one n x n 5-point problem
+    (the kernels every batched group runs, one problem slot per launch)."""
+    import torch
+
+    import workloads as W
+    from paper_0805_3041_amd import mg
+
+    s = mg.Solver(n, n, eps_x=eps, smoother="rbgs", nu_pre=nu, nu_post=nu, precision=head)
+    rhs = torch.tensor(W.aniso_rhs(n, 2), device="cuda")
+    scratch = torch.zeros_like(rhs)
+    times = {which: s.profile_pass(rhs, scratch, 0, which, reps=50) for which in (0, 1)}
+    dom = 1 if times[1] >= times[0] else 0
+    kernel = s.pass_kernel_name(0, dom)
+    s.close()
+    alg = BYTES_PER_NODE[(head, dom)] * n * n
+    ach = alg / (times[dom] * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": None, "kernel": kernel, "avg_us": times[dom], "bytes_per_launch": alg,
+            "bytes_per_node": BYTES_PER_NODE[(head, dom)], "nodes": n * n, "other_pass_us": times[1 - dom],
+            "note": f"one {n}x{n} problem of the batch"}
+
+
+def batch256(args):
+    """Workload batch256: 256 independent 5-point problems, n drawn uniformly
+    from {129, 257, 513, 1025} and eps = 10^U(-3, 0) (seed 4), rhs_i = N(0, 1)
+    (seed 1000 + i), x0 = 0, red-black GS 2/2, F-cycles until every problem
+    reaches 1e-10 (converged problems are masked out of later cycles)."""
+    import torch
+
+    import workloads as W
+    from paper_0805_3041_amd import mg
+
+    ns, eps = W.batch_problems(256, 4)
+    rhs = [torch.tensor(W.batch_rhs(n, i), device="cuda") for i, n in enumerate(ns)]
+    unknowns = sum((n - 2) ** 2 for n in ns)
+
+    def run(B, steps, warmup):
+        xs = [torch.zeros_like(r) for r in rhs]
+        for _ in range(warmup):
+            for x in xs:
+                x.zero_()
+            B.solve(rhs, xs, TOL, args.max_cycles)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = None
+        for _ in range(steps):
+            for x in xs:
+                x.zero_()
+            _, infos = B.solve(rhs, xs, TOL, args.max_cycles)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, infos
+
+    head = args.precision
+    other = "fp64" if head == "mixed" else "mixed"
+    B = mg.BatchedSolver([(n, n) for n in ns], eps, smoother="rbgs", nu_pre=args.nu, nu_post=args.nu, precision=head)
+    wall_h, infos_h = run(B, args.steps, args.warmup)
+    B.close()
+    bad = [i for i, info in enumerate(infos_h) if info.status != mg.MG_OK]
+    if bad:
+        raise SystemExit(f"{len(bad)} batched problems did not converge (first: {bad[0]})")
+    B = mg.BatchedSolver([(n, n) for n in ns], eps, smoother="rbgs", nu_pre=args.nu, nu_post=args.nu,
+                         precision=other)
+    steps_o = max(1, args.steps // 2)
+    wall_o, infos_o = run(B, steps_o, 1)
+    B.close()
+    cycles = [info.cycles for info in infos_h]
+    out = {
+        "metric": "unknowns/s to 1e-10 rel. residual",
+        "value": unknowns * args.steps / wall_h,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall_h / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-inner/f64-outer" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "batch256: 256 problems -(eps u_xx + u_yy) = N(0,1), n in {129,257,513,1025} "
+                               f"drawn uniformly, eps = 10^U(-3,0) (seed 4), {unknowns} unknowns, red-black GS "
+                               f"{args.nu}/{args.nu}, F-cycle, x0=0, tol 1e-10", "precision": head},
+        "roofline": _roofline_single(1025, 1e-3, head, args.nu),
+        "cycles": {"min": min(cycles), "max": max(cycles), "sum": sum(cycles)},
+        f"value_{other}": unknowns * steps_o / wall_o,
+        "speedup_mixed_over_fp64": ((wall_o / steps_o) / (wall_h / args.steps)) if head == "mixed"
+        else ((wall_h / args.steps) / (wall_o / steps_o)),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(ns, eps, cycles, args.nu, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batch(ns, eps, cycles, nu, seconds):
+    """Oracle F-cycles on a 257 x 257 problem of the batch for about
+    `seconds`; its cost per unknown-cycle times sum_i unknowns_i * cycles_i."""
+    import numpy as np
+
+    from oracle import mg_oracle as O
+    import workloads as W
+
+    n = 257
+    g = O.Grid(n, n)
+    h = O.hierarchy_5pt(g, 1e-2, 1.0, O.Options(smoother="rbgs", nu_pre=nu, nu_post=nu))
+    b = g.pack(W.batch_rhs(n, 0))
+    x = np.zeros(g.n_unknowns)
+    done = 0
+    t0 = time.perf_counter()
+    while done < 2 or time.perf_counter() - t0 < seconds:
+        x = O.mg_cycle(h, 0, x, b, "F")
+        done += 1
+    t = (time.perf_counter() - t0) / done
+    per = t / g.n_unknowns
+    work = sum((m - 2) ** 2 * c for m, c in zip(ns, cycles))
+    unknowns = sum((m - 2) ** 2 for m in ns)
+    return {"value": unknowns / (per * work), "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} FP64 F-cycles of a 257x257 problem ({t:.3f} s per cycle), scaled linearly to the "
+                      f"batch's unknowns times each problem's cycle count",
+            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
+
+
+def grf2049(args):
+    """Workload grf2049: -div(a grad u) = f on 2049^2 nodes (2048^2 cells),
+    a = exp(g), g a Gaussian random field (squared-exponential covariance,
+    length 0.1, sigma 1, seed 5), f = 2 pi^2 sin(pi x) sin(pi y), loss
+    0.5 ||u - u*||^2; one step = forward solve + adjoint solve + dL/da, dL/df
+    (FP64, four-colour GS 2/2, both solves to 1e-10)."""
+    import torch
+
+    import workloads as W
+    from paper_0805_3041_amd import autograd as AG
+
+    n = 2049
+    a, f, ustar = W.grf_problem(n, 5)
+    at = torch.tensor(a, device="cuda")
+    ft = torch.tensor(f, device="cuda")
+    us = torch.tensor(ustar, device="cuda")
+    unknowns = (n - 2) ** 2
+
+    def step():
+        aa = at.clone().requires_grad_(True)
+        ff = ft.clone().requires_grad_(True)
+        u = AG.solve(aa, ff, tol=TOL, max_cycles=args.max_cycles)
+        loss = 0.5 * torch.sum((u - us) ** 2)
+        loss.backward()
+        return aa.grad, ff.grad
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        da, df = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {
+        "metric": "unknowns/s to 1e-10 rel. residual (forward + adjoint gradient)",
+        "value": unknowns * args.steps / wall,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "grf2049: -div(a grad u) = 2 pi^2 sin(pi x) sin(pi y) on 2049^2 nodes, a = exp(GRF, "
+                               "length 0.1, sigma 1, seed 5) per cell, Q1, four-colour GS 2/2, F-cycle; forward + "
+                               "adjoint solve to 1e-10 and dL/da, dL/df of 0.5 ||u - u*||^2", "precision": "fp64"},
+        "grad_norms": {"dL_da": float(torch.linalg.vector_norm(da)), "dL_df": float(torch.linalg.vector_norm(df))},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_grf(unknowns, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_grf(unknowns_full, seconds):
+    """The oracle's gradient (direct sparse forward and adjoint solves plus
+    dL/da) on the 129 x 129 version of the problem, repeated for about
+    `seconds`, scaled linearly in unknowns (direct solves grow faster than
+    linearly, so this overstates the CPU rate at full size)."""
+    from oracle import mg_oracle as O
+    import workloads as W
+
+    n = 129
+    a, f, ustar = W.grf_problem(n, 5)
+    g = O.Grid(n, n)
+    done = 0
+    t0 = time.perf_counter()
+    while done < 1 or time.perf_counter() - t0 < seconds:
+        O.adjoint_gradient(g, a, f, ustar)
+        done += 1
+    t = (time.perf_counter() - t0) / done
+    return {"value": g.n_unknowns / t, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} oracle gradients (direct forward + adjoint solves, dL/da) at 129x129 ({t:.2f} s "
+                      f"each), rate per unknown applied unchanged to {unknowns_full} unknowns",
+            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
+
+
 def main():
     args = parse()
     if args.stats_summary:
@@ -364,6 +566,10 @@ def main():
         sys.exit(2)
     if args.workload == "annulus4097":
         return annulus(args)
+    if args.workload == "batch256":
+        return batch256(args)
+    if args.workload == "grf2049":
+        return grf2049(args)
     import numpy as np
     import torch
 
