@@ -217,6 +217,26 @@ __device__ __forceinline__ Cf<T> sub_coefs(const Level<T>& L, const MG_LDS T* bl
   }
 }
 
+// LDS level array around the node at p: rows below and above at offsets
+// so (-nx, or +(ny-1) nx across a periodic seam) and no (+nx, or -(ny-1) nx).
+template <typename T>
+struct LXO {
+  const MG_LDS T* p;
+  int so, no;
+  __device__ __forceinline__ T at(int di, int dj) const { return p[(dj < 0 ? so : (dj > 0 ? no : 0)) + di]; }
+};
+
+// Offsets of the rows below and above row j of an LDS level (periodic seam).
+__device__ __forceinline__ void row_offsets(int j, int nx, int ny, int py, int& so, int& no) {
+  so = (py && j == 0) ? (ny - 1) * nx : -nx;
+  no = (py && j == ny - 1) ? -(ny - 1) * nx : nx;
+}
+
+// Gauss-Seidel update of colour c.  Thread -> (column slot k, row group);
+// a thread's column is fixed for the op (row groups step by an even number
+// of rows, so the colour's column offset is the same on all its rows), its
+// rows advance by a uniform stride, and coefficients that depend on the
+// column only are read once.
 template <typename T, int K, bool B1>
 __device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int c, int ncol,
                            int tid) {
@@ -225,42 +245,42 @@ __device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, co
   const int lo = py ? 0 : 1, hi = py ? ny - 1 : ny - 2;
   const int kl = ceil_log2((nx - 1) >> 1);
   const int k = tid & ((1 << kl) - 1);
-  const int rg = SUB_NT >> kl;
-  int j = lo + (tid >> kl), jstep = rg;
-  int first_fixed = -1;
+  const int rg = SUB_NT >> kl;  // even: kl <= 9 for every LDS level
+  int j, jstep, first;
   if (ncol == 4) {
     const int j0 = lo + (((lo & 1) != (c >> 1)) ? 1 : 0);
     j = j0 + 2 * (tid >> kl);
     jstep = 2 * rg;
-    first_fixed = (c & 1) ? 1 : 2;
+    first = (c & 1) ? 1 : 2;
+  } else {
+    j = lo + (tid >> kl);
+    jstep = rg;
+    first = 1 + ((((1 + j) & 1) != c) ? 1 : 0);
   }
-  for (; j <= hi; j += NB * jstep) {
-    int pos[NB], ii[NB], jj[NB], jms[NB];
-    bool ok[NB];
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int ju = j + u * jstep;
-      const int first = first_fixed > 0 ? first_fixed : 1 + ((((1 + ju) & 1) != c) ? 1 : 0);
-      const int i = first + 2 * k;
-      ok[u] = ju <= hi && i <= nx - 2;
-      ii[u] = i;
-      jj[u] = ju;
-      jms[u] = wrap_dn(ju, ny, py);
-      pos[u] = ju * nx + i;
-    }
+  const int i = first + 2 * k;
+  if (i > nx - 2) return;
+  const bool col_only = K == ST5 || B1;
+  Cf<T> col{};
+  if (col_only) col = sub_coefs<T, K, B1>(L, bl, i, 0, 0);
+  const int dpos = jstep * nx;
+  int pos = j * nx + i;
+  for (; j <= hi; j += NB * jstep, pos += NB * dpos) {
     Nbr<T> v[NB];
     Cf<T> a[NB];
     T bp[NB];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      if (!ok[u]) continue;
-      v[u] = gather<K>(L, lgx(x, nx, ii[u], jj[u], jms[u], wrap_up(jj[u], ny, py)), false);
-      bp[u] = b[pos[u]];
-      a[u] = sub_coefs<T, K, B1>(L, bl, ii[u], jj[u], jms[u]);
+      const int ju = j + u * jstep;
+      if (ju > hi) continue;
+      int so, no;
+      row_offsets(ju, nx, ny, py, so, no);
+      v[u] = gather<K>(L, LXO<T>{x + pos + u * dpos, so, no}, false);
+      bp[u] = b[pos + u * dpos];
+      a[u] = col_only ? col : sub_coefs<T, K, B1>(L, bl, i, ju, wrap_dn(ju, ny, py));
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u)
-      if (ok[u]) x[pos[u]] = gs_v<K>(L, a[u], v[u], bp[u]);
+      if (j + u * jstep <= hi) x[pos + u * dpos] = gs_v<K>(L, a[u], v[u], bp[u]);
   }
 }
 
@@ -273,8 +293,12 @@ __device__ void lds_jacobi(const Level<T>& L, const MG_LDS T* src, MG_LDS T* dst
   const int kl = ceil_log2(nx - 2);
   const int i = 1 + (tid & ((1 << kl) - 1));
   if (i > nx - 2) return;
-  const int jstep = SUB_NT >> kl;
-  for (int j = lo + (tid >> kl); j <= hi; j += NB * jstep) {
+  const bool col_only = K == ST5 || B1;
+  Cf<T> col{};
+  if (col_only) col = sub_coefs<T, K, B1>(L, bl, i, 0, 0);
+  const int jstep = SUB_NT >> kl, dpos = jstep * nx;
+  int j = lo + (tid >> kl), pos = j * nx + i;
+  for (; j <= hi; j += NB * jstep, pos += NB * dpos) {
     Nbr<T> v[NB];
     Cf<T> a[NB];
     T bp[NB];
@@ -282,16 +306,15 @@ __device__ void lds_jacobi(const Level<T>& L, const MG_LDS T* src, MG_LDS T* dst
     for (int u = 0; u < NB; ++u) {
       const int ju = j + u * jstep;
       if (ju > hi) continue;
-      const int jm = wrap_dn(ju, ny, py);
-      v[u] = gather<K>(L, lgx(src, nx, i, ju, jm, wrap_up(ju, ny, py)), true);
-      bp[u] = b[ju * nx + i];
-      a[u] = sub_coefs<T, K, B1>(L, bl, i, ju, jm);
+      int so, no;
+      row_offsets(ju, nx, ny, py, so, no);
+      v[u] = gather<K>(L, LXO<T>{src + pos + u * dpos, so, no}, true);
+      bp[u] = b[pos + u * dpos];
+      a[u] = col_only ? col : sub_coefs<T, K, B1>(L, bl, i, ju, wrap_dn(ju, ny, py));
     }
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int ju = j + u * jstep;
-      if (ju <= hi) dst[ju * nx + i] = jac_v<K>(L, a[u], v[u], bp[u], omega);
-    }
+    for (int u = 0; u < NB; ++u)
+      if (j + u * jstep <= hi) dst[pos + u * dpos] = jac_v<K>(L, a[u], v[u], bp[u], omega);
   }
 }
 
