@@ -278,10 +278,13 @@ TileGeom choose_tile(mg_handle h, const Group& G, int l, int H, bool post) {
       return n * elem;
     };
     const bool force = mode == MG_TILES_WIDE;
-    int TYw = h->opts.tile_y > 0 ? h->opts.tile_y : 32;
+    // FP32: up to 32 rows within WIDE_LDS_TARGET (two workgroups per CU);
+    // FP64: up to 40 rows in one workgroup's LDS (taller tiles, less halo,
+    // measured faster than two shorter tiles per CU)
+    const size_t cap = elem == sizeof(float) ? WIDE_LDS_TARGET : FUSED_LDS_MAX;
+    int TYw = h->opts.tile_y > 0 ? h->opts.tile_y : (elem == sizeof(float) ? 32 : 40);
     if (h->opts.tile_y == 0)
-      while (TYw > (force ? 2 : 16) && ((!force && ntiles(TXw, TYw) < 256) || wbytes(TYw) > WIDE_LDS_TARGET))
-        TYw -= 2;
+      while (TYw > (force ? 2 : 16) && ((!force && ntiles(TXw, TYw) < 256) || wbytes(TYw) > cap)) TYw -= 2;
     if ((force || ntiles(TXw, TYw) >= 256) && wbytes(TYw) <= FUSED_LDS_MAX) return wide_geom(s.nx, s.ny, TYw, H);
   }
   if (!fixed) {
