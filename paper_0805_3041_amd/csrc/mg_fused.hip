@@ -320,7 +320,9 @@ __global__ void __launch_bounds__(FT) k_pre(const Level<T>* __restrict__ Fs, con
                                             int TY, int H, int ntx, int nty, int nsteps, T omega) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Level<T> F = Fs[blockIdx.z];
-  if (F.st->done) return;
+  // the solve-finished flag is read now and tested once the region's loads
+  // are in flight (a finished problem's kernels store nothing)
+  const int done = F.st->done;
   const Level<T> C = Cs[blockIdx.z];
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
@@ -360,6 +362,7 @@ __global__ void __launch_bounds__(FT) k_pre(const Level<T>* __restrict__ Fs, con
     }
   }
   __syncthreads();
+  if (done) return;
 
   MG_LDS T* xs;
   if (tile_edge<T, K, B1>(F, m, W, R))
@@ -414,7 +417,7 @@ __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, co
   __shared__ double sh[FT / 64];
   const Level<T> F = Fs[blockIdx.z];
   SolveState* st = F.st;
-  if (st->done) return;
+  const int done = st->done;  // tested once the region's loads are in flight
   const Level<T> C = Cs[blockIdx.z];
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
@@ -492,6 +495,7 @@ __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, co
     }
   }
   __syncthreads();
+  if (done) return;
 
   MG_LDS T* xs;
   if (tile_edge<T, K, B1>(F, m, W, R))
@@ -779,7 +783,7 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
   constexpr int P = wide_narr<NCOL>() * WW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Level<T> F = Fs[blockIdx.z];
-  if (F.st->done) return;
+  const int done = F.st->done;  // tested once the region's loads are in flight
   const Level<T> C = Cs[blockIdx.z];
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
@@ -830,6 +834,7 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
     }
   }
   __syncthreads();
+  if (done) return;
 
   const int xsrc = wsmooth<T, K, NCOL, B1>(F, m, lds, bl, R, nsteps, omega);
   if (xsrc == 0)
@@ -904,7 +909,7 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
   __shared__ double sh[FT / 64];
   const Level<T> F = Fs[blockIdx.z];
   SolveState* st = F.st;
-  if (st->done) return;
+  const int done = st->done;  // tested once the region's loads are in flight
   const Level<T> C = Cs[blockIdx.z];
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
@@ -999,6 +1004,7 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
     }
   }
   __syncthreads();
+  if (done) return;
 
   const int xsrc = wsmooth<T, K, NCOL, B1>(F, m, lds, bl, R, nsteps, omega);
 
