@@ -189,6 +189,34 @@ BYTES_PER_NODE = {
     ("mixed", 0): 4 + 4 + 4 + 1 + 1,
     ("mixed", 1): 4 + 4 + 1 + 8 + 8 + 4,
 }
+# Level 1 (a coarse level: plain post-pass, 4- or 8-byte values):
+#   pre-pass : read x, b; write t; write coarse b and x (1/4 node each) = 3.5 w
+#   post-pass: read t, b, coarse x (1/4); write x                      = 3.25 w
+BYTES_PER_NODE_L1 = {
+    ("fp64", 0): 28, ("fp64", 1): 26,
+    ("mixed", 0): 14, ("mixed", 1): 13,
+}
+
+
+def fine_levels_roofline(s, rhs, scratch, head, times0, reps):
+    """Algorithmic bytes of the fused passes of levels 0 and 1 (the levels
+    that carry most of a cycle's bytes) over their summed device time."""
+    shape1 = s.level_shape(1) if s.nlevels > 1 else None
+    total_b = sum(BYTES_PER_NODE[(head, w)] for w in (0, 1)) * rhs.numel()
+    total_t = times0[0] + times0[1]
+    per = {}
+    if shape1 is not None:
+        try:
+            t1 = {w: s.profile_pass(rhs, scratch, 1, w, reps=reps) for w in (0, 1)}
+        except Exception:
+            t1 = None
+        if t1 is not None:
+            n1 = shape1[0] * shape1[1]
+            total_b += sum(BYTES_PER_NODE_L1[(head, w)] for w in (0, 1)) * n1
+            total_t += t1[0] + t1[1]
+            per = {"level1_pre_us": t1[0], "level1_post_us": t1[1]}
+    ach = total_b / (total_t * 1e-6) / 1e9
+    return {"achieved": ach, "frac": ach / HBM_PEAK_GBS, "unit": "GB/s", "bytes": total_b, "us": total_t, **per}
 
 
 def cpu_model() -> str:
@@ -279,6 +307,7 @@ def annulus(args):
     times = {which: s.profile_pass(rhs, scratch, 0, which, reps=20) for which in (0, 1)}
     dom = 1 if times[1] >= times[0] else 0
     kernel_name = s.pass_kernel_name(0, dom)
+    levels01 = fine_levels_roofline(s, rhs, scratch, head, times, 20)
     s.close()
     alg_bytes = BYTES_PER_NODE[(head, dom)] * nx * ny
     achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
@@ -308,7 +337,7 @@ def annulus(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel_name,
                      "avg_us": times[dom], "bytes_per_launch": alg_bytes, "bytes_per_node": BYTES_PER_NODE[(head, dom)],
-                     "nodes": nx * ny, "other_pass_us": times[1 - dom]},
+                     "nodes": nx * ny, "other_pass_us": times[1 - dom], "levels_0_1": levels01},
         "cycles": info_h.cycles,
         "rel_res": info_h.rel_res,
         "us_per_cycle": 1e6 * info_h.seconds / max(1, info_h.cycles),
@@ -617,6 +646,7 @@ def main():
     times = {which: s0.profile_pass(rhs, scratch, 0, which, reps=100) for which in (0, 1)}
     dom = 1 if times[1] >= times[0] else 0
     kernel_name = s0.pass_kernel_name(0, dom)
+    levels01 = fine_levels_roofline(s0, rhs, scratch, head, times, 100)
     nodes = n * n
     alg_bytes = BYTES_PER_NODE[(head, dom)] * nodes
     achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
@@ -655,7 +685,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel_name, "avg_us": times[dom], "bytes_per_launch": alg_bytes,
                      "bytes_per_node": BYTES_PER_NODE[(head, dom)], "nodes": nodes,
-                     "other_pass_us": times[1 - dom]},
+                     "other_pass_us": times[1 - dom], "levels_0_1": levels01},
         "cycles": {f"{e:g}": i.cycles for e, i in zip(eps_list, infos_h)},
         "rel_res": {f"{e:g}": i.rel_res for e, i in zip(eps_list, infos_h)},
         "us_per_cycle": {f"{e:g}": 1e6 * i.seconds / max(1, i.cycles) for e, i in zip(eps_list, infos_h)},

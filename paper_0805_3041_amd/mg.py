@@ -301,6 +301,10 @@ class Solver:
         self.opts = make_options(**opt)
         self.h = mg_setup(self.grid, self.coeffs, levels, self.opts)
 
+    def level_shape(self, level: int):
+        """(nx, ny) stored shape of a level."""
+        return mg_level_shape(self.h, level)
+
     @property
     def nlevels(self) -> int:
         return mg_num_levels(self.h)

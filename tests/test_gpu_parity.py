@@ -379,3 +379,33 @@ def test_fused_solve_matches_per_op_solve(precision):
         assert np.array_equal(xa, xb)
         # same iterates; the norms are summed in a different order (tiles vs rows)
         np.testing.assert_allclose(ia.history, ib.history, rtol=1e-14, atol=0)
+
+
+# ----------------------------------------------------------------------------- asymptotic rate
+
+RATE_CASES = [
+    dict(nx=33, ny=33, eps=1.0, smoother="rbgs"),
+    dict(nx=33, ny=33, eps=0.1, smoother="rbgs"),
+    dict(nx=33, ny=32, periodic_y=True, q1="annulus", smoother="gs4c"),
+    dict(nx=17, ny=17, eps=1.0, smoother="jacobi"),
+]
+
+
+@pytest.mark.parametrize("case", RATE_CASES, ids=[str(i) for i in range(len(RATE_CASES))])
+def test_asymptotic_rate_matches_cycle_matrix_spectral_radius(case):
+    """With b = 0 the GPU's F-cycles are a power iteration of the cycle's
+    iteration matrix M (built by the oracle from unit vectors): the measured
+    asymptotic rate (geometric mean of the residual ratios over the last 10
+    of 40 cycles, random start) is within 5 % of the spectral radius of M."""
+    p = Problem(**case)
+    M = O.cycle_matrix(p.oracle(), "F")
+    rho = max(abs(np.linalg.eigvals(M)))
+    s = p.solver()
+    x = torch.tensor(W.uniform_field(p.nx, p.ny, 7, p.periodic_y), device="cuda")
+    rhs = torch.zeros_like(x)
+    info = s.solve(rhs, x, tol=1e-300, max_cycles=40, history=True)
+    s.close()
+    h = np.asarray(info.history)
+    assert len(h) == 41 and np.all(h > 0)
+    rate = (h[-1] / h[-11]) ** 0.1
+    assert abs(rate - rho) <= 0.05 * rho, (rate, rho)
