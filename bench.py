@@ -501,6 +501,32 @@ def cpu_baseline_batch(ns, eps, cycles, nu, seconds):
             "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
 
 
+# 2-D 9-point bands (grf2049): the fused passes also read the six bands C,
+# E, N, NE, NW, D of every node (FP64).
+BAND_BYTES_2D = 6 * 8
+
+
+def _roofline_grf(n, at, ft):
+    """Roofline of the finest-level fused passes of the grf2049 operator (the
+    solver the forward and adjoint solves build)."""
+    import torch
+
+    from paper_0805_3041_amd import mg
+
+    s = mg.Solver(n, n, kx=at, ky=at, smoother="gs4c")
+    scratch = torch.zeros_like(ft)
+    times = {which: s.profile_pass(ft, scratch, 0, which, reps=20) for which in (0, 1)}
+    dom = 1 if times[1] >= times[0] else 0
+    kernel = s.pass_kernel_name(0, dom)
+    s.close()
+    bpn = BYTES_PER_NODE[("fp64", dom)] + BAND_BYTES_2D
+    alg = bpn * n * n
+    ach = alg / (times[dom] * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": stored_traffic("grf2049", kernel), "kernel": kernel, "avg_us": times[dom],
+            "bytes_per_launch": alg, "bytes_per_node": bpn, "nodes": n * n, "other_pass_us": times[1 - dom]}
+
+
 def grf2049(args):
     """Workload grf2049: -div(a grad u) = f on 2049^2 nodes (2048^2 cells),
     a = exp(g), g a Gaussian random field (squared-exponential covariance,
@@ -551,6 +577,7 @@ def grf2049(args):
         "config": {"workload": "grf2049: -div(a grad u) = 2 pi^2 sin(pi x) sin(pi y) on 2049^2 nodes, a = exp(GRF, "
                                "length 0.1, sigma 1, seed 5) per cell, Q1, four-colour GS 2/2, F-cycle; forward + "
                                "adjoint solve to 1e-10 and dL/da, dL/df of 0.5 ||u - u*||^2", "precision": "fp64"},
+        "roofline": _roofline_grf(n, at, ft),
         "grad_norms": {"dL_da": float(torch.linalg.vector_norm(da)), "dL_df": float(torch.linalg.vector_norm(df))},
     }
     if not args.no_cpu_baseline:
