@@ -19,6 +19,10 @@ better Multigrid Solver Convergence", KAIST 2008):
   "Smoothers" section with C = D (Jacobi) and C = D + L (Gauss-Seidel, omega=1,
   "The choice of C"), the Gauss-Seidel ordering being red-black (5-point) or
   four-colour (9-point);
+* the line smoothers of "The choice of C" and "Smoothing": TRI (C = the
+  tridiagonal part of A along x or y lines, damped by omega), ADI (a TRI step
+  along x then one along y), GSTRI (Gauss-Seidel over whole lines, each line
+  solved exactly, lines in zebra order) and GSADI (GSTRI along x then y);
 * the recursive algorithm MG(l, u, g) of "The Multigrid Technique" (pre-smooth,
   restrict the defect, solve recursively from a zero start, add the prolonged
   correction with omega_l = 1, post-smooth, exact solve on the coarsest level),
@@ -354,6 +358,64 @@ def colour_sets(g: Grid, ncolours: int) -> list[np.ndarray]:
     raise ValueError("ncolours must be 2 or 4")
 
 
+LINE_SMOOTHERS = ("tri_x", "tri_y", "adi", "gstri_x", "gstri_y", "gsadi")
+
+
+def _unknown_ij(g: Grid) -> tuple[np.ndarray, np.ndarray]:
+    """Stored (i, j) of every unknown, in unknown-vector order."""
+    J, I = np.meshgrid(np.array(g.uy), np.array(g.ux), indexing="ij")
+    return I.reshape(-1), J.reshape(-1)
+
+
+def line_part(g: Grid, A, direction: str) -> sp.csr_matrix:
+    """Tridiagonal preconditioner of the TRI smoothers ("The choice of C": D
+    plus the first sub- and super-diagonals in the ordering that runs along the
+    lines): the entries of A that couple an unknown with itself and with its
+    two neighbours on the same grid line, lines along x (rows, "TRIx") or
+    along y (columns, "TRIy"; the neighbours wrap across a periodic seam)."""
+    I, J = _unknown_ij(g)
+    a = sp.coo_matrix(A)
+    r, c = a.row, a.col
+    if direction == "x":
+        keep = (J[r] == J[c]) & (np.abs(I[r] - I[c]) <= 1)
+    elif direction == "y":
+        dj = np.abs(J[r] - J[c])
+        if g.periodic_y:
+            dj = np.minimum(dj, g.ny - dj)
+        keep = (I[r] == I[c]) & (dj <= 1)
+    else:
+        raise ValueError("direction must be 'x' or 'y'")
+    return sp.csr_matrix((a.data[keep], (r[keep], c[keep])), shape=A.shape)
+
+
+def line_colour_sets(g: Grid, direction: str) -> list[np.ndarray]:
+    """Unknowns of the two zebra line colours, in sweep order: lines along x
+    are rows j, lines along y columns i; colour 0 = even stored index, first."""
+    I, J = _unknown_ij(g)
+    key = J if direction == "x" else I
+    return [np.nonzero(key % 2 == 0)[0], np.nonzero(key % 2 == 1)[0]]
+
+
+def tri_step(A, T, x, b, omega):
+    """Preconditioned Richardson with C = T (TRI, line Jacobi):
+    x + omega T^{-1} (b - A x), every line solved exactly at once."""
+    return x + omega * spla.spsolve(sp.csc_matrix(T), b - A @ x)
+
+
+def line_gs_step(A, x, b, sets):
+    """Gauss-Seidel over lines (GSTRI, omega = 1): for each line colour in
+    turn, the lines of that colour are solved exactly with the latest values
+    on the lines of the other colour (lines of one colour do not couple)."""
+    x = x.copy()
+    A = sp.csr_matrix(A)
+    n = len(x)
+    for s in sets:
+        rest = np.setdiff1d(np.arange(n), s)
+        rhs = b[s] - A[s][:, rest] @ x[rest]
+        x[s] = spla.spsolve(sp.csc_matrix(A[s][:, s]), rhs)
+    return x
+
+
 def jacobi_step(A, diag, x, b, omega):
     """Preconditioned Richardson with C = D: x + omega D^{-1} (b - A x)."""
     return x + omega * (b - A @ x) / diag
@@ -377,7 +439,7 @@ def coloured_gs_step(A, diag, x, b, colours, omega=1.0):
 @dataclass
 class Options:
     cycle: str = "F"          # "F" or "V"
-    smoother: str = "rbgs"    # "jacobi", "rbgs" (2 colours), "gs4c" (4 colours)
+    smoother: str = "rbgs"    # "jacobi", "rbgs" (2 colours), "gs4c" (4 colours), or one of LINE_SMOOTHERS
     nu_pre: int = 2
     nu_post: int = 2
     omega: float = 0.8        # Jacobi damping; Gauss-Seidel uses 1
@@ -393,6 +455,7 @@ class Hierarchy:
     colours: list
     chol: tuple = None        # Cholesky factor of the coarsest operator (FP64)
     opts: Options = field(default_factory=Options)
+    lines: list = None        # line smoothers: per level {"Tx", "Ty", "sx", "sy"}
 
     @property
     def nlevels(self) -> int:
@@ -401,9 +464,13 @@ class Hierarchy:
     def astype(self, dtype) -> "Hierarchy":
         """Copy whose level operators, transfers and vectors are in ``dtype``;
         the coarsest factor stays FP64."""
+        lines = None
+        if self.lines is not None:
+            lines = [{"Tx": L["Tx"].astype(dtype), "Ty": L["Ty"].astype(dtype), "sx": L["sx"], "sy": L["sy"]}
+                     for L in self.lines]
         return Hierarchy(self.grids, [a.astype(dtype) for a in self.A], [r.astype(dtype) for r in self.R],
                          [p.astype(dtype) for p in self.P], [d.astype(dtype) for d in self.diag],
-                         self.colours, self.chol, self.opts)
+                         self.colours, self.chol, self.opts, lines)
 
 
 def build_hierarchy(g: Grid, A0: sp.spmatrix, opts: Options, levels: int = 0,
@@ -420,11 +487,15 @@ def build_hierarchy(g: Grid, A0: sp.spmatrix, opts: Options, levels: int = 0,
             A.append(rediscretise(grids[l + 1]).tocsr())
         else:
             A.append((R[l] @ A[l] @ P[l]).tocsr())
-    ncol = {"jacobi": 0, "rbgs": 2, "gs4c": 4}[opts.smoother]
+    ncol = 0 if opts.smoother in LINE_SMOOTHERS else {"jacobi": 0, "rbgs": 2, "gs4c": 4}[opts.smoother]
     colours = [colour_sets(gl, ncol) if ncol else None for gl in grids]
     diag = [a.diagonal().copy() for a in A]
     chol = sla.cho_factor(A[-1].toarray(), lower=True)
-    return Hierarchy(grids, A, R, P, diag, colours, chol, opts)
+    lines = None
+    if opts.smoother in LINE_SMOOTHERS:
+        lines = [{"Tx": line_part(gl, a, "x"), "Ty": line_part(gl, a, "y"), "sx": line_colour_sets(gl, "x"),
+                  "sy": line_colour_sets(gl, "y")} for gl, a in zip(grids, A)]
+    return Hierarchy(grids, A, R, P, diag, colours, chol, opts, lines)
 
 
 def hierarchy_5pt(g: Grid, eps_x=1.0, eps_y=1.0, opts=None, levels=0) -> Hierarchy:
@@ -439,11 +510,28 @@ def hierarchy_q1(g: Grid, kx, ky, opts=None, levels=0, separable=False) -> Hiera
     return build_hierarchy(g, A0, opts, levels, rediscretise=None)
 
 
+def line_smoothing_step(h: Hierarchy, l: int, x, g):
+    """One step of a line smoother on level l (an ADI or GSADI step is the
+    x-line half followed by the y-line half)."""
+    o, A, L = h.opts, h.A[l], h.lines[l]
+    if o.smoother in ("tri_x", "adi"):
+        x = tri_step(A, L["Tx"], x, g, o.omega)
+    if o.smoother in ("tri_y", "adi"):
+        x = tri_step(A, L["Ty"], x, g, o.omega)
+    if o.smoother in ("gstri_x", "gsadi"):
+        x = line_gs_step(A, x, g, L["sx"])
+    if o.smoother in ("gstri_y", "gsadi"):
+        x = line_gs_step(A, x, g, L["sy"])
+    return x
+
+
 def smooth(h: Hierarchy, l: int, x, g, steps: int):
     o = h.opts
     for _ in range(steps):
         if o.smoother == "jacobi":
             x = jacobi_step(h.A[l], h.diag[l], x, g, o.omega)
+        elif o.smoother in LINE_SMOOTHERS:
+            x = line_smoothing_step(h, l, x, g)
         else:
             x = coloured_gs_step(h.A[l], h.diag[l], x, g, h.colours[l], 1.0)
     return x
