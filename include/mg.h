@@ -60,7 +60,28 @@ typedef enum {
 
 enum { MG_COEF_CONST5 = 0, MG_COEF_CELL9 = 1 };
 enum { MG_CYCLE_F = 0, MG_CYCLE_V = 1 };
-enum { MG_SMOOTH_JACOBI = 0, MG_SMOOTH_RBGS = 1, MG_SMOOTH_GS4C = 2 };
+/* Smoothers (the preconditioner C of the Richardson step x <- x + omega
+ * C^-1 (b - A x), "The choice of C" and "Smoothing"): damped point Jacobi;
+ * point Gauss-Seidel in red-black (5-point) or four-colour (9-point) order;
+ * line smoothers whose C is the tridiagonal part of A along x lines (rows) or
+ * y lines (columns): TRI_X / TRI_Y damped by omega, ADI = a TRI_X then a
+ * TRI_Y step, GSTRI_X / GSTRI_Y Gauss-Seidel over whole lines in zebra order
+ * (even stored line index first, every line solved exactly), GSADI = a
+ * GSTRI_X then a GSTRI_Y step.  Line smoothers run every level visit as one
+ * launch per line sweep (no fused tiles); lines along a periodic direction
+ * (TRI_Y, ADI, GSTRI_Y, GSADI with periodic_y) and batched handles are
+ * MG_EUNSUPPORTED. */
+enum {
+  MG_SMOOTH_JACOBI = 0,
+  MG_SMOOTH_RBGS = 1,
+  MG_SMOOTH_GS4C = 2,
+  MG_SMOOTH_TRI_X = 3,
+  MG_SMOOTH_TRI_Y = 4,
+  MG_SMOOTH_ADI = 5,
+  MG_SMOOTH_GSTRI_X = 6,
+  MG_SMOOTH_GSTRI_Y = 7,
+  MG_SMOOTH_GSADI = 8
+};
 enum { MG_PREC_FP64 = 0, MG_PREC_MIXED = 1 };
 enum { MG_TILES_FUSED = 0, MG_TILES_PER_OP = 1, MG_TILES_NARROW = 2, MG_TILES_WIDE = 3 };
 
@@ -88,8 +109,8 @@ typedef struct {
   int32_t kx_1d_along_x;
 } mg_coeffs;
 
-/* Options.  nu_pre, nu_post in [0, 8].  omega: Jacobi damping (Gauss-Seidel
- * uses omega = 1).  precision MG_PREC_MIXED runs every cycle in FP32 inside an
+/* Options.  nu_pre, nu_post in [0, 8].  omega: Jacobi and TRI / ADI damping
+ * (the Gauss-Seidel smoothers use omega = 1).  precision MG_PREC_MIXED runs every cycle in FP32 inside an
  * FP64 defect-correction loop (x, rhs stay FP64 at the boundary).
  * coarse_cta_nodes: levels with at most this many stored nodes run inside one
  * persistent workgroup (0 = the largest levels whose sub-hierarchy fits in

@@ -36,7 +36,7 @@ thread_local std::string g_thread_err;
 
 constexpr int MAX_BATCH = 4096;
 
-enum HostOpType { H_COLOR = 0, H_JACOBI, H_COPY, H_DR, H_PROLONG, H_COARSE, H_SUB, H_PRE, H_POST };
+enum HostOpType { H_COLOR = 0, H_JACOBI, H_COPY, H_DR, H_PROLONG, H_COARSE, H_SUB, H_PRE, H_POST, H_LINE };
 
 struct HostOp {
   int type, level, arg;
@@ -93,7 +93,9 @@ struct mg_handle_s {
   int kind = MG_COEF_CONST5;
   int oned = 0;
   mg_options opts{};
-  int ncol = 0;                      // 0 Jacobi, 2 red-black, 4 four-colour
+  int ncol = 0;                      // 0 Jacobi (and line smoothers), 2 red-black, 4 four-colour
+  int line = 0;                      // line smoothers: directions swept (bit 0 x, bit 1 y)
+  bool line_jac = false;             // line smoothers: Jacobi (TRI) rather than Gauss-Seidel
   std::vector<double> eps_x, eps_y;  // per problem (5-point)
   hipStream_t stream = nullptr;
   std::string err;
@@ -171,11 +173,28 @@ struct Gen {
   const Group& G;
   int threshold;  // 0: the largest levels whose sub-hierarchy fits in LDS
   bool small(int l) const {
+    if (h->line) return false;  // line sweeps run as launches on every level
     const LevelShape& s = G.shp[l];
     if (threshold > 0) return (long)s.nx * s.ny <= threshold;
     return sub_footprint(h, G, l) <= SUB_LDS_BUDGET;
   }
   void smooth(std::vector<Abs>& out, int l, int steps) const {
+    if (h->line) {
+      int par = 0;  // Jacobi ping-pong: 0 x -> t, 1 t -> x
+      for (int s = 0; s < steps; ++s)
+        for (int dir = 0; dir < 2; ++dir) {
+          if (!((h->line >> dir) & 1)) continue;
+          if (h->line_jac) {
+            out.push_back({H_LINE, l, line_arg(dir, true, par)});
+            par ^= 1;
+          } else {
+            out.push_back({H_LINE, l, line_arg(dir, false, 0)});
+            out.push_back({H_LINE, l, line_arg(dir, false, 1)});
+          }
+        }
+      if (par) out.push_back({H_COPY, l, 0});
+      return;
+    }
     if (h->ncol == 0) {
       int dir = 0;
       for (int s = 0; s < steps; ++s) {
@@ -220,7 +239,7 @@ struct Gen {
       out.push_back({H_SUB, l, kind, (int)subs.size() - 1});
       return;
     }
-    const bool fused = h->opts.tile_mode != MG_TILES_PER_OP;
+    const bool fused = h->opts.tile_mode != MG_TILES_PER_OP && !h->line;
     std::vector<Abs> tmp;
     if (fused) {
       out.push_back({H_PRE, l, 0, -1});
@@ -328,6 +347,7 @@ mg_status build_program(mg_handle h, Group& G) {
       cnt.push_back((int)s.size());
     }
     for (const Abs& a : s) {
+      if (a.type == H_LINE) return fail(h, MG_EUNSUPPORTED, "line sweeps inside a coarse-level program");
       int t = OP_COLOR;
       switch (a.type) {
         case H_COLOR: t = OP_COLOR; break;
@@ -367,6 +387,7 @@ hipError_t run_op(mg_handle h, const Group& G, const HostOp& op, Level<T>* dL, L
     case H_DR: return launch_dr<T>(Ls, Cs, G.shp[l + 1], ns, st);
     case H_PROLONG: return launch_prolong<T>(Ls, Cs, s, ns, st);
     case H_COARSE: return launch_coarse<T>(Ls, G.dcholp, G.ncu, ns, st);
+    case H_LINE: return launch_line<T>(Ls, s, op.arg, omega, stencil_kind(h), ns, st);
     case H_PRE:
       return launch_pre<T>(Ls, Cs, G.gpre[l], h->opts.nu_pre, h->ncol, omega, stencil_kind(h), h->oned, l == 0, ns,
                            st);
@@ -459,15 +480,34 @@ mg_status check_grid(const mg_grid* g) {
   return MG_OK;
 }
 
+// Line smoothers: the directions whose lines a smoothing step sweeps (bit 0
+// x, bit 1 y; x first) and whether the lines are relaxed by Jacobi (TRI, ADI)
+// or Gauss-Seidel (GSTRI, GSADI).
+int line_dirs(int smoother) {
+  switch (smoother) {
+    case MG_SMOOTH_TRI_X:
+    case MG_SMOOTH_GSTRI_X: return 1;
+    case MG_SMOOTH_TRI_Y:
+    case MG_SMOOTH_GSTRI_Y: return 2;
+    case MG_SMOOTH_ADI:
+    case MG_SMOOTH_GSADI: return 3;
+    default: return 0;
+  }
+}
+bool line_jacobi(int smoother) {
+  return smoother == MG_SMOOTH_TRI_X || smoother == MG_SMOOTH_TRI_Y || smoother == MG_SMOOTH_ADI;
+}
+
 mg_status check_opts(const mg_options* o, int kind) {
   if (!o) return fail(nullptr, MG_EINVAL, "options is NULL");
   if (o->cycle != MG_CYCLE_F && o->cycle != MG_CYCLE_V) return fail(nullptr, MG_EINVAL, "cycle must be F or V");
-  if (o->smoother < MG_SMOOTH_JACOBI || o->smoother > MG_SMOOTH_GS4C) return fail(nullptr, MG_EINVAL, "bad smoother");
+  if (o->smoother < MG_SMOOTH_JACOBI || o->smoother > MG_SMOOTH_GSADI) return fail(nullptr, MG_EINVAL, "bad smoother");
   if (o->smoother == MG_SMOOTH_RBGS && kind == MG_COEF_CELL9)
     return fail(nullptr, MG_EUNSUPPORTED, "red-black ordering does not decouple the 9-point stencil; use GS4C");
   if (o->nu_pre < 0 || o->nu_pre > 8 || o->nu_post < 0 || o->nu_post > 8)
     return fail(nullptr, MG_EINVAL, "nu_pre and nu_post must be in [0, 8]");
-  if (o->smoother == MG_SMOOTH_JACOBI && !finite_pos(o->omega)) return fail(nullptr, MG_EINVAL, "omega must be > 0");
+  if ((o->smoother == MG_SMOOTH_JACOBI || line_jacobi(o->smoother)) && !finite_pos(o->omega))
+    return fail(nullptr, MG_EINVAL, "omega must be > 0");
   if (o->precision != MG_PREC_FP64 && o->precision != MG_PREC_MIXED) return fail(nullptr, MG_EINVAL, "bad precision");
   if (o->coarse_cta_nodes < 0) return fail(nullptr, MG_EINVAL, "coarse_cta_nodes must be >= 0");
   if (o->tile_mode < MG_TILES_FUSED || o->tile_mode > MG_TILES_WIDE) return fail(nullptr, MG_EINVAL, "bad tile_mode");
@@ -526,6 +566,21 @@ int max_levels(int nx, int ny, int py) {
 // Shapes, buffers, operators, coarsest factors and descriptors of a group.
 // Problem p = G.probs[s] uses h->eps_x[p], h->eps_y[p] (5-point) or the
 // coefficient arrays in coeffs (9-point, single-problem handles only).
+// Line-smoother storage of one level (factors for each swept direction and
+// the forward-sweep scratch, all [ny][pitch]) and its factors.
+template <typename T>
+hipError_t alloc_line_factors(mg_handle h, Level<T>& L, const LevelShape& sh) {
+  const size_t n = (size_t)L.pitch * sh.ny;
+  hipError_t e = hipSuccess;
+  for (int dir = 0; dir < 2; ++dir) {
+    if (!((h->line >> dir) & 1)) continue;
+    if ((e = h->dalloc(&L.lcp[dir], n * sizeof(T))) != hipSuccess) return e;
+    if ((e = h->dalloc(&L.lid[dir], n * sizeof(T))) != hipSuccess) return e;
+    if ((e = launch_line_factor<T>(L, dir, h->stream)) != hipSuccess) return e;
+  }
+  return h->dalloc(&L.lr, n * sizeof(T));
+}
+
 mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t levels) {
   const mg_grid& grid = G.grid;
   const int py = grid.periodic_y ? 1 : 0;
@@ -645,6 +700,19 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
     }
   }
 
+  // line smoothers: Thomas factors of every line of the cycle's hierarchy
+  if (h->line) {
+    for (int s = 0; s < ns; ++s)
+      for (int l = 0; l < G.nlev; ++l) {
+        const LevelShape& sh = G.shp[l];
+        if (mixed) {
+          HIPCHK(h, alloc_line_factors(h, G.l32(l, s), sh));
+        } else {
+          HIPCHK(h, alloc_line_factors(h, G.l64(l, s), sh));
+        }
+      }
+  }
+
   // coarsest operator of each slot: dense matrix, Cholesky factor and the
   // inverse the coarse solve applies (FP64)
   {
@@ -706,7 +774,9 @@ mg_status upload_descriptors(mg_handle h, Group& G) {
 
 // Common part of mg_setup and mg_setup_batched after the groups are formed.
 mg_status setup_handle(mg_handle h, const mg_coeffs* coeffs, int32_t levels) {
-  h->ncol = h->opts.smoother == MG_SMOOTH_JACOBI ? 0 : (h->opts.smoother == MG_SMOOTH_RBGS ? 2 : 4);
+  h->line = line_dirs(h->opts.smoother);
+  h->line_jac = line_jacobi(h->opts.smoother);
+  h->ncol = (h->opts.smoother == MG_SMOOTH_JACOBI || h->line) ? 0 : (h->opts.smoother == MG_SMOOTH_RBGS ? 2 : 4);
   h->stream = static_cast<hipStream_t>(h->opts.stream);
   HIPCHK(h, hipEventCreate(&h->ev0));
   HIPCHK(h, hipEventCreate(&h->ev1));
@@ -911,6 +981,8 @@ mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, int32_t levels,
   s = check_opts(opts, coeffs->kind);
   if (s != MG_OK) return s;
   if (levels < 0) return fail(nullptr, MG_EINVAL, "levels must be >= 0");
+  if ((line_dirs(opts->smoother) & 2) && grid->periodic_y)
+    return fail(nullptr, MG_EUNSUPPORTED, "line smoothers along a periodic direction (y lines with periodic_y)");
 
   mg_handle h = new mg_handle_s();
   h->opts = *opts;
@@ -952,6 +1024,7 @@ mg_status mg_setup_batched(const mg_grid* grids, const mg_coeffs* coeffs, int32_
   }
   mg_status s = check_opts(opts, MG_COEF_CONST5);
   if (s != MG_OK) return s;
+  if (line_dirs(opts->smoother)) return fail(nullptr, MG_EUNSUPPORTED, "batched solves take point smoothers only");
 
   mg_handle h = new mg_handle_s();
   h->batched = true;

@@ -53,6 +53,9 @@ struct Level {
   int bpitch;             // ST9: band row pitch (0: one row for every j)
   int bstride;
   SolveState* st;         // owning problem's state
+  T* lcp[2];              // line smoothers: per direction (0 x-lines, 1 y-lines) the Thomas factors
+  T* lid[2];              //   c_n / den_n and 1 / den_n of every node's line, [ny][pitch]
+  T* lr;                  //   forward-sweep values of the running line solve, [ny][pitch]
 };
 
 // Host-built op of the coarse-level interpreter (one workgroup runs a list).
@@ -64,6 +67,12 @@ enum OpType {
   OP_PROLONG = 4,   // x(level) += P x(level+1)
   OP_COARSE = 5,    // exact solve on the coarsest `level`
 };
+
+// Argument of a line-smoothing op: bit 0 direction (0: lines along x, 1:
+// along y), bit 1 Jacobi (TRI) instead of Gauss-Seidel (GSTRI), bits 2+ the
+// line colour (Gauss-Seidel: lines whose stored index has that parity) or the
+// Jacobi ping-pong direction (0: x -> t, 1: t -> x).
+constexpr int line_arg(int dir, bool jacobi, int sel) { return dir | ((jacobi ? 1 : 0) << 1) | (sel << 2); }
 
 struct DOp {
   int type, level, arg, pad;

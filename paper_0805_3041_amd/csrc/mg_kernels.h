@@ -34,6 +34,13 @@ template <typename T>
 hipError_t launch_prolong(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& f, int nslots, hipStream_t st);
 template <typename T>
 hipError_t launch_coarse(const Level<T>* Ls, const double* const* chol, int n, int nslots, hipStream_t st);
+// Thomas factors of the lines along `dir` of one level (L: host copy of its descriptor)
+template <typename T>
+hipError_t launch_line_factor(const Level<T>& L, int dir, hipStream_t st);
+// one line-smoothing op (arg from line_arg) on level s of every slot
+template <typename T>
+hipError_t launch_line(const Level<T>* Ls, const LevelShape& s, int arg, T omega, int kind, int nslots,
+                       hipStream_t st);
 template <typename T>
 hipError_t launch_subcycle(const Level<T>* levs, int nlev, const DOp* prog, const int* beg, const int* cnt,
                            const double* const* chol, int ncu, T omega, int ncol, int nslots, hipStream_t st);

@@ -180,6 +180,163 @@ __global__ void __launch_bounds__(NT) k_coarse(const Level<T>* __restrict__ Ls, 
   body_coarse(L, chol[blockIdx.z], n, threadIdx.x, NT);
 }
 
+// --------------------------------------------------------------------------- line smoothers
+// Lines along x are the rows j of unknowns (n-th node i = 1 + n), lines along
+// y the columns i (n-th node j = 1 + n; Dirichlet in y only).  The tridiagonal
+// part of A on a line couples node n with n - 1 (a), itself (d) and n + 1 (c);
+// its Thomas factors c_n / den_n and 1 / den_n (den_n = d_n - a_n c_{n-1} /
+// den_{n-1}) are formed once per level at setup.  One thread solves one line.
+
+constexpr int LT = 64;  // threads (lines) per workgroup of the line kernels
+
+__device__ __forceinline__ void line_node(int dir, int line, int n, int& i, int& j) {
+  if (dir == 0) {
+    i = 1 + n;
+    j = line;
+  } else {
+    i = line;
+    j = 1 + n;
+  }
+}
+
+// Line couplings of node (i, j): a (previous node on the line), d, c (next).
+template <int K, typename T>
+__device__ __forceinline__ void line_coefs(const Level<T>& L, int dir, const Cf<T>& cf, T& a, T& d, T& c) {
+  if (is5<K>(L)) {
+    const T o = dir == 0 ? -L.cx : -L.cy;
+    a = o;
+    c = o;
+    d = L.dg;
+  } else {
+    a = dir == 0 ? cf.Ew : cf.Ns;
+    c = dir == 0 ? cf.Ep : cf.Np;
+    d = cf.C;
+  }
+}
+
+// Sum over the couplings of node p to nodes off its line, a_pq x_q.
+template <int K, typename T>
+__device__ __forceinline__ T off_line(const Level<T>& L, int dir, const Cf<T>& a, const Nbr<T>& v) {
+  if (is5<K>(L)) return dir == 0 ? -L.cy * (v.s + v.n) : -L.cx * (v.w + v.e);
+  T s;
+  if (dir == 0) {
+    s = a.Np * v.n;
+    s = fma(a.Ns, v.s, s);
+  } else {
+    s = a.Ep * v.e;
+    s = fma(a.Ew, v.w, s);
+  }
+  s = fma(a.NEp, v.ne, s);
+  s = fma(a.NEsw, v.sw, s);
+  s = fma(a.NWp, v.nw, s);
+  s = fma(a.NWse, v.se, s);
+  return s;
+}
+
+// Line `t` of a launch: every line (Jacobi) or every other line of parity
+// `colour` (Gauss-Seidel); -1 past the last.
+template <typename T>
+__device__ __forceinline__ int line_of(const Level<T>& L, int dir, bool all, int colour, int t) {
+  const int lo = dir == 0 ? row_lo(L) : 1, hi = dir == 0 ? row_hi(L) : L.nx - 2;
+  const int line = all ? lo + t : lo + (((lo & 1) != colour) ? 1 : 0) + 2 * t;
+  return line <= hi ? line : -1;
+}
+
+template <typename T, int K>
+__global__ void __launch_bounds__(LT) k_line_factor(Level<T> L, int dir) {
+  const int line = line_of(L, dir, true, 0, blockIdx.x * LT + threadIdx.x);
+  if (line < 0) return;
+  const int m = dir == 0 ? L.nx - 2 : L.ny - 2;
+  T* cp = L.lcp[dir];
+  T* id = L.lid[dir];
+  T cprev = (T)0;
+  for (int n = 0; n < m; ++n) {
+    int i, j;
+    line_node(dir, line, n, i, j);
+    const Cf<T> cf = coefs<K>(L, i, j, wrap_dn(j, L.ny, L.py));
+    T a, d, c;
+    line_coefs<K>(L, dir, cf, a, d, c);
+    const T inv = (T)1 / (d - a * cprev);
+    cprev = c * inv;
+    const size_t q = (size_t)j * L.pitch + i;
+    cp[q] = cprev;
+    id[q] = inv;
+  }
+}
+
+// One line-smoothing op (arg: see line_arg).  Gauss-Seidel: x on the lines
+// of one colour <- exact solution of their tridiagonal systems with the
+// off-line couplings on the right-hand side (lines of one colour do not
+// couple).  Jacobi (TRI): dst = src + omega T^-1 (b - A src).
+template <typename T, int K>
+__global__ void __launch_bounds__(LT) k_line(const Level<T>* __restrict__ Ls, int arg, T omega) {
+  const Level<T> L = Ls[blockIdx.z];
+  if (L.st->done) return;
+  const int dir = arg & 1, sel = arg >> 2;
+  const bool jac = (arg >> 1) & 1;
+  const int line = line_of(L, dir, jac, sel, blockIdx.x * LT + threadIdx.x);
+  if (line < 0) return;
+  const T* src = (jac && sel) ? L.t : L.x;
+  T* dst = jac ? (sel ? L.x : L.t) : L.x;
+  const int m = dir == 0 ? L.nx - 2 : L.ny - 2;
+  const T* cp = L.lcp[dir];
+  const T* id = L.lid[dir];
+  T* rp = L.lr;
+  T prev = (T)0;
+  for (int n = 0; n < m; ++n) {
+    int i, j;
+    line_node(dir, line, n, i, j);
+    const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
+    const size_t q = (size_t)j * L.pitch + i;
+    const GX<T> g{src + (size_t)jm * L.pitch + i, src + q, src + (size_t)jp * L.pitch + i};
+    const Cf<T> cf = coefs<K>(L, i, j, jm);
+    T a, d, c;
+    line_coefs<K>(L, dir, cf, a, d, c);
+    const T r = jac ? defect_v<K>(L, cf, gather<K>(L, g, true), L.b[q])
+                    : L.b[q] - off_line<K>(L, dir, cf, gather<K>(L, g, false));
+    prev = (r - a * prev) * id[q];
+    rp[q] = prev;
+  }
+  T u = (T)0;
+  for (int n = m - 1; n >= 0; --n) {
+    int i, j;
+    line_node(dir, line, n, i, j);
+    const size_t q = (size_t)j * L.pitch + i;
+    u = rp[q] - cp[q] * u;
+    dst[q] = jac ? src[q] + omega * u : u;
+  }
+}
+
+template <typename T>
+int line_count(const Level<T>& L, int dir) {
+  return dir == 0 ? (L.py ? L.ny : L.ny - 2) : L.nx - 2;
+}
+
+template <typename T>
+hipError_t launch_line_factor(const Level<T>& L, int dir, hipStream_t st) {
+  const int nb = (line_count(L, dir) + LT - 1) / LT;
+  if (L.kind == ST5)
+    hipLaunchKernelGGL((k_line_factor<T, ST5>), dim3(nb), dim3(LT), 0, st, L, dir);
+  else
+    hipLaunchKernelGGL((k_line_factor<T, ST9>), dim3(nb), dim3(LT), 0, st, L, dir);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_line(const Level<T>* Ls, const LevelShape& s, int arg, T omega, int kind, int nslots,
+                       hipStream_t st) {
+  const int dir = arg & 1;
+  const bool jac = (arg >> 1) & 1;
+  int lines = dir == 0 ? s.nrows : s.nx - 2;
+  if (!jac) lines = (lines + 1) / 2;
+  const dim3 grid((lines + LT - 1) / LT, 1, nslots);
+  if (kind == ST5)
+    hipLaunchKernelGGL((k_line<T, ST5>), grid, dim3(LT), 0, st, Ls, arg, omega);
+  else
+    hipLaunchKernelGGL((k_line<T, ST9>), grid, dim3(LT), 0, st, Ls, arg, omega);
+  return hipGetLastError();
+}
+
 // --------------------------------------------------------------------------- op bodies on LDS levels
 // Levels held in LDS as dense [ny][nx] arrays (row pitch nx).  Threads map to
 // (column, row group) with power-of-two column groups and 32-bit offsets, so
@@ -1143,6 +1300,8 @@ hipError_t launch_coeff_grad(const double* u, const double* lam, double* g, int 
   template hipError_t launch_dr<T>(const Level<T>*, const Level<T>*, const LevelShape&, int, hipStream_t);        \
   template hipError_t launch_prolong<T>(const Level<T>*, const Level<T>*, const LevelShape&, int, hipStream_t);   \
   template hipError_t launch_coarse<T>(const Level<T>*, const double* const*, int, int, hipStream_t);             \
+  template hipError_t launch_line_factor<T>(const Level<T>&, int, hipStream_t);                                    \
+  template hipError_t launch_line<T>(const Level<T>*, const LevelShape&, int, T, int, int, hipStream_t);          \
   template hipError_t launch_subcycle<T>(const Level<T>*, int, const DOp*, const int*, const int*,                \
                                          const double* const*, int, T, int, int, hipStream_t);                     \
   template hipError_t launch_resnorm<T>(const Level<T>*, const LevelShape&, int, T*, const Level<float>*, int, bool, \

@@ -65,7 +65,12 @@ def _setup(mg, grid, coeffs, levels=0, **opt):
     dict(opt=dict(nu_pre=9)),
     dict(opt=dict(nu_post=-1)),
     dict(opt=dict(cycle=7)),
-    dict(opt=dict(smoother=3)),
+    dict(opt=dict(smoother=9)),
+    dict(opt=dict(smoother=-1)),
+    dict(opt=dict(smoother=3, omega=0.0)),          # TRI_X needs a damping omega > 0
+    dict(opt=dict(smoother=5, omega=float("nan"))),  # ADI likewise
+    dict(grid=(65, 64, 0, 1, 1.0, 1.0), opt=dict(smoother=7), status=-4),  # y lines on a periodic direction
+    dict(grid=(65, 64, 0, 1, 1.0, 1.0), opt=dict(smoother=8), status=-4),
     dict(opt=dict(precision=5)),
     dict(opt=dict(smoother=0, omega=float("inf"))),
     dict(opt=dict(coarse_cta_nodes=-5)),
