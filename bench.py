@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="aniso1025", choices=["aniso1025", "annulus4097", "batch256", "grf2049"])
     ap.add_argument("--nu", type=int, default=2)
+    ap.add_argument("--smoother", default=None,
+                    choices=["tri_x", "tri_y", "adi", "gstri_x", "gstri_y", "gsadi"],
+                    help="aniso1025 / annulus4097 with a line smoother instead of the workload's point smoother")
+    ap.add_argument("--omega", type=float, default=0.8, help="damping of the TRI and ADI line smoothers")
     ap.add_argument("--x0", default="zero", choices=["zero", "uniform"])
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--max-cycles", type=int, default=20000)
@@ -229,7 +233,7 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(n, eps_list, cycles_per_eps, nu, seconds):
+def cpu_baseline(n, eps_list, cycles_per_eps, nu, seconds, smoother="rbgs", omega=0.8):
     """The oracle (FP64, scipy.sparse, one thread) runs F-cycles of the
     workload's hardest problem for about `seconds`; its time per cycle times
     the cycles the workload needs gives its unknowns/s."""
@@ -240,7 +244,7 @@ def cpu_baseline(n, eps_list, cycles_per_eps, nu, seconds):
 
     g = O.Grid(n, n)
     eps = min(eps_list)
-    h = O.hierarchy_5pt(g, eps, 1.0, O.Options(smoother="rbgs", nu_pre=nu, nu_post=nu))
+    h = O.hierarchy_5pt(g, eps, 1.0, O.Options(smoother=smoother, nu_pre=nu, nu_post=nu, omega=omega))
     b = g.pack(W.aniso_rhs(n, 2))
     x = np.zeros(g.n_unknowns)
     done = 0
@@ -279,9 +283,11 @@ def annulus(args):
     rhs = torch.tensor(W.annulus_rhs(nx, ny, 3), device="cuda")
     unknowns = (nx - 2) * ny
 
+    smoother = args.smoother or "gs4c"
+
     def make(precision):
-        return mg.Solver(nx, ny, periodic_y=True, kx=kxt, ky=kyt, kx_1d_along_x=True, smoother="gs4c",
-                         nu_pre=args.nu, nu_post=args.nu, precision=precision)
+        return mg.Solver(nx, ny, periodic_y=True, kx=kxt, ky=kyt, kx_1d_along_x=True, smoother=smoother,
+                         nu_pre=args.nu, nu_post=args.nu, omega=args.omega, precision=precision)
 
     def run(s, steps, warmup):
         x = torch.zeros_like(rhs)
@@ -304,20 +310,28 @@ def annulus(args):
     if info_h.status != mg.MG_OK:
         raise SystemExit(f"solve did not converge: {mg.status_string(info_h.status)} rel_res {info_h.rel_res:.3e}")
     scratch = torch.zeros_like(rhs)
-    times = {which: s.profile_pass(rhs, scratch, 0, which, reps=20) for which in (0, 1)}
-    dom = 1 if times[1] >= times[0] else 0
-    kernel_name = s.pass_kernel_name(0, dom)
-    levels01 = fine_levels_roofline(s, rhs, scratch, head, times, 20)
+    if args.smoother:
+        roofline = line_roofline(s, rhs, scratch, head, nx, ny, True, smoother, 1)
+    else:
+        times = {which: s.profile_pass(rhs, scratch, 0, which, reps=20) for which in (0, 1)}
+        dom = 1 if times[1] >= times[0] else 0
+        kernel_name = s.pass_kernel_name(0, dom)
+        levels01 = fine_levels_roofline(s, rhs, scratch, head, times, 20)
+        alg_bytes = BYTES_PER_NODE[(head, dom)] * nx * ny
+        achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic("annulus4097", kernel_name),
+                    "kernel": kernel_name, "avg_us": times[dom], "bytes_per_launch": alg_bytes,
+                    "bytes_per_node": BYTES_PER_NODE[(head, dom)], "nodes": nx * ny,
+                    "other_pass_us": times[1 - dom], "levels_0_1": levels01}
     s.close()
-    alg_bytes = BYTES_PER_NODE[(head, dom)] * nx * ny
-    achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
     s = make(other)
     steps_o = max(1, args.steps // 2)
     wall_o, info_o, _ = run(s, steps_o, 1)
     s.close()
     if args.calibrate_copy:
         calibrate_copy()
-    traffic = stored_traffic("annulus4097", kernel_name)
+    smoothing = SMOOTHER_NAMES[smoother] if args.smoother else "four-colour GS"
     out = {
         "metric": "unknowns/s to 1e-10 rel. residual",
         "value": unknowns * args.steps / wall_h,
@@ -332,12 +346,9 @@ def annulus(args):
         "dtype": "f32-inner/f64-outer" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": "annulus4097: polar annulus r in [0.5,1], theta periodic, mapped to the unit square, "
-                               "Q1 with kx=4 pi r, ky=1/(4 pi r), 4097x4096 nodes, f = N(0,1), four-colour GS "
+                               f"Q1 with kx=4 pi r, ky=1/(4 pi r), 4097x4096 nodes, f = N(0,1), {smoothing} "
                                f"{args.nu}/{args.nu}, F-cycle to 5x4, x0=0, tol 1e-10", "precision": head},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel_name,
-                     "avg_us": times[dom], "bytes_per_launch": alg_bytes, "bytes_per_node": BYTES_PER_NODE[(head, dom)],
-                     "nodes": nx * ny, "other_pass_us": times[1 - dom], "levels_0_1": levels01},
+        "roofline": roofline,
         "cycles": info_h.cycles,
         "rel_res": info_h.rel_res,
         "us_per_cycle": 1e6 * info_h.seconds / max(1, info_h.cycles),
@@ -347,11 +358,12 @@ def annulus(args):
         else ((wall_h / args.steps) / (wall_o / steps_o)),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_annulus(info_h.cycles, args.nu, args.cpu_seconds, unknowns)
+        out["cpu_baseline"] = cpu_baseline_annulus(info_h.cycles, args.nu, args.cpu_seconds, unknowns, smoother,
+                                                   args.omega)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_annulus(cycles, nu, seconds, unknowns_full):
+def cpu_baseline_annulus(cycles, nu, seconds, unknowns_full, smoother="gs4c", omega=0.8):
     """Oracle F-cycles on the 1025 x 1024 annulus for about `seconds`; its cost
     per unknown-cycle, scaled to the full grid and the cycles the full solve
     needs (the cycle's work is linear in the number of unknowns)."""
@@ -363,7 +375,7 @@ def cpu_baseline_annulus(cycles, nu, seconds, unknowns_full):
     n = 1025
     g = O.Grid(n, n - 1, periodic_y=True)
     kx, ky = W.annulus_cell_coefficients(n)
-    h = O.hierarchy_q1(g, kx, ky, O.Options(smoother="gs4c", nu_pre=nu, nu_post=nu), separable=True)
+    h = O.hierarchy_q1(g, kx, ky, O.Options(smoother=smoother, nu_pre=nu, nu_post=nu, omega=omega), separable=True)
     b = g.pack(W.annulus_rhs(n, n - 1, 3))
     x = np.zeros(g.n_unknowns)
     done = 0
@@ -377,6 +389,38 @@ def cpu_baseline_annulus(cycles, nu, seconds, unknowns_full):
             "sample": f"{done} FP64 F-cycles on the 1025x1024 annulus ({t:.2f} s per cycle), scaled linearly to "
                       f"4097x4096 and the {cycles} cycles of the full solve",
             "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
+
+
+# Line sweep (one launch of k_line), per node of the lines it solves: read b,
+# the off-line neighbours (once), the two Thomas factors, write and re-read the
+# forward-sweep value, write x: 7 values (+ six bands when they vary in 2-D).
+LINE_VALUES_PER_NODE = 7
+
+SMOOTHER_NAMES = {"tri_x": "TRI (x lines)", "tri_y": "TRI (y lines)", "adi": "ADI", "gstri_x": "GSTRI (x lines)",
+                  "gstri_y": "GSTRI (y lines)", "gsadi": "GSADI"}
+
+
+def line_roofline(s, rhs, scratch, head, nx, ny, periodic_y, smoother, stencil, bands_2d=False, reps=20):
+    """Roofline of the first line sweep of the finest level (one launch)."""
+    us = s.profile_pass(rhs, scratch, 0, 2, reps=reps)
+    w = 4 if head == "mixed" else 8
+    first_y = smoother in ("tri_y", "gstri_y")
+    jac = smoother in ("tri_x", "tri_y", "adi")
+    if first_y:
+        lines = [i for i in range(1, nx - 1) if jac or i % 2 == 0]
+        m = ny - 2
+    else:
+        rows = range(0, ny) if periodic_y else range(1, ny - 1)
+        lines = [j for j in rows if jac or j % 2 == 0]
+        m = nx - 2
+    nodes = len(lines) * m
+    bpn = (LINE_VALUES_PER_NODE + (6 if bands_2d else 0)) * w
+    alg = bpn * nodes
+    ach = alg / (us * 1e-6) / 1e9
+    t = "float" if head == "mixed" else "double"
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": None, "kernel": f"mg::k_line<{t}, {stencil}>", "avg_us": us, "bytes_per_launch": alg,
+            "bytes_per_node": bpn, "nodes": nodes}
 
 
 def _roofline_single(n, eps, head, nu):
@@ -638,9 +682,11 @@ def main():
     x0 = torch.tensor(W.aniso_x0(n, args.x0, 1), device="cuda")
     unknowns = (n - 2) ** 2
 
+    smoother = args.smoother or "rbgs"
+
     def make(precision):
-        return [mg.Solver(n, n, eps_x=e, smoother="rbgs", nu_pre=args.nu, nu_post=args.nu, precision=precision)
-                for e in eps_list]
+        return [mg.Solver(n, n, eps_x=e, smoother=smoother, nu_pre=args.nu, nu_post=args.nu, omega=args.omega,
+                          precision=precision) for e in eps_list]
 
     def run(solvers, steps, warmup):
         xs = [x0.clone() for _ in solvers]
@@ -670,13 +716,21 @@ def main():
     # roofline: finest-level post-pass of the headline precision, HIP events on the solver's stream
     scratch = x0.clone()
     s0 = solvers[0]
-    times = {which: s0.profile_pass(rhs, scratch, 0, which, reps=100) for which in (0, 1)}
-    dom = 1 if times[1] >= times[0] else 0
-    kernel_name = s0.pass_kernel_name(0, dom)
-    levels01 = fine_levels_roofline(s0, rhs, scratch, head, times, 100)
-    nodes = n * n
-    alg_bytes = BYTES_PER_NODE[(head, dom)] * nodes
-    achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
+    if args.smoother:
+        roofline = line_roofline(s0, rhs, scratch, head, n, n, False, smoother, 0, reps=100)
+    else:
+        times = {which: s0.profile_pass(rhs, scratch, 0, which, reps=100) for which in (0, 1)}
+        dom = 1 if times[1] >= times[0] else 0
+        kernel_name = s0.pass_kernel_name(0, dom)
+        levels01 = fine_levels_roofline(s0, rhs, scratch, head, times, 100)
+        nodes = n * n
+        alg_bytes = BYTES_PER_NODE[(head, dom)] * nodes
+        achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic("aniso1025", kernel_name),
+                    "kernel": kernel_name, "avg_us": times[dom], "bytes_per_launch": alg_bytes,
+                    "bytes_per_node": BYTES_PER_NODE[(head, dom)], "nodes": nodes,
+                    "other_pass_us": times[1 - dom], "levels_0_1": levels01}
     for s in solvers:
         s.close()
 
@@ -690,7 +744,7 @@ def main():
         calibrate_copy()
 
     total = unknowns * len(eps_list)
-    traffic = stored_traffic("aniso1025", kernel_name)
+    smoothing = SMOOTHER_NAMES[smoother] if args.smoother else "red-black GS"
     out = {
         "metric": "unknowns/s to 1e-10 rel. residual",
         "value": total * args.steps / wall_h,
@@ -705,14 +759,10 @@ def main():
         "dtype": "f32-inner/f64-outer" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": f"aniso1025: -(eps u_xx + u_yy) = N(0,1) on 1025x1025 nodes, eps in "
-                               f"{{{','.join(f'{e:g}' for e in eps_list)}}}, 5-point FD, red-black GS "
+                               f"{{{','.join(f'{e:g}' for e in eps_list)}}}, 5-point FD, {smoothing} "
                                f"{args.nu}/{args.nu}, F-cycle to 3x3, x0={args.x0}, tol 1e-10",
                    "precision": head},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kernel_name, "avg_us": times[dom], "bytes_per_launch": alg_bytes,
-                     "bytes_per_node": BYTES_PER_NODE[(head, dom)], "nodes": nodes,
-                     "other_pass_us": times[1 - dom], "levels_0_1": levels01},
+        "roofline": roofline,
         "cycles": {f"{e:g}": i.cycles for e, i in zip(eps_list, infos_h)},
         "rel_res": {f"{e:g}": i.rel_res for e, i in zip(eps_list, infos_h)},
         "us_per_cycle": {f"{e:g}": 1e6 * i.seconds / max(1, i.cycles) for e, i in zip(eps_list, infos_h)},
@@ -722,7 +772,8 @@ def main():
         else ((wall_h / args.steps) / (wall_o / steps_o)),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, eps_list, [i.cycles for i in infos_h], args.nu, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(n, eps_list, [i.cycles for i in infos_h], args.nu, args.cpu_seconds,
+                                           smoother, args.omega)
     print(json.dumps(out), flush=True)
 
 

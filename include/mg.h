@@ -173,12 +173,15 @@ mg_status mg_residual(mg_handle h, const double* rhs, const double* x, double* r
 mg_status mg_coeff_grad(mg_handle h, const double* u, const double* lam, double* dL_dk);
 
 /* Measurement helper (for benchmarks, not part of a solve): runs the fused
- * pre-pass (which = 0) or post-pass (which = 1) of `level` once, then `reps`
- * more times between two HIP events on the handle's stream, and returns the
- * average device time per launch in *avg_us.  rhs and x are the finest-level
- * arrays as for mg_solve; x is used as scratch and its content is
- * overwritten.  MG_EUNSUPPORTED if that level has no fused pass (it runs in
- * the single-workgroup coarse kernel or tile_mode is MG_TILES_PER_OP). */
+ * pre-pass (which = 0) or post-pass (which = 1) of `level` once, or with a
+ * line smoother (which = 2) the first line sweep of the level's smoothing (one
+ * launch: lines along the first swept direction, colour 0 or x -> t), then
+ * `reps` more times between two HIP events on the handle's stream, and
+ * returns the average device time per launch in *avg_us.  rhs and x are the
+ * finest-level arrays as for mg_solve; x is used as scratch and its content
+ * is overwritten.  MG_EUNSUPPORTED if that level has no such pass (it runs in
+ * the single-workgroup coarse kernel, tile_mode is MG_TILES_PER_OP, or the
+ * smoother is not of the asked kind). */
 mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t level, int32_t which, int32_t reps,
                           double* avg_us);
 

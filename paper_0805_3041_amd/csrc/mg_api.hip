@@ -803,6 +803,7 @@ mg_status setup_handle(mg_handle h, const mg_coeffs* coeffs, int32_t levels) {
     if (bad) return fail(h, MG_EINVAL, std::to_string(bad) + " coefficient values are not finite and > 0");
   }
   HIPCHK(h, h->mixed() ? prepare_subcycle_lds<float>() : prepare_subcycle_lds<double>());
+  if (h->line) HIPCHK(h, h->mixed() ? prepare_line_cr<float>() : prepare_line_cr<double>());
   HIPCHK(h, h->mixed() ? prepare_fused<float>() : prepare_fused<double>());
   for (Group& G : h->groups) {
     mg_status s = setup_group(h, G, coeffs, levels);
@@ -1180,14 +1181,16 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
   mg_status s = single_only(h);
   if (s != MG_OK) return s;
   if (!rhs || !x || !avg_us) return fail(h, MG_EINVAL, "rhs, x and avg_us must not be NULL");
-  if (which != 0 && which != 1) return fail(h, MG_EINVAL, "which must be 0 (pre-pass) or 1 (post-pass)");
+  if (which < 0 || which > 2) return fail(h, MG_EINVAL, "which must be 0 (pre-pass), 1 (post-pass) or 2 (line sweep)");
   if (reps < 1 || reps > 100000) return fail(h, MG_EINVAL, "reps must be in [1, 100000]");
   Group& G = h->groups[0];
   if (level < 0 || level >= G.nlev) return fail(h, MG_EINVAL, "level out of range");
   const HostOp* found = nullptr;
   for (const HostOp& op : G.prog)
-    if (op.type == (which == 0 ? H_PRE : H_POST) && op.level == level) found = &op;
-  if (!found) return fail(h, MG_EUNSUPPORTED, "no fused pass of that kind runs on this level");
+    if (op.type == (which == 0 ? H_PRE : (which == 1 ? H_POST : H_LINE)) && op.level == level && !found)
+      found = &op;
+  if (!found)
+    return fail(h, MG_EUNSUPPORTED, which == 2 ? "no line sweep runs on this level" : "no fused pass of that kind runs on this level");
   hipStream_t st = h->stream;
   const double* rr[1] = {rhs};
   double* xx[1] = {x};
@@ -1196,6 +1199,10 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
   const int l = level;
   const int kind = stencil_kind(h);
   auto launch = [&]() -> hipError_t {
+    if (which == 2) {
+      if (h->mixed()) return launch_line<float>(G.dL32 + l, G.shp[l], found->arg, (float)h->opts.omega, kind, 1, st);
+      return launch_line<double>(G.dL64 + l, G.shp[l], found->arg, h->opts.omega, kind, 1, st);
+    }
     if (h->mixed()) {
       if (which == 0)
         return launch_pre<float>(G.dL32 + l, G.dL32 + l + 1, G.gpre[l], h->opts.nu_pre, h->ncol,

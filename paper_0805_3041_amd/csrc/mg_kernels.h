@@ -37,7 +37,12 @@ hipError_t launch_coarse(const Level<T>* Ls, const double* const* chol, int n, i
 // Thomas factors of the lines along `dir` of one level (L: host copy of its descriptor)
 template <typename T>
 hipError_t launch_line_factor(const Level<T>& L, int dir, hipStream_t st);
-// one line-smoothing op (arg from line_arg) on level s of every slot
+// allows the cyclic-reduction line kernels their LDS (once per process)
+template <typename T>
+hipError_t prepare_line_cr();
+// one line-smoothing op (arg from line_arg) on level s of every slot: cyclic
+// reduction in LDS, one workgroup per line, or one thread per line (Thomas,
+// factors from setup) for lines too long for LDS
 template <typename T>
 hipError_t launch_line(const Level<T>* Ls, const LevelShape& s, int arg, T omega, int kind, int nslots,
                        hipStream_t st);

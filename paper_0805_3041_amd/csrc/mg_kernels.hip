@@ -282,7 +282,10 @@ __global__ void __launch_bounds__(LT) k_line(const Level<T>* __restrict__ Ls, in
   const T* cp = L.lcp[dir];
   const T* id = L.lid[dir];
   T* rp = L.lr;
+  // the loads of a node do not depend on the running recurrence: unrolled so
+  // that several nodes' loads are in flight at once
   T prev = (T)0;
+#pragma unroll 8
   for (int n = 0; n < m; ++n) {
     int i, j;
     line_node(dir, line, n, i, j);
@@ -298,12 +301,98 @@ __global__ void __launch_bounds__(LT) k_line(const Level<T>* __restrict__ Ls, in
     rp[q] = prev;
   }
   T u = (T)0;
+#pragma unroll 8
   for (int n = m - 1; n >= 0; --n) {
     int i, j;
     line_node(dir, line, n, i, j);
     const size_t q = (size_t)j * L.pitch + i;
     u = rp[q] - cp[q] * u;
     dst[q] = jac ? src[q] + omega * u : u;
+  }
+}
+
+// The same op by cyclic reduction in LDS: one workgroup per line.  The
+// line's tridiagonal system (a, d, c and the right-hand side of the Jacobi or
+// Gauss-Seidel form above) is loaded into LDS; forward reduction eliminates,
+// level by level, the couplings of the equations at (1-based) multiples of
+// 2s to their neighbours at distance s; the one equation left is solved and
+// back substitution recovers the rest, one barrier per level.  Every update
+// of a level reads equations no update of that level writes, so all arrays
+// are reduced in place.
+constexpr int LCR_NT = 256;                    // threads per line
+constexpr size_t LCR_LDS_MAX = 140 * 1024;     // lines with 4 m values up to this size use this kernel
+
+template <typename T, int K>
+__global__ void __launch_bounds__(LCR_NT) k_line_cr(const Level<T>* __restrict__ Ls, int arg, T omega) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const Level<T> L = Ls[blockIdx.z];
+  if (L.st->done) return;
+  const int dir = arg & 1, sel = arg >> 2;
+  const bool jac = (arg >> 1) & 1;
+  const int line = line_of(L, dir, jac, sel, blockIdx.x);
+  if (line < 0) return;  // uniform over the workgroup
+  const int tid = threadIdx.x;
+  const int m = dir == 0 ? L.nx - 2 : L.ny - 2;
+  MG_LDS T* A = lds_cast<T>(smem_raw);
+  MG_LDS T* D = A + m;
+  MG_LDS T* C = D + m;
+  MG_LDS T* R = C + m;
+  const T* src = (jac && sel) ? L.t : L.x;
+  T* dst = jac ? (sel ? L.x : L.t) : L.x;
+  for (int n = tid; n < m; n += LCR_NT) {
+    int i, j;
+    line_node(dir, line, n, i, j);
+    const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
+    const size_t q = (size_t)j * L.pitch + i;
+    const GX<T> g{src + (size_t)jm * L.pitch + i, src + q, src + (size_t)jp * L.pitch + i};
+    const Cf<T> cf = coefs<K>(L, i, j, jm);
+    T a, d, c;
+    line_coefs<K>(L, dir, cf, a, d, c);
+    A[n] = n == 0 ? (T)0 : a;          // the line's end nodes couple to boundary values (zero)
+    C[n] = n == m - 1 ? (T)0 : c;
+    D[n] = d;
+    R[n] = jac ? defect_v<K>(L, cf, gather<K>(L, g, true), L.b[q])
+               : L.b[q] - off_line<K>(L, dir, cf, gather<K>(L, g, false));
+  }
+  __syncthreads();
+  int s = 1;
+  for (; 2 * s <= m; s *= 2) {
+    for (int t = tid + 1; 2 * s * t <= m; t += LCR_NT) {
+      const int p = 2 * s * t - 1, pl = p - s, pr = p + s;  // 0-based; pl >= 0
+      const T al = -A[p] / D[pl];
+      T nd = D[p] + al * C[pl];
+      T nr = R[p] + al * R[pl];
+      T nc = (T)0;
+      if (pr < m) {
+        const T ga = -C[p] / D[pr];
+        nd += ga * A[pr];
+        nr += ga * R[pr];
+        nc = ga * C[pr];
+      }
+      A[p] = al * A[pl];
+      C[p] = nc;
+      D[p] = nd;
+      R[p] = nr;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) R[s - 1] = R[s - 1] / D[s - 1];  // the equation at s couples to nothing
+  __syncthreads();
+  for (s >>= 1; s >= 1; s >>= 1) {
+    for (int t = tid; (2 * t + 1) * s <= m; t += LCR_NT) {
+      const int p = (2 * t + 1) * s - 1, pl = p - s, pr = p + s;
+      T v = R[p];
+      if (pl >= 0) v -= A[p] * R[pl];
+      if (pr < m) v -= C[p] * R[pr];
+      R[p] = v / D[p];
+    }
+    __syncthreads();
+  }
+  for (int n = tid; n < m; n += LCR_NT) {
+    int i, j;
+    line_node(dir, line, n, i, j);
+    const size_t q = (size_t)j * L.pitch + i;
+    dst[q] = jac ? src[q] + omega * R[n] : R[n];
   }
 }
 
@@ -323,12 +412,31 @@ hipError_t launch_line_factor(const Level<T>& L, int dir, hipStream_t st) {
 }
 
 template <typename T>
+hipError_t prepare_line_cr() {
+  for (const void* k : {(const void*)k_line_cr<T, ST5>, (const void*)k_line_cr<T, ST9>}) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LCR_LDS_MAX);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
 hipError_t launch_line(const Level<T>* Ls, const LevelShape& s, int arg, T omega, int kind, int nslots,
                        hipStream_t st) {
   const int dir = arg & 1;
   const bool jac = (arg >> 1) & 1;
   int lines = dir == 0 ? s.nrows : s.nx - 2;
   if (!jac) lines = (lines + 1) / 2;
+  const int m = dir == 0 ? s.nx - 2 : s.ny - 2;
+  const size_t lds = 4 * (size_t)m * sizeof(T);
+  if (lds <= LCR_LDS_MAX) {
+    const dim3 grid(lines, 1, nslots);
+    if (kind == ST5)
+      hipLaunchKernelGGL((k_line_cr<T, ST5>), grid, dim3(LCR_NT), lds, st, Ls, arg, omega);
+    else
+      hipLaunchKernelGGL((k_line_cr<T, ST9>), grid, dim3(LCR_NT), lds, st, Ls, arg, omega);
+    return hipGetLastError();
+  }
   const dim3 grid((lines + LT - 1) / LT, 1, nslots);
   if (kind == ST5)
     hipLaunchKernelGGL((k_line<T, ST5>), grid, dim3(LT), 0, st, Ls, arg, omega);
@@ -1301,6 +1409,7 @@ hipError_t launch_coeff_grad(const double* u, const double* lam, double* g, int 
   template hipError_t launch_prolong<T>(const Level<T>*, const Level<T>*, const LevelShape&, int, hipStream_t);   \
   template hipError_t launch_coarse<T>(const Level<T>*, const double* const*, int, int, hipStream_t);             \
   template hipError_t launch_line_factor<T>(const Level<T>&, int, hipStream_t);                                    \
+  template hipError_t prepare_line_cr<T>();                                                                        \
   template hipError_t launch_line<T>(const Level<T>*, const LevelShape&, int, T, int, int, hipStream_t);          \
   template hipError_t launch_subcycle<T>(const Level<T>*, int, const DOp*, const int*, const int*,                \
                                          const double* const*, int, T, int, int, hipStream_t);                     \

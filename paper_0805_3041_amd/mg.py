@@ -332,7 +332,8 @@ class Solver:
         return mg_coeff_grad(self.h, u, lam, out)
 
     def profile_pass(self, rhs: torch.Tensor, x: torch.Tensor, level: int, which: int, reps: int = 50) -> float:
-        """Average device time (us) of one fused pre-pass (which=0) or post-pass (1) on `level`."""
+        """Average device time (us) of one fused pre-pass (which=0) or post-pass (1) on `level`, or with
+        a line smoother (which=2) of its first line sweep."""
         return mg_profile_pass(self.h, rhs, x, level, which, reps)
 
     def pass_info(self, level: int, which: int) -> dict:

@@ -1,5 +1,6 @@
 """GPU parity of the line smoothers (TRI, ADI, GSTRI, GSADI): the library's
-line sweeps (one thread per line, Thomas factors formed at setup) against the
+line sweeps (cyclic reduction in LDS, one workgroup per line; one thread per
+line with Thomas factors from setup for lines too long for LDS) against the
 oracle's sparse line solves on the same seeded inputs, per cycle to 1e-12
 relative max-norm in FP64; cycle counts to tolerance equal; the mixed form
 reaches the tolerance; unsupported combinations are rejected."""
@@ -103,3 +104,15 @@ def test_unsupported_combinations_are_rejected():
     with pytest.raises(mg.MGError) as e:
         Problem(65, 65, smoother="tri_x", omega=0.0).solver()
     assert e.value.status == mg.MG_EINVAL
+
+
+@pytest.mark.parametrize("smoother", ["tri_x", "gstri_x"])
+def test_long_lines_use_the_thread_per_line_solver(smoother):
+    """4609 x 17 nodes: the finest x lines (4607 unknowns, 4 x 4607 FP64 values
+    > 140 KB of LDS) are solved by one thread each with the Thomas factors from
+    setup, the coarser ones by cyclic reduction; both agree with the oracle.
+    A line solve is global along the line, so two correct solve orders differ
+    by about cond(T) u: eps = 0.01 keeps cond(T) near 2.5e3 on these lines
+    (at eps = 4 it is 6e5 and the difference reaches 1e-12)."""
+    p = Problem(4609, 17, eps=0.01, smoother=smoother, omega=0.8)
+    check_parity(p, W.normal_field(4609, 17, 2), np.zeros((17, 4609)), 3)
