@@ -438,7 +438,7 @@ def coloured_gs_step(A, diag, x, b, colours, omega=1.0):
 
 @dataclass
 class Options:
-    cycle: str = "F"          # "F" or "V"
+    cycle: str = "F"          # "F", "V" or "W"
     smoother: str = "rbgs"    # "jacobi", "rbgs" (2 colours), "gs4c" (4 colours), or one of LINE_SMOOTHERS
     nu_pre: int = 2
     nu_post: int = 2
@@ -544,10 +544,11 @@ def coarse_solve(h: Hierarchy, g):
 
 
 def mg_cycle(h: Hierarchy, l: int, x, g, kind: str = "F"):
-    """MG(l, u, g) of "The Multigrid Technique" with p = 1 for a V-cycle; an
-    F-cycle gives the coarse problem one F-cycle then one V-cycle, each level's
-    coarse start being zero.  Level 0 is the finest here (the paper counts
-    levels upwards from 1 = coarsest)."""
+    """MG(l, u, g) of "The Multigrid Technique" with p = 1 for a V-cycle and
+    p = 2 for a W-cycle (two recursive W-cycles, the second starting from the
+    first's result); an F-cycle gives the coarse problem one F-cycle then one
+    V-cycle.  Each level's coarse start is zero.  Level 0 is the finest here
+    (the paper counts levels upwards from 1 = coarsest)."""
     if l == h.nlevels - 1:
         return coarse_solve(h, g)
     o = h.opts
@@ -558,6 +559,9 @@ def mg_cycle(h: Hierarchy, l: int, x, g, kind: str = "F"):
     if kind == "F":
         e = mg_cycle(h, l + 1, e, gc, "F")
         e = mg_cycle(h, l + 1, e, gc, "V")
+    elif kind == "W":
+        e = mg_cycle(h, l + 1, e, gc, "W")
+        e = mg_cycle(h, l + 1, e, gc, "W")
     else:
         e = mg_cycle(h, l + 1, e, gc, "V")
     x = x + h.P[l] @ e                                    # u += omega_l P u_{l-1}, omega_l = 1

@@ -387,6 +387,7 @@ def _dense_error_propagators(h, kind):
     """Error propagation of the recursive algorithm written as dense matrices:
     E_V(l) = S_post (I - P (I - E_V(l+1)) A_{l+1}^{-1} R A_l) S_pre,
     E_F(l) = S_post (I - P (I - E_V(l+1) E_F(l+1)) A_{l+1}^{-1} R A_l) S_pre,
+    E_W(l) = S_post (I - P (I - E_W(l+1)^2) A_{l+1}^{-1} R A_l) S_pre,
     E(coarsest) = 0; S from the smoother's C (I - omega D^{-1} A, or I - (D + L)^{-1} A per colour order)."""
     L = h.nlevels
     def S(l):
@@ -401,8 +402,10 @@ def _dense_error_propagators(h, kind):
         return Q.T @ Sp @ Q
     EV = [None] * L
     EF = [None] * L
+    EW = [None] * L
     EV[L - 1] = np.zeros((h.grids[-1].n_unknowns,) * 2)
     EF[L - 1] = EV[L - 1]
+    EW[L - 1] = EV[L - 1]
     for l in range(L - 2, -1, -1):
         A = h.A[l].toarray()
         Ac = h.A[l + 1].toarray()
@@ -414,21 +417,35 @@ def _dense_error_propagators(h, kind):
         I = np.eye(A.shape[0])
         EV[l] = Spost @ (I - P @ (np.eye(Ac.shape[0]) - EV[l + 1]) @ cgc) @ Spre
         EF[l] = Spost @ (I - P @ (np.eye(Ac.shape[0]) - EV[l + 1] @ EF[l + 1]) @ cgc) @ Spre
-    return EF[0] if kind == "F" else EV[0]
+        EW[l] = Spost @ (I - P @ (np.eye(Ac.shape[0]) - EW[l + 1] @ EW[l + 1]) @ cgc) @ Spre
+    return {"F": EF, "V": EV, "W": EW}[kind][0]
 
 
 @pytest.mark.parametrize("smoother,levels", [("rbgs", 3), ("jacobi", 4), ("rbgs", 2)])
 def test_cycle_matrix_equals_dense_recursion(smoother, levels):
-    """The oracle's F- and V-cycle iteration matrices equal the dense
-    error-propagation recursion; with 2 levels F = V = two-grid."""
+    """The oracle's F-, V- and W-cycle iteration matrices equal the dense
+    error-propagation recursion; with 2 levels F = V = W = two-grid."""
     g = O.Grid(17, 17)
     h = O.hierarchy_5pt(g, 0.5, 1.0, O.Options(smoother=smoother, nu_pre=2, nu_post=1), levels=levels)
-    for kind in ("F", "V"):
+    for kind in ("F", "V", "W"):
         M = O.cycle_matrix(h, kind)
         E = _dense_error_propagators(h, kind)
         np.testing.assert_allclose(M, E, atol=1e-11)
     if levels == 2:
         np.testing.assert_allclose(O.cycle_matrix(h, "F"), O.cycle_matrix(h, "V"), atol=1e-14)
+        np.testing.assert_allclose(O.cycle_matrix(h, "W"), O.cycle_matrix(h, "V"), atol=1e-14)
+
+
+def test_w_cycle_rate_between_two_grid_and_v():
+    """W-cycles come closer to the two-grid rate than V-cycles: on 33^2
+    Poisson with red-black GS 1/1, rho(two-grid) <= rho(W) <= rho(V)."""
+    g = O.Grid(33, 33)
+    opts = O.Options(smoother="rbgs", nu_pre=1, nu_post=1)
+    rho = {}
+    for kind, levels in (("two-grid", 2), ("W", 0), ("V", 0)):
+        h = O.hierarchy_5pt(g, 1.0, 1.0, opts, levels=levels)
+        rho[kind] = max(abs(np.linalg.eigvals(O.cycle_matrix(h, "V" if kind == "two-grid" else kind))))
+    assert rho["two-grid"] <= rho["W"] + 1e-12 <= rho["V"] + 2e-12
 
 
 def test_cycle_matrix_q1_gs4c_dense_recursion():
