@@ -59,7 +59,10 @@ typedef enum {
 } mg_status;
 
 enum { MG_COEF_CONST5 = 0, MG_COEF_CELL9 = 1 };
-enum { MG_CYCLE_F = 0, MG_CYCLE_V = 1 };
+/* Cycles (MG(l, u, g) of "The Multigrid Technique"): F gives the coarse
+ * problem one F-cycle then one V-cycle; V one V-cycle (p = 1); W two
+ * W-cycles, the second from the first's result (p = 2). */
+enum { MG_CYCLE_F = 0, MG_CYCLE_V = 1, MG_CYCLE_W = 2 };
 /* Smoothers (the preconditioner C of the Richardson step x <- x + omega
  * C^-1 (b - A x), "The choice of C" and "Smoothing"): damped point Jacobi;
  * point Gauss-Seidel in red-black (5-point) or four-colour (9-point) order;

@@ -218,6 +218,9 @@ struct Gen {
     if (kind == MG_CYCLE_F) {
       expand(out, l + 1, MG_CYCLE_F);
       expand(out, l + 1, MG_CYCLE_V);
+    } else if (kind == MG_CYCLE_W) {
+      expand(out, l + 1, MG_CYCLE_W);
+      expand(out, l + 1, MG_CYCLE_W);
     } else {
       expand(out, l + 1, MG_CYCLE_V);
     }
@@ -251,6 +254,9 @@ struct Gen {
     if (kind == MG_CYCLE_F) {
       host(out, subs, l + 1, MG_CYCLE_F);
       host(out, subs, l + 1, MG_CYCLE_V);
+    } else if (kind == MG_CYCLE_W) {
+      host(out, subs, l + 1, MG_CYCLE_W);
+      host(out, subs, l + 1, MG_CYCLE_W);
     } else {
       host(out, subs, l + 1, MG_CYCLE_V);
     }
@@ -500,7 +506,8 @@ bool line_jacobi(int smoother) {
 
 mg_status check_opts(const mg_options* o, int kind) {
   if (!o) return fail(nullptr, MG_EINVAL, "options is NULL");
-  if (o->cycle != MG_CYCLE_F && o->cycle != MG_CYCLE_V) return fail(nullptr, MG_EINVAL, "cycle must be F or V");
+  if (o->cycle != MG_CYCLE_F && o->cycle != MG_CYCLE_V && o->cycle != MG_CYCLE_W)
+    return fail(nullptr, MG_EINVAL, "cycle must be F, V or W");
   if (o->smoother < MG_SMOOTH_JACOBI || o->smoother > MG_SMOOTH_GSADI) return fail(nullptr, MG_EINVAL, "bad smoother");
   if (o->smoother == MG_SMOOTH_RBGS && kind == MG_COEF_CELL9)
     return fail(nullptr, MG_EUNSUPPORTED, "red-black ordering does not decouple the 9-point stencil; use GS4C");

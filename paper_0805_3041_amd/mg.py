@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmg.so")
 MG_OK, MG_NOT_CONVERGED, MG_DIVERGED = 0, 1, 2
 MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_EUNSUPPORTED = -1, -2, -3, -4
 MG_COEF_CONST5, MG_COEF_CELL9 = 0, 1
-MG_CYCLE_F, MG_CYCLE_V = 0, 1
+MG_CYCLE_F, MG_CYCLE_V, MG_CYCLE_W = 0, 1, 2
 MG_SMOOTH_JACOBI, MG_SMOOTH_RBGS, MG_SMOOTH_GS4C = 0, 1, 2
 MG_SMOOTH_TRI_X, MG_SMOOTH_TRI_Y, MG_SMOOTH_ADI = 3, 4, 5
 MG_SMOOTH_GSTRI_X, MG_SMOOTH_GSTRI_Y, MG_SMOOTH_GSADI = 6, 7, 8
@@ -30,7 +30,7 @@ MG_TILES_FUSED, MG_TILES_PER_OP, MG_TILES_NARROW, MG_TILES_WIDE = 0, 1, 2, 3
 SMOOTHERS = {"jacobi": MG_SMOOTH_JACOBI, "rbgs": MG_SMOOTH_RBGS, "gs4c": MG_SMOOTH_GS4C,
              "tri_x": MG_SMOOTH_TRI_X, "tri_y": MG_SMOOTH_TRI_Y, "adi": MG_SMOOTH_ADI,
              "gstri_x": MG_SMOOTH_GSTRI_X, "gstri_y": MG_SMOOTH_GSTRI_Y, "gsadi": MG_SMOOTH_GSADI}
-CYCLES = {"F": MG_CYCLE_F, "V": MG_CYCLE_V}
+CYCLES = {"F": MG_CYCLE_F, "V": MG_CYCLE_V, "W": MG_CYCLE_W}
 PRECISIONS = {"fp64": MG_PREC_FP64, "mixed": MG_PREC_MIXED}
 
 EXPORTED = (

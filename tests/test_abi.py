@@ -65,6 +65,7 @@ def _setup(mg, grid, coeffs, levels=0, **opt):
     dict(opt=dict(nu_pre=9)),
     dict(opt=dict(nu_post=-1)),
     dict(opt=dict(cycle=7)),
+    dict(opt=dict(cycle=3)),
     dict(opt=dict(smoother=9)),
     dict(opt=dict(smoother=-1)),
     dict(opt=dict(smoother=3, omega=0.0)),          # TRI_X needs a damping omega > 0

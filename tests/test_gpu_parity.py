@@ -150,6 +150,21 @@ def test_v_cycle(smoother):
     check_parity(p, W.normal_field(65, 65, 7), np.zeros((65, 65)), 3, coarse_cta_nodes=300)
 
 
+@pytest.mark.parametrize("cta", [0, 300])
+@pytest.mark.parametrize("smoother", ["jacobi", "rbgs", "gstri_y"])
+def test_w_cycle(smoother, cta):
+    """W-cycles (two recursive W-cycles per level) through the fused passes,
+    the one-workgroup coarse kernel in LDS (cta 0) or in global memory
+    (cta 300), and the line sweeps."""
+    p = Problem(129, 129, eps=0.1, smoother=smoother, cycle="W", nu_pre=1, nu_post=1)
+    check_parity(p, W.normal_field(129, 129, 7), W.uniform_field(129, 129, 1), 3, coarse_cta_nodes=cta)
+
+
+def test_w_cycle_annulus():
+    p = Problem(129, 128, periodic_y=True, q1="annulus", smoother="gs4c", cycle="W")
+    check_parity(p, W.normal_field(129, 128, 3, True), np.zeros((128, 129)), 2)
+
+
 @pytest.mark.slow
 def test_aniso1025_full_size_two_cycles():
     n = 1025
