@@ -27,6 +27,7 @@ better Multigrid Solver Convergence", KAIST 2008):
   restrict the defect, solve recursively from a zero start, add the prolonged
   correction with omega_l = 1, post-smooth, exact solve on the coarsest level),
   run as the F-cycle the Abstract names;
+* a start vector by nested iteration ("Start-Vector Choice");
 * the stopping test on the relative residual, a mixed-precision
   defect-correction form, and the adjoint gradient of a least-squares loss with
   respect to the per-cell coefficient.
@@ -566,6 +567,23 @@ def mg_cycle(h: Hierarchy, l: int, x, g, kind: str = "F"):
         e = mg_cycle(h, l + 1, e, gc, "V")
     x = x + h.P[l] @ e                                    # u += omega_l P u_{l-1}, omega_l = 1
     return smooth(h, l, x, g, o.nu_post)                  # post-smoothing
+
+
+def nested_start(h: Hierarchy, b, kind: str = None):
+    """Start vector by nested iteration ("Start-Vector Choice": begin on the
+    coarsest level and work up to the finest): the right-hand side is
+    restricted to every level (b_{l+1} = R b_l), the coarsest problem is solved
+    exactly, and on each finer level l >= 1 the prolonged coarser result is
+    improved by one cycle of the hierarchy's kind with rhs b_l; the finest
+    start is the prolongation of level 1's result."""
+    kind = kind or h.opts.cycle
+    bs = [np.asarray(b, dtype=np.float64)]
+    for l in range(h.nlevels - 1):
+        bs.append(h.R[l] @ bs[-1])
+    x = coarse_solve(h, bs[-1])
+    for l in range(h.nlevels - 2, 0, -1):
+        x = mg_cycle(h, l, h.P[l] @ x, bs[l], kind)
+    return h.P[0] @ x if h.nlevels > 1 else x
 
 
 def residual_norm(h: Hierarchy, b, x) -> float:

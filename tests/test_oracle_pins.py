@@ -634,3 +634,53 @@ def test_hierarchy_shapes():
     assert gs[0].n_unknowns == 4095 * 4096
     with pytest.raises(ValueError):
         O.hierarchy_grids(O.Grid(65, 65), levels=7)
+
+
+# ----------------------------------------------------------------- nested-iteration start vector
+
+
+def test_nested_start_two_levels_is_coarse_grid_solution():
+    """With two levels the start is P A_1^{-1} R b (dense solve)."""
+    g = O.Grid(17, 17)
+    h = O.hierarchy_5pt(g, 0.3, 1.0, O.Options(), levels=2)
+    b = np.random.default_rng(4).standard_normal(g.n_unknowns)
+    want = h.P[0].toarray() @ np.linalg.solve(h.A[1].toarray(), h.R[0].toarray() @ b)
+    np.testing.assert_allclose(O.nested_start(h, b), want, rtol=1e-12, atol=1e-13 * np.abs(want).max())
+
+
+def test_nested_start_three_levels_composition():
+    """With three levels: x_2 = A_2^{-1} R R b (dense), one cycle on level 1
+    from P x_2 (its error propagation from the dense recursion), then P."""
+    g = O.Grid(17, 17)
+    h = O.hierarchy_5pt(g, 1.0, 1.0, O.Options(smoother="jacobi", omega=0.8, nu_pre=1, nu_post=1), levels=3)
+    b = np.random.default_rng(5).standard_normal(g.n_unknowns)
+    R0, R1, P0, P1 = (m.toarray() for m in (h.R[0], h.R[1], h.P[0], h.P[1]))
+    A1, A2 = h.A[1].toarray(), h.A[2].toarray()
+    b1 = R0 @ b
+    x1_exact = np.linalg.solve(A1, b1)
+    start1 = P1 @ np.linalg.solve(A2, R1 @ b1)
+    # one two-grid cycle on level 1 (its coarse level is the exact coarsest solve):
+    n1 = A1.shape[0]
+    S = np.eye(n1) - 0.8 * A1 / np.diag(A1)[:, None]
+    E = S @ (np.eye(n1) - P1 @ np.linalg.solve(A2, R1 @ A1)) @ S
+    x1 = x1_exact + E @ (start1 - x1_exact)
+    want = P0 @ x1
+    np.testing.assert_allclose(O.nested_start(h, b), want, rtol=1e-11, atol=1e-12 * np.abs(want).max())
+
+
+def test_nested_start_is_second_order_accurate():
+    """Nested iteration reaches the discretisation's order: for the
+    manufactured sine problem the start vector's distance to the discrete
+    solution falls by 4 per halving of h (65^2, 129^2, 257^2), like the
+    discretisation error itself, so cycles from it only need to remove a
+    fixed factor of error on every grid."""
+    errs = []
+    for n in (65, 129, 257):
+        g = O.Grid(n, n)
+        h = O.hierarchy_5pt(g, 1.0, 1.0, O.Options(smoother="rbgs", cycle="F"))
+        f, u = W.manufactured_sine(n)
+        b = g.pack(f)
+        x_disc = O.solve(h, b, np.zeros(g.n_unknowns), 1e-13, 50).x
+        errs.append(np.abs(O.nested_start(h, b) - x_disc).max())
+    for a, c in zip(errs, errs[1:]):
+        assert 3.5 < a / c < 4.5, errs
