@@ -175,6 +175,16 @@ mg_status mg_residual(mg_handle h, const double* rhs, const double* x, double* r
  * arrays [ny][nx]; dL_dk: device cell array [ncy][ncx]. */
 mg_status mg_coeff_grad(mg_handle h, const double* u, const double* lam, double* dL_dk);
 
+/* Start vector by nested iteration ("Start-Vector Choice": begin on the
+ * coarsest level and work up to the finest): rhs is restricted by full
+ * weighting to every level, the coarsest problem solved exactly, and on each
+ * finer level below the finest the prolonged coarser result is improved by
+ * one cycle of the handle's kind; x (device, [ny][nx], overwritten) receives
+ * the prolongation of that result, ready for mg_solve.  The mixed form runs
+ * it in FP32 on (float) rhs.  Single-problem handles only (MG_EUNSUPPORTED
+ * for batched ones); MG_EINVAL for NULL arrays. */
+mg_status mg_start_nested(mg_handle h, const double* rhs, double* x);
+
 /* Measurement helper (for benchmarks, not part of a solve): runs the fused
  * pre-pass (which = 0) or post-pass (which = 1) of `level` once, or with a
  * line smoother (which = 2) the first line sweep of the level's smoothing (one

@@ -938,6 +938,29 @@ mg_status finish_solve(mg_handle h, float* ms) {
   return MG_OK;
 }
 
+// Nested iteration on the hierarchy of type T (the one the cycles run on),
+// its finest x zero and its finest b the right-hand side: restrictions down,
+// the coarsest solve, then per level upwards the prolongation and one cycle,
+// finally the prolongation into the finest x.  Every op is its own launch.
+template <typename T>
+hipError_t nested_pass(mg_handle h, Group& G, Level<T>* dL, Level<T>* dP, T omega, hipStream_t st) {
+  const int c = G.nlev - 1;
+  Gen g{h, G, 0};
+  hipError_t e = hipSuccess;
+  auto run = [&](int type, int l) { return run_op<T>(h, G, HostOp{type, l, 0, -1}, dL, dP, omega, st); };
+  for (int l = 0; l < c; ++l)  // b_{l+1} = R b_l (x_l = 0), x_{l+1} = 0
+    if ((e = run(H_DR, l)) != hipSuccess) return e;
+  if ((e = run(H_COARSE, c)) != hipSuccess) return e;
+  for (int l = c - 1; l >= 1; --l) {
+    if ((e = run(H_PROLONG, l)) != hipSuccess) return e;  // x_l = P x_{l+1}
+    std::vector<Abs> ops;
+    g.expand(ops, l, h->opts.cycle);
+    for (const Abs& a : ops)
+      if ((e = run_op<T>(h, G, HostOp{a.type, a.level, a.arg, -1}, dL, dP, omega, st)) != hipSuccess) return e;
+  }
+  return c >= 1 ? run(H_PROLONG, 0) : hipSuccess;
+}
+
 }  // namespace
 
 // ============================================================================ C ABI
@@ -1232,6 +1255,31 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
   *avg_us = 1e3 * ms / reps;
   return MG_OK;
+}
+
+mg_status mg_start_nested(mg_handle h, const double* rhs, double* x) {
+  mg_status s = single_only(h);
+  if (s != MG_OK) return s;
+  if (!rhs || !x) return fail(h, MG_EINVAL, "rhs and x must be device arrays");
+  Group& G = h->groups[0];
+  const LevelShape& s0 = G.shp[0];
+  hipStream_t st = h->stream;
+  HIPCHK(h, hipMemsetAsync(x, 0, (size_t)s0.nx * s0.ny * sizeof(double), st));
+  if (h->mixed()) {
+    const Level<float>& E = G.l32(0, 0);
+    HIPCHK(h, hipMemsetAsync(E.x, 0, (size_t)E.pitch * s0.ny * sizeof(float), st));
+  }
+  const double* rr[1] = {rhs};
+  double* xx[1] = {x};
+  s = begin_solve(h, rr, xx, 1e-300);  // descriptors; r0 = ||b|| (mixed: the FP32 finest rhs = (float) b)
+  if (s != MG_OK) return s;
+  if (h->mixed()) {
+    HIPCHK(h, nested_pass<float>(h, G, G.dL32, G.dP32, (float)h->opts.omega, st));
+    HIPCHK(h, launch_outer_update(G.dL64, G.dL32, s0, 1, st));  // x = (double) e, e = 0
+  } else {
+    HIPCHK(h, nested_pass<double>(h, G, G.dL64, G.dP64, h->opts.omega, st));
+  }
+  return sync_check(h);
 }
 
 mg_status mg_coeff_grad(mg_handle h, const double* u, const double* lam, double* dL_dk) {

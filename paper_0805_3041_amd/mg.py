@@ -36,7 +36,7 @@ PRECISIONS = {"fp64": MG_PREC_FP64, "mixed": MG_PREC_MIXED}
 EXPORTED = (
     "mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
     "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_shape", "mg_num_levels", "mg_profile_pass",
-    "mg_pass_info",
+    "mg_pass_info", "mg_start_nested",
 )
 
 
@@ -95,8 +95,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_profile_pass.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, P(ctypes.c_double)]
     lib.mg_pass_info.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32)]
+    lib.mg_start_nested.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     for name in ("mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
-                 "mg_destroy", "mg_level_shape", "mg_profile_pass", "mg_pass_info"):
+                 "mg_destroy", "mg_level_shape", "mg_profile_pass", "mg_pass_info", "mg_start_nested"):
         getattr(lib, name).restype = ctypes.c_int
     lib.mg_num_levels.restype = ctypes.c_int32
     _lib = lib
@@ -193,6 +194,13 @@ def mg_coeff_grad(h, u: torch.Tensor, lam: torch.Tensor, out: torch.Tensor) -> t
     if s != MG_OK:
         raise MGError(s, last_error(h))
     return out
+
+
+def mg_start_nested(h, rhs: torch.Tensor, x: torch.Tensor) -> None:
+    lib = load_library()
+    s = lib.mg_start_nested(h, _ptr(rhs), _ptr(x))
+    if s != MG_OK:
+        raise MGError(s, last_error(h))
 
 
 def mg_profile_pass(h, rhs: torch.Tensor, x: torch.Tensor, level: int, which: int, reps: int) -> float:
@@ -330,6 +338,12 @@ class Solver:
         ncy = self.ny if self.periodic_y else self.ny - 1
         out = torch.empty((ncy, self.nx - 1), dtype=torch.float64, device=u.device)
         return mg_coeff_grad(self.h, u, lam, out)
+
+    def nested_start(self, rhs: torch.Tensor, x: torch.Tensor) -> None:
+        """Overwrite x with the nested-iteration start vector for rhs (mg_start_nested)."""
+        _check_f64(rhs, (self.ny, self.nx), "rhs")
+        _check_f64(x, (self.ny, self.nx), "x")
+        mg_start_nested(self.h, rhs, x)
 
     def profile_pass(self, rhs: torch.Tensor, x: torch.Tensor, level: int, which: int, reps: int = 50) -> float:
         """Average device time (us) of one fused pre-pass (which=0) or post-pass (1) on `level`, or with

@@ -424,3 +424,62 @@ def test_asymptotic_rate_matches_cycle_matrix_spectral_radius(case):
     assert len(h) == 41 and np.all(h > 0)
     rate = (h[-1] / h[-11]) ** 0.1
     assert abs(rate - rho) <= 0.05 * rho, (rate, rho)
+
+
+# ----------------------------------------------------------------------------- nested-iteration start vector
+
+
+NESTED_CASES = [
+    dict(nx=65, ny=65, eps=1.0, smoother="rbgs", cycle="F"),
+    dict(nx=129, ny=129, eps=0.1, smoother="rbgs", cycle="V"),
+    dict(nx=65, ny=65, eps=1.0, smoother="jacobi", cycle="W"),
+    dict(nx=129, ny=128, periodic_y=True, q1="annulus", smoother="gs4c", cycle="F"),
+    dict(nx=129, ny=129, eps=1e-3, smoother="gstri_y", cycle="F"),
+]
+
+
+@pytest.mark.parametrize("case", NESTED_CASES, ids=[str(i) for i in range(len(NESTED_CASES))])
+def test_nested_start_matches_oracle(case):
+    """mg_start_nested against the oracle's nested iteration (1e-12), then a
+    solve from it needs no more cycles than from zero."""
+    p = Problem(**case)
+    g = p.grid()
+    rhs = p.rhs(5)
+    want = O.nested_start(p.oracle(), g.pack(rhs))
+    s = p.solver()
+    try:
+        r = torch.tensor(rhs, device="cuda")
+        x = torch.full_like(r, 3.0)  # overwritten
+        s.nested_start(r, x)
+        got = x.cpu().numpy()
+        err = np.abs(g.pack(got) - want).max() / np.abs(want).max()
+        assert err <= PARITY, err
+        full = g.unpack(want)
+        assert np.all(got[full == 0] == 0) or p.periodic_y
+        info_n = s.solve(r, x, tol=1e-10, max_cycles=200)
+        x.zero_()
+        info_z = s.solve(r, x, tol=1e-10, max_cycles=200)
+    finally:
+        s.close()
+    assert info_n.status == 0 and info_z.status == 0
+    assert info_n.cycles <= info_z.cycles
+
+
+def test_nested_start_mixed_precision():
+    """The mixed form runs the nested iteration in FP32: the start is within
+    FP32 rounding of the oracle's FP64 one and the solve converges from it."""
+    p = Problem(257, 257, eps=1.0, smoother="rbgs")
+    g = p.grid()
+    rhs = p.rhs(5)
+    want = O.nested_start(p.oracle(), g.pack(rhs))
+    s = p.solver(precision="mixed")
+    try:
+        r = torch.tensor(rhs, device="cuda")
+        x = torch.zeros_like(r)
+        s.nested_start(r, x)
+        err = np.abs(g.pack(x.cpu().numpy()) - want).max() / np.abs(want).max()
+        assert err <= 1e-5, err
+        info = s.solve(r, x, tol=1e-10, max_cycles=100)
+    finally:
+        s.close()
+    assert info.status == 0
