@@ -42,7 +42,9 @@ def parse():
                     choices=["tri_x", "tri_y", "adi", "gstri_x", "gstri_y", "gsadi"],
                     help="aniso1025 / annulus4097 with a line smoother instead of the workload's point smoother")
     ap.add_argument("--omega", type=float, default=0.8, help="damping of the TRI and ADI line smoothers")
-    ap.add_argument("--x0", default="zero", choices=["zero", "uniform"])
+    ap.add_argument("--x0", default="zero", choices=["zero", "uniform", "nested"],
+                    help="start vector; nested = mg_start_nested inside the timed region")
+    ap.add_argument("--levels", type=int, default=0, help="number of levels (0 = coarsen as far as possible)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--max-cycles", type=int, default=20000)
     ap.add_argument("--eps", type=float, default=None, help="one eps of the workload only (profiling runs)")
@@ -287,18 +289,24 @@ def annulus(args):
 
     def make(precision):
         return mg.Solver(nx, ny, periodic_y=True, kx=kxt, ky=kyt, kx_1d_along_x=True, smoother=smoother,
-                         nu_pre=args.nu, nu_post=args.nu, omega=args.omega, precision=precision)
+                         nu_pre=args.nu, nu_post=args.nu, omega=args.omega, precision=precision, levels=args.levels)
+
+    def start(s, x):
+        if args.x0 == "nested":
+            s.nested_start(rhs, x)
+        else:
+            x.zero_()
 
     def run(s, steps, warmup):
         x = torch.zeros_like(rhs)
         for _ in range(warmup):
-            x.zero_()
+            start(s, x)
             s.solve(rhs, x, TOL, args.max_cycles, history=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = None
         for _ in range(steps):
-            x.zero_()
+            start(s, x)
             info = s.solve(rhs, x, TOL, args.max_cycles, history=False)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, info, x
@@ -347,7 +355,9 @@ def annulus(args):
         "data": "synthetic",
         "config": {"workload": "annulus4097: polar annulus r in [0.5,1], theta periodic, mapped to the unit square, "
                                f"Q1 with kx=4 pi r, ky=1/(4 pi r), 4097x4096 nodes, f = N(0,1), {smoothing} "
-                               f"{args.nu}/{args.nu}, F-cycle to 5x4, x0=0, tol 1e-10", "precision": head},
+                               f"{args.nu}/{args.nu}, F-cycle to "
+                               + (f"{args.levels} levels" if args.levels else "5x4")
+                               + f", x0={'nested' if args.x0 == 'nested' else '0'}, tol 1e-10", "precision": head},
         "roofline": roofline,
         "cycles": info_h.cycles,
         "rel_res": info_h.rel_res,
@@ -679,20 +689,26 @@ def main():
     n = 1025
     eps_list = list(W.ANISO_EPS) if args.eps is None else [args.eps]
     rhs = torch.tensor(W.aniso_rhs(n, 2), device="cuda")
-    x0 = torch.tensor(W.aniso_x0(n, args.x0, 1), device="cuda")
+    x0 = torch.tensor(W.aniso_x0(n, "zero" if args.x0 == "nested" else args.x0, 1), device="cuda")
     unknowns = (n - 2) ** 2
 
     smoother = args.smoother or "rbgs"
 
     def make(precision):
         return [mg.Solver(n, n, eps_x=e, smoother=smoother, nu_pre=args.nu, nu_post=args.nu, omega=args.omega,
-                          precision=precision) for e in eps_list]
+                          precision=precision, levels=args.levels) for e in eps_list]
+
+    def start(s, x):
+        if args.x0 == "nested":
+            s.nested_start(rhs, x)
+        else:
+            x.copy_(x0)
 
     def run(solvers, steps, warmup):
         xs = [x0.clone() for _ in solvers]
         for _ in range(warmup):
             for s, x in zip(solvers, xs):
-                x.copy_(x0)
+                start(s, x)
                 s.solve(rhs, x, TOL, args.max_cycles, history=False)
         torch.cuda.synchronize()
         infos = []
@@ -700,7 +716,7 @@ def main():
         for _ in range(steps):
             infos = []
             for s, x in zip(solvers, xs):
-                x.copy_(x0)
+                start(s, x)
                 infos.append(s.solve(rhs, x, TOL, args.max_cycles, history=False))
         torch.cuda.synchronize()
         return time.perf_counter() - t0, infos
@@ -760,7 +776,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"aniso1025: -(eps u_xx + u_yy) = N(0,1) on 1025x1025 nodes, eps in "
                                f"{{{','.join(f'{e:g}' for e in eps_list)}}}, 5-point FD, {smoothing} "
-                               f"{args.nu}/{args.nu}, F-cycle to 3x3, x0={args.x0}, tol 1e-10",
+                               f"{args.nu}/{args.nu}, F-cycle to "
+                               + (f"{args.levels} levels" if args.levels else "3x3")
+                               + f", x0={args.x0}, tol 1e-10",
                    "precision": head},
         "roofline": roofline,
         "cycles": {f"{e:g}": i.cycles for e, i in zip(eps_list, infos_h)},

@@ -483,3 +483,11 @@ def test_nested_start_mixed_precision():
     finally:
         s.close()
     assert info.status == 0
+
+
+@pytest.mark.parametrize("levels", [2, 3, 4, 5])
+def test_level_count(levels):
+    """Fewer levels (the "Grid levels" study): the coarsest grid grows (up to
+    33^2 = 961 unknowns for two levels) and is still solved exactly."""
+    p = Problem(65, 65, eps=0.3, smoother="rbgs", levels=levels)
+    check_parity(p, W.normal_field(65, 65, 2), W.uniform_field(65, 65, 1), 3)
