@@ -165,6 +165,7 @@ size_t sub_footprint(mg_handle h, const Group& G, int l) {
   const bool bands = stencil_kind(h) == ST9 && h->oned;  // 1-D bands staged in LDS too
   size_t n = 0;
   for (int k = l; k < G.nlev; ++k) n += (size_t)G.shp[k].nx * G.shp[k].ny * narr + (bands ? NBANDS * G.shp[k].nx : 0);
+  if (h->line) n += 4 * (size_t)(G.shp[l].nx - 2) * G.shp[l].nrows;  // line-sweep scratch (largest level)
   return n * elem;
 }
 
@@ -173,7 +174,6 @@ struct Gen {
   const Group& G;
   int threshold;  // 0: the largest levels whose sub-hierarchy fits in LDS
   bool small(int l) const {
-    if (h->line) return false;  // line sweeps run as launches on every level
     const LevelShape& s = G.shp[l];
     if (threshold > 0) return (long)s.nx * s.ny <= threshold;
     return sub_footprint(h, G, l) <= SUB_LDS_BUDGET;
@@ -353,7 +353,6 @@ mg_status build_program(mg_handle h, Group& G) {
       cnt.push_back((int)s.size());
     }
     for (const Abs& a : s) {
-      if (a.type == H_LINE) return fail(h, MG_EUNSUPPORTED, "line sweeps inside a coarse-level program");
       int t = OP_COLOR;
       switch (a.type) {
         case H_COLOR: t = OP_COLOR; break;
@@ -362,6 +361,7 @@ mg_status build_program(mg_handle h, Group& G) {
         case H_DR: t = OP_DR; break;
         case H_PROLONG: t = OP_PROLONG; break;
         case H_COARSE: t = OP_COARSE; break;
+        case H_LINE: t = OP_LINE; break;
       }
       flat.push_back({t, a.level, a.arg, 0});
     }

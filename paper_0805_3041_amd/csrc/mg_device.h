@@ -66,6 +66,7 @@ enum OpType {
   OP_DR = 3,        // restrict the defect of `level` into b of level+1, zero x of level+1
   OP_PROLONG = 4,   // x(level) += P x(level+1)
   OP_COARSE = 5,    // exact solve on the coarsest `level`
+  OP_LINE = 6,      // line sweep on `level`, arg as line_arg
 };
 
 // Argument of a line-smoothing op: bit 0 direction (0: lines along x, 1:

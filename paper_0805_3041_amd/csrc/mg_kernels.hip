@@ -269,12 +269,10 @@ __global__ void __launch_bounds__(LT) k_line_factor(Level<T> L, int dir) {
 // off-line couplings on the right-hand side (lines of one colour do not
 // couple).  Jacobi (TRI): dst = src + omega T^-1 (b - A src).
 template <typename T, int K>
-__global__ void __launch_bounds__(LT) k_line(const Level<T>* __restrict__ Ls, int arg, T omega) {
-  const Level<T> L = Ls[blockIdx.z];
-  if (L.st->done) return;
+__device__ void line_thomas(const Level<T>& L, int arg, T omega, int t) {
   const int dir = arg & 1, sel = arg >> 2;
   const bool jac = (arg >> 1) & 1;
-  const int line = line_of(L, dir, jac, sel, blockIdx.x * LT + threadIdx.x);
+  const int line = line_of(L, dir, jac, sel, t);
   if (line < 0) return;
   const T* src = (jac && sel) ? L.t : L.x;
   T* dst = jac ? (sel ? L.x : L.t) : L.x;
@@ -309,6 +307,13 @@ __global__ void __launch_bounds__(LT) k_line(const Level<T>* __restrict__ Ls, in
     u = rp[q] - cp[q] * u;
     dst[q] = jac ? src[q] + omega * u : u;
   }
+}
+
+template <typename T, int K>
+__global__ void __launch_bounds__(LT) k_line(const Level<T>* __restrict__ Ls, int arg, T omega) {
+  const Level<T> L = Ls[blockIdx.z];
+  if (L.st->done) return;
+  line_thomas<T, K>(L, arg, omega, blockIdx.x * LT + threadIdx.x);
 }
 
 // The same op by cyclic reduction in LDS: one workgroup per line.  The
@@ -647,6 +652,102 @@ __device__ void lds_prolong(const Level<T>& F, MG_LDS T* xf, const Level<T>& C, 
   }
 }
 
+// Line sweep of an LDS level inside the coarse-level kernel: every line of
+// the op (all lines for Jacobi, one zebra colour for Gauss-Seidel) is solved
+// at once by cyclic reduction in the scratch `scr` (4 values per node of the
+// swept lines), each reduction level one workgroup barrier; the arithmetic
+// per equation is that of k_line_cr.  Called by every thread of the
+// workgroup.
+template <typename T, int K, bool B1>
+__device__ void lds_line(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, MG_LDS T* t, const MG_LDS T* bl,
+                         MG_LDS T* scr, int arg, T omega, int tid) {
+  const int nx = L.nx, ny = L.ny, py = L.py;
+  const int dir = arg & 1, sel = arg >> 2;
+  const bool jac = (arg >> 1) & 1;
+  const int m = dir == 0 ? nx - 2 : ny - 2;
+  const int lo = dir == 0 ? (py ? 0 : 1) : 1, hi = dir == 0 ? (py ? ny - 1 : ny - 2) : nx - 2;
+  const int first = jac ? lo : lo + (((lo & 1) != sel) ? 1 : 0);
+  const int step = jac ? 1 : 2;
+  const int nl = hi >= first ? (hi - first) / step + 1 : 0;
+  const MG_LDS T* src = (jac && sel) ? t : x;
+  MG_LDS T* dst = jac ? (sel ? x : t) : x;
+  const int tot = nl * m;
+  MG_LDS T* A = scr;
+  MG_LDS T* D = A + tot;
+  MG_LDS T* C = D + tot;
+  MG_LDS T* R = C + tot;
+  const FDiv dm(m);
+  for (int idx = tid; idx < tot; idx += SUB_NT) {
+    const int li = dm.q(idx), n = idx - li * m;
+    int i, j;
+    line_node(dir, first + step * li, n, i, j);
+    const int jm = wrap_dn(j, ny, py);
+    int so, no;
+    row_offsets(j, nx, ny, py, so, no);
+    const int p = j * nx + i;
+    const Cf<T> cf = sub_coefs<T, K, B1>(L, bl, i, j, jm);
+    T a, d, c;
+    line_coefs<K>(L, dir, cf, a, d, c);
+    A[idx] = n == 0 ? (T)0 : a;
+    C[idx] = n == m - 1 ? (T)0 : c;
+    D[idx] = d;
+    R[idx] = jac ? defect_v<K>(L, cf, gather<K>(L, LXO<T>{src + p, so, no}, true), b[p])
+                 : b[p] - off_line<K>(L, dir, cf, gather<K>(L, LXO<T>{src + p, so, no}, false));
+  }
+  __syncthreads();
+  int s = 1;
+  for (; 2 * s <= m; s *= 2) {
+    const int u = m / (2 * s);  // reductions per line at this level
+    const FDiv du(u);
+    for (int idx = tid; idx < nl * u; idx += SUB_NT) {
+      const int li = du.q(idx), base = li * m;
+      const int pp = 2 * s * (idx - li * u + 1) - 1;  // position on the line (0-based)
+      const int p = base + pp, pl = p - s, pr = p + s;
+      const T al = -A[p] / D[pl];
+      T nd = D[p] + al * C[pl];
+      T nr = R[p] + al * R[pl];
+      T nc = (T)0;
+      if (pp + s < m) {
+        const T ga = -C[p] / D[pr];
+        nd += ga * A[pr];
+        nr += ga * R[pr];
+        nc = ga * C[pr];
+      }
+      A[p] = al * A[pl];
+      C[p] = nc;
+      D[p] = nd;
+      R[p] = nr;
+    }
+    __syncthreads();
+  }
+  for (int li = tid; li < nl; li += SUB_NT) {
+    const int q = li * m + s - 1;
+    R[q] = R[q] / D[q];
+  }
+  __syncthreads();
+  for (s >>= 1; s >= 1; s >>= 1) {
+    const int v = (m / s + 1) / 2;  // odd multiples of s on a line
+    const FDiv dv(v);
+    for (int idx = tid; idx < nl * v; idx += SUB_NT) {
+      const int li = dv.q(idx), base = li * m;
+      const int pp = (2 * (idx - li * v) + 1) * s - 1;
+      const int p = base + pp;
+      T w = R[p];
+      if (pp - s >= 0) w -= A[p] * R[p - s];
+      if (pp + s < m) w -= C[p] * R[p + s];
+      R[p] = w / D[p];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < tot; idx += SUB_NT) {
+    const int li = dm.q(idx), n = idx - li * m;
+    int i, j;
+    line_node(dir, first + step * li, n, i, j);
+    const int p = j * nx + i;
+    dst[p] = jac ? src[p] + omega * R[idx] : R[idx];
+  }
+}
+
 // Single-workgroup interpreter: runs ops [beg[slot], beg[slot] + cnt[slot]) of
 // `prog` on the levels of its slot (levs + slot * nlev), one barrier between
 // ops.  Used for every level small enough that a launch per op would cost
@@ -655,7 +756,8 @@ __device__ void lds_prolong(const Level<T>& F, MG_LDS T* xf, const Level<T>& C, 
 // IN_LDS: every level from `top` down also lives in LDS (x, b and, for
 // Jacobi, t as dense [ny][nx] arrays): the top level's x and b are read once
 // and x written back at exit; coarser levels never leave LDS.  Bands
-// (9-point operators) are read from global memory.
+// (9-point operators) are read from global memory, 1-D bands from an LDS
+// copy; line sweeps use a scratch after the levels.
 __device__ __forceinline__ int pack_op(const DOp& o) { return o.type | (o.level << 4) | (o.arg << 12); }
 
 template <typename T, bool IN_LDS, int K, bool B1 = false>
@@ -668,6 +770,7 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
   MG_LDS T* lds = lds_cast<T>(smem_raw);
   __shared__ int offs[MAX_LEVELS + 1];
   __shared__ int boffs[MAX_LEVELS];  // B1: LDS offset of each level's bands
+  __shared__ int soff;               // LDS offset of the line-sweep scratch
   __shared__ int sops[MAX_SUB_OPS];
   const int slot = blockIdx.z;
   const Level<T>* Ls = levs + (size_t)slot * nlev;
@@ -689,6 +792,7 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
         boffs[l] = o;
         o += NBANDS * Ls[l].nx;
       }
+    soff = o;
   }
   __syncthreads();
   if (IN_LDS) {
@@ -760,6 +864,7 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
           break;
         }
         case OP_COARSE: body_coarse(L, chol[slot], ncu, tid, SUB_NT); break;
+        case OP_LINE: lds_line<T, K, B1>(L, xl, bl, tl, bands, lds + soff, arg, omega, tid); break;
         default: break;
       }
     } else {
@@ -770,6 +875,9 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
         case OP_DR: body_dr(L, Ls[l + 1], tid, SUB_NT); break;
         case OP_PROLONG: body_prolong(L, Ls[l + 1], tid, SUB_NT); break;
         case OP_COARSE: body_coarse(L, chol[slot], ncu, tid, SUB_NT); break;
+        case OP_LINE:
+          for (int t0 = 0; t0 < L.nx + L.ny; t0 += SUB_NT) line_thomas<T, K>(L, arg, omega, t0 + tid);
+          break;
         default: break;
       }
     }

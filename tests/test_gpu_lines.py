@@ -116,3 +116,13 @@ def test_long_lines_use_the_thread_per_line_solver(smoother):
     (at eps = 4 it is 6e5 and the difference reaches 1e-12)."""
     p = Problem(4609, 17, eps=0.01, smoother=smoother, omega=0.8)
     check_parity(p, W.normal_field(4609, 17, 2), np.zeros((17, 4609)), 3)
+
+
+@pytest.mark.parametrize("cta", [300, 5000])
+@pytest.mark.parametrize("smoother", ["adi", "gsadi"])
+def test_coarse_levels_in_global_memory(smoother, cta):
+    """Levels of at most `cta` nodes run in the one-workgroup coarse kernel
+    reading global memory (one thread per line, Thomas factors from setup);
+    the default keeps them in LDS (cyclic reduction over all lines at once)."""
+    p = Problem(129, 129, eps=0.05, smoother=smoother, omega=0.8)
+    check_parity(p, W.normal_field(129, 129, 2), W.uniform_field(129, 129, 1), 3, coarse_cta_nodes=cta)
