@@ -320,9 +320,12 @@ __global__ void __launch_bounds__(FT) k_pre(const Level<T>* __restrict__ Fs, con
                                             int TY, int H, int ntx, int nty, int nsteps, T omega) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Level<T> F = Fs[blockIdx.z];
-  // the solve-finished flag is read now and tested once the region's loads
-  // are in flight (a finished problem's kernels store nothing)
+  // the solve-finished flag is read now and, for one problem, tested once the
+  // region's loads are in flight (a finished problem's kernels store
+  // nothing); a batched launch tests it at once, since most of its slots are
+  // finished in most cycles
   const int done = F.st->done;
+  if (gridDim.z > 1 && done) return;
   const Level<T> C = Cs[blockIdx.z];
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
@@ -417,7 +420,8 @@ __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, co
   __shared__ double sh[FT / 64];
   const Level<T> F = Fs[blockIdx.z];
   SolveState* st = F.st;
-  const int done = st->done;  // tested once the region's loads are in flight
+  const int done = st->done;  // one problem: tested once the region's loads are in flight
+  if (gridDim.z > 1 && done) return;
   const Level<T> C = Cs[blockIdx.z];
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
@@ -783,7 +787,8 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
   constexpr int P = wide_narr<NCOL>() * WW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Level<T> F = Fs[blockIdx.z];
-  const int done = F.st->done;  // tested once the region's loads are in flight
+  const int done = F.st->done;  // one problem: tested once the region's loads are in flight
+  if (gridDim.z > 1 && done) return;
   const Level<T> C = Cs[blockIdx.z];
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
@@ -909,7 +914,8 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
   __shared__ double sh[FT / 64];
   const Level<T> F = Fs[blockIdx.z];
   SolveState* st = F.st;
-  const int done = st->done;  // tested once the region's loads are in flight
+  const int done = st->done;  // one problem: tested once the region's loads are in flight
+  if (gridDim.z > 1 && done) return;
   const Level<T> C = Cs[blockIdx.z];
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
