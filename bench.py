@@ -555,9 +555,10 @@ def cpu_baseline_batch(ns, eps, cycles, nu, seconds):
             "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
 
 
-# 2-D 9-point bands (grf2049): the fused passes also read the six bands C,
-# E, N, NE, NW, D of every node (FP64).
-BAND_BYTES_2D = 6 * 8
+# Cell coefficients (grf2049): the finest fused passes form the 9-point
+# couplings from the per-cell coefficient a (kx = ky = a, one FP64 value per
+# cell, one cell per node) instead of reading six bands per node.
+CELL_BYTES_ISO = 8
 
 
 def _roofline_grf(n, at, ft, calibrate=False):
@@ -575,7 +576,7 @@ def _roofline_grf(n, at, ft, calibrate=False):
     s.close()
     if calibrate:
         calibrate_copy()
-    bpn = BYTES_PER_NODE[("fp64", dom)] + BAND_BYTES_2D
+    bpn = BYTES_PER_NODE[("fp64", dom)] + CELL_BYTES_ISO
     alg = bpn * n * n
     ach = alg / (times[dom] * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,

@@ -704,6 +704,46 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
         M.bpitch = L.bpitch;
         M.bstride = bstride;
       }
+      // finest level, coefficients varying in both directions, not run by
+      // the coarse-level interpreter: own copies of the per-cell kx, ky,
+      // from which the kernels of that level form its couplings (one copy
+      // when the caller passes the same array for both)
+      if (l == 0 && !h->oned && !Gen{h, G, h->opts.coarse_cta_nodes}.small(0)) {
+        const int ncy = sh.py ? sh.ny : sh.ny - 1;
+        const size_t nc = (size_t)ncx * ncy;
+        const bool same = coeffs->kx == coeffs->ky;
+        double* kc[2] = {nullptr, nullptr};
+        for (int d = 0; d < (same ? 1 : 2); ++d) {
+          HIPCHK(h, h->dalloc(&kc[d], nc * sizeof(double)));
+          HIPCHK(h, hipMemcpyAsync(kc[d], d == 0 ? coeffs->kx : coeffs->ky, nc * sizeof(double),
+                                   hipMemcpyDeviceToDevice, h->stream));
+        }
+        if (same) kc[1] = kc[0];
+        const double ax = 1.0 / (G.hx[0] * G.hx[0]), ay = 1.0 / (G.hy[0] * G.hy[0]);
+        L.kcx = kc[0];
+        L.kcy = kc[1];
+        L.kcpitch = ncx;
+        L.kc3x = ax / 3.0;
+        L.kc3y = ay / 3.0;
+        L.kc6x = ax / 6.0;
+        L.kc6y = ay / 6.0;
+        if (mixed) {
+          float* kf[2] = {nullptr, nullptr};
+          for (int d = 0; d < (same ? 1 : 2); ++d) {
+            HIPCHK(h, h->dalloc(&kf[d], nc * sizeof(float)));
+            HIPCHK(h, launch_to_float(kc[d], kf[d], (long)nc, h->stream));
+          }
+          if (same) kf[1] = kf[0];
+          Level<float>& M = G.l32(l, 0);
+          M.kcx = kf[0];
+          M.kcy = kf[1];
+          M.kcpitch = ncx;
+          M.kc3x = (float)L.kc3x;
+          M.kc3y = (float)L.kc3y;
+          M.kc6x = (float)L.kc6x;
+          M.kc6y = (float)L.kc6y;
+        }
+      }
     }
   }
 

@@ -56,6 +56,16 @@ struct Level {
   T* lcp[2];              // line smoothers: per direction (0 x-lines, 1 y-lines) the Thomas factors
   T* lid[2];              //   c_n / den_n and 1 / den_n of every node's line, [ny][pitch]
   T* lr;                  //   forward-sweep values of the running line solve, [ny][pitch]
+  // Finest level of a problem whose Q1 coefficients vary over the cells in
+  // both directions, when the coarse-level interpreter does not run it: the
+  // per-cell kx and ky ([ncy][kcpitch], cell (i, j) spanning nodes i..i+1,
+  // j..j+1; one array when kx and ky are the same).  Kernels form a node's
+  // couplings from its four cells (cell_coefs) instead of reading the six
+  // bands.  Null elsewhere.
+  const T* kcx;
+  const T* kcy;
+  int kcpitch;
+  T kc3x, kc3y, kc6x, kc6y;  // 1/(3 hx^2), 1/(3 hy^2), 1/(6 hx^2), 1/(6 hy^2)
 };
 
 // Host-built op of the coarse-level interpreter (one workgroup runs a list).
@@ -206,11 +216,49 @@ __device__ __forceinline__ Nbr<T> gather(const Level<T>& L, const X& x, bool cen
   return v;
 }
 
-// Coefficients at interior node (i, j); jm is j's wrapped lower row.
-template <int K = KDYN, typename T>
+// Coefficients at interior node (i, j) of a level with per-cell kx, ky:
+// the bilinear element's couplings summed over the node's four cells SW
+// (i-1, jm), SE (i, jm), NW (i-1, j), NE (i, j).  Each coupling collects the
+// cells its two nodes share (east: SE and NE, north: NW and NE, the
+// diagonals one cell each), the diagonal all four, with the per-cell terms
+// of the element matrix kx/hx^2 K1 (x) M1 + ky/hy^2 M1 (x) K1 (K1 = [1 -1;
+// -1 1], M1 = [1/3 1/6; 1/6 1/3]): diagonal (cx + cy)/3, east -cx/3 + cy/6,
+// north cx/6 - cy/3, corner -(cx + cy)/6, cx = kx/hx^2, cy = ky/hy^2.  The
+// same operator as the bands k_q1_bands assembles, up to rounding.
+template <typename T>
+__device__ __forceinline__ Cf<T> cell_coefs(const Level<T>& L, int i, int j, int jm) {
+  const T* xs = L.kcx + (size_t)jm * L.kcpitch + i - 1;
+  const T* xn = L.kcx + (size_t)j * L.kcpitch + i - 1;
+  const T* ys = L.kcy + (size_t)jm * L.kcpitch + i - 1;
+  const T* yn = L.kcy + (size_t)j * L.kcpitch + i - 1;
+  const T xsw = xs[0], xse = xs[1], xnw = xn[0], xne = xn[1];
+  const T ysw = ys[0], yse = ys[1], ynw = yn[0], yne = yn[1];
+  Cf<T> c;
+  c.C = L.kc3x * ((xsw + xse) + (xnw + xne)) + L.kc3y * ((ysw + yse) + (ynw + yne));
+  c.Ep = L.kc6y * (yse + yne) - L.kc3x * (xse + xne);
+  c.Ew = L.kc6y * (ysw + ynw) - L.kc3x * (xsw + xnw);
+  c.Np = L.kc6x * (xnw + xne) - L.kc3y * (ynw + yne);
+  c.Ns = L.kc6x * (xsw + xse) - L.kc3y * (ysw + yse);
+  c.NEp = -(L.kc6x * xne + L.kc6y * yne);
+  c.NEsw = -(L.kc6x * xsw + L.kc6y * ysw);
+  c.NWp = -(L.kc6x * xnw + L.kc6y * ynw);
+  c.NWse = -(L.kc6x * xse + L.kc6y * yse);
+  c.D = (T)1 / c.C;
+  return c;
+}
+
+// Coefficients at interior node (i, j); jm is j's wrapped lower row.  From
+// the four cells where the level keeps them (every kernel that can run the
+// finest level then forms the same values), else from the bands.  CELLS
+// false leaves the cell path out of kernels that only run coarser levels
+// (the coarse-level interpreter, whose registers it would spill).
+template <int K = KDYN, bool CELLS = true, typename T>
 __device__ __forceinline__ Cf<T> coefs(const Level<T>& L, int i, int j, int jm) {
   Cf<T> c{};
   if (is5<K>(L)) return c;
+  if constexpr (CELLS) {
+    if (L.kcx) return cell_coefs(L, i, j, jm);
+  }
   const size_t rp = (size_t)j * L.bpitch, rs = (size_t)jm * L.bpitch;
   c.C = bandp(L, 0)[rp + i];
   c.Ep = bandp(L, 1)[rp + i];
@@ -266,19 +314,19 @@ __device__ __forceinline__ T jac_v(const Level<T>& L, const Cf<T>& a, const Nbr<
 }
 
 // Accessor forms (gather, then the value functions above).
-template <int K = KDYN, typename T, typename X>
+template <int K = KDYN, bool CELLS = true, typename T, typename X>
 __device__ __forceinline__ T gs_val(const Level<T>& L, const X& x, T bp, int i, int j, int jm) {
-  return gs_v<K>(L, coefs<K>(L, i, j, jm), gather<K>(L, x, false), bp);
+  return gs_v<K>(L, coefs<K, CELLS>(L, i, j, jm), gather<K>(L, x, false), bp);
 }
 
-template <int K = KDYN, typename T, typename X>
+template <int K = KDYN, bool CELLS = true, typename T, typename X>
 __device__ __forceinline__ T defect_val(const Level<T>& L, const X& x, T bp, int i, int j, int jm) {
-  return defect_v<K>(L, coefs<K>(L, i, j, jm), gather<K>(L, x, true), bp);
+  return defect_v<K>(L, coefs<K, CELLS>(L, i, j, jm), gather<K>(L, x, true), bp);
 }
 
-template <int K = KDYN, typename T, typename X>
+template <int K = KDYN, bool CELLS = true, typename T, typename X>
 __device__ __forceinline__ T jac_val(const Level<T>& L, const X& x, T bp, int i, int j, int jm, T omega) {
-  return jac_v<K>(L, coefs<K>(L, i, j, jm), gather<K>(L, x, true), bp, omega);
+  return jac_v<K>(L, coefs<K, CELLS>(L, i, j, jm), gather<K>(L, x, true), bp, omega);
 }
 
 // Full weighting of a 3x3 block of fine defects d[row][col] (row 0 = south):
@@ -293,16 +341,16 @@ __device__ __forceinline__ T fw_row(T dw, T dc, T de) {
 }
 
 // Convenience wrappers over a global array.
-template <typename T>
+template <bool CELLS = true, typename T>
 __device__ __forceinline__ T gs_value(const Level<T>& L, const T* __restrict__ x, const T* __restrict__ b,
                                       int i, int j, int jm, int jp) {
-  return gs_val(L, gx(x, L.pitch, i, j, jm, jp), b[(size_t)j * L.pitch + i], i, j, jm);
+  return gs_val<KDYN, CELLS>(L, gx(x, L.pitch, i, j, jm, jp), b[(size_t)j * L.pitch + i], i, j, jm);
 }
 
-template <typename T>
+template <bool CELLS = true, typename T>
 __device__ __forceinline__ T defect_at(const Level<T>& L, const T* __restrict__ x, const T* __restrict__ b,
                                        int i, int j, int jm, int jp) {
-  return defect_val(L, gx(x, L.pitch, i, j, jm, jp), b[(size_t)j * L.pitch + i], i, j, jm);
+  return defect_val<KDYN, CELLS>(L, gx(x, L.pitch, i, j, jm, jp), b[(size_t)j * L.pitch + i], i, j, jm);
 }
 
 template <typename T>
@@ -312,15 +360,15 @@ __device__ __forceinline__ T defect_masked(const Level<T>& L, const T* __restric
   return defect_val(L, m, b[(size_t)j * L.pitch + i], i, j, jm);
 }
 
-template <typename T>
+template <bool CELLS = true, typename T>
 __device__ __forceinline__ T jacobi_value(const Level<T>& L, const T* __restrict__ x, const T* __restrict__ b,
                                           int i, int j, int jm, int jp, T omega) {
-  return jac_val(L, gx(x, L.pitch, i, j, jm, jp), b[(size_t)j * L.pitch + i], i, j, jm, omega);
+  return jac_val<KDYN, CELLS>(L, gx(x, L.pitch, i, j, jm, jp), b[(size_t)j * L.pitch + i], i, j, jm, omega);
 }
 
 // Full-weighting restriction of the fine defect at coarse node (I, J),
 // centred on fine node (2I, 2J).
-template <typename T>
+template <bool CELLS = true, typename T>
 __device__ __forceinline__ T restrict_defect(const Level<T>& F, const T* __restrict__ x, const T* __restrict__ b,
                                              int I, int J) {
   const int i0 = 2 * I;
@@ -334,9 +382,9 @@ __device__ __forceinline__ T restrict_defect(const Level<T>& F, const T* __restr
     const int j = rows[r];
     const int jjm = wrap_dn(j, F.ny, F.py);
     const int jjp = wrap_up(j, F.ny, F.py);
-    const T dw = defect_at(F, x, b, i0 - 1, j, jjm, jjp);
-    const T dc = defect_at(F, x, b, i0, j, jjm, jjp);
-    const T de = defect_at(F, x, b, i0 + 1, j, jjm, jjp);
+    const T dw = defect_at<CELLS>(F, x, b, i0 - 1, j, jjm, jjp);
+    const T dc = defect_at<CELLS>(F, x, b, i0, j, jjm, jjp);
+    const T de = defect_at<CELLS>(F, x, b, i0 + 1, j, jjm, jjp);
     acc[r] = fw_row(dw, dc, de);
   }
   return fw_combine(acc[0], acc[1], acc[2]);

@@ -620,7 +620,9 @@ __device__ __forceinline__ Cf<T> wcoef_cols(const MG_LDS T* bl, int A) {
 }
 
 // Coefficients of node (gi, row lj) for a sweep: hoisted column values
-// (B1), the level's global bands (2-D), or none (5-point).
+// (B1), from global memory (2-D: the four cells of a finest level that
+// keeps them, which stay in L2 across the sweeps of a pass, else the six
+// bands), or none (5-point).
 template <typename T, int K, bool B1>
 __device__ __forceinline__ Cf<T> wcoef(const Level<T>& L, const WMap& m, const Cf<T>& col, int gi, int lj) {
   if constexpr (K == ST5 || B1) {

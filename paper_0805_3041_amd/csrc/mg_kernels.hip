@@ -46,7 +46,9 @@ struct ColourSet {
 // --------------------------------------------------------------------------- op bodies
 // Each body processes the op's nodes idx = tid, tid + nth, ...
 
-template <typename T>
+// CELLS: whether the kernel can run a finest level that forms its couplings
+// from per-cell coefficients (false in the coarse-level interpreter).
+template <typename T, bool CELLS = true>
 __device__ void body_colour(const Level<T>& L, int c, int ncol, int tid, int nth) {
   ColourSet<T> S(L, c, ncol);
   const int n = S.count();
@@ -54,11 +56,11 @@ __device__ void body_colour(const Level<T>& L, int c, int ncol, int tid, int nth
     int i, j;
     if (!S.node(L, c, ncol, idx, i, j)) continue;
     const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
-    L.x[(size_t)j * L.pitch + i] = gs_value(L, L.x, L.b, i, j, jm, jp);
+    L.x[(size_t)j * L.pitch + i] = gs_value<CELLS>(L, L.x, L.b, i, j, jm, jp);
   }
 }
 
-template <typename T>
+template <typename T, bool CELLS = true>
 __device__ void body_jacobi(const Level<T>& L, int dir, T omega, int tid, int nth) {
   const T* src = dir == 0 ? L.x : L.t;
   T* dst = dir == 0 ? L.t : L.x;
@@ -69,7 +71,7 @@ __device__ void body_jacobi(const Level<T>& L, int dir, T omega, int tid, int nt
     const int i = idx - r * ni + 1;
     const int j = lo + r;
     const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
-    dst[(size_t)j * L.pitch + i] = jacobi_value(L, src, L.b, i, j, jm, jp, omega);
+    dst[(size_t)j * L.pitch + i] = jacobi_value<CELLS>(L, src, L.b, i, j, jm, jp, omega);
   }
 }
 
@@ -84,7 +86,7 @@ __device__ void body_copy(const Level<T>& L, int tid, int nth) {
   }
 }
 
-template <typename T>
+template <typename T, bool CELLS = true>
 __device__ void body_dr(const Level<T>& F, const Level<T>& C, int tid, int nth) {
   const int lo = row_lo(C), nr = row_hi(C) - lo + 1, ni = C.nx - 2;
   const int n = nr * ni;
@@ -93,7 +95,7 @@ __device__ void body_dr(const Level<T>& F, const Level<T>& C, int tid, int nth) 
     const int I = idx - r * ni + 1;
     const int J = lo + r;
     const size_t p = (size_t)J * C.pitch + I;
-    C.b[p] = restrict_defect(F, F.x, F.b, I, J);
+    C.b[p] = restrict_defect<CELLS>(F, F.x, F.b, I, J);
     C.x[p] = (T)0;
   }
 }
@@ -268,7 +270,7 @@ __global__ void __launch_bounds__(LT) k_line_factor(Level<T> L, int dir) {
 // of one colour <- exact solution of their tridiagonal systems with the
 // off-line couplings on the right-hand side (lines of one colour do not
 // couple).  Jacobi (TRI): dst = src + omega T^-1 (b - A src).
-template <typename T, int K>
+template <typename T, int K, bool CELLS = true>
 __device__ void line_thomas(const Level<T>& L, int arg, T omega, int t) {
   const int dir = arg & 1, sel = arg >> 2;
   const bool jac = (arg >> 1) & 1;
@@ -464,7 +466,8 @@ __device__ __forceinline__ LX3<T> lgx(const MG_LDS T* x, int nx, int i, int j, i
 
 // Coefficients of node (i, j) on an LDS-resident level: B1 (9-point bands
 // that vary along x only) from the level's LDS copy of its bands (band k at
-// bl + k nx, the same values as coefs()), otherwise coefs().
+// bl + k nx, the same values as coefs()), otherwise the bands (the
+// interpreter runs coarse levels only, which keep no cell coefficients).
 template <typename T, int K, bool B1>
 __device__ __forceinline__ Cf<T> sub_coefs(const Level<T>& L, const MG_LDS T* bl, int i, int j, int jm) {
   if constexpr (K == ST9 && B1) {
@@ -483,7 +486,7 @@ __device__ __forceinline__ Cf<T> sub_coefs(const Level<T>& L, const MG_LDS T* bl
     c.D = p[BAND_D * nx];
     return c;
   } else {
-    return coefs<K>(L, i, j, jm);
+    return coefs<K, false>(L, i, j, jm);
   }
 }
 
@@ -869,14 +872,14 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
       }
     } else {
       switch (type) {
-        case OP_COLOR: body_colour(L, arg, ncol, tid, SUB_NT); break;
-        case OP_JACOBI: body_jacobi(L, arg, omega, tid, SUB_NT); break;
+        case OP_COLOR: body_colour<T, false>(L, arg, ncol, tid, SUB_NT); break;
+        case OP_JACOBI: body_jacobi<T, false>(L, arg, omega, tid, SUB_NT); break;
         case OP_COPY: body_copy(L, tid, SUB_NT); break;
-        case OP_DR: body_dr(L, Ls[l + 1], tid, SUB_NT); break;
+        case OP_DR: body_dr<T, false>(L, Ls[l + 1], tid, SUB_NT); break;
         case OP_PROLONG: body_prolong(L, Ls[l + 1], tid, SUB_NT); break;
         case OP_COARSE: body_coarse(L, chol[slot], ncu, tid, SUB_NT); break;
         case OP_LINE:
-          for (int t0 = 0; t0 < L.nx + L.ny; t0 += SUB_NT) line_thomas<T, K>(L, arg, omega, t0 + tid);
+          for (int t0 = 0; t0 < L.nx + L.ny; t0 += SUB_NT) line_thomas<T, K, false>(L, arg, omega, t0 + tid);
           break;
         default: break;
       }
