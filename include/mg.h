@@ -175,6 +175,23 @@ mg_status mg_residual(mg_handle h, const double* rhs, const double* x, double* r
  * arrays [ny][nx]; dL_dk: device cell array [ncy][ncx]. */
 mg_status mg_coeff_grad(mg_handle h, const double* u, const double* lam, double* dL_dk);
 
+/* Replace the cell coefficients of a handle made by mg_setup with
+ * MG_COEF_CELL9: every level's operator A_l (Multigrid algorithm, "The
+ * Multigrid Technique": the finest Q1 operator from kx, ky, the Galerkin
+ * operators below it, the coarsest inverse, line-smoother factors) is
+ * rebuilt in the handle's existing device buffers, as mg_setup would build
+ * it for these coefficients, without allocating; the next mg_solve uses it.
+ * For loops that solve with changing coefficients (gradient steps).  coeffs:
+ * kind MG_COEF_CELL9 and kx_1d_along_x as at setup; kx, ky device arrays of
+ * the layout mg_setup reads, read during the call only (the handle keeps its
+ * own copies).  If kx and ky were the same array at setup they must be the
+ * same array here.  Waits for the rebuild.  MG_EUNSUPPORTED for a batched
+ * handle; MG_EINVAL for a NULL handle or coeffs, other coefficient kinds, a
+ * changed layout, invalid values (not finite and > 0) or a coarsest
+ * operator that is not positive definite.  After an error past the argument
+ * checks the handle's operators are undefined until a successful update. */
+mg_status mg_update_coeffs(mg_handle h, const mg_coeffs* coeffs);
+
 /* Start vector by nested iteration ("Start-Vector Choice": begin on the
  * coarsest level and work up to the finest): rhs is restricted by full
  * weighting to every level, the coarsest problem solved exactly, and on each

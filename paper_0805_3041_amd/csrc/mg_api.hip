@@ -70,6 +70,8 @@ struct Group {
   std::vector<double*> band64;
   std::vector<float*> band32;
   double** dcholp = nullptr;  // inverse of each slot's coarsest operator
+  std::vector<double*> chol, cinv;  // per slot: coarsest dense matrix / Cholesky factor, its inverse
+  int* dinfo = nullptr;             // per slot: Cholesky status
   std::vector<TileGeom> gpre, gpost;
   bool norm_fused = false;   // FP64: the finest post-pass applies the stopping test
   bool mixed_fused = false;  // mixed: the finest post-pass adds e into the FP64 iterate
@@ -97,6 +99,7 @@ struct mg_handle_s {
   int line = 0;                      // line smoothers: directions swept (bit 0 x, bit 1 y)
   bool line_jac = false;             // line smoothers: Jacobi (TRI) rather than Gauss-Seidel
   std::vector<double> eps_x, eps_y;  // per problem (5-point)
+  int* dcount = nullptr;             // cell coefficients: count of invalid values (setup and update)
   hipStream_t stream = nullptr;
   std::string err;
 
@@ -583,9 +586,91 @@ hipError_t alloc_line_factors(mg_handle h, Level<T>& L, const LevelShape& sh) {
     if (!((h->line >> dir) & 1)) continue;
     if ((e = h->dalloc(&L.lcp[dir], n * sizeof(T))) != hipSuccess) return e;
     if ((e = h->dalloc(&L.lid[dir], n * sizeof(T))) != hipSuccess) return e;
-    if ((e = launch_line_factor<T>(L, dir, h->stream)) != hipSuccess) return e;
   }
   return h->dalloc(&L.lr, n * sizeof(T));
+}
+
+// Thomas factors of every line of every level (after the operators).
+hipError_t assemble_line_factors(mg_handle h, Group& G) {
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < G.ns; ++s)
+    for (int l = 0; l < G.nlev; ++l)
+      for (int dir = 0; dir < 2; ++dir) {
+        if (!((h->line >> dir) & 1)) continue;
+        e = h->mixed() ? launch_line_factor<float>(G.l32(l, s), dir, h->stream)
+                       : launch_line_factor<double>(G.l64(l, s), dir, h->stream);
+        if (e != hipSuccess) return e;
+      }
+  return hipSuccess;
+}
+
+// Operators of a cell-coefficient problem in the buffers setup_group
+// allocated: finest bands from kx, ky, Galerkin bands of the coarser levels,
+// inverse diagonals, the FP32 copies of a mixed hierarchy and the finest
+// level's cell copies.  Queued on the handle's stream.
+hipError_t assemble_cell9(mg_handle h, Group& G, const mg_coeffs* coeffs) {
+  const mg_grid& grid = G.grid;
+  const int ncx = grid.nx - 1;
+  hipError_t e = hipSuccess;
+  for (int l = 0; l < G.nlev; ++l) {
+    const LevelShape& sh = G.shp[l];
+    const Level<double>& L = G.l64(l, 0);
+    const int brows = h->oned ? 1 : sh.ny;
+    if (l == 0) {
+      e = launch_q1_bands(G.band64[0], L.bstride, L.bpitch, brows, sh.nx, sh.ny, sh.py, coeffs->kx, coeffs->ky,
+                          h->oned ? 0 : ncx, G.hx[0], G.hy[0], h->stream);
+    } else {
+      const LevelShape& f = G.shp[l - 1];
+      const Level<double>& Lf = G.l64(l - 1, 0);
+      e = launch_rap(G.band64[l], L.bstride, L.bpitch, brows, sh.nx, sh.ny, G.band64[l - 1], Lf.bstride, Lf.bpitch,
+                     f.nx, f.ny, sh.py, h->stream);
+    }
+    if (e != hipSuccess) return e;
+    if ((e = launch_inv_diag(G.band64[l], L.bstride, h->stream)) != hipSuccess) return e;
+    if (h->mixed() && (e = launch_to_float(G.band64[l], G.band32[l], (long)NBANDS * L.bstride, h->stream)) != hipSuccess)
+      return e;
+  }
+  const Level<double>& L0 = G.l64(0, 0);
+  if (L0.kcx) {
+    const LevelShape& sh = G.shp[0];
+    const size_t nc = (size_t)ncx * (sh.py ? sh.ny : sh.ny - 1);
+    const bool two = L0.kcy != L0.kcx;
+    e = hipMemcpyAsync((void*)L0.kcx, coeffs->kx, nc * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess && two)
+      e = hipMemcpyAsync((void*)L0.kcy, coeffs->ky, nc * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return e;
+    if (h->mixed()) {
+      const Level<float>& M = G.l32(0, 0);
+      if ((e = launch_to_float(L0.kcx, (float*)M.kcx, (long)nc, h->stream)) != hipSuccess) return e;
+      if (two && (e = launch_to_float(L0.kcy, (float*)M.kcy, (long)nc, h->stream)) != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+// Dense coarsest operator of each slot, its Cholesky factor and the inverse
+// the coarse solve applies, in the buffers setup_group allocated; waits for
+// them and fails when an operator is not positive definite.
+mg_status assemble_coarsest(mg_handle h, Group& G) {
+  const int n = G.ncu;
+  const LevelShape& sc = G.shp.back();
+  for (int s = 0; s < G.ns; ++s) {
+    const Level<double>& L = G.l64(G.nlev - 1, s);
+    // the dense matrix is accumulated into a cleared buffer (it holds the
+    // previous factor after an earlier assembly)
+    HIPCHK(h, hipMemsetAsync(G.chol[s], 0, (size_t)n * n * sizeof(double), h->stream));
+    HIPCHK(h, launch_dense_coarse(G.chol[s], n, sc.nx, sc.ny, sc.py, L.kind, L.cx, L.cy, L.dg, L.band, L.bstride,
+                                  L.bpitch, h->stream));
+    HIPCHK(h, launch_cholesky(G.chol[s], n, G.dinfo + s, h->stream));
+    HIPCHK(h, launch_chol_inverse(G.chol[s], G.cinv[s], n, h->stream));
+  }
+  std::vector<int> info(G.ns, 0);
+  HIPCHK(h, hipMemcpyAsync(info.data(), G.dinfo, (size_t)G.ns * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  mg_status st = sync_check(h);
+  if (st != MG_OK) return st;
+  for (int s = 0; s < G.ns; ++s)
+    if (info[s]) return fail(h, MG_EINVAL, "coarsest operator is not positive definite");
+  return MG_OK;
 }
 
 mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t levels) {
@@ -670,26 +755,16 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
       }
     }
   } else {
+    // bands of every level, the finest level's cell copies (filled by
+    // assemble_cell9)
     const int ncx = grid.nx - 1;
     G.band64.resize(G.nlev);
     G.band32.resize(G.nlev);
     for (int l = 0; l < G.nlev; ++l) {
       const LevelShape& sh = G.shp[l];
       const int bp = round_up(sh.nx, 16);
-      const int brows = h->oned ? 1 : sh.ny;
-      const int bstride = bp * brows;
+      const int bstride = bp * (h->oned ? 1 : sh.ny);
       HIPCHK(h, h->dalloc(&G.band64[l], (size_t)NBANDS * bstride * sizeof(double)));
-      if (l == 0) {
-        HIPCHK(h, launch_q1_bands(G.band64[0], bstride, h->oned ? 0 : bp, brows, sh.nx, sh.ny, sh.py, coeffs->kx,
-                                  coeffs->ky, h->oned ? 0 : ncx, G.hx[0], G.hy[0], h->stream));
-      } else {
-        const LevelShape& f = G.shp[l - 1];
-        const int fbp = round_up(f.nx, 16);
-        const int fbstride = fbp * (h->oned ? 1 : f.ny);
-        HIPCHK(h, launch_rap(G.band64[l], bstride, h->oned ? 0 : bp, brows, sh.nx, sh.ny, G.band64[l - 1], fbstride,
-                             h->oned ? 0 : fbp, f.nx, f.ny, sh.py, h->stream));
-      }
-      HIPCHK(h, launch_inv_diag(G.band64[l], bstride, h->stream));
       Level<double>& L = G.l64(l, 0);
       L.kind = ST9;
       L.band = G.band64[l];
@@ -697,54 +772,48 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
       L.bstride = bstride;
       if (mixed) {
         HIPCHK(h, h->dalloc(&G.band32[l], (size_t)NBANDS * bstride * sizeof(float)));
-        HIPCHK(h, launch_to_float(G.band64[l], G.band32[l], (long)NBANDS * bstride, h->stream));
         Level<float>& M = G.l32(l, 0);
         M.kind = ST9;
         M.band = G.band32[l];
         M.bpitch = L.bpitch;
         M.bstride = bstride;
       }
-      // finest level, coefficients varying in both directions, not run by
-      // the coarse-level interpreter: own copies of the per-cell kx, ky,
-      // from which the kernels of that level form its couplings (one copy
-      // when the caller passes the same array for both)
-      if (l == 0 && !h->oned && !Gen{h, G, h->opts.coarse_cta_nodes}.small(0)) {
-        const int ncy = sh.py ? sh.ny : sh.ny - 1;
-        const size_t nc = (size_t)ncx * ncy;
-        const bool same = coeffs->kx == coeffs->ky;
-        double* kc[2] = {nullptr, nullptr};
-        for (int d = 0; d < (same ? 1 : 2); ++d) {
-          HIPCHK(h, h->dalloc(&kc[d], nc * sizeof(double)));
-          HIPCHK(h, hipMemcpyAsync(kc[d], d == 0 ? coeffs->kx : coeffs->ky, nc * sizeof(double),
-                                   hipMemcpyDeviceToDevice, h->stream));
-        }
-        if (same) kc[1] = kc[0];
-        const double ax = 1.0 / (G.hx[0] * G.hx[0]), ay = 1.0 / (G.hy[0] * G.hy[0]);
-        L.kcx = kc[0];
-        L.kcy = kc[1];
-        L.kcpitch = ncx;
-        L.kc3x = ax / 3.0;
-        L.kc3y = ay / 3.0;
-        L.kc6x = ax / 6.0;
-        L.kc6y = ay / 6.0;
-        if (mixed) {
-          float* kf[2] = {nullptr, nullptr};
-          for (int d = 0; d < (same ? 1 : 2); ++d) {
-            HIPCHK(h, h->dalloc(&kf[d], nc * sizeof(float)));
-            HIPCHK(h, launch_to_float(kc[d], kf[d], (long)nc, h->stream));
-          }
-          if (same) kf[1] = kf[0];
-          Level<float>& M = G.l32(l, 0);
-          M.kcx = kf[0];
-          M.kcy = kf[1];
-          M.kcpitch = ncx;
-          M.kc3x = (float)L.kc3x;
-          M.kc3y = (float)L.kc3y;
-          M.kc6x = (float)L.kc6x;
-          M.kc6y = (float)L.kc6y;
-        }
+    }
+    // finest level, coefficients varying in both directions, not run by the
+    // coarse-level interpreter: own copies of the per-cell kx, ky, from which
+    // the kernels of that level form its couplings (one copy when the caller
+    // passes the same array for both)
+    if (!h->oned && !Gen{h, G, h->opts.coarse_cta_nodes}.small(0)) {
+      const LevelShape& sh = G.shp[0];
+      const size_t nc = (size_t)ncx * (sh.py ? sh.ny : sh.ny - 1);
+      const bool same = coeffs->kx == coeffs->ky;
+      Level<double>& L = G.l64(0, 0);
+      double* kc[2] = {nullptr, nullptr};
+      for (int d = 0; d < (same ? 1 : 2); ++d) HIPCHK(h, h->dalloc(&kc[d], nc * sizeof(double)));
+      if (same) kc[1] = kc[0];
+      const double ax = 1.0 / (G.hx[0] * G.hx[0]), ay = 1.0 / (G.hy[0] * G.hy[0]);
+      L.kcx = kc[0];
+      L.kcy = kc[1];
+      L.kcpitch = ncx;
+      L.kc3x = ax / 3.0;
+      L.kc3y = ay / 3.0;
+      L.kc6x = ax / 6.0;
+      L.kc6y = ay / 6.0;
+      if (mixed) {
+        float* kf[2] = {nullptr, nullptr};
+        for (int d = 0; d < (same ? 1 : 2); ++d) HIPCHK(h, h->dalloc(&kf[d], nc * sizeof(float)));
+        if (same) kf[1] = kf[0];
+        Level<float>& M = G.l32(0, 0);
+        M.kcx = kf[0];
+        M.kcy = kf[1];
+        M.kcpitch = ncx;
+        M.kc3x = (float)L.kc3x;
+        M.kc3y = (float)L.kc3y;
+        M.kc6x = (float)L.kc6x;
+        M.kc6y = (float)L.kc6y;
       }
     }
+    HIPCHK(h, assemble_cell9(h, G, coeffs));
   }
 
   // line smoothers: Thomas factors of every line of the cycle's hierarchy
@@ -758,32 +827,25 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
           HIPCHK(h, alloc_line_factors(h, G.l64(l, s), sh));
         }
       }
+    HIPCHK(h, assemble_line_factors(h, G));
   }
 
   // coarsest operator of each slot: dense matrix, Cholesky factor and the
   // inverse the coarse solve applies (FP64)
   {
     const int n = G.ncu;
-    std::vector<double*> chol(ns, nullptr), inv(ns, nullptr);
-    int* dinfo = nullptr;
-    HIPCHK(h, h->dalloc(&dinfo, (size_t)ns * sizeof(int)));
+    G.chol.assign(ns, nullptr);
+    G.cinv.assign(ns, nullptr);
+    HIPCHK(h, h->dalloc(&G.dinfo, (size_t)ns * sizeof(int)));
     for (int s = 0; s < ns; ++s) {
-      const Level<double>& L = G.l64(G.nlev - 1, s);
-      HIPCHK(h, h->dalloc(&chol[s], (size_t)n * n * sizeof(double)));
-      HIPCHK(h, h->dalloc(&inv[s], (size_t)n * n * sizeof(double)));
-      HIPCHK(h, launch_dense_coarse(chol[s], n, sc.nx, sc.ny, sc.py, L.kind, L.cx, L.cy, L.dg, L.band, L.bstride,
-                                    L.bpitch, h->stream));
-      HIPCHK(h, launch_cholesky(chol[s], n, dinfo + s, h->stream));
-      HIPCHK(h, launch_chol_inverse(chol[s], inv[s], n, h->stream));
+      HIPCHK(h, h->dalloc(&G.chol[s], (size_t)n * n * sizeof(double)));
+      HIPCHK(h, h->dalloc(&G.cinv[s], (size_t)n * n * sizeof(double)));
     }
-    std::vector<int> info(ns, 0);
-    HIPCHK(h, hipMemcpyAsync(info.data(), dinfo, (size_t)ns * sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, h->dalloc(&G.dcholp, (size_t)ns * sizeof(double*)));
-    HIPCHK(h, hipMemcpyAsync(G.dcholp, inv.data(), (size_t)ns * sizeof(double*), hipMemcpyHostToDevice, h->stream));
-    mg_status st = sync_check(h);
+    HIPCHK(h, hipMemcpyAsync(G.dcholp, G.cinv.data(), (size_t)ns * sizeof(double*), hipMemcpyHostToDevice,
+                             h->stream));
+    mg_status st = assemble_coarsest(h, G);
     if (st != MG_OK) return st;
-    for (int s = 0; s < ns; ++s)
-      if (info[s]) return fail(h, MG_EINVAL, "coarsest operator is not positive definite");
   }
 
   // descriptors: level-major and problem-major copies
@@ -819,6 +881,23 @@ mg_status upload_descriptors(mg_handle h, Group& G) {
   return MG_OK;
 }
 
+// Counts the cell coefficients that are not finite and > 0 (one read-only
+// device pass over kx and ky) and fails if there are any.
+mg_status check_cell_coeffs(mg_handle h, const mg_coeffs* coeffs) {
+  const mg_grid& grid = h->groups[0].grid;
+  const int ncx = grid.nx - 1, ncy = grid.periodic_y ? grid.ny : grid.ny - 1;
+  const long nc = h->oned ? ncx : (long)ncx * ncy;
+  HIPCHK(h, hipMemsetAsync(h->dcount, 0, sizeof(int), h->stream));
+  HIPCHK(h, launch_count_bad(coeffs->kx, nc, h->dcount, h->stream));
+  HIPCHK(h, launch_count_bad(coeffs->ky, nc, h->dcount, h->stream));
+  int bad = 0;
+  HIPCHK(h, hipMemcpyAsync(&bad, h->dcount, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  mg_status s = sync_check(h);
+  if (s != MG_OK) return s;
+  if (bad) return fail(h, MG_EINVAL, std::to_string(bad) + " coefficient values are not finite and > 0");
+  return MG_OK;
+}
+
 // Common part of mg_setup and mg_setup_batched after the groups are formed.
 mg_status setup_handle(mg_handle h, const mg_coeffs* coeffs, int32_t levels) {
   h->line = line_dirs(h->opts.smoother);
@@ -836,18 +915,9 @@ mg_status setup_handle(mg_handle h, const mg_coeffs* coeffs, int32_t levels) {
 
   // coefficient checks (read-only device pass)
   if (h->kind == MG_COEF_CELL9) {
-    const mg_grid& grid = h->groups[0].grid;
-    const int ncx = grid.nx - 1, ncy = grid.periodic_y ? grid.ny : grid.ny - 1;
-    int* dcount = nullptr;
-    HIPCHK(h, h->dalloc(&dcount, sizeof(int)));
-    const long nc = h->oned ? ncx : (long)ncx * ncy;
-    HIPCHK(h, launch_count_bad(coeffs->kx, nc, dcount, h->stream));
-    HIPCHK(h, launch_count_bad(coeffs->ky, nc, dcount, h->stream));
-    int bad = 0;
-    HIPCHK(h, hipMemcpyAsync(&bad, dcount, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    mg_status s = sync_check(h);
+    HIPCHK(h, h->dalloc(&h->dcount, sizeof(int)));
+    mg_status s = check_cell_coeffs(h, coeffs);
     if (s != MG_OK) return s;
-    if (bad) return fail(h, MG_EINVAL, std::to_string(bad) + " coefficient values are not finite and > 0");
   }
   HIPCHK(h, h->mixed() ? prepare_subcycle_lds<float>() : prepare_subcycle_lds<double>());
   if (h->line) HIPCHK(h, h->mixed() ? prepare_line_cr<float>() : prepare_line_cr<double>());
@@ -1295,6 +1365,25 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
   *avg_us = 1e3 * ms / reps;
   return MG_OK;
+}
+
+mg_status mg_update_coeffs(mg_handle h, const mg_coeffs* coeffs) {
+  mg_status s = single_only(h);
+  if (s != MG_OK) return s;
+  if (!coeffs) return fail(h, MG_EINVAL, "coeffs is NULL");
+  if (h->kind != MG_COEF_CELL9 || coeffs->kind != MG_COEF_CELL9)
+    return fail(h, MG_EINVAL, "coefficient update needs cell coefficients, at setup and now");
+  if ((coeffs->kx_1d_along_x ? 1 : 0) != h->oned) return fail(h, MG_EINVAL, "kx_1d_along_x differs from setup");
+  if (!coeffs->kx || !coeffs->ky) return fail(h, MG_EINVAL, "kx and ky must be device arrays");
+  Group& G = h->groups[0];
+  const Level<double>& L0 = G.l64(0, 0);
+  if (L0.kcx && L0.kcx == L0.kcy && coeffs->kx != coeffs->ky)
+    return fail(h, MG_EINVAL, "kx and ky were one array at setup and must be one array here");
+  s = check_cell_coeffs(h, coeffs);
+  if (s != MG_OK) return s;
+  HIPCHK(h, assemble_cell9(h, G, coeffs));
+  if (h->line) HIPCHK(h, assemble_line_factors(h, G));
+  return assemble_coarsest(h, G);
 }
 
 mg_status mg_start_nested(mg_handle h, const double* rhs, double* x) {

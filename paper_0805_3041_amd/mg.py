@@ -36,7 +36,7 @@ PRECISIONS = {"fp64": MG_PREC_FP64, "mixed": MG_PREC_MIXED}
 EXPORTED = (
     "mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
     "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_shape", "mg_num_levels", "mg_profile_pass",
-    "mg_pass_info", "mg_start_nested",
+    "mg_pass_info", "mg_start_nested", "mg_update_coeffs",
 )
 
 
@@ -96,8 +96,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.c_int32, P(ctypes.c_double)]
     lib.mg_pass_info.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32)]
     lib.mg_start_nested.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.mg_update_coeffs.argtypes = [ctypes.c_void_p, P(mg_coeffs)]
     for name in ("mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
-                 "mg_destroy", "mg_level_shape", "mg_profile_pass", "mg_pass_info", "mg_start_nested"):
+                 "mg_destroy", "mg_level_shape", "mg_profile_pass", "mg_pass_info", "mg_start_nested",
+                 "mg_update_coeffs"):
         getattr(lib, name).restype = ctypes.c_int
     lib.mg_num_levels.restype = ctypes.c_int32
     _lib = lib
@@ -194,6 +196,13 @@ def mg_coeff_grad(h, u: torch.Tensor, lam: torch.Tensor, out: torch.Tensor) -> t
     if s != MG_OK:
         raise MGError(s, last_error(h))
     return out
+
+
+def mg_update_coeffs(h, coeffs: mg_coeffs) -> None:
+    lib = load_library()
+    s = lib.mg_update_coeffs(h, ctypes.byref(coeffs))
+    if s != MG_OK:
+        raise MGError(s, last_error(h))
 
 
 def mg_start_nested(h, rhs: torch.Tensor, x: torch.Tensor) -> None:
@@ -305,13 +314,23 @@ class Solver:
             self.coeffs = mg_coeffs(MG_COEF_CONST5, eps_x, eps_y, None, None, 0)
             self._keep = ()
         else:
-            ky = kx if ky is None else ky
-            kx = kx.contiguous().to(torch.float64)
-            ky = ky.contiguous().to(torch.float64)
-            self._keep = (kx, ky)
-            self.coeffs = mg_coeffs(MG_COEF_CELL9, 0.0, 0.0, _ptr(kx), _ptr(ky), 1 if kx_1d_along_x else 0)
+            self.coeffs = self._cell_coeffs(kx, ky, kx_1d_along_x)
         self.opts = make_options(**opt)
         self.h = mg_setup(self.grid, self.coeffs, levels, self.opts)
+
+    def _cell_coeffs(self, kx: torch.Tensor, ky: torch.Tensor | None, oned: bool) -> mg_coeffs:
+        same = ky is None or ky is kx
+        kx = kx.contiguous().to(torch.float64)
+        ky = kx if same else ky.contiguous().to(torch.float64)
+        self._keep = (kx, ky)
+        return mg_coeffs(MG_COEF_CELL9, 0.0, 0.0, _ptr(kx), _ptr(ky), 1 if oned else 0)
+
+    def update_coefficients(self, kx: torch.Tensor, ky: torch.Tensor | None = None) -> None:
+        """Rebuild every level's operator for new cell coefficients in the
+        handle's buffers (mg_update_coeffs); same layout as at construction,
+        and ky omitted (or kx itself) if it was omitted there."""
+        self.coeffs = self._cell_coeffs(kx, ky, bool(self.coeffs.kx_1d_along_x))
+        mg_update_coeffs(self.h, self.coeffs)
 
     def level_shape(self, level: int):
         """(nx, ny) stored shape of a level."""

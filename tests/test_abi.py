@@ -105,6 +105,7 @@ def test_null_handle_calls_are_rejected(mg):
     assert lib.mg_residual(None, None, None, None, ctypes.byref(nrm)) == mg.MG_EINVAL
     assert lib.mg_coeff_grad(None, None, None, None) == mg.MG_EINVAL
     assert lib.mg_start_nested(None, None, None) == mg.MG_EINVAL
+    assert lib.mg_update_coeffs(None, None) == mg.MG_EINVAL
     us = ctypes.c_double()
     assert lib.mg_profile_pass(None, None, None, 0, 2, 1, ctypes.byref(us)) == mg.MG_EINVAL
     assert lib.mg_destroy(None) == mg.MG_OK
