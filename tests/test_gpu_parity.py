@@ -396,6 +396,31 @@ def test_fused_solve_matches_per_op_solve(precision):
         np.testing.assert_allclose(ia.history, ib.history, rtol=1e-14, atol=0)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_tile_per_cu_on_the_finest_level(precision):
+    """1025^2 nodes: between one and two wide tiles per CU the tile chooser
+    takes tiles tall enough for at most one per CU (256 workgroups); two
+    cycles give the per-op kernels' iterate bit for bit."""
+    n = 1025
+    p = Problem(n, n, eps=0.01)
+    rhs = torch.tensor(W.aniso_rhs(n, 2), device="cuda")
+    x0 = torch.tensor(W.uniform_field(n, n, 22), device="cuda")
+    out = []
+    for mode in ("per_op", "fused"):
+        s = p.solver(precision=precision, tile_mode=mode)
+        try:
+            if mode == "fused":
+                for which in (0, 1):
+                    info = s.pass_info(0, which)
+                    assert info["wide"] == 1 and info["workgroups"] <= 256, info
+            x = x0.clone()
+            s.solve(rhs, x, 1e-300, 2, history=False)
+            out.append(x)
+        finally:
+            s.close()
+    assert torch.equal(out[0], out[1])
+
+
 # ----------------------------------------------------------------------------- asymptotic rate
 
 RATE_CASES = [
