@@ -42,6 +42,8 @@ def parse():
                     choices=["tri_x", "tri_y", "adi", "gstri_x", "gstri_y", "gsadi"],
                     help="aniso1025 / annulus4097 with a line smoother instead of the workload's point smoother")
     ap.add_argument("--omega", type=float, default=0.8, help="damping of the TRI and ADI line smoothers")
+    ap.add_argument("--sor", type=float, default=1.0,
+                    help="aniso1025 / annulus4097: SOR factor of the point Gauss-Seidel smoother (1 = Gauss-Seidel)")
     ap.add_argument("--x0", default="zero", choices=["zero", "uniform", "nested"],
                     help="start vector; nested = mg_start_nested inside the timed region")
     ap.add_argument("--levels", type=int, default=0, help="number of levels (0 = coarsen as far as possible)")
@@ -235,7 +237,7 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(n, eps_list, cycles_per_eps, nu, seconds, smoother="rbgs", omega=0.8):
+def cpu_baseline(n, eps_list, cycles_per_eps, nu, seconds, smoother="rbgs", omega=0.8, sor=1.0):
     """The oracle (FP64, scipy.sparse, one thread) runs F-cycles of the
     workload's hardest problem for about `seconds`; its time per cycle times
     the cycles the workload needs gives its unknowns/s."""
@@ -246,7 +248,7 @@ def cpu_baseline(n, eps_list, cycles_per_eps, nu, seconds, smoother="rbgs", omeg
 
     g = O.Grid(n, n)
     eps = min(eps_list)
-    h = O.hierarchy_5pt(g, eps, 1.0, O.Options(smoother=smoother, nu_pre=nu, nu_post=nu, omega=omega))
+    h = O.hierarchy_5pt(g, eps, 1.0, O.Options(smoother=smoother, nu_pre=nu, nu_post=nu, omega=omega, sor=sor))
     b = g.pack(W.aniso_rhs(n, 2))
     x = np.zeros(g.n_unknowns)
     done = 0
@@ -289,7 +291,8 @@ def annulus(args):
 
     def make(precision):
         return mg.Solver(nx, ny, periodic_y=True, kx=kxt, ky=kyt, kx_1d_along_x=True, smoother=smoother,
-                         nu_pre=args.nu, nu_post=args.nu, omega=args.omega, precision=precision, levels=args.levels)
+                         nu_pre=args.nu, nu_post=args.nu, omega=args.omega, sor=args.sor, precision=precision,
+                         levels=args.levels)
 
     def start(s, x):
         if args.x0 == "nested":
@@ -340,6 +343,8 @@ def annulus(args):
     if args.calibrate_copy:
         calibrate_copy()
     smoothing = SMOOTHER_NAMES[smoother] if args.smoother else "four-colour GS"
+    if not args.smoother and args.sor != 1.0:
+        smoothing = f"four-colour SOR (omega {args.sor:g})"
     out = {
         "metric": "unknowns/s to 1e-10 rel. residual",
         "value": unknowns * args.steps / wall_h,
@@ -369,11 +374,11 @@ def annulus(args):
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_annulus(info_h.cycles, args.nu, args.cpu_seconds, unknowns, smoother,
-                                                   args.omega)
+                                                   args.omega, args.sor)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_annulus(cycles, nu, seconds, unknowns_full, smoother="gs4c", omega=0.8):
+def cpu_baseline_annulus(cycles, nu, seconds, unknowns_full, smoother="gs4c", omega=0.8, sor=1.0):
     """Oracle F-cycles on the 1025 x 1024 annulus for about `seconds`; its cost
     per unknown-cycle, scaled to the full grid and the cycles the full solve
     needs (the cycle's work is linear in the number of unknowns)."""
@@ -385,7 +390,8 @@ def cpu_baseline_annulus(cycles, nu, seconds, unknowns_full, smoother="gs4c", om
     n = 1025
     g = O.Grid(n, n - 1, periodic_y=True)
     kx, ky = W.annulus_cell_coefficients(n)
-    h = O.hierarchy_q1(g, kx, ky, O.Options(smoother=smoother, nu_pre=nu, nu_post=nu, omega=omega), separable=True)
+    h = O.hierarchy_q1(g, kx, ky, O.Options(smoother=smoother, nu_pre=nu, nu_post=nu, omega=omega, sor=sor),
+                       separable=True)
     b = g.pack(W.annulus_rhs(n, n - 1, 3))
     x = np.zeros(g.n_unknowns)
     done = 0
@@ -706,7 +712,7 @@ def main():
 
     def make(precision):
         return [mg.Solver(n, n, eps_x=e, smoother=smoother, nu_pre=args.nu, nu_post=args.nu, omega=args.omega,
-                          precision=precision, levels=args.levels) for e in eps_list]
+                          sor=args.sor, precision=precision, levels=args.levels) for e in eps_list]
 
     def start(s, x):
         if args.x0 == "nested":
@@ -771,6 +777,8 @@ def main():
 
     total = unknowns * len(eps_list)
     smoothing = SMOOTHER_NAMES[smoother] if args.smoother else "red-black GS"
+    if not args.smoother and args.sor != 1.0:
+        smoothing = f"red-black SOR (omega {args.sor:g})"
     out = {
         "metric": "unknowns/s to 1e-10 rel. residual",
         "value": total * args.steps / wall_h,
@@ -801,7 +809,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, eps_list, [i.cycles for i in infos_h], args.nu, args.cpu_seconds,
-                                           smoother, args.omega)
+                                           smoother, args.omega, args.sor)
     print(json.dumps(out), flush=True)
 
 

@@ -112,8 +112,12 @@ typedef struct {
   int32_t kx_1d_along_x;
 } mg_coeffs;
 
-/* Options.  nu_pre, nu_post in [0, 8].  omega: Jacobi and TRI / ADI damping
- * (the Gauss-Seidel smoothers use omega = 1).  precision MG_PREC_MIXED runs every cycle in FP32 inside an
+/* Options.  nu_pre, nu_post in [0, 8].  omega: Jacobi and TRI / ADI damping.
+ * sor: relaxation factor of the point Gauss-Seidel smoothers (RBGS, GS4C),
+ * the SOR form C = D + sor L of "The choice of C" with L the couplings to
+ * earlier colours, each node x <- x + sor (x_GS - x); in (0, 2), 0 means 1
+ * (plain Gauss-Seidel, bit for bit the same as sor = 1); ignored by the
+ * other smoothers.  precision MG_PREC_MIXED runs every cycle in FP32 inside an
  * FP64 defect-correction loop (x, rhs stay FP64 at the boundary).
  * coarse_cta_nodes: levels with at most this many stored nodes run inside one
  * persistent workgroup (0 = the largest levels whose sub-hierarchy fits in
@@ -137,6 +141,7 @@ typedef struct {
   int32_t tile_mode;
   int32_t tile_x, tile_y;
   void* stream;
+  double sor;
 } mg_options;
 
 /* Solve report.  history (nullable, host) receives the residual norms

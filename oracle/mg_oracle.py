@@ -16,9 +16,10 @@ better Multigrid Solver Convergence", KAIST 2008):
   as a bilinear (Q1) finite-element matrix assembled element by element from
   per-cell coefficients;
 * the preconditioned Richardson smoother x <- x - omega C^{-1}(A x - b) of the
-  "Smoothers" section with C = D (Jacobi) and C = D + L (Gauss-Seidel, omega=1,
-  "The choice of C"), the Gauss-Seidel ordering being red-black (5-point) or
-  four-colour (9-point);
+  "Smoothers" section with C = D (Jacobi) and C = D + omega L (Gauss-Seidel at
+  omega = 1, SOR otherwise, "The choice of C"; Options.sor), the Gauss-Seidel
+  ordering being red-black (5-point) or four-colour (9-point) and L the
+  couplings to earlier colours;
 * the line smoothers of "The choice of C" and "Smoothing": TRI (C = the
   tridiagonal part of A along x or y lines, damped by omega), ADI (a TRI step
   along x then one along y), GSTRI (Gauss-Seidel over whole lines, each line
@@ -443,7 +444,8 @@ class Options:
     smoother: str = "rbgs"    # "jacobi", "rbgs" (2 colours), "gs4c" (4 colours), or one of LINE_SMOOTHERS
     nu_pre: int = 2
     nu_post: int = 2
-    omega: float = 0.8        # Jacobi damping; Gauss-Seidel uses 1
+    omega: float = 0.8        # Jacobi and TRI / ADI damping
+    sor: float = 1.0          # Gauss-Seidel / SOR factor in (0, 2) ("The choice of C": C = D + omega L); 1 = GS
 
 
 @dataclass
@@ -534,7 +536,7 @@ def smooth(h: Hierarchy, l: int, x, g, steps: int):
         elif o.smoother in LINE_SMOOTHERS:
             x = line_smoothing_step(h, l, x, g)
         else:
-            x = coloured_gs_step(h.A[l], h.diag[l], x, g, h.colours[l], 1.0)
+            x = coloured_gs_step(h.A[l], h.diag[l], x, g, h.colours[l], o.sor)
     return x
 
 

@@ -274,6 +274,13 @@ struct Gen {
   }
 };
 
+// Relaxation factor the smoothing kernels receive: the SOR factor for the
+// point Gauss-Seidel smoothers (0 stands for 1), omega for the others.
+double relax(mg_handle h) {
+  if (h->ncol > 0) return h->opts.sor == 0.0 ? 1.0 : h->opts.sor;
+  return h->opts.omega;
+}
+
 // Halo of a fused pass: one node per colour sweep (or Jacobi step), plus 2
 // for the defect and its restriction (pre) or 1 for the residual (post).
 int sweeps(mg_handle h, int steps) { return h->ncol == 0 ? steps : steps * h->ncol; }
@@ -333,6 +340,15 @@ TileGeom choose_tile(mg_handle h, const Group& G, int l, int H, bool post) {
   if (!fixed) {
     while (ntiles(TX, TY) < CHIP_CUS && TY > 8) TY >>= 1;
     while (ntiles(TX, TY) < CHIP_CUS && TX > 16) TX >>= 1;
+    // as for wide tiles: at most one tile per CU when there are between one
+    // and two per CU (513^2: 297 -> 234 tiles of 64 x 20)
+    const long nt = ntiles(TX, TY);
+    if (h->opts.tile_y == 0 && nt > CHIP_CUS && nt <= 2 * CHIP_CUS)
+      for (int ty = TY + 2; 4 * (ty + 2 * H) <= 5 * (TY + 2 * H) && bytes(TX, ty) <= FUSED_LDS_MAX; ty += 2)
+        if (ntiles(TX, ty) <= CHIP_CUS) {
+          TY = ty;
+          break;
+        }
   }
   while (bytes(TX, TY) > FUSED_LDS_MAX && TY > 2) TY >>= 1;
   while (bytes(TX, TY) > FUSED_LDS_MAX && TX > 2) TX >>= 1;
@@ -405,7 +421,7 @@ hipError_t run_op(mg_handle h, const Group& G, const HostOp& op, Level<T>* dL, L
   Level<T>* Ls = dL + (size_t)l * ns;
   Level<T>* Cs = dL + (size_t)(l + 1) * ns;
   switch (op.type) {
-    case H_COLOR: return launch_colour<T>(Ls, s, op.arg, h->ncol, ns, st);
+    case H_COLOR: return launch_colour<T>(Ls, s, op.arg, h->ncol, omega, ns, st);
     case H_JACOBI: return launch_jacobi<T>(Ls, s, op.arg, omega, ns, st);
     case H_COPY: return launch_copy<T>(Ls, s, ns, st);
     case H_DR: return launch_dr<T>(Ls, Cs, G.shp[l + 1], ns, st);
@@ -436,13 +452,13 @@ hipError_t enqueue_cycle(mg_handle h, const Group& G, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (!h->mixed()) {
     for (const HostOp& op : G.prog)
-      if ((e = run_op<double>(h, G, op, G.dL64, G.dP64, h->opts.omega, st)) != hipSuccess) return e;
+      if ((e = run_op<double>(h, G, op, G.dL64, G.dP64, relax(h), st)) != hipSuccess) return e;
     if (G.norm_fused) return hipSuccess;
     return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, nullptr, stencil_kind(h), h->oned, G.ns,
                                   st);
   }
   for (const HostOp& op : G.prog)
-    if ((e = run_op<float>(h, G, op, G.dL32, G.dP32, (float)h->opts.omega, st)) != hipSuccess) return e;
+    if ((e = run_op<float>(h, G, op, G.dL32, G.dP32, (float)relax(h), st)) != hipSuccess) return e;
   if (!G.mixed_fused && (e = launch_outer_update(G.dL64, G.dL32, G.shp[0], G.ns, st)) != hipSuccess) return e;
   return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, G.dL32, stencil_kind(h), h->oned, G.ns, st);
 }
@@ -533,6 +549,8 @@ mg_status check_opts(const mg_options* o, int kind) {
     return fail(nullptr, MG_EINVAL, "nu_pre and nu_post must be in [0, 8]");
   if ((o->smoother == MG_SMOOTH_JACOBI || line_jacobi(o->smoother)) && !finite_pos(o->omega))
     return fail(nullptr, MG_EINVAL, "omega must be > 0");
+  if (!(o->sor == 0.0 || (o->sor > 0.0 && o->sor < 2.0)))
+    return fail(nullptr, MG_EINVAL, "sor must be in (0, 2), or 0 for plain Gauss-Seidel");
   if (o->precision != MG_PREC_FP64 && o->precision != MG_PREC_MIXED) return fail(nullptr, MG_EINVAL, "bad precision");
   if (o->coarse_cta_nodes < 0) return fail(nullptr, MG_EINVAL, "coarse_cta_nodes must be >= 0");
   if (o->tile_mode < MG_TILES_FUSED || o->tile_mode > MG_TILES_WIDE) return fail(nullptr, MG_EINVAL, "bad tile_mode");
@@ -1361,14 +1379,14 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
     if (h->mixed()) {
       if (which == 0)
         return launch_pre<float>(G.dL32 + l, G.dL32 + l + 1, G.gpre[l], h->opts.nu_pre, h->ncol,
-                                 (float)h->opts.omega, kind, h->oned, l == 0, 1, st);
+                                 (float)relax(h), kind, h->oned, l == 0, 1, st);
       return launch_post<float>(G.dL32 + l, G.dL32 + l + 1, G.gpost[l], h->opts.nu_post, h->ncol,
-                                (float)h->opts.omega, found->arg, G.dL64, kind, h->oned, l == 0, 1, st, false);
+                                (float)relax(h), found->arg, G.dL64, kind, h->oned, l == 0, 1, st, false);
     }
     if (which == 0)
-      return launch_pre<double>(G.dL64 + l, G.dL64 + l + 1, G.gpre[l], h->opts.nu_pre, h->ncol, h->opts.omega,
+      return launch_pre<double>(G.dL64 + l, G.dL64 + l + 1, G.gpre[l], h->opts.nu_pre, h->ncol, relax(h),
                                 kind, h->oned, l == 0, 1, st);
-    return launch_post<double>(G.dL64 + l, G.dL64 + l + 1, G.gpost[l], h->opts.nu_post, h->ncol, h->opts.omega,
+    return launch_post<double>(G.dL64 + l, G.dL64 + l + 1, G.gpost[l], h->opts.nu_post, h->ncol, relax(h),
                                found->arg, G.dL64, kind, h->oned, l == 0, 1, st, false);
   };
   HIPCHK(h, launch());
@@ -1418,10 +1436,10 @@ mg_status mg_start_nested(mg_handle h, const double* rhs, double* x) {
   s = begin_solve(h, rr, xx, 1e-300);  // descriptors; r0 = ||b|| (mixed: the FP32 finest rhs = (float) b)
   if (s != MG_OK) return s;
   if (h->mixed()) {
-    HIPCHK(h, nested_pass<float>(h, G, G.dL32, G.dP32, (float)h->opts.omega, st));
+    HIPCHK(h, nested_pass<float>(h, G, G.dL32, G.dP32, (float)relax(h), st));
     HIPCHK(h, launch_outer_update(G.dL64, G.dL32, s0, 1, st));  // x = (double) e, e = 0
   } else {
-    HIPCHK(h, nested_pass<double>(h, G, G.dL64, G.dP64, h->opts.omega, st));
+    HIPCHK(h, nested_pass<double>(h, G, G.dL64, G.dP64, relax(h), st));
   }
   return sync_check(h);
 }

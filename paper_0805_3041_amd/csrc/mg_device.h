@@ -300,6 +300,14 @@ __device__ __forceinline__ T gs_v(const Level<T>& L, const Cf<T>& a, const Nbr<T
   return (bp - offd<K>(L, a, v)) * inv_diag<K>(L, a);
 }
 
+// Relaxed Gauss-Seidel value (SOR, C = D + omega L in colour order): the
+// node's old value xc moved by omega towards its Gauss-Seidel value gs;
+// omega = 1 returns gs itself.
+template <typename T>
+__device__ __forceinline__ T sor_v(T gs, T xc, T omega) {
+  return omega == (T)1 ? gs : fma(omega, gs - xc, xc);
+}
+
 // Defect b_p - (A x)_p.
 template <int K = KDYN, typename T>
 __device__ __forceinline__ T defect_v(const Level<T>& L, const Cf<T>& a, const Nbr<T>& v, T bp) {

@@ -123,7 +123,7 @@ __device__ __forceinline__ int wrap_once(int j, int ny, int py) {
 // holds (i + j) mod 2 == c.  Parities are those of global indices.
 template <typename T, int K, int NCOL, bool B1, bool EDGE>
 __device__ void sweep_colour(const Level<T>& L, const TileMap& m, MG_LDS T* x, const MG_LDS T* b,
-                             const MG_LDS T* bl, int W, int R, int s, int c) {
+                             const MG_LDS T* bl, int W, int R, int s, int c, T omega) {
   constexpr int NB = nbatch(K);
   const int hiW = W - s, hiR = R - s;
   int li0 = s, lj0 = s, rs = 1, nk, nr, par = 0;
@@ -175,7 +175,7 @@ __device__ void sweep_colour(const Level<T>& L, const TileMap& m, MG_LDS T* x, c
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u)
-      if (ok[u]) x[pos[u]] = gs_v<K>(L, a[u], v[u], bp[u]);
+      if (ok[u]) x[pos[u]] = sor_v(gs_v<K>(L, a[u], v[u], bp[u]), x[pos[u]], omega);
   }
 }
 
@@ -252,7 +252,7 @@ __device__ MG_LDS T* tile_smooth(const Level<T>& L, const TileMap& m, MG_LDS T* 
   } else {
     for (int k = 0; k < nsteps; ++k) {
       for (int c = 0; c < NCOL; ++c, ++s) {
-        sweep_colour<T, K, NCOL, B1, EDGE>(L, m, x, b, bl, W, R, s, c);
+        sweep_colour<T, K, NCOL, B1, EDGE>(L, m, x, b, bl, W, R, s, c, omega);
         __syncthreads();
       }
     }
@@ -642,7 +642,7 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // column is an unknown of the colour store.
 template <typename T, int K, int NCOL, bool B1, int Q>
 __device__ void wcolour_rows(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG_LDS T* bl, int hiR, int lj0,
-                             int rstep, int A, bool lane_ok, int gi) {
+                             int rstep, int A, bool lane_ok, int gi, T omega) {
   constexpr int P = wide_narr<NCOL>() * WW;
   constexpr int own = Q ? WH : 0;
   Cf<T> col{};
@@ -652,7 +652,8 @@ __device__ void wcolour_rows(const Level<T>& L, const WMap& m, MG_LDS T* lds, co
   const int step = rstep * NWAVE;
   auto node = [&](int lj) -> T {
     const Nbr<T> v = wgather<T, K, P, Q, false>(lds + (lj - 1) * P + A);
-    return gs_v<K>(L, wcoef<T, K, B1>(L, m, col, gi, lj), v, lds[lj * P + WW + own + A]);
+    const T gs = gs_v<K>(L, wcoef<T, K, B1>(L, m, col, gi, lj), v, lds[lj * P + WW + own + A]);
+    return omega == (T)1 ? gs : sor_v(gs, lds[lj * P + own + A], omega);
   };
   int lj = lj0 + rstep * wave_id();
   for (; lj + step < hiR; lj += 2 * step) {
@@ -680,7 +681,7 @@ __device__ void wcolour_rows(const Level<T>& L, const WMap& m, MG_LDS T* lds, co
 // sweep_colour; i0, j0 are even, so local and global parities agree up to H).
 template <typename T, int K, int NCOL, bool B1>
 __device__ void wsweep_colour(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG_LDS T* bl, int R, int s,
-                              int c) {
+                              int c, T omega) {
   const int wave = wave_id(), lane = threadIdx.x & 63;
   int q, lj0, rstep;
   if constexpr (NCOL == 4) {
@@ -700,9 +701,9 @@ __device__ void wsweep_colour(const Level<T>& L, const WMap& m, MG_LDS T* lds, c
   // give it an interior column for global band reads
   const int gi = lane_ok ? m.gi(li) : 1;
   if (q)
-    wcolour_rows<T, K, NCOL, B1, 1>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi);
+    wcolour_rows<T, K, NCOL, B1, 1>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi, omega);
   else
-    wcolour_rows<T, K, NCOL, B1, 0>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi);
+    wcolour_rows<T, K, NCOL, B1, 0>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi, omega);
 }
 
 // Every node of the region shrunk by s, both column parities per lane and
@@ -767,7 +768,7 @@ __device__ int wsmooth(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG
     int s = 1;
     for (int k = 0; k < nsteps; ++k)
       for (int c = 0; c < NCOL; ++c, ++s) {
-        wsweep_colour<T, K, NCOL, B1>(L, m, lds, bl, R, s, c);
+        wsweep_colour<T, K, NCOL, B1>(L, m, lds, bl, R, s, c, omega);
         __syncthreads();
       }
     return 0;

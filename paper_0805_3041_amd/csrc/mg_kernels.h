@@ -23,7 +23,8 @@ struct LevelShape {
 };
 
 template <typename T>
-hipError_t launch_colour(const Level<T>* Ls, const LevelShape& s, int c, int ncol, int nslots, hipStream_t st);
+hipError_t launch_colour(const Level<T>* Ls, const LevelShape& s, int c, int ncol, T omega, int nslots,
+                         hipStream_t st);
 template <typename T>
 hipError_t launch_jacobi(const Level<T>* Ls, const LevelShape& s, int dir, T omega, int nslots, hipStream_t st);
 template <typename T>

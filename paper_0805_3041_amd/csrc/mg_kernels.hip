@@ -49,14 +49,15 @@ struct ColourSet {
 // CELLS: whether the kernel can run a finest level that forms its couplings
 // from per-cell coefficients (false in the coarse-level interpreter).
 template <typename T, bool CELLS = true>
-__device__ void body_colour(const Level<T>& L, int c, int ncol, int tid, int nth) {
+__device__ void body_colour(const Level<T>& L, int c, int ncol, T omega, int tid, int nth) {
   ColourSet<T> S(L, c, ncol);
   const int n = S.count();
   for (int idx = tid; idx < n; idx += nth) {
     int i, j;
     if (!S.node(L, c, ncol, idx, i, j)) continue;
     const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
-    L.x[(size_t)j * L.pitch + i] = gs_value<CELLS>(L, L.x, L.b, i, j, jm, jp);
+    const size_t p = (size_t)j * L.pitch + i;
+    L.x[p] = sor_v(gs_value<CELLS>(L, L.x, L.b, i, j, jm, jp), L.x[p], omega);
   }
 }
 
@@ -138,10 +139,10 @@ __device__ void body_coarse(const Level<T>& L, const double* __restrict__ Ainv, 
 // --------------------------------------------------------------------------- per-op kernels
 
 template <typename T>
-__global__ void __launch_bounds__(NT) k_colour(const Level<T>* __restrict__ Ls, int c, int ncol) {
+__global__ void __launch_bounds__(NT) k_colour(const Level<T>* __restrict__ Ls, int c, int ncol, T omega) {
   const Level<T> L = Ls[blockIdx.z];
   if (L.st->done) return;
-  body_colour(L, c, ncol, blockIdx.x * NT + threadIdx.x, gridDim.x * NT);
+  body_colour(L, c, ncol, omega, blockIdx.x * NT + threadIdx.x, gridDim.x * NT);
 }
 
 template <typename T>
@@ -512,7 +513,7 @@ __device__ __forceinline__ void row_offsets(int j, int nx, int ny, int py, int& 
 // column only are read once.
 template <typename T, int K, bool B1>
 __device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int c, int ncol,
-                           int tid) {
+                           T omega, int tid) {
   constexpr int NB = nbatch(K);
   const int nx = L.nx, ny = L.ny, py = L.py;
   const int lo = py ? 0 : 1, hi = py ? ny - 1 : ny - 2;
@@ -553,7 +554,7 @@ __device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, co
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u)
-      if (j + u * jstep <= hi) x[pos + u * dpos] = gs_v<K>(L, a[u], v[u], bp[u]);
+      if (j + u * jstep <= hi) x[pos + u * dpos] = sor_v(gs_v<K>(L, a[u], v[u], bp[u]), x[pos + u * dpos], omega);
   }
 }
 
@@ -851,7 +852,7 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
       MG_LDS T* tl = bl + L.nx * L.ny;
       const MG_LDS T* bands = B1 ? lds + boffs[l] : nullptr;
       switch (type) {
-        case OP_COLOR: lds_colour<T, K, B1>(L, xl, bl, bands, arg, ncol, tid); break;
+        case OP_COLOR: lds_colour<T, K, B1>(L, xl, bl, bands, arg, ncol, omega, tid); break;
         case OP_JACOBI:
           lds_jacobi<T, K, B1>(L, arg == 0 ? xl : tl, arg == 0 ? tl : xl, bl, bands, omega, tid);
           break;
@@ -872,7 +873,7 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
       }
     } else {
       switch (type) {
-        case OP_COLOR: body_colour<T, false>(L, arg, ncol, tid, SUB_NT); break;
+        case OP_COLOR: body_colour<T, false>(L, arg, ncol, omega, tid, SUB_NT); break;
         case OP_JACOBI: body_jacobi<T, false>(L, arg, omega, tid, SUB_NT); break;
         case OP_COPY: body_copy(L, tid, SUB_NT); break;
         case OP_DR: body_dr<T, false>(L, Ls[l + 1], tid, SUB_NT); break;
@@ -1330,10 +1331,11 @@ __global__ void k_coeff_grad(const double* __restrict__ u, const double* __restr
 static inline unsigned blocks_for(long n, int per = NT) { return (unsigned)((n + per - 1) / per); }
 
 template <typename T>
-hipError_t launch_colour(const Level<T>* Ls, const LevelShape& s, int c, int ncol, int nslots, hipStream_t st) {
+hipError_t launch_colour(const Level<T>* Ls, const LevelShape& s, int c, int ncol, T omega, int nslots,
+                         hipStream_t st) {
   const int nk = (s.nx - 1) / 2 + 1;
   const int nrows = ncol == 2 ? s.nrows : (s.nrows + 1) / 2;
-  hipLaunchKernelGGL(k_colour<T>, dim3(blocks_for((long)nk * nrows), 1, nslots), dim3(NT), 0, st, Ls, c, ncol);
+  hipLaunchKernelGGL(k_colour<T>, dim3(blocks_for((long)nk * nrows), 1, nslots), dim3(NT), 0, st, Ls, c, ncol, omega);
   return hipGetLastError();
 }
 
@@ -1513,7 +1515,7 @@ hipError_t launch_coeff_grad(const double* u, const double* lam, double* g, int 
 }
 
 #define MG_INSTANTIATE(T)                                                                                          \
-  template hipError_t launch_colour<T>(const Level<T>*, const LevelShape&, int, int, int, hipStream_t);           \
+  template hipError_t launch_colour<T>(const Level<T>*, const LevelShape&, int, int, T, int, hipStream_t);           \
   template hipError_t launch_jacobi<T>(const Level<T>*, const LevelShape&, int, T, int, hipStream_t);             \
   template hipError_t launch_copy<T>(const Level<T>*, const LevelShape&, int, hipStream_t);                       \
   template hipError_t launch_dr<T>(const Level<T>*, const Level<T>*, const LevelShape&, int, hipStream_t);        \

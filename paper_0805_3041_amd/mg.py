@@ -54,7 +54,7 @@ class mg_options(ctypes.Structure):
     _fields_ = [("cycle", ctypes.c_int32), ("smoother", ctypes.c_int32), ("nu_pre", ctypes.c_int32),
                 ("nu_post", ctypes.c_int32), ("omega", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("coarse_cta_nodes", ctypes.c_int32), ("tile_mode", ctypes.c_int32), ("tile_x", ctypes.c_int32),
-                ("tile_y", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("tile_y", ctypes.c_int32), ("stream", ctypes.c_void_p), ("sor", ctypes.c_double)]
 
 
 class mg_info(ctypes.Structure):
@@ -296,10 +296,10 @@ TILE_MODES = {"fused": MG_TILES_FUSED, "per_op": MG_TILES_PER_OP, "narrow": MG_T
 
 
 def make_options(cycle="F", smoother="rbgs", nu_pre=2, nu_post=2, omega=0.8, precision="fp64",
-                 coarse_cta_nodes=0, tile_mode="fused", tile_x=0, tile_y=0, stream=None) -> mg_options:
+                 coarse_cta_nodes=0, tile_mode="fused", tile_x=0, tile_y=0, stream=None, sor=1.0) -> mg_options:
     return mg_options(CYCLES[cycle], SMOOTHERS[smoother], int(nu_pre), int(nu_post), float(omega),
                       PRECISIONS[precision], int(coarse_cta_nodes), TILE_MODES[tile_mode], int(tile_x), int(tile_y),
-                      _stream_ptr(stream))
+                      _stream_ptr(stream), float(sor))
 
 
 class Solver:

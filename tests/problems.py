@@ -22,6 +22,7 @@ class Problem:
     nu_pre: int = 2
     nu_post: int = 2
     omega: float = 0.8
+    sor: float = 1.0
     cycle: str = "F"
     levels: int = 0
 
@@ -43,7 +44,7 @@ class Problem:
     def oracle(self):
         g = self.grid()
         opts = O.Options(cycle=self.cycle, smoother=self.smoother, nu_pre=self.nu_pre, nu_post=self.nu_post,
-                         omega=self.omega)
+                         omega=self.omega, sor=self.sor)
         c = self.coefficients()
         if c is None:
             return O.hierarchy_5pt(g, self.eps, 1.0, opts, self.levels)
@@ -57,7 +58,7 @@ class Problem:
         from paper_0805_3041_amd import mg
         c = self.coefficients()
         kw = dict(periodic_y=self.periodic_y, levels=self.levels, cycle=self.cycle, smoother=self.smoother,
-                  nu_pre=self.nu_pre, nu_post=self.nu_post, omega=self.omega, precision=precision,
+                  nu_pre=self.nu_pre, nu_post=self.nu_post, omega=self.omega, sor=self.sor, precision=precision,
                   coarse_cta_nodes=coarse_cta_nodes, **extra)
         if c is None:
             return mg.Solver(self.nx, self.ny, eps_x=self.eps, eps_y=1.0, **kw)

@@ -67,6 +67,9 @@ def _setup(mg, grid, coeffs, levels=0, **opt):
     dict(opt=dict(cycle=7)),
     dict(opt=dict(cycle=3)),
     dict(opt=dict(smoother=9)),
+    dict(opt=dict(sor=2.0)),
+    dict(opt=dict(sor=-0.5)),
+    dict(opt=dict(sor=float("nan"))),
     dict(opt=dict(smoother=-1)),
     dict(opt=dict(smoother=3, omega=0.0)),          # TRI_X needs a damping omega > 0
     dict(opt=dict(smoother=5, omega=float("nan"))),  # ADI likewise

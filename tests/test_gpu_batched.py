@@ -84,7 +84,10 @@ def test_batched_to_tolerance_statuses_and_cycles():
         assert info.status == mg.MG_OK and infos[i].status == mg.MG_OK
         assert infos[i].cycles == info.cycles, (i, infos[i].cycles, info.cycles)
         assert torch.equal(x, xb[i])
-        np.testing.assert_array_equal(infos[i].history, info.history)
+        # same iterates; the tile heights of a batch are chosen for all its
+        # problems' tiles together, so its residual norms may be summed over
+        # other tiles than a single solve's
+        np.testing.assert_allclose(infos[i].history, info.history, rtol=1e-14, atol=0)
 
 
 def test_batched_max_cycles_and_masking():

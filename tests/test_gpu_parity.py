@@ -342,6 +342,9 @@ FUSED_CASES = [
     dict(p=dict(nx=289, ny=161, eps=0.3, smoother="rbgs"), cta=100, wide_ty=6),
     dict(p=dict(nx=257, ny=256, periodic_y=True, q1="annulus", smoother="gs4c"), cta=300, wide_ty=10),
     dict(p=dict(nx=257, ny=256, periodic_y=True, q1="annulus", smoother="jacobi", nu_pre=2, nu_post=3), cta=300),
+    dict(p=dict(nx=257, ny=257, eps=0.1, smoother="rbgs", sor=1.4), cta=300),
+    dict(p=dict(nx=129, ny=129, q1="grf", smoother="gs4c", sor=0.8), cta=300),
+    dict(p=dict(nx=257, ny=256, periodic_y=True, q1="annulus", smoother="gs4c", sor=1.25), cta=300, wide_ty=10),
 ]
 
 
@@ -419,6 +422,63 @@ def test_one_tile_per_cu_on_the_finest_level(precision):
         finally:
             s.close()
     assert torch.equal(out[0], out[1])
+
+
+# ----------------------------------------------------------------------------- SOR
+
+
+SOR_CASES = [
+    dict(p=dict(nx=65, ny=65, eps=0.1, smoother="rbgs", sor=1.3), cta=0),      # all in the LDS interpreter
+    dict(p=dict(nx=129, ny=129, eps=0.1, smoother="rbgs", sor=1.3), cta=300),  # fused levels + interpreter
+    dict(p=dict(nx=129, ny=129, eps=0.1, smoother="rbgs", sor=0.7), cta=5000),  # interpreter on global memory
+    dict(p=dict(nx=129, ny=129, q1="grf", smoother="gs4c", sor=1.2), cta=300),
+    dict(p=dict(nx=129, ny=128, periodic_y=True, q1="annulus", smoother="gs4c", sor=1.2), cta=300),
+]
+
+
+@pytest.mark.parametrize("case", SOR_CASES, ids=[str(i) for i in range(len(SOR_CASES))])
+def test_sor_per_cycle(case):
+    """Over- and under-relaxed colour Gauss-Seidel (SOR, C = D + omega L)
+    against the oracle, cycle by cycle."""
+    p = Problem(**case["p"])
+    check_parity(p, W.normal_field(p.nx, p.ny, 2, p.periodic_y), W.uniform_field(p.nx, p.ny, 1, p.periodic_y), 3,
+                 coarse_cta_nodes=case["cta"])
+
+
+def test_sor_mixed_precision_reaches_tolerance():
+    from oracle import mg_oracle as O
+    n = 257
+    p = Problem(n, n, eps=0.05, sor=1.2)
+    g = p.grid()
+    rhs = W.normal_field(n, n, 2)
+    s = p.solver(precision="mixed")
+    try:
+        x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        info = s.solve(torch.tensor(rhs, device="cuda"), x, tol=1e-10, max_cycles=200)
+    finally:
+        s.close()
+    assert info.status == 0
+    h = p.oracle()
+    b = g.pack(rhs)
+    rel = O.residual_norm(h, b, g.pack(x.cpu().numpy())) / O.residual_norm(h, b, np.zeros_like(b))
+    assert rel <= 1e-10
+
+
+def test_sor_zero_stands_for_one():
+    """sor = 0 (a zero-initialised option struct) is sor = 1, plain
+    Gauss-Seidel, bit for bit; another factor changes the iterate."""
+    n = 129
+    rhs = torch.tensor(W.normal_field(n, n, 2), device="cuda")
+    out = []
+    for sor in (1.0, 0.0, 1.3):
+        s = Problem(n, n, eps=0.1, sor=sor).solver(coarse_cta_nodes=300)
+        try:
+            x = torch.zeros_like(rhs)
+            s.solve(rhs, x, 1e-300, 3, history=False)
+            out.append(x)
+        finally:
+            s.close()
+    assert torch.equal(out[0], out[1]) and not torch.equal(out[0], out[2])
 
 
 # ----------------------------------------------------------------------------- asymptotic rate
