@@ -301,11 +301,14 @@ __device__ __forceinline__ T gs_v(const Level<T>& L, const Cf<T>& a, const Nbr<T
 }
 
 // Relaxed Gauss-Seidel value (SOR, C = D + omega L in colour order): the
-// node's old value xc moved by omega towards its Gauss-Seidel value gs;
-// omega = 1 returns gs itself.
-template <typename T>
-__device__ __forceinline__ T sor_v(T gs, T xc, T omega) {
-  return omega == (T)1 ? gs : fma(omega, gs - xc, xc);
+// node's old value *xp moved by omega towards its Gauss-Seidel value gs;
+// omega = 1 returns gs itself without loading the old value (omega is
+// uniform, so plain Gauss-Seidel sweeps issue no extra load).
+template <typename T, typename P>
+__device__ __forceinline__ T sor_v(T gs, P xp, T omega) {
+  if (omega == (T)1) return gs;
+  const T xc = *xp;
+  return fma(omega, gs - xc, xc);
 }
 
 // Defect b_p - (A x)_p.

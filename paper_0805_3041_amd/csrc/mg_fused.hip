@@ -175,7 +175,7 @@ __device__ void sweep_colour(const Level<T>& L, const TileMap& m, MG_LDS T* x, c
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u)
-      if (ok[u]) x[pos[u]] = sor_v(gs_v<K>(L, a[u], v[u], bp[u]), x[pos[u]], omega);
+      if (ok[u]) x[pos[u]] = sor_v(gs_v<K>(L, a[u], v[u], bp[u]), x + pos[u], omega);
   }
 }
 
@@ -652,8 +652,8 @@ __device__ void wcolour_rows(const Level<T>& L, const WMap& m, MG_LDS T* lds, co
   const int step = rstep * NWAVE;
   auto node = [&](int lj) -> T {
     const Nbr<T> v = wgather<T, K, P, Q, false>(lds + (lj - 1) * P + A);
-    const T gs = gs_v<K>(L, wcoef<T, K, B1>(L, m, col, gi, lj), v, lds[lj * P + WW + own + A]);
-    return omega == (T)1 ? gs : sor_v(gs, lds[lj * P + own + A], omega);
+    return sor_v(gs_v<K>(L, wcoef<T, K, B1>(L, m, col, gi, lj), v, lds[lj * P + WW + own + A]), lds + lj * P + own + A,
+                 omega);
   };
   int lj = lj0 + rstep * wave_id();
   for (; lj + step < hiR; lj += 2 * step) {

@@ -57,7 +57,7 @@ __device__ void body_colour(const Level<T>& L, int c, int ncol, T omega, int tid
     if (!S.node(L, c, ncol, idx, i, j)) continue;
     const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
     const size_t p = (size_t)j * L.pitch + i;
-    L.x[p] = sor_v(gs_value<CELLS>(L, L.x, L.b, i, j, jm, jp), L.x[p], omega);
+    L.x[p] = sor_v(gs_value<CELLS>(L, L.x, L.b, i, j, jm, jp), L.x + p, omega);
   }
 }
 
@@ -554,7 +554,7 @@ __device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, co
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u)
-      if (j + u * jstep <= hi) x[pos + u * dpos] = sor_v(gs_v<K>(L, a[u], v[u], bp[u]), x[pos + u * dpos], omega);
+      if (j + u * jstep <= hi) x[pos + u * dpos] = sor_v(gs_v<K>(L, a[u], v[u], bp[u]), x + pos + u * dpos, omega);
   }
 }
 
