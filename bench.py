@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="aniso1025", choices=["aniso1025", "annulus4097", "batch256", "grf2049"])
+    ap.add_argument("--workload", default="aniso1025",
+                    choices=["aniso1025", "annulus4097", "batch256", "grf2049", "sphere2049"])
     ap.add_argument("--nu", type=int, default=2)
     ap.add_argument("--smoother", default=None,
                     choices=["tri_x", "tri_y", "adi", "gstri_x", "gstri_y", "gsadi"],
@@ -416,7 +417,7 @@ SMOOTHER_NAMES = {"tri_x": "TRI (x lines)", "tri_y": "TRI (y lines)", "adi": "AD
                   "gstri_y": "GSTRI (y lines)", "gsadi": "GSADI"}
 
 
-def line_roofline(s, rhs, scratch, head, nx, ny, periodic_y, smoother, stencil, bands_2d=False, reps=20):
+def line_roofline(s, rhs, scratch, head, nx, ny, periodic_y, smoother, stencil, bands_2d=False, reps=20, cells=0):
     """Roofline of the first line sweep of the finest level (one launch)."""
     us = s.profile_pass(rhs, scratch, 0, 2, reps=reps)
     w = 4 if head == "mixed" else 8
@@ -430,7 +431,7 @@ def line_roofline(s, rhs, scratch, head, nx, ny, periodic_y, smoother, stencil, 
         lines = [j for j in rows if jac or j % 2 == 0]
         m = nx - 2
     nodes = len(lines) * m
-    bpn = (LINE_VALUES_PER_NODE + (6 if bands_2d else 0)) * w
+    bpn = (LINE_VALUES_PER_NODE + (6 if bands_2d else 0) + cells) * w
     alg = bpn * nodes
     ach = alg / (us * 1e-6) / 1e9
     t = "float" if head == "mixed" else "double"
@@ -655,6 +656,131 @@ def grf2049(args):
     print(json.dumps(out), flush=True)
 
 
+def sphere2049(args):
+    """Workload sphere2049: -Laplace(u) in spherical coordinates (axisymmetric
+    shell section r in [0.5, 1], theta in [0.1 pi, 0.9 pi], the weak form
+    weighted by r^2 sin(theta)) mapped to the unit square, 2049^2 nodes, Q1
+    with per-cell kx = r^2 sin(theta) Lt/Lr and ky = sin(theta) Lr/Lt (two
+    arrays varying in both directions), f = N(0,1) (seed 3); four-colour GS
+    2/2 or the --smoother line smoother, F-cycle to 1e-10."""
+    import torch
+
+    import workloads as W
+    from paper_0805_3041_amd import mg
+
+    n = 2049
+    kx, ky = W.sphere_cell_coefficients(n, n)
+    kxt, kyt = torch.tensor(kx, device="cuda"), torch.tensor(ky, device="cuda")
+    rhs = torch.tensor(W.normal_field(n, n, 3), device="cuda")
+    unknowns = (n - 2) ** 2
+    smoother = args.smoother or "gs4c"
+
+    def make(precision):
+        return mg.Solver(n, n, kx=kxt, ky=kyt, smoother=smoother, nu_pre=args.nu, nu_post=args.nu,
+                         omega=args.omega, sor=args.sor, precision=precision, levels=args.levels)
+
+    def run(s, steps, warmup):
+        x = torch.zeros_like(rhs)
+        for _ in range(warmup):
+            x.zero_()
+            s.solve(rhs, x, TOL, args.max_cycles, history=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = None
+        for _ in range(steps):
+            x.zero_()
+            info = s.solve(rhs, x, TOL, args.max_cycles, history=False)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, info
+
+    head = args.precision
+    other = "fp64" if head == "mixed" else "mixed"
+    w = 4 if head == "mixed" else 8
+    s = make(head)
+    wall_h, info_h = run(s, args.steps, args.warmup)
+    if info_h.status != mg.MG_OK:
+        raise SystemExit(f"solve did not converge: {mg.status_string(info_h.status)} rel_res {info_h.rel_res:.3e}")
+    scratch = torch.zeros_like(rhs)
+    if args.smoother:
+        roofline = line_roofline(s, rhs, scratch, head, n, n, False, smoother, 1, cells=2)
+    else:
+        times = {which: s.profile_pass(rhs, scratch, 0, which, reps=20) for which in (0, 1)}
+        dom = 1 if times[1] >= times[0] else 0
+        kernel_name = s.pass_kernel_name(0, dom)
+        bpn = BYTES_PER_NODE[(head, dom)] + 2 * w  # + the two cell coefficients
+        alg = bpn * n * n
+        achieved = alg / (times[dom] * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic("sphere2049", kernel_name),
+                    "kernel": kernel_name, "avg_us": times[dom], "bytes_per_launch": alg, "bytes_per_node": bpn,
+                    "nodes": n * n, "other_pass_us": times[1 - dom]}
+    s.close()
+    s = make(other)
+    steps_o = max(1, args.steps // 2)
+    wall_o, info_o = run(s, steps_o, 1)
+    s.close()
+    smoothing = SMOOTHER_NAMES[smoother] if args.smoother else "four-colour GS"
+    if not args.smoother and args.sor != 1.0:
+        smoothing = f"four-colour SOR (omega {args.sor:g})"
+    out = {
+        "metric": "unknowns/s to 1e-10 rel. residual",
+        "value": unknowns * args.steps / wall_h,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall_h / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-inner/f64-outer" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "sphere2049: -Laplace(u) in spherical coordinates, r in [0.5,1], theta in "
+                               "[0.1 pi,0.9 pi], weight r^2 sin(theta), mapped to the unit square, 2049x2049 "
+                               f"nodes, Q1 with per-cell kx, ky, f = N(0,1), {smoothing} {args.nu}/{args.nu}, "
+                               "F-cycle, x0=0, tol 1e-10", "precision": head},
+        "roofline": roofline,
+        "cycles": info_h.cycles,
+        "rel_res": info_h.rel_res,
+        "us_per_cycle": 1e6 * info_h.seconds / max(1, info_h.cycles),
+        f"value_{other}": unknowns * steps_o / wall_o,
+        f"cycles_{other}": info_o.cycles,
+        "speedup_mixed_over_fp64": ((wall_o / steps_o) / (wall_h / args.steps)) if head == "mixed"
+        else ((wall_h / args.steps) / (wall_o / steps_o)),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_sphere(info_h.cycles, args.nu, args.cpu_seconds, unknowns, smoother,
+                                                  args.omega, args.sor)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_sphere(cycles, nu, seconds, unknowns_full, smoother, omega, sor):
+    """Oracle F-cycles on the 257 x 257 spherical problem for about
+    `seconds`; its time per unknown-cycle times the GPU's cycles and the full
+    problem's unknowns."""
+    import numpy as np
+
+    from oracle import mg_oracle as O
+    import workloads as W
+
+    n = 257
+    g = O.Grid(n, n)
+    kx, ky = W.sphere_cell_coefficients(n, n)
+    h = O.hierarchy_q1(g, kx, ky, O.Options(smoother=smoother, nu_pre=nu, nu_post=nu, omega=omega, sor=sor))
+    b = g.pack(W.normal_field(n, n, 3))
+    x = np.zeros(g.n_unknowns)
+    done = 0
+    t0 = time.perf_counter()
+    while done < 2 or time.perf_counter() - t0 < seconds:
+        x = O.mg_cycle(h, 0, x, b, "F")
+        done += 1
+    per = (time.perf_counter() - t0) / done / g.n_unknowns
+    return {"value": unknowns_full / (per * unknowns_full * cycles), "unit": "unknowns/s", "cores": 1,
+            "kind": "oracle", "sample": f"{done} FP64 F-cycles of the 257x257 spherical problem, scaled linearly "
+                                        f"to 2049^2 unknowns times the GPU's {cycles} cycles",
+            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
+
+
 def cpu_baseline_grf(unknowns_full, seconds):
     """The oracle's gradient (direct sparse forward and adjoint solves plus
     dL/da) on the 129 x 129 version of the problem, repeated for about
@@ -696,6 +822,8 @@ def main():
         return batch256(args)
     if args.workload == "grf2049":
         return grf2049(args)
+    if args.workload == "sphere2049":
+        return sphere2049(args)
     import numpy as np
     import torch
 

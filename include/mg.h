@@ -197,8 +197,9 @@ mg_status mg_coeff_grad(mg_handle h, const double* u, const double* lam, double*
  * checks the handle's operators are undefined until a successful update. */
 mg_status mg_update_coeffs(mg_handle h, const mg_coeffs* coeffs);
 
-/* Start vector by nested iteration ("Start-Vector Choice": begin on the
- * coarsest level and work up to the finest): rhs is restricted by full
+/* Start vector by nested iteration (section "Start-Vector Choice": the
+ * solution starts on the coarsest grid and is carried level by level to the
+ * finest one): rhs is restricted by full
  * weighting to every level, the coarsest problem solved exactly, and on each
  * finer level below the finest the prolonged coarser result is improved by
  * one cycle of the handle's kind; x (device, [ny][nx], overwritten) receives

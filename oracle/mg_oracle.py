@@ -572,8 +572,9 @@ def mg_cycle(h: Hierarchy, l: int, x, g, kind: str = "F"):
 
 
 def nested_start(h: Hierarchy, b, kind: str = None):
-    """Start vector by nested iteration ("Start-Vector Choice": begin on the
-    coarsest level and work up to the finest): the right-hand side is
+    """Start vector by nested iteration (section "Start-Vector Choice": the
+    solution starts on the coarsest grid and is carried level by level to the
+    finest one): the right-hand side is
     restricted to every level (b_{l+1} = R b_l), the coarsest problem is solved
     exactly, and on each finer level l >= 1 the prolonged coarser result is
     improved by one cycle of the hierarchy's kind with rhs b_l; the finest

@@ -17,7 +17,7 @@ class Problem:
     ny: int
     periodic_y: bool = False
     eps: float = 1.0
-    q1: str | None = None        # None (5-point), "annulus", "grf"
+    q1: str | None = None        # None (5-point), "annulus", "grf", "sphere"
     smoother: str = "rbgs"
     nu_pre: int = 2
     nu_post: int = 2
@@ -34,6 +34,9 @@ class Problem:
         if self.q1 == "annulus":
             kx, ky = W.annulus_cell_coefficients(self.nx)
             return kx, ky, True
+        if self.q1 == "sphere":
+            kx, ky = W.sphere_cell_coefficients(self.nx, self.ny)
+            return kx, ky, False
         if self.q1 == "grf":
             ncy = self.ny if self.periodic_y else self.ny - 1
             assert ncy == self.nx - 1

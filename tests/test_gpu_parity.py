@@ -343,6 +343,7 @@ FUSED_CASES = [
     dict(p=dict(nx=257, ny=256, periodic_y=True, q1="annulus", smoother="gs4c"), cta=300, wide_ty=10),
     dict(p=dict(nx=257, ny=256, periodic_y=True, q1="annulus", smoother="jacobi", nu_pre=2, nu_post=3), cta=300),
     dict(p=dict(nx=257, ny=257, eps=0.1, smoother="rbgs", sor=1.4), cta=300),
+    dict(p=dict(nx=257, ny=257, q1="sphere", smoother="gs4c"), cta=300),
     dict(p=dict(nx=129, ny=129, q1="grf", smoother="gs4c", sor=0.8), cta=300),
     dict(p=dict(nx=257, ny=256, periodic_y=True, q1="annulus", smoother="gs4c", sor=1.25), cta=300, wide_ty=10),
 ]

@@ -103,6 +103,47 @@ def annulus_cell_coefficients(nx: int):
     return kx, ky
 
 
+# Spherical coordinates (r, theta) of an axisymmetric shell section, away
+# from the axis: r in [0.5, 1], theta in [0.1 pi, 0.9 pi].
+SPHERE_R0, SPHERE_R1 = 0.5, 1.0
+SPHERE_T0, SPHERE_T1 = 0.1 * np.pi, 0.9 * np.pi
+
+
+def sphere_cell_coefficients(nx: int, ny: int):
+    """Per-cell ([ny-1][nx-1]) coefficients of -Laplace(u) in spherical
+    coordinates (axisymmetric), whose weak form carries the volume weight
+    r^2 sin(theta): int (r^2 sin(theta) u_r v_r + sin(theta) u_theta v_theta)
+    dr dtheta.  Mapped to the unit square (r = R0 + Lr xi, theta = T0 +
+    Lt eta) it becomes int (kx u_xi v_xi + ky u_eta v_eta) dxi deta with
+    kx = r^2 sin(theta) Lt / Lr and ky = sin(theta) Lr / Lt, evaluated at
+    the cell midpoint; both vary over the cells in both directions."""
+    lr, lt = SPHERE_R1 - SPHERE_R0, SPHERE_T1 - SPHERE_T0
+    xi = (np.arange(nx - 1) + 0.5) / (nx - 1)
+    eta = (np.arange(ny - 1) + 0.5) / (ny - 1)
+    R, T = np.meshgrid(SPHERE_R0 + lr * xi, SPHERE_T0 + lt * eta)
+    kx = R * R * np.sin(T) * lt / lr
+    ky = np.sin(T) * lr / lt
+    return np.ascontiguousarray(kx), np.ascontiguousarray(ky)
+
+
+def sphere_manufactured(n: int):
+    """u = sin(pi xi) sin(pi eta) (zero on the boundary) and the nodal values
+    of -d/dxi (kx u_xi) - d/deta (ky u_eta) for the continuous kx, ky of
+    sphere_cell_coefficients, written out by the product rule; returns
+    (f, u) as [n][n] arrays."""
+    lr, lt = SPHERE_R1 - SPHERE_R0, SPHERE_T1 - SPHERE_T0
+    X, Y = node_coords(n, n)
+    r, t = SPHERE_R0 + lr * X, SPHERE_T0 + lt * Y
+    sx, cx = np.sin(np.pi * X), np.cos(np.pi * X)
+    sy, cy = np.sin(np.pi * Y), np.cos(np.pi * Y)
+    u = sx * sy
+    # d/dxi (kx u_xi), kx = r^2 sin(t) lt/lr, dr/dxi = lr
+    d_x = (lt / lr) * np.sin(t) * sy * np.pi * (2.0 * r * lr * cx - r * r * np.pi * sx)
+    # d/deta (ky u_eta), ky = sin(t) lr/lt, dt/deta = lt
+    d_y = (lr / lt) * sx * np.pi * (lt * np.cos(t) * cy - np.pi * np.sin(t) * sy)
+    return zero_boundary(-(d_x + d_y)), zero_boundary(u)
+
+
 def annulus_radius(nx: int, ny: int) -> np.ndarray:
     X, _ = node_coords(nx, ny, periodic_y=True)
     return ANNULUS_R0 + (ANNULUS_R1 - ANNULUS_R0) * X
