@@ -435,8 +435,10 @@ def line_roofline(s, rhs, scratch, head, nx, ny, periodic_y, smoother, stencil, 
     alg = bpn * nodes
     ach = alg / (us * 1e-6) / 1e9
     t = "float" if head == "mixed" else "double"
+    # lines whose 4 m values fit 140 KB of LDS run the cyclic-reduction kernel
+    kernel = "k_line_cr" if 4 * m * w <= 140 * 1024 else "k_line"
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": None, "kernel": f"mg::k_line<{t}, {stencil}>", "avg_us": us, "bytes_per_launch": alg,
+            "traffic": None, "kernel": f"mg::{kernel}<{t}, {stencil}>", "avg_us": us, "bytes_per_launch": alg,
             "bytes_per_node": bpn, "nodes": nodes}
 
 
