@@ -721,6 +721,8 @@ def sphere2049(args):
     steps_o = max(1, args.steps // 2)
     wall_o, info_o = run(s, steps_o, 1)
     s.close()
+    if args.calibrate_copy:
+        calibrate_copy()
     smoothing = SMOOTHER_NAMES[smoother] if args.smoother else "four-colour GS"
     if not args.smoother and args.sor != 1.0:
         smoothing = f"four-colour SOR (omega {args.sor:g})"
