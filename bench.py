@@ -817,7 +817,7 @@ def main():
         sys.stdout.write(traffic_summary(*args.traffic_summary, args.command))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: collectives and multi-GPU sharding are not "
+        print(json.dumps({"error": "this library runs on one GPU only: collectives and multi-GPU sharding are not "
                                    "built; run with --gpus 1"}), flush=True)
         sys.exit(2)
     if args.workload == "annulus4097":
