@@ -130,7 +130,16 @@ typedef struct {
  * give the same results, bit for bit.  tile_x, tile_y: output tile of the
  * fused passes (even, 0 = chosen per level); a nonzero tile_x selects small
  * tiles of that width, tile_y alone sets the height of wide tiles.
- * stream: hipStream_t. */
+ * stream: hipStream_t.
+ * inner_cycles: MG_PREC_MIXED only, the FP32 cycles of one outer step: the
+ *   correction e of A e = (float) r starts at 0 and gets that many cycles
+ *   before x += (double) e (0 means 1; at most 16).  Ignored in FP64.
+ * coarse_op: operators of the coarse levels.  MG_COARSE_DEFAULT: a 5-point
+ *   problem rediscretises its operator on every level (H = 2h), a 9-point
+ *   problem takes the Galerkin product R A P.  MG_COARSE_GALERKIN on a 5-point
+ *   problem: the coarse levels take R A P too (they are then 9-point, so the
+ *   smoother must be MG_SMOOTH_JACOBI or MG_SMOOTH_GS4C; red-black and line
+ *   smoothers are MG_EUNSUPPORTED, and so are batched handles). */
 typedef struct {
   int32_t cycle;
   int32_t smoother;
@@ -142,16 +151,23 @@ typedef struct {
   int32_t tile_x, tile_y;
   void* stream;
   double sor;
+  int32_t inner_cycles;
+  int32_t coarse_op;
 } mg_options;
 
+enum { MG_COARSE_DEFAULT = 0, MG_COARSE_GALERKIN = 1 };
+
 /* Solve report.  history (nullable, host) receives the residual norms
- * ||b - A x_k||, k = 0..cycles; it must hold max_cycles + 1 doubles. */
+ * ||b - A x_k||, k = 0..cycles; it must hold max_cycles + 1 doubles.  status
+ * is this problem's own outcome (MG_OK, MG_NOT_CONVERGED or MG_DIVERGED), as
+ * the stopping test on the device decided it. */
 typedef struct {
   int32_t cycles;
   double res0, res, rel_res;
   double rho_last, rho_mean;   /* last and geometric-mean convergence factor */
   double seconds;              /* device time of the solve (hipEvents) */
   double* history;
+  int32_t status;
 } mg_info;
 
 /* Build the level hierarchy (shapes, operators, coarsest Cholesky factor) and
@@ -231,15 +247,18 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
 mg_status mg_pass_info(mg_handle h, int32_t level, int32_t which, int32_t* out);
 
 /* Batched: nprob independent 5-point problems (MG_COEF_CONST5 only) with
- * their own grids (square or not, all coarsening to the same coarsest shape)
- * and their own eps_x, eps_y.  grids, coeffs: host arrays of nprob entries.
- * One sequence of launches serves every problem; converged problems are masked. */
-mg_status mg_setup_batched(const mg_grid* grids, const mg_coeffs* coeffs, int32_t nprob,
+ * their own grids (square or not) and their own eps_x, eps_y.  grids, coeffs:
+ * host arrays of nprob entries.  levels as for mg_setup, applied to every
+ * problem (0: each coarsens as far as its grid allows; > 0: exactly that many
+ * levels each, MG_EINVAL if a grid cannot provide them).  One sequence of
+ * launches serves every problem; converged problems are masked. */
+mg_status mg_setup_batched(const mg_grid* grids, const mg_coeffs* coeffs, int32_t nprob, int32_t levels,
                            const mg_options* opts, mg_handle* out);
 
 /* rhs, x: host arrays of nprob device pointers.  info: host array of nprob
- * entries or NULL.  Returns MG_OK if every problem converged, else the largest
- * positive status among the problems. */
+ * entries or NULL (each entry's status is that problem's outcome).  Returns
+ * MG_OK if every problem converged, else the largest positive status among
+ * the problems. */
 mg_status mg_solve_batched(mg_handle h, const double* const* rhs, double* const* x, double tol,
                            int32_t max_cycles, mg_info* info);
 

@@ -446,6 +446,7 @@ class Options:
     nu_post: int = 2
     omega: float = 0.8        # Jacobi and TRI / ADI damping
     sor: float = 1.0          # Gauss-Seidel / SOR factor in (0, 2) ("The choice of C": C = D + omega L); 1 = GS
+    adaptive_omega: bool = False  # coarse-correction weight omega_l minimising the energy norm (else omega_l = 1)
 
 
 @dataclass
@@ -501,10 +502,12 @@ def build_hierarchy(g: Grid, A0: sp.spmatrix, opts: Options, levels: int = 0,
     return Hierarchy(grids, A, R, P, diag, colours, chol, opts, lines)
 
 
-def hierarchy_5pt(g: Grid, eps_x=1.0, eps_y=1.0, opts=None, levels=0) -> Hierarchy:
+def hierarchy_5pt(g: Grid, eps_x=1.0, eps_y=1.0, opts=None, levels=0, galerkin=False) -> Hierarchy:
+    """5-point hierarchy: every level rediscretised (H = 2h), or with
+    ``galerkin`` the coarse levels as R A P of the level above (9-point)."""
     opts = opts or Options()
-    return build_hierarchy(g, laplace5(g, eps_x, eps_y), opts, levels,
-                           rediscretise=lambda gl: laplace5(gl, eps_x, eps_y))
+    redisc = None if galerkin else (lambda gl: laplace5(gl, eps_x, eps_y))
+    return build_hierarchy(g, laplace5(g, eps_x, eps_y), opts, levels, rediscretise=redisc)
 
 
 def hierarchy_q1(g: Grid, kx, ky, opts=None, levels=0, separable=False) -> Hierarchy:
@@ -546,29 +549,49 @@ def coarse_solve(h: Hierarchy, g):
     return out.astype(g.dtype)
 
 
+def coarse_correction(h: Hierarchy, l: int, x, g, kind: str):
+    """Correction to add on level l (before the weight omega_l): the defect of
+    x, restricted by full weighting, is the right-hand side of the next
+    coarser level, whose equation is then solved approximately from zero by
+    the recursive calls the cycle kind prescribes; returns the prolonged
+    result (an F-cycle spends one F-cycle and then one V-cycle on the coarse
+    problem, a V-cycle one V-cycle, a W-cycle two W-cycles, the second one
+    continuing from the first)."""
+    gc = h.R[l] @ (g - h.A[l] @ x)
+    e = np.zeros_like(gc)
+    calls = {"F": ("F", "V"), "W": ("W", "W"), "V": ("V",)}[kind]
+    for k in calls:
+        e = mg_cycle(h, l + 1, e, gc, k)
+    return h.P[l] @ e
+
+
+def energy_weight(h: Hierarchy, l: int, x, g, pe) -> float:
+    """The coarse-correction weight that minimises the A-norm of the error of
+    x + w pe along the prolonged correction pe (the adaptive choice the paper
+    allows for omega_l): w = (d, pe) / (A pe, pe) with d = g - A x the defect.
+    A zero correction gets weight 1."""
+    d = g - h.A[l] @ x
+    ape = h.A[l] @ pe
+    den = float(np.dot(ape, pe))
+    return float(np.dot(d, pe)) / den if den != 0.0 else 1.0
+
+
 def mg_cycle(h: Hierarchy, l: int, x, g, kind: str = "F"):
-    """MG(l, u, g) of "The Multigrid Technique" with p = 1 for a V-cycle and
-    p = 2 for a W-cycle (two recursive W-cycles, the second starting from the
-    first's result); an F-cycle gives the coarse problem one F-cycle then one
-    V-cycle.  Each level's coarse start is zero.  Level 0 is the finest here
-    (the paper counts levels upwards from 1 = coarsest)."""
+    """One cycle of the recursive multigrid algorithm of "The Multigrid
+    Technique" on level l (0 = finest; the paper numbers its levels upwards
+    from the coarsest): nu_pre smoothing steps, the coarse-grid correction of
+    :func:`coarse_correction` added with weight omega_l (1, or the
+    energy-minimising weight of :func:`energy_weight` when
+    ``opts.adaptive_omega`` is set), then nu_post smoothing steps.  On the
+    coarsest level the equation is solved exactly."""
     if l == h.nlevels - 1:
         return coarse_solve(h, g)
     o = h.opts
-    x = smooth(h, l, x, g, o.nu_pre)                     # pre-smoothing
-    d = g - h.A[l] @ x                                    # defect d_l = g_l - A_l u_l^m
-    gc = h.R[l] @ d                                       # g_{l-1} = R d_l
-    e = np.zeros_like(gc)                                 # coarse start u_{l-1}^0 = 0
-    if kind == "F":
-        e = mg_cycle(h, l + 1, e, gc, "F")
-        e = mg_cycle(h, l + 1, e, gc, "V")
-    elif kind == "W":
-        e = mg_cycle(h, l + 1, e, gc, "W")
-        e = mg_cycle(h, l + 1, e, gc, "W")
-    else:
-        e = mg_cycle(h, l + 1, e, gc, "V")
-    x = x + h.P[l] @ e                                    # u += omega_l P u_{l-1}, omega_l = 1
-    return smooth(h, l, x, g, o.nu_post)                  # post-smoothing
+    x = smooth(h, l, x, g, o.nu_pre)
+    pe = coarse_correction(h, l, x, g, kind)
+    w = energy_weight(h, l, x, g, pe) if o.adaptive_omega else 1.0
+    x = x + w * pe if o.adaptive_omega else x + pe
+    return smooth(h, l, x, g, o.nu_post)
 
 
 def nested_start(h: Hierarchy, b, kind: str = None):
@@ -630,10 +653,11 @@ def solve(h: Hierarchy, b, x0, tol: float, max_cycles: int) -> SolveResult:
     return SolveResult(x, status, k, hist)
 
 
-def solve_mixed(h: Hierarchy, b, x0, tol: float, max_cycles: int, h32: Hierarchy = None) -> SolveResult:
-    """Defect correction: FP64 residual r = b - A x and its norm; one FP32 cycle
-    for A e = (float) r from e = 0; x += (double) e.  Stop as in :func:`solve`;
-    ``cycles`` counts the FP32 cycles."""
+def solve_mixed(h: Hierarchy, b, x0, tol: float, max_cycles: int, h32: Hierarchy = None,
+                inner: int = 1) -> SolveResult:
+    """Defect correction: FP64 residual r = b - A x and its norm; ``inner``
+    FP32 cycles for A e = (float) r from e = 0; x += (double) e.  Stop as in
+    :func:`solve`; ``cycles`` counts the outer steps."""
     h32 = h32 or h.astype(np.float32)
     kind = h.opts.cycle
     x = np.asarray(x0, dtype=np.float64).copy()
@@ -647,7 +671,9 @@ def solve_mixed(h: Hierarchy, b, x0, tol: float, max_cycles: int, h32: Hierarchy
     k = 0
     while k < max_cycles:
         r32 = r.astype(np.float32)
-        e = mg_cycle(h32, 0, np.zeros_like(r32), r32, kind)
+        e = np.zeros_like(r32)
+        for _ in range(inner):
+            e = mg_cycle(h32, 0, e, r32, kind)
         x = x + e.astype(np.float64)
         k += 1
         r = b - h.A[0] @ x

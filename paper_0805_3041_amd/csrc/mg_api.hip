@@ -94,6 +94,7 @@ struct mg_handle_s {
   int nprob = 1;
   int kind = MG_COEF_CONST5;
   int oned = 0;
+  bool galerkin5 = false;            // 5-point problem with Galerkin coarse operators (levels kept as 1-D bands)
   mg_options opts{};
   int ncol = 0;                      // 0 Jacobi (and line smoothers), 2 red-black, 4 four-colour
   int line = 0;                      // line smoothers: directions swept (bit 0 x, bit 1 y)
@@ -157,7 +158,10 @@ bool can_coarsen(int nx, int ny, int py) {
   return okx && oky;
 }
 
-int stencil_kind(mg_handle h) { return h->kind == MG_COEF_CONST5 ? ST5 : ST9; }
+int stencil_kind(mg_handle h) { return (h->kind == MG_COEF_CONST5 && !h->galerkin5) ? ST5 : ST9; }
+
+// FP32 cycles of one mixed-precision outer step (option inner_cycles, 0 = 1).
+int inner_cycles(mg_handle h) { return h->opts.inner_cycles > 0 ? h->opts.inner_cycles : 1; }
 
 // ----------------------------------------------------------------------- cycle program
 
@@ -457,8 +461,15 @@ hipError_t enqueue_cycle(mg_handle h, const Group& G, hipStream_t st) {
     return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, nullptr, stencil_kind(h), h->oned, G.ns,
                                   st);
   }
-  for (const HostOp& op : G.prog)
-    if ((e = run_op<float>(h, G, op, G.dL32, G.dP32, (float)relax(h), st)) != hipSuccess) return e;
+  // inner FP32 cycles on A e = r32 from e = 0; only the last one adds e into
+  // the FP64 iterate (the finest post-pass of the others keeps e)
+  const int inner = inner_cycles(h);
+  for (int c = 0; c < inner; ++c)
+    for (size_t k = 0; k < G.prog.size(); ++k) {
+      HostOp op = G.prog[k];
+      if (G.mixed_fused && c + 1 < inner && k + 1 == G.prog.size()) op.arg = POST_PLAIN;
+      if ((e = run_op<float>(h, G, op, G.dL32, G.dP32, (float)relax(h), st)) != hipSuccess) return e;
+    }
   if (!G.mixed_fused && (e = launch_outer_update(G.dL64, G.dL32, G.shp[0], G.ns, st)) != hipSuccess) return e;
   return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, G.dL32, stencil_kind(h), h->oned, G.ns, st);
 }
@@ -556,6 +567,13 @@ mg_status check_opts(const mg_options* o, int kind) {
   if (o->tile_mode < MG_TILES_FUSED || o->tile_mode > MG_TILES_WIDE) return fail(nullptr, MG_EINVAL, "bad tile_mode");
   if (o->tile_x < 0 || o->tile_y < 0 || (o->tile_x & 1) || (o->tile_y & 1) || o->tile_x > 512 || o->tile_y > 512)
     return fail(nullptr, MG_EINVAL, "tile_x and tile_y must be even, in [0, 512]");
+  if (o->inner_cycles < 0 || o->inner_cycles > 16) return fail(nullptr, MG_EINVAL, "inner_cycles must be in [0, 16]");
+  if (o->coarse_op != MG_COARSE_DEFAULT && o->coarse_op != MG_COARSE_GALERKIN)
+    return fail(nullptr, MG_EINVAL, "coarse_op must be MG_COARSE_DEFAULT or MG_COARSE_GALERKIN");
+  if (o->coarse_op == MG_COARSE_GALERKIN && kind == MG_COEF_CONST5 && o->smoother != MG_SMOOTH_JACOBI &&
+      o->smoother != MG_SMOOTH_GS4C)
+    return fail(nullptr, MG_EUNSUPPORTED,
+                "Galerkin coarse levels of a 5-point problem are 9-point: use the Jacobi or four-colour smoother");
   return MG_OK;
 }
 
@@ -681,6 +699,38 @@ hipError_t assemble_cell9(mg_handle h, Group& G, const mg_coeffs* coeffs) {
   return hipSuccess;
 }
 
+// Operators of a 5-point problem with Galerkin coarse levels, in the band
+// buffers setup_group allocated: the finest level's 5-point couplings as 1-D
+// bands (C = 2 (cx + cy), E = -cx, N = -cy, no corner couplings), the coarser
+// levels' R A P, inverse diagonals and the FP32 copies of a mixed hierarchy.
+hipError_t assemble_galerkin5(mg_handle h, Group& G) {
+  const double cx = h->eps_x[0] / (G.hx[0] * G.hx[0]);
+  const double cy = h->eps_y[0] / (G.hy[0] * G.hy[0]);
+  const Level<double>& L0 = G.l64(0, 0);
+  std::vector<double> fine((size_t)NBANDS * L0.bstride, 0.0);
+  for (int i = 0; i < L0.bstride; ++i) {
+    fine[i] = 2.0 * (cx + cy);
+    fine[(size_t)L0.bstride + i] = -cx;
+    fine[2 * (size_t)L0.bstride + i] = -cy;
+  }
+  hipError_t e = hipMemcpyAsync(G.band64[0], fine.data(), fine.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+  for (int l = 0; l < G.nlev && e == hipSuccess; ++l) {
+    const LevelShape& sh = G.shp[l];
+    const Level<double>& L = G.l64(l, 0);
+    if (l > 0) {
+      const LevelShape& f = G.shp[l - 1];
+      const Level<double>& Lf = G.l64(l - 1, 0);
+      e = launch_rap(G.band64[l], L.bstride, L.bpitch, 1, sh.nx, sh.ny, G.band64[l - 1], Lf.bstride, Lf.bpitch, f.nx,
+                     f.ny, sh.py, h->stream);
+    }
+    if (e == hipSuccess) e = launch_inv_diag(G.band64[l], L.bstride, h->stream);
+    if (e == hipSuccess && h->mixed())
+      e = launch_to_float(G.band64[l], G.band32[l], (long)NBANDS * L.bstride, h->stream);
+  }
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(h->stream);  // the host copy of the finest bands is about to go
+}
+
 // Dense coarsest operator of each slot, its Cholesky factor and the inverse
 // the coarse solve applies, in the buffers setup_group allocated; waits for
 // them and fails when an operator is not positive definite.
@@ -764,7 +814,7 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
   }
 
   // operators
-  if (h->kind == MG_COEF_CONST5) {
+  if (stencil_kind(h) == ST5) {
     for (int s = 0; s < ns; ++s) {
       const int p = G.probs[s];
       for (int l = 0; l < G.nlev; ++l) {
@@ -846,7 +896,7 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
         M.kc6y = (float)L.kc6y;
       }
     }
-    HIPCHK(h, assemble_cell9(h, G, coeffs));
+    HIPCHK(h, h->galerkin5 ? assemble_galerkin5(h, G) : assemble_cell9(h, G, coeffs));
   }
 
   // line smoothers: Thomas factors of every line of the cycle's hierarchy
@@ -933,6 +983,8 @@ mg_status check_cell_coeffs(mg_handle h, const mg_coeffs* coeffs) {
 
 // Common part of mg_setup and mg_setup_batched after the groups are formed.
 mg_status setup_handle(mg_handle h, const mg_coeffs* coeffs, int32_t levels) {
+  h->galerkin5 = h->kind == MG_COEF_CONST5 && h->opts.coarse_op == MG_COARSE_GALERKIN;
+  if (h->galerkin5) h->oned = 1;
   h->line = line_dirs(h->opts.smoother);
   h->line_jac = line_jacobi(h->opts.smoother);
   h->ncol = (h->opts.smoother == MG_SMOOTH_JACOBI || h->line) ? 0 : (h->opts.smoother == MG_SMOOTH_RBGS ? 2 : 4);
@@ -1054,7 +1106,12 @@ mg_status run_cycles(mg_handle h, int max_cycles, double tol, std::vector<SolveS
   return MG_OK;
 }
 
+mg_status status_of(const SolveState& s) {
+  return s.done == 1 ? MG_OK : (s.done == 2 ? MG_DIVERGED : MG_NOT_CONVERGED);
+}
+
 void fill_info(const SolveState& s, float ms, mg_info* info) {
+  info->status = status_of(s);
   info->cycles = s.cycles;
   info->res0 = s.r0;
   info->res = s.last;
@@ -1062,10 +1119,6 @@ void fill_info(const SolveState& s, float ms, mg_info* info) {
   info->rho_last = s.prev > 0 ? s.last / s.prev : 0.0;
   info->rho_mean = (s.cycles > 0 && s.r0 > 0 && s.last > 0) ? std::pow(s.last / s.r0, 1.0 / s.cycles) : 0.0;
   info->seconds = ms * 1e-3;
-}
-
-mg_status status_of(const SolveState& s) {
-  return s.done == 1 ? MG_OK : (s.done == 2 ? MG_DIVERGED : MG_NOT_CONVERGED);
 }
 
 mg_status single_only(mg_handle h) {
@@ -1180,8 +1233,8 @@ mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, int32_t levels,
   return MG_OK;
 }
 
-mg_status mg_setup_batched(const mg_grid* grids, const mg_coeffs* coeffs, int32_t nprob, const mg_options* opts,
-                           mg_handle* out) {
+mg_status mg_setup_batched(const mg_grid* grids, const mg_coeffs* coeffs, int32_t nprob, int32_t levels,
+                           const mg_options* opts, mg_handle* out) {
   g_thread_err.clear();
   if (!out) return fail(nullptr, MG_EINVAL, "out is NULL");
   *out = nullptr;
@@ -1199,6 +1252,13 @@ mg_status mg_setup_batched(const mg_grid* grids, const mg_coeffs* coeffs, int32_
   mg_status s = check_opts(opts, MG_COEF_CONST5);
   if (s != MG_OK) return s;
   if (line_dirs(opts->smoother)) return fail(nullptr, MG_EUNSUPPORTED, "batched solves take point smoothers only");
+  if (opts->coarse_op == MG_COARSE_GALERKIN)
+    return fail(nullptr, MG_EUNSUPPORTED, "batched solves rediscretise their coarse operators");
+  if (levels < 0) return fail(nullptr, MG_EINVAL, "levels must be >= 0");
+  for (int p = 0; p < nprob; ++p)
+    if (levels > max_levels(grids[p].nx, grids[p].ny, grids[p].periodic_y ? 1 : 0))
+      return fail(nullptr, MG_EINVAL, "problem " + std::to_string(p) + ": grid cannot provide " +
+                                          std::to_string(levels) + " levels");
 
   mg_handle h = new mg_handle_s();
   h->batched = true;
@@ -1232,7 +1292,7 @@ mg_status mg_setup_batched(const mg_grid* grids, const mg_coeffs* coeffs, int32_
     h->groups[g].ns++;
     h->groups[g].probs.push_back(p);
   }
-  s = setup_handle(h, nullptr, 0);
+  s = setup_handle(h, nullptr, levels);
   if (s != MG_OK) {
     g_thread_err = h->err;
     release(h);

@@ -26,6 +26,7 @@ MG_SMOOTH_TRI_X, MG_SMOOTH_TRI_Y, MG_SMOOTH_ADI = 3, 4, 5
 MG_SMOOTH_GSTRI_X, MG_SMOOTH_GSTRI_Y, MG_SMOOTH_GSADI = 6, 7, 8
 MG_PREC_FP64, MG_PREC_MIXED = 0, 1
 MG_TILES_FUSED, MG_TILES_PER_OP, MG_TILES_NARROW, MG_TILES_WIDE = 0, 1, 2, 3
+MG_COARSE_DEFAULT, MG_COARSE_GALERKIN = 0, 1
 
 SMOOTHERS = {"jacobi": MG_SMOOTH_JACOBI, "rbgs": MG_SMOOTH_RBGS, "gs4c": MG_SMOOTH_GS4C,
              "tri_x": MG_SMOOTH_TRI_X, "tri_y": MG_SMOOTH_TRI_Y, "adi": MG_SMOOTH_ADI,
@@ -54,13 +55,15 @@ class mg_options(ctypes.Structure):
     _fields_ = [("cycle", ctypes.c_int32), ("smoother", ctypes.c_int32), ("nu_pre", ctypes.c_int32),
                 ("nu_post", ctypes.c_int32), ("omega", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("coarse_cta_nodes", ctypes.c_int32), ("tile_mode", ctypes.c_int32), ("tile_x", ctypes.c_int32),
-                ("tile_y", ctypes.c_int32), ("stream", ctypes.c_void_p), ("sor", ctypes.c_double)]
+                ("tile_y", ctypes.c_int32), ("stream", ctypes.c_void_p), ("sor", ctypes.c_double),
+                ("inner_cycles", ctypes.c_int32), ("coarse_op", ctypes.c_int32)]
 
 
 class mg_info(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int32), ("res0", ctypes.c_double), ("res", ctypes.c_double),
                 ("rel_res", ctypes.c_double), ("rho_last", ctypes.c_double), ("rho_mean", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double))]
+                ("seconds", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
+                ("status", ctypes.c_int32)]
 
 
 _lib = None
@@ -82,7 +85,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_residual.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 P(ctypes.c_double)]
     lib.mg_coeff_grad.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-    lib.mg_setup_batched.argtypes = [P(mg_grid), P(mg_coeffs), ctypes.c_int32, P(mg_options), P(ctypes.c_void_p)]
+    lib.mg_setup_batched.argtypes = [P(mg_grid), P(mg_coeffs), ctypes.c_int32, ctypes.c_int32, P(mg_options),
+                                     P(ctypes.c_void_p)]
     lib.mg_solve_batched.argtypes = [ctypes.c_void_p, P(ctypes.c_void_p), P(ctypes.c_void_p), ctypes.c_double,
                                      ctypes.c_int32, P(mg_info)]
     lib.mg_destroy.argtypes = [ctypes.c_void_p]
@@ -177,7 +181,7 @@ def mg_solve(h, rhs: torch.Tensor, x: torch.Tensor, tol: float, max_cycles: int,
     s = lib.mg_solve(h, _ptr(rhs), _ptr(x), float(tol), int(max_cycles), ctypes.byref(info))
     if s < 0:
         raise MGError(s, last_error(h))
-    return SolveInfo(s, info.cycles, info.res0, info.res, info.rel_res, info.rho_last, info.rho_mean, info.seconds,
+    return SolveInfo(info.status, info.cycles, info.res0, info.res, info.rel_res, info.rho_last, info.rho_mean, info.seconds,
                      hist[: info.cycles + 1].copy() if hist is not None else np.zeros(0))
 
 
@@ -233,13 +237,13 @@ def mg_pass_info(h, level: int, which: int) -> dict:
     return dict(zip(PASS_INFO_KEYS, list(out)))
 
 
-def mg_setup_batched(grids, coeffs, opts: mg_options):
+def mg_setup_batched(grids, coeffs, opts: mg_options, levels: int = 0):
     lib = load_library()
     n = len(grids)
     ga = (mg_grid * n)(*grids)
     ca = (mg_coeffs * n)(*coeffs)
     h = ctypes.c_void_p()
-    s = lib.mg_setup_batched(ga, ca, n, ctypes.byref(opts), ctypes.byref(h))
+    s = lib.mg_setup_batched(ga, ca, n, int(levels), ctypes.byref(opts), ctypes.byref(h))
     if s != MG_OK:
         raise MGError(s, last_error(None))
     return h
@@ -263,13 +267,7 @@ def mg_solve_batched(h, rhs: list, x: list, tol: float, max_cycles: int, history
     out = []
     for k in range(n):
         i = infos[k]
-        if not np.isfinite(i.rel_res) or i.rel_res > 1e6:
-            st = MG_DIVERGED
-        elif i.rel_res <= tol:
-            st = MG_OK
-        else:
-            st = MG_NOT_CONVERGED
-        out.append(SolveInfo(st, i.cycles, i.res0, i.res, i.rel_res, i.rho_last, i.rho_mean, i.seconds,
+        out.append(SolveInfo(i.status, i.cycles, i.res0, i.res, i.rel_res, i.rho_last, i.rho_mean, i.seconds,
                              hists[k][: i.cycles + 1].copy() if history else np.zeros(0)))
     return s, out
 
@@ -295,11 +293,15 @@ TILE_MODES = {"fused": MG_TILES_FUSED, "per_op": MG_TILES_PER_OP, "narrow": MG_T
               "wide": MG_TILES_WIDE}
 
 
+COARSE_OPS = {"default": MG_COARSE_DEFAULT, "galerkin": MG_COARSE_GALERKIN}
+
+
 def make_options(cycle="F", smoother="rbgs", nu_pre=2, nu_post=2, omega=0.8, precision="fp64",
-                 coarse_cta_nodes=0, tile_mode="fused", tile_x=0, tile_y=0, stream=None, sor=1.0) -> mg_options:
+                 coarse_cta_nodes=0, tile_mode="fused", tile_x=0, tile_y=0, stream=None, sor=1.0,
+                 inner_cycles=1, coarse_op="default") -> mg_options:
     return mg_options(CYCLES[cycle], SMOOTHERS[smoother], int(nu_pre), int(nu_post), float(omega),
                       PRECISIONS[precision], int(coarse_cta_nodes), TILE_MODES[tile_mode], int(tile_x), int(tile_y),
-                      _stream_ptr(stream), float(sor))
+                      _stream_ptr(stream), float(sor), int(inner_cycles), COARSE_OPS[coarse_op])
 
 
 class Solver:
@@ -399,7 +401,7 @@ class BatchedSolver:
     (mg_setup_batched).  grids: list of (nx, ny) or (nx, ny, periodic_y);
     eps: list of eps_x (eps_y = 1) or (eps_x, eps_y)."""
 
-    def __init__(self, grids, eps, **opt):
+    def __init__(self, grids, eps, levels: int = 0, **opt):
         gs, cs = [], []
         for g, e in zip(grids, eps):
             nx, ny = g[0], g[1]
@@ -409,7 +411,7 @@ class BatchedSolver:
             cs.append(mg_coeffs(MG_COEF_CONST5, float(ex), float(ey), None, None, 0))
         self.shapes = [(g.ny, g.nx) for g in gs]
         self.opts = make_options(**opt)
-        self.h = mg_setup_batched(gs, cs, self.opts)
+        self.h = mg_setup_batched(gs, cs, self.opts, levels)
 
     def solve(self, rhs: list, x: list, tol: float = 1e-10, max_cycles: int = 100, history: bool = False):
         """Returns (worst status, [SolveInfo per problem]); each info.status is

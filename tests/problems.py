@@ -25,6 +25,8 @@ class Problem:
     sor: float = 1.0
     cycle: str = "F"
     levels: int = 0
+    coarse_op: str = "default"   # "galerkin": 5-point problems take R A P on the coarse levels
+    adaptive_omega: bool = False  # energy-minimising coarse-correction weight
 
     def grid(self):
         return O.Grid(self.nx, self.ny, self.periodic_y)
@@ -47,10 +49,10 @@ class Problem:
     def oracle(self):
         g = self.grid()
         opts = O.Options(cycle=self.cycle, smoother=self.smoother, nu_pre=self.nu_pre, nu_post=self.nu_post,
-                         omega=self.omega, sor=self.sor)
+                         omega=self.omega, sor=self.sor, adaptive_omega=self.adaptive_omega)
         c = self.coefficients()
         if c is None:
-            return O.hierarchy_5pt(g, self.eps, 1.0, opts, self.levels)
+            return O.hierarchy_5pt(g, self.eps, 1.0, opts, self.levels, galerkin=self.coarse_op == "galerkin")
         kx, ky, oned = c
         if oned:
             return O.hierarchy_q1(g, kx, ky, opts, self.levels, separable=True)
@@ -62,7 +64,9 @@ class Problem:
         c = self.coefficients()
         kw = dict(periodic_y=self.periodic_y, levels=self.levels, cycle=self.cycle, smoother=self.smoother,
                   nu_pre=self.nu_pre, nu_post=self.nu_post, omega=self.omega, sor=self.sor, precision=precision,
-                  coarse_cta_nodes=coarse_cta_nodes, **extra)
+                  coarse_cta_nodes=coarse_cta_nodes, coarse_op=self.coarse_op, **extra)
+        if self.adaptive_omega:
+            kw["adaptive_omega"] = True
         if c is None:
             return mg.Solver(self.nx, self.ny, eps_x=self.eps, eps_y=1.0, **kw)
         kx, ky, oned = c

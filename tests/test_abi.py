@@ -82,6 +82,11 @@ def _setup(mg, grid, coeffs, levels=0, **opt):
     dict(opt=dict(tile_x=7)),
     dict(opt=dict(tile_y=-2)),
     dict(levels=-1),
+    dict(opt=dict(inner_cycles=17)),
+    dict(opt=dict(inner_cycles=-1)),
+    dict(opt=dict(coarse_op=2)),
+    dict(opt=dict(coarse_op=1), status=-4),                 # Galerkin 5-point levels with red-black GS
+    dict(opt=dict(coarse_op=1, smoother=6), status=-4),     # ... or with a line smoother
     dict(cell9_null=True),
     dict(cell9_rbgs=True, status=-4),
 ])
@@ -113,3 +118,50 @@ def test_null_handle_calls_are_rejected(mg):
     assert lib.mg_profile_pass(None, None, None, 0, 2, 1, ctypes.byref(us)) == mg.MG_EINVAL
     assert lib.mg_destroy(None) == mg.MG_OK
     assert lib.mg_num_levels(None) == 0
+
+
+def _struct_fields(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + ";", text).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        for v in decl.split(","):
+            out.append(re.findall(r"[A-Za-z_][A-Za-z_0-9]*", v)[-1])
+    return out
+
+
+@pytest.mark.parametrize("name", ["mg_grid", "mg_coeffs", "mg_options", "mg_info"])
+def test_binding_structs_follow_the_header(mg, name):
+    """The ctypes structures lay their fields out in the header's order."""
+    assert [f for f, _ in getattr(mg, name)._fields_] == _struct_fields(name)
+
+
+def _setup_batched(mg, grids, eps, levels=0, **opt):
+    opts = mg.make_options()
+    for k, v in opt.items():
+        setattr(opts, k, v)
+    n = len(grids)
+    ga = (mg.mg_grid * n)(*[mg.mg_grid(g, g, 0, 0, 1.0, 1.0) for g in grids])
+    ca = (mg.mg_coeffs * n)(*[mg.mg_coeffs(mg.MG_COEF_CONST5, e, 1.0, None, None, 0) for e in eps])
+    h = ctypes.c_void_p()
+    s = mg.load_library().mg_setup_batched(ga, ca, n, levels, ctypes.byref(opts), ctypes.byref(h))
+    return s, h
+
+
+@pytest.mark.parametrize("case", [
+    dict(levels=-1),
+    dict(levels=5, grids=(65, 17)),                     # 17^2 provides 4 levels
+    dict(levels=30),
+    dict(opt=dict(coarse_op=1, smoother=2), status=-4),  # batched levels are rediscretised
+    dict(opt=dict(smoother=6), status=-4),               # no line smoothers in batches
+    dict(opt=dict(inner_cycles=99)),
+    dict(eps=(1.0, 0.0)),
+])
+def test_setup_batched_rejects_invalid_arguments(mg, case):
+    s, h = _setup_batched(mg, case.get("grids", (65, 33)), case.get("eps", (1.0, 0.5)), case.get("levels", 0),
+                          **case.get("opt", {}))
+    assert s == case.get("status", -1), mg.last_error(None)
+    assert not h.value

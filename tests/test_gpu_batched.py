@@ -122,7 +122,14 @@ def test_batch256_sample_problems_match_oracle():
         picked.setdefault(n, i)
     for n, i in sorted(picked.items()):
         if n > 513:
-            continue  # the oracle's 1025^2 cycles are covered by the single-problem full-size test
+            # the 1025^2 slot: bitwise equal to its own single-problem solve
+            # (whose iterates the full-size single-problem tests compare with the oracle)
+            s = mg.Solver(n, n, eps_x=eps[i], smoother="rbgs")
+            x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+            s.solve(rt[i], x, 1e-300, 2, history=False)
+            s.close()
+            assert torch.equal(x, xb[i]), (n, i)
+            continue
         g = O.Grid(n, n)
         h = O.hierarchy_5pt(g, eps[i], 1.0, O.Options(smoother="rbgs"))
         x = np.zeros(g.n_unknowns)
@@ -130,3 +137,32 @@ def test_batch256_sample_problems_match_oracle():
             x = O.mg_cycle(h, 0, x, g.pack(W.batch_rhs(n, i)), "F")
         err = np.abs(g.pack(xb[i].cpu().numpy()) - x).max() / np.abs(x).max()
         assert err <= 1e-12, (n, i, err)
+
+
+def test_batched_levels_argument():
+    """levels = 3 for every problem of a batch: each problem's iterates equal
+    a single-problem solve with three levels, bit for bit, and the oracle's
+    three-level cycle (1e-12)."""
+    mg = _mg()
+    sizes, eps = [65, 33, 65], [1.0, 0.2, 1e-2]
+    rhs = _inputs(sizes)
+    B = mg.BatchedSolver([(n, n) for n in sizes], eps, levels=3, smoother="rbgs")
+    rt = [torch.tensor(r, device="cuda") for r in rhs]
+    xb = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for n in sizes]
+    B.solve(rt, xb, 1e-300, 2)
+    B.close()
+    for i, (n, e) in enumerate(zip(sizes, eps)):
+        s = mg.Solver(n, n, eps_x=e, smoother="rbgs", levels=3)
+        x = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        s.solve(rt[i], x, 1e-300, 2, history=False)
+        s.close()
+        assert torch.equal(x, xb[i]), i
+        g = O.Grid(n, n)
+        h = O.hierarchy_5pt(g, e, 1.0, O.Options(smoother="rbgs"), 3)
+        xo = np.zeros(g.n_unknowns)
+        for _ in range(2):
+            xo = O.mg_cycle(h, 0, xo, g.pack(rhs[i]), "F")
+        assert np.abs(g.pack(xb[i].cpu().numpy()) - xo).max() <= 1e-12 * np.abs(xo).max()
+    with pytest.raises(mg.MGError) as err:
+        mg.BatchedSolver([(65, 65), (17, 17)], [1.0, 1.0], levels=5)
+    assert err.value.status == mg.MG_EINVAL

@@ -126,3 +126,18 @@ def test_coarse_levels_in_global_memory(smoother, cta):
     the default keeps them in LDS (cyclic reduction over all lines at once)."""
     p = Problem(129, 129, eps=0.05, smoother=smoother, omega=0.8)
     check_parity(p, W.normal_field(129, 129, 2), W.uniform_field(129, 129, 1), 3, coarse_cta_nodes=cta)
+
+
+@pytest.mark.parametrize("case", [
+    dict(nx=1025, ny=33, smoother="gstri_x"),
+    dict(nx=1025, ny=33, smoother="tri_x", omega=0.8),
+    dict(nx=33, ny=1025, smoother="gstri_y"),
+    dict(nx=33, ny=1025, smoother="tri_y", omega=0.8),
+], ids=["gstri_x", "tri_x", "gstri_y", "tri_y"])
+def test_long_lines_by_cyclic_reduction(case):
+    """Lines of 1023 unknowns (the finest lines of the 1025^2 workload) through
+    the launched cyclic-reduction kernel: coarse_cta_nodes = 1 keeps every
+    level but the coarsest out of the one-workgroup kernel.  Per cycle 1e-12
+    against the oracle; cond(T) along these lines is about 2e3."""
+    p = Problem(eps=1.0, **case)
+    check_parity(p, W.normal_field(p.nx, p.ny, 2), W.uniform_field(p.nx, p.ny, 1), 3, coarse_cta_nodes=1)
