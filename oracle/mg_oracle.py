@@ -657,8 +657,11 @@ def solve_mixed(h: Hierarchy, b, x0, tol: float, max_cycles: int, h32: Hierarchy
                 inner: int = 1) -> SolveResult:
     """Defect correction: FP64 residual r = b - A x and its norm; ``inner``
     FP32 cycles for A e = (float) r from e = 0; x += (double) e.  Stop as in
-    :func:`solve`; ``cycles`` counts the outer steps."""
+    :func:`solve`; ``cycles`` counts the outer steps.  The inner hierarchy
+    ``h32`` (default: ``h`` in FP32) sets the inner precision; r is rounded to
+    its type."""
     h32 = h32 or h.astype(np.float32)
+    inner_type = h32.A[0].dtype
     kind = h.opts.cycle
     x = np.asarray(x0, dtype=np.float64).copy()
     b = np.asarray(b, dtype=np.float64)
@@ -670,7 +673,7 @@ def solve_mixed(h: Hierarchy, b, x0, tol: float, max_cycles: int, h32: Hierarchy
     status = NOT_CONVERGED
     k = 0
     while k < max_cycles:
-        r32 = r.astype(np.float32)
+        r32 = r.astype(inner_type)
         e = np.zeros_like(r32)
         for _ in range(inner):
             e = mg_cycle(h32, 0, e, r32, kind)

@@ -597,8 +597,10 @@ def test_level_count(levels):
 def test_mixed_inner_cycles_match_oracle():
     """inner_cycles = 2: each outer step gives the FP32 correction two cycles
     from zero before x += e.  The first step agrees with the oracle's mixed
-    form to FP32 rounding; the solve reaches 1e-10 by the oracle's FP64
-    residual in fewer outer steps than with one inner cycle."""
+    form to FP32 rounding: each of the two FP32 cycles adds rounding of the
+    size the single-cycle bound (1e-5) allows, so the bound here is 2e-5; the
+    solve reaches 1e-10 by the oracle's FP64 residual in fewer outer steps
+    than with one inner cycle."""
     n = 129
     p = Problem(n, n, eps=0.1)
     g = p.grid()
@@ -612,7 +614,7 @@ def test_mixed_inner_cycles_match_oracle():
         x = torch.zeros_like(r)
         s.solve(r, x, 1e-300, 1, history=False)
         err = np.abs(g.pack(x.cpu().numpy()) - one.x).max() / np.abs(one.x).max()
-        assert err <= 1e-5, err
+        assert err <= 2e-5, err
         x.zero_()
         info2 = s.solve(r, x, 1e-10, 200)
         xs = x.cpu().numpy()

@@ -543,6 +543,83 @@ def test_mixed_precision_converges_like_fp64():
         assert O.residual_norm(h, b, r32.x) <= 1e-10 * r32.history[0]
 
 
+@pytest.mark.parametrize("inner", [1, 2, 3])
+def test_mixed_inner_cycles_in_fp64_equal_plain_cycles(inner):
+    """Defect correction with an FP64 inner hierarchy: one outer step with k
+    inner cycles from e = 0 equals k plain cycles from x (the cycle is affine:
+    cycle(x, b) = x + cycle(0, b - A x)), so the mixed form's inner loop is
+    pinned against the plain cycle independently of FP32 rounding."""
+    g = O.Grid(33, 33)
+    h = O.hierarchy_5pt(g, 0.1, 1.0, O.Options(smoother="rbgs"))
+    rng = np.random.default_rng(11)
+    b, x0 = rng.standard_normal((2, g.n_unknowns))
+    one = O.solve_mixed(h, b, x0, 1e-300, 1, h32=h, inner=inner)
+    x = x0.copy()
+    for _ in range(inner):
+        x = O.mg_cycle(h, 0, x, b, "F")
+    np.testing.assert_allclose(one.x, x, rtol=0, atol=1e-12 * np.abs(x).max())
+
+
+def _energy_error(A, xs, v):
+    e = v - xs
+    return float(e @ (A @ e))
+
+
+@pytest.mark.parametrize("eps", [1.0, 0.05])
+def test_energy_weight_minimises_the_energy_error(eps):
+    """The adaptive coarse-correction weight minimises ||x + w P v - x*||_A
+    over w: E(w) is an exact quadratic, fitted through three points with x*
+    from a dense solve, and its vertex equals energy_weight (a wrong sign, a
+    plain (P v, P v) denominator or the residual in place of the defect moves
+    it); no other w on a fine scan does better."""
+    g = O.Grid(17, 17)
+    h = O.hierarchy_5pt(g, eps, 1.0, O.Options(smoother="rbgs", nu_pre=1))
+    A = h.A[0]
+    rng = np.random.default_rng(12)
+    b = rng.standard_normal(g.n_unknowns)
+    xs = np.linalg.solve(A.toarray(), b)
+    x = O.smooth(h, 0, rng.standard_normal(g.n_unknowns), b, 1)
+    pe = O.coarse_correction(h, 0, x, b, "F")
+    w = O.energy_weight(h, 0, x, b, pe)
+    ws = np.array([-1.0, 0.5, 2.0])
+    c2, c1, _ = np.polyfit(ws, [_energy_error(A, xs, x + t * pe) for t in ws], 2)
+    assert abs(w - (-c1 / (2 * c2))) <= 1e-10 * abs(w)
+    scan = np.linspace(w - 0.5, w + 0.5, 101)
+    assert _energy_error(A, xs, x + w * pe) <= min(_energy_error(A, xs, x + t * pe) for t in scan) * (1 + 1e-12)
+
+
+def test_energy_weight_of_exact_galerkin_two_grid_is_one():
+    """With a Galerkin coarse operator A_c = R A P (P = 4 R^T) solved exactly,
+    P A_c^-1 R d is the A-orthogonal projection of the error onto range(P), so
+    the energy-minimising weight along it is exactly 1; with the rediscretised
+    5-point coarse operator it is not."""
+    g = O.Grid(17, 17)
+    rng = np.random.default_rng(13)
+    b, x = rng.standard_normal((2, g.n_unknowns))
+    ws = {}
+    for galerkin in (True, False):
+        h = O.hierarchy_5pt(g, 1.0, 1.0, O.Options(smoother="rbgs"), levels=2, galerkin=galerkin)
+        pe = O.coarse_correction(h, 0, x, b, "V")
+        ws[galerkin] = O.energy_weight(h, 0, x, b, pe)
+    assert abs(ws[True] - 1.0) <= 1e-12
+    assert abs(ws[False] - 1.0) > 1e-3
+
+
+def test_adaptive_cycle_lowers_the_energy_error_after_correction():
+    """A cycle with the adaptive weight and no post-smoothing ends with an
+    energy error no larger than the same cycle with omega_l = 1 (the weight
+    minimises it along the same correction)."""
+    g = O.Grid(33, 33)
+    rng = np.random.default_rng(14)
+    b, x0 = rng.standard_normal((2, g.n_unknowns))
+    out = {}
+    for adaptive in (False, True):
+        h = O.hierarchy_5pt(g, 0.3, 1.0, O.Options(smoother="rbgs", nu_post=0, adaptive_omega=adaptive))
+        out[adaptive] = O.mg_cycle(h, 0, x0, b, "F")
+    xs = np.linalg.solve(h.A[0].toarray(), b)
+    assert _energy_error(h.A[0], xs, out[True]) <= _energy_error(h.A[0], xs, out[False]) * (1 + 1e-12)
+
+
 # ----------------------------------------------------------------- adjoint
 
 
