@@ -1,24 +1,28 @@
 """Throughput of the multigrid F-cycle solve on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload aniso1025]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload annulus4097]
 
-Workload aniso1025: -(eps u_xx + u_yy) = f on the unit square, 1025 x 1025
-nodes, zero Dirichlet, 5-point finite differences, f = N(0, 1) (seed 2),
-x0 = 0, red-black Gauss-Seidel 2/2, F-cycle over 10 levels down to 3 x 3.
-One step solves the four problems eps in {1, 1e-1, 1e-2, 1e-3} to a 1e-10
-relative residual (||b - A x_k|| <= 1e-10 ||b - A x_0||), inputs resident in
-device memory.  `value` = unknowns solved per second in the headline
-precision (FP32 cycles inside FP64 defect correction); the FP64 form is
-timed beside it.  `roofline` reports the finest-level post-pass (the
-heaviest HBM pass of a cycle) timed with HIP events on the solver's stream;
-`cpu_baseline` times the CPU oracle on a bounded sample of the same
-workload.  Prints one JSON line.
+Default workload annulus4097: the polar annulus r in [0.5, 1], theta
+periodic, mapped to the unit square (Q1 finite elements with kx = 4 pi r,
+ky = 1/(4 pi r)), 4097 x 4096 nodes (16,773,120 unknowns; FP64 x, b and the
+defect take 403 MB, beyond the 256 MB last-level cache), f = N(0, 1) (seed
+3), x0 = 0, four-colour Gauss-Seidel 2/2, F-cycle over 11 levels, solved to
+a 1e-10 relative residual (||b - A x_k|| <= 1e-10 ||b - A x_0||) with inputs
+resident in device memory.  `value` = unknowns solved per second in the
+headline precision (FP32 cycles inside FP64 defect correction); the FP64
+form is timed beside it and the two solutions are compared.  `roofline`
+reports the dominant finest-level fused pass timed with HIP events on the
+solver's stream; `cpu_baseline` times the CPU oracle on a bounded sample of
+the same workload with one process and with one process per core.  Other
+workloads: aniso1025, batch256, grf2049, sphere2049 (see their functions).
+Prints one JSON line.
 """
 
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import platform
 import sys
@@ -36,7 +40,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="aniso1025",
+    ap.add_argument("--workload", default="annulus4097",
                     choices=["aniso1025", "annulus4097", "batch256", "grf2049", "sphere2049"])
     ap.add_argument("--nu", type=int, default=2)
     ap.add_argument("--smoother", default=None,
@@ -52,7 +56,8 @@ def parse():
     ap.add_argument("--max-cycles", type=int, default=20000)
     ap.add_argument("--eps", type=float, default=None, help="one eps of the workload only (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="timed budget of each oracle sample (one process, then one per core)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 512 MiB (HBM counter calibration)")
     ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
@@ -238,45 +243,184 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(n, eps_list, cycles_per_eps, nu, seconds, smoother="rbgs", omega=0.8, sor=1.0):
-    """The oracle (FP64, scipy.sparse, one thread) runs F-cycles of the
-    workload's hardest problem for about `seconds`; its time per cycle times
-    the cycles the workload needs gives its unknowns/s."""
+# ----------------------------------------------------------------------------- CPU baseline (the oracle)
+#
+# The oracle (FP64, scipy.sparse) runs F-cycles of a bounded sample of the
+# workload: one process, then one process per host core (up to the 16 cores a
+# one-GPU share has), each on its own copy of the sample problem, started
+# together.  Both rates are unknown-cycles per second; they become unknowns/s
+# to tolerance once the GPU run has given the cycle counts.  The pools run
+# before anything touches the GPU (the workers are forked).
+
+MAX_POOL = 16
+
+
+def pool_size() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(MAX_POOL, n))
+
+
+def _oracle_sample(spec):
+    """(step, unknowns per step) of one oracle sample problem."""
     import numpy as np
 
     from oracle import mg_oracle as O
     import workloads as W
 
-    g = O.Grid(n, n)
-    eps = min(eps_list)
-    h = O.hierarchy_5pt(g, eps, 1.0, O.Options(smoother=smoother, nu_pre=nu, nu_post=nu, omega=omega, sor=sor))
-    b = g.pack(W.aniso_rhs(n, 2))
-    x = np.zeros(g.n_unknowns)
-    done = 0
-    t0 = time.perf_counter()
-    while done < 2 or time.perf_counter() - t0 < seconds:
-        x = O.mg_cycle(h, 0, x, b, "F")
-        done += 1
-    t = (time.perf_counter() - t0) / done
-    total_cycles = sum(cycles_per_eps)
-    unknowns = (n - 2) ** 2 * len(eps_list)
+    kind = spec["kind"]
+    opts = O.Options(smoother=spec.get("smoother", "rbgs"), nu_pre=spec.get("nu", 2), nu_post=spec.get("nu", 2),
+                     omega=spec.get("omega", 0.8), sor=spec.get("sor", 1.0))
+    n = spec["n"]
+    if kind == "grf":
+        a, f, ustar = W.grf_problem(n, 5)
+        g = O.Grid(n, n)
+        return (lambda: O.adjoint_gradient(g, a, f, ustar)), g.n_unknowns
+    if kind == "annulus":
+        g = O.Grid(n, n - 1, periodic_y=True)
+        kx, ky = W.annulus_cell_coefficients(n)
+        h = O.hierarchy_q1(g, kx, ky, opts, separable=True)
+        b = g.pack(W.annulus_rhs(n, n - 1, 3))
+    elif kind == "sphere":
+        g = O.Grid(n, n)
+        kx, ky = W.sphere_cell_coefficients(n, n)
+        h = O.hierarchy_q1(g, kx, ky, opts)
+        b = g.pack(W.normal_field(n, n, 3))
+    else:  # 5-point anisotropic problem
+        g = O.Grid(n, n)
+        h = O.hierarchy_5pt(g, spec["eps"], 1.0, opts)
+        b = g.pack(W.aniso_rhs(n, 2))
+    state = {"x": np.zeros(g.n_unknowns)}
+
+    def step():
+        state["x"] = O.mg_cycle(h, 0, state["x"], b, "F")
+
+    return step, g.n_unknowns
+
+
+def _oracle_worker(spec, seconds, barrier, queue):
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(1):
+        step, unknowns = _oracle_sample(spec)
+        barrier.wait(timeout=600)
+        done = 0
+        t0 = time.perf_counter()
+        while done < 2 or time.perf_counter() - t0 < seconds:
+            step()
+            done += 1
+        queue.put((unknowns, done, time.perf_counter() - t0))
+
+
+def oracle_rates(spec, seconds):
+    """Oracle throughput in unknown-steps per second with one process and with
+    pool_size() processes (one sample problem each, timed together)."""
+    import multiprocessing as mp
+
+    ctx = mp.get_context("fork")
+    out = {}
+    for procs in sorted({1, pool_size()}):
+        barrier, queue = ctx.Barrier(procs), ctx.Queue()
+        ps = [ctx.Process(target=_oracle_worker, args=(spec, seconds, barrier, queue)) for _ in range(procs)]
+        for p in ps:
+            p.start()
+        res = [queue.get(timeout=seconds + 900) for _ in ps]
+        for p in ps:
+            p.join(timeout=60)
+        if any(p.exitcode != 0 for p in ps):
+            raise RuntimeError("an oracle worker failed")
+        out[procs] = {"rate": sum(u * d / t for u, d, t in res), "steps": sum(d for _, d, _ in res),
+                      "seconds": max(t for _, _, t in res), "unknowns": res[0][0]}
+    out["what"] = _describe(spec)
+    return out
+
+
+def _describe(spec):
+    return {"annulus": "FP64 F-cycles on the {n}x{m} annulus", "sphere": "FP64 F-cycles of the {n}x{n} spherical "
+            "problem", "grf": "oracle gradients (direct forward + adjoint solves, dL/da) at {n}x{n}",
+            "aniso": "FP64 F-cycles of the eps={eps:g} 5-point problem at {n}x{n}"}[spec["kind"]].format(
+        n=spec["n"], m=spec["n"] - 1, eps=spec.get("eps", 1.0))
+
+
+def cpu_baseline_from_rates(rates, steps_per_unknown_solved, scale_note):
+    """unknowns/s to tolerance of the oracle: its unknown-step rate divided by
+    the steps one solved unknown needs (cycles to tolerance, or 1 for a
+    gradient), for all cores ("value") and for one core ("single_core")."""
+    procs = max(k for k in rates if isinstance(k, int))
+    one = rates[1]
+    many = rates[procs]
     return {
-        "value": unknowns / (t * total_cycles),
+        "value": many["rate"] / steps_per_unknown_solved,
         "unit": "unknowns/s",
-        "cores": 1,
+        "cores": procs,
         "kind": "oracle",
-        "sample": f"{done} FP64 F-cycles of the eps={eps:g} problem at {n}x{n} ({t:.3f} s per cycle), "
-                  f"scaled to the {total_cycles} cycles the workload needs",
+        "sample": f"{rates['what']}: {procs} processes (one core each) ran {many['steps']} steps in "
+                  f"{many['seconds']:.1f} s, one process {one['steps']} steps in {one['seconds']:.1f} s; "
+                  f"{scale_note} (extrapolated)",
+        "single_core": {"value": one["rate"] / steps_per_unknown_solved, "cores": 1},
         "host_cpu": cpu_model(),
         "host_threads_available": os.cpu_count(),
     }
 
 
-def annulus(args):
+def baseline_spec(args):
+    """The oracle sample of each workload."""
+    w = args.workload
+    sm = args.smoother
+    if w == "annulus4097":
+        return {"kind": "annulus", "n": 1025, "smoother": sm or "gs4c", "nu": args.nu, "omega": args.omega,
+                "sor": args.sor}
+    if w == "aniso1025":
+        eps = min(__import__("workloads").ANISO_EPS) if args.eps is None else args.eps
+        return {"kind": "aniso", "n": 1025, "eps": eps, "smoother": sm or "rbgs", "nu": args.nu,
+                "omega": args.omega, "sor": args.sor}
+    if w == "batch256":
+        return {"kind": "aniso", "n": 257, "eps": 1e-2, "smoother": "rbgs", "nu": args.nu}
+    if w == "sphere2049":
+        return {"kind": "sphere", "n": 257, "smoother": sm or "gs4c", "nu": args.nu, "omega": args.omega,
+                "sor": args.sor}
+    if w == "grf2049":
+        return {"kind": "grf", "n": 129}
+    raise ValueError(w)
+
+
+def oracle_sampled_residual(x_stored, rows=4000, seed=51):
+    """The oracle's FP64 residual b - A x of an annulus4097 solution at `rows`
+    sampled nodes, each row assembled from its cells' element matrices; returns
+    the relative 2-norm estimated from the samples (sqrt of the mean square
+    times the number of unknowns, over ||b||) and the largest sampled entry."""
+    import numpy as np
+
+    from oracle import mg_oracle as O
+    import workloads as W
+
+    nx, ny = 4097, 4096
+    g = O.Grid(nx, ny, periodic_y=True)
+    kx, ky = W.annulus_cell_coefficients(nx)
+    KX = np.broadcast_to(kx, (g.ncy, g.ncx))
+    KY = np.broadcast_to(ky, (g.ncy, g.ncx))
+    b = W.annulus_rhs(nx, ny, 3)
+    rng = np.random.default_rng(seed)
+    r = []
+    for _ in range(rows):
+        i = int(rng.integers(1, nx - 1))
+        j = int(rng.integers(0, ny))
+        row = O.q1_row(g, KX, KY, i, j)
+        r.append(b[j, i] - sum(v * x_stored[jq, iq] for (jq, iq), v in row.items()))
+    r = np.array(r)
+    est = math.sqrt(float(np.mean(r * r)) * g.n_unknowns) / float(np.linalg.norm(b))
+    return {"rows": rows, "est_rel_res": est, "max_abs": float(np.abs(r).max())}
+
+
+def annulus(args, rates=None):
     """Workload annulus4097: r in [0.5, 1], theta periodic, mapped to the unit
     square (Q1, kx = 4 pi r, ky = 1/(4 pi r) per radial cell), 4097 radial x
     4096 angular nodes (16,773,120 unknowns), f = N(0, 1) (seed 3), x0 = 0,
-    four-colour Gauss-Seidel 2/2, F-cycle over 11 levels down to 5 x 4."""
+    four-colour Gauss-Seidel 2/2, F-cycle over 11 levels down to 5 x 4.  The
+    mixed form (FP32 cycles inside FP64 defect correction) is the headline,
+    the FP64 form is timed beside it, and the two solutions are compared."""
     import torch
 
     import workloads as W
@@ -301,7 +445,7 @@ def annulus(args):
         else:
             x.zero_()
 
-    def run(s, steps, warmup):
+    def run(s, steps, warmup, label):
         x = torch.zeros_like(rhs)
         for _ in range(warmup):
             start(s, x)
@@ -313,14 +457,16 @@ def annulus(args):
             start(s, x)
             info = s.solve(rhs, x, TOL, args.max_cycles, history=False)
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, info, x
+        wall = time.perf_counter() - t0
+        if info.status != mg.MG_OK:
+            raise SystemExit(f"{label} solve did not converge: {mg.status_string(info.status)} "
+                             f"rel_res {info.rel_res:.3e}")
+        return wall, info, x
 
     head = args.precision
     other = "fp64" if head == "mixed" else "mixed"
     s = make(head)
-    wall_h, info_h, x = run(s, args.steps, args.warmup)
-    if info_h.status != mg.MG_OK:
-        raise SystemExit(f"solve did not converge: {mg.status_string(info_h.status)} rel_res {info_h.rel_res:.3e}")
+    wall_h, info_h, x_h = run(s, args.steps, args.warmup, head)
     scratch = torch.zeros_like(rhs)
     if args.smoother:
         roofline = line_roofline(s, rhs, scratch, head, nx, ny, True, smoother, 1)
@@ -337,15 +483,19 @@ def annulus(args):
                     "bytes_per_node": BYTES_PER_NODE[(head, dom)], "nodes": nx * ny,
                     "other_pass_us": times[1 - dom], "levels_0_1": levels01}
     s.close()
+    del scratch
     s = make(other)
     steps_o = max(1, args.steps // 2)
-    wall_o, info_o, _ = run(s, steps_o, 1)
+    wall_o, info_o, x_o = run(s, steps_o, 1, other)
     s.close()
+    x_m, x_64 = (x_h, x_o) if head == "mixed" else (x_o, x_h)
+    err_vs_fp64 = float((x_m - x_64).abs().max() / x_64.abs().max())
     if args.calibrate_copy:
         calibrate_copy()
     smoothing = SMOOTHER_NAMES[smoother] if args.smoother else "four-colour GS"
     if not args.smoother and args.sor != 1.0:
         smoothing = f"four-colour SOR (omega {args.sor:g})"
+    info_m, info_64 = (info_h, info_o) if head == "mixed" else (info_o, info_h)
     out = {
         "metric": "unknowns/s to 1e-10 rel. residual",
         "value": unknowns * args.steps / wall_h,
@@ -370,42 +520,19 @@ def annulus(args):
         "us_per_cycle": 1e6 * info_h.seconds / max(1, info_h.cycles),
         f"value_{other}": unknowns * steps_o / wall_o,
         f"cycles_{other}": info_o.cycles,
+        f"rel_res_{other}": info_o.rel_res,
+        f"us_per_cycle_{other}": 1e6 * info_o.seconds / max(1, info_o.cycles),
         "speedup_mixed_over_fp64": ((wall_o / steps_o) / (wall_h / args.steps)) if head == "mixed"
         else ((wall_h / args.steps) / (wall_o / steps_o)),
+        "mixed_vs_fp64_max_rel_diff": err_vs_fp64,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_annulus(info_h.cycles, args.nu, args.cpu_seconds, unknowns, smoother,
-                                                   args.omega, args.sor)
+    if rates is not None:
+        cb = cpu_baseline_from_rates(rates, info_64.cycles,
+                                     f"rate per unknown-cycle applied to 4097x4096 and the {info_64.cycles} "
+                                     f"cycles of the FP64 solve")
+        cb["oracle_residual_of_mixed_solution"] = oracle_sampled_residual(x_m.cpu().numpy())
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
-
-
-def cpu_baseline_annulus(cycles, nu, seconds, unknowns_full, smoother="gs4c", omega=0.8, sor=1.0):
-    """Oracle F-cycles on the 1025 x 1024 annulus for about `seconds`; its cost
-    per unknown-cycle, scaled to the full grid and the cycles the full solve
-    needs (the cycle's work is linear in the number of unknowns)."""
-    import numpy as np
-
-    from oracle import mg_oracle as O
-    import workloads as W
-
-    n = 1025
-    g = O.Grid(n, n - 1, periodic_y=True)
-    kx, ky = W.annulus_cell_coefficients(n)
-    h = O.hierarchy_q1(g, kx, ky, O.Options(smoother=smoother, nu_pre=nu, nu_post=nu, omega=omega, sor=sor),
-                       separable=True)
-    b = g.pack(W.annulus_rhs(n, n - 1, 3))
-    x = np.zeros(g.n_unknowns)
-    done = 0
-    t0 = time.perf_counter()
-    while done < 2 or time.perf_counter() - t0 < seconds:
-        x = O.mg_cycle(h, 0, x, b, "F")
-        done += 1
-    t = (time.perf_counter() - t0) / done
-    per_unknown_cycle = t / g.n_unknowns
-    return {"value": 1.0 / (per_unknown_cycle * cycles), "unit": "unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} FP64 F-cycles on the 1025x1024 annulus ({t:.2f} s per cycle), scaled linearly to "
-                      f"4097x4096 and the {cycles} cycles of the full solve",
-            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
 
 
 # Line sweep (one launch of k_line), per node of the lines it solves: read b,
@@ -465,7 +592,7 @@ def _roofline_single(n, eps, head, nu):
             "note": f"one {n}x{n} problem of the batch"}
 
 
-def batch256(args):
+def batch256(args, rates=None):
     """Workload batch256: 256 independent 5-point problems, n drawn uniformly
     from {129, 257, 513, 1025} and eps = 10^U(-3, 0) (seed 4), rhs_i = N(0, 1)
     (seed 1000 + i), x0 = 0, red-black GS 2/2, F-cycles until every problem
@@ -508,6 +635,9 @@ def batch256(args):
     steps_o = max(1, args.steps // 2)
     wall_o, infos_o = run(B, steps_o, 1)
     B.close()
+    bad = [i for i, info in enumerate(infos_o) if info.status != mg.MG_OK]
+    if bad:
+        raise SystemExit(f"{len(bad)} batched {other} problems did not converge (first: {bad[0]})")
     cycles = [info.cycles for info in infos_h]
     out = {
         "metric": "unknowns/s to 1e-10 rel. residual",
@@ -531,37 +661,11 @@ def batch256(args):
         "speedup_mixed_over_fp64": ((wall_o / steps_o) / (wall_h / args.steps)) if head == "mixed"
         else ((wall_h / args.steps) / (wall_o / steps_o)),
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_batch(ns, eps, cycles, args.nu, args.cpu_seconds)
+    if rates is not None:
+        work = sum((m - 2) ** 2 * c for m, c in zip(ns, cycles))
+        out["cpu_baseline"] = cpu_baseline_from_rates(
+            rates, work / unknowns, "rate per unknown-cycle applied to each problem's unknowns times its cycles")
     print(json.dumps(out), flush=True)
-
-
-def cpu_baseline_batch(ns, eps, cycles, nu, seconds):
-    """Oracle F-cycles on a 257 x 257 problem of the batch for about
-    `seconds`; its cost per unknown-cycle times sum_i unknowns_i * cycles_i."""
-    import numpy as np
-
-    from oracle import mg_oracle as O
-    import workloads as W
-
-    n = 257
-    g = O.Grid(n, n)
-    h = O.hierarchy_5pt(g, 1e-2, 1.0, O.Options(smoother="rbgs", nu_pre=nu, nu_post=nu))
-    b = g.pack(W.batch_rhs(n, 0))
-    x = np.zeros(g.n_unknowns)
-    done = 0
-    t0 = time.perf_counter()
-    while done < 2 or time.perf_counter() - t0 < seconds:
-        x = O.mg_cycle(h, 0, x, b, "F")
-        done += 1
-    t = (time.perf_counter() - t0) / done
-    per = t / g.n_unknowns
-    work = sum((m - 2) ** 2 * c for m, c in zip(ns, cycles))
-    unknowns = sum((m - 2) ** 2 for m in ns)
-    return {"value": unknowns / (per * work), "unit": "unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} FP64 F-cycles of a 257x257 problem ({t:.3f} s per cycle), scaled linearly to the "
-                      f"batch's unknowns times each problem's cycle count",
-            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
 
 
 # Cell coefficients (grf2049): the finest fused passes form the 9-point
@@ -593,7 +697,7 @@ def _roofline_grf(n, at, ft, calibrate=False):
             "bytes_per_launch": alg, "bytes_per_node": bpn, "nodes": n * n, "other_pass_us": times[1 - dom]}
 
 
-def grf2049(args):
+def grf2049(args, rates=None):
     """Workload grf2049: -div(a grad u) = f on 2049^2 nodes (2048^2 cells),
     a = exp(g), g a Gaussian random field (squared-exponential covariance,
     length 0.1, sigma 1, seed 5), f = 2 pi^2 sin(pi x) sin(pi y), loss
@@ -653,12 +757,14 @@ def grf2049(args):
         "roofline": _roofline_grf(n, at, ft, args.calibrate_copy),
         "grad_norms": {"dL_da": float(torch.linalg.vector_norm(da)), "dL_df": float(torch.linalg.vector_norm(df))},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_grf(unknowns, args.cpu_seconds)
+    if rates is not None:
+        out["cpu_baseline"] = cpu_baseline_from_rates(
+            rates, 1.0, f"rate per unknown applied unchanged to {unknowns} unknowns (direct solves grow faster "
+                        "than linearly, so this overstates the CPU rate at full size)")
     print(json.dumps(out), flush=True)
 
 
-def sphere2049(args):
+def sphere2049(args, rates=None):
     """Workload sphere2049: -Laplace(u) in spherical coordinates (axisymmetric
     shell section r in [0.5, 1], theta in [0.1 pi, 0.9 pi], the weak form
     weighted by r^2 sin(theta)) mapped to the unit square, 2049^2 nodes, Q1
@@ -752,60 +858,10 @@ def sphere2049(args):
         "speedup_mixed_over_fp64": ((wall_o / steps_o) / (wall_h / args.steps)) if head == "mixed"
         else ((wall_h / args.steps) / (wall_o / steps_o)),
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_sphere(info_h.cycles, args.nu, args.cpu_seconds, unknowns, smoother,
-                                                  args.omega, args.sor)
+    if rates is not None:
+        out["cpu_baseline"] = cpu_baseline_from_rates(
+            rates, info_h.cycles, f"rate per unknown-cycle applied to 2049^2 and the GPU's {info_h.cycles} cycles")
     print(json.dumps(out), flush=True)
-
-
-def cpu_baseline_sphere(cycles, nu, seconds, unknowns_full, smoother, omega, sor):
-    """Oracle F-cycles on the 257 x 257 spherical problem for about
-    `seconds`; its time per unknown-cycle times the GPU's cycles and the full
-    problem's unknowns."""
-    import numpy as np
-
-    from oracle import mg_oracle as O
-    import workloads as W
-
-    n = 257
-    g = O.Grid(n, n)
-    kx, ky = W.sphere_cell_coefficients(n, n)
-    h = O.hierarchy_q1(g, kx, ky, O.Options(smoother=smoother, nu_pre=nu, nu_post=nu, omega=omega, sor=sor))
-    b = g.pack(W.normal_field(n, n, 3))
-    x = np.zeros(g.n_unknowns)
-    done = 0
-    t0 = time.perf_counter()
-    while done < 2 or time.perf_counter() - t0 < seconds:
-        x = O.mg_cycle(h, 0, x, b, "F")
-        done += 1
-    per = (time.perf_counter() - t0) / done / g.n_unknowns
-    return {"value": unknowns_full / (per * unknowns_full * cycles), "unit": "unknowns/s", "cores": 1,
-            "kind": "oracle", "sample": f"{done} FP64 F-cycles of the 257x257 spherical problem, scaled linearly "
-                                        f"to 2049^2 unknowns times the GPU's {cycles} cycles",
-            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
-
-
-def cpu_baseline_grf(unknowns_full, seconds):
-    """The oracle's gradient (direct sparse forward and adjoint solves plus
-    dL/da) on the 129 x 129 version of the problem, repeated for about
-    `seconds`, scaled linearly in unknowns (direct solves grow faster than
-    linearly, so this overstates the CPU rate at full size)."""
-    from oracle import mg_oracle as O
-    import workloads as W
-
-    n = 129
-    a, f, ustar = W.grf_problem(n, 5)
-    g = O.Grid(n, n)
-    done = 0
-    t0 = time.perf_counter()
-    while done < 1 or time.perf_counter() - t0 < seconds:
-        O.adjoint_gradient(g, a, f, ustar)
-        done += 1
-    t = (time.perf_counter() - t0) / done
-    return {"value": g.n_unknowns / t, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} oracle gradients (direct forward + adjoint solves, dL/da) at 129x129 ({t:.2f} s "
-                      f"each), rate per unknown applied unchanged to {unknowns_full} unknowns",
-            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
 
 
 def main():
@@ -820,14 +876,26 @@ def main():
         print(json.dumps({"error": "this library runs on one GPU only: collectives and multi-GPU sharding are not "
                                    "built; run with --gpus 1"}), flush=True)
         sys.exit(2)
+    # the oracle's pools are forked before anything touches the GPU
+    rates = None if args.no_cpu_baseline else oracle_rates(baseline_spec(args), args.cpu_seconds)
     if args.workload == "annulus4097":
-        return annulus(args)
+        return annulus(args, rates)
     if args.workload == "batch256":
-        return batch256(args)
+        return batch256(args, rates)
     if args.workload == "grf2049":
-        return grf2049(args)
+        return grf2049(args, rates)
     if args.workload == "sphere2049":
-        return sphere2049(args)
+        return sphere2049(args, rates)
+    return aniso1025(args, rates)
+
+
+def aniso1025(args, rates=None):
+    """Workload aniso1025: -(eps u_xx + u_yy) = f on the unit square, 1025 x
+    1025 nodes, zero Dirichlet, 5-point finite differences, f = N(0, 1) (seed
+    2), x0 = 0, red-black Gauss-Seidel 2/2, F-cycle over 10 levels down to
+    3 x 3; one step solves the four problems eps in {1, 1e-1, 1e-2, 1e-3}.
+    Its working set (8.4 MB per array) stays in the 256 MB last-level cache,
+    so its bandwidth figures are L2-miss bandwidth rather than HBM."""
     import numpy as np
     import torch
 
@@ -890,7 +958,9 @@ def main():
         nodes = n * n
         alg_bytes = BYTES_PER_NODE[(head, dom)] * nodes
         achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        roofline = {"bound": "hbm", "measured": "L2-miss bandwidth: the 1025^2 working set stays in the 256 MB "
+                                                "last-level cache",
+                    "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic("aniso1025", kernel_name),
                     "kernel": kernel_name, "avg_us": times[dom], "bytes_per_launch": alg_bytes,
                     "bytes_per_node": BYTES_PER_NODE[(head, dom)], "nodes": nodes,
@@ -903,6 +973,9 @@ def main():
     wall_o, infos_o = run(solvers_o, steps_o, 1)
     for s in solvers_o:
         s.close()
+    for i in infos_o:
+        if i.status != mg.MG_OK:
+            raise SystemExit(f"{other} solve did not converge: {mg.status_string(i.status)} rel_res {i.rel_res:.3e}")
 
     if args.calibrate_copy:
         calibrate_copy()
@@ -939,9 +1012,11 @@ def main():
         "speedup_mixed_over_fp64": ((wall_o / steps_o) / (wall_h / args.steps)) if head == "mixed"
         else ((wall_h / args.steps) / (wall_o / steps_o)),
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, eps_list, [i.cycles for i in infos_h], args.nu, args.cpu_seconds,
-                                           smoother, args.omega, args.sor)
+    if rates is not None:
+        total_cycles = sum(i.cycles for i in infos_h)
+        out["cpu_baseline"] = cpu_baseline_from_rates(
+            rates, total_cycles / len(eps_list),
+            f"rate per unknown-cycle applied to the {total_cycles} cycles the {len(eps_list)} problems need")
     print(json.dumps(out), flush=True)
 
 
