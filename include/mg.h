@@ -262,6 +262,27 @@ mg_status mg_setup_batched(const mg_grid* grids, const mg_coeffs* coeffs, int32_
 mg_status mg_solve_batched(mg_handle h, const double* const* rhs, double* const* x, double tol,
                            int32_t max_cycles, mg_info* info);
 
+/* mg_residual without a handle and without allocating, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): r = rhs - A x (r nullable: device
+ * array [ny][nx], its Dirichlet boundary nodes written 0) and *norm2 =
+ * ||r||_2 over the unknowns (host), for the operator that grid and coeffs
+ * describe as for mg_setup -- MG_COEF_CONST5, or MG_COEF_CELL9 whose
+ * couplings are formed at each node from the caller's cell arrays kx, ky
+ * (device, read during the call; finite and > 0, not checked) -- the same
+ * values as mg_residual on a handle for that grid and operator, up to
+ * rounding for MG_COEF_CELL9 (mg_residual reads assembled bands there).
+ * stream: hipStream_t (NULL = the null stream); the call waits for it once.
+ * It allocates nothing: its scratch (level descriptor, norm state and at most
+ * 1024 partial sums, 9 KiB) is one static device array per GPU, held until
+ * the process ends, and every call on a GPU shares it -- calls that overlap
+ * on one GPU (two threads or two streams) race and must be serialised by the
+ * caller.  Sizes: nx and ny at most 65537 (MG_EINVAL beyond, before any
+ * device work); other errors as for mg_setup's grid and coefficient checks
+ * and mg_residual's. */
+mg_status mg_residual_noalloc(const mg_grid* grid, const mg_coeffs* coeffs, const double* rhs, const double* x,
+                              double* r, double* norm2, void* stream);
+
 /* Frees everything the handle owns (never caller memory).  NULL is accepted. */
 mg_status mg_destroy(mg_handle h);
 

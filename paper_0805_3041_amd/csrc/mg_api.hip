@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -1520,6 +1521,144 @@ mg_status mg_destroy(mg_handle h) {
   if (!h) return MG_OK;
   release(h);
   delete h;
+  return MG_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------- residual without allocation
+//
+// mg_residual_noalloc: the residual and its norm (the kernels of mg_residual)
+// for callers that cannot allocate device memory.  Its device scratch -- the
+// finest-level descriptor, the norm state and the per-workgroup partial sums
+// of the norm reduction -- lives in one file-scope device array per GPU,
+// reached through the address hipGetSymbolAddress gives on that device.
+
+namespace {
+
+constexpr size_t NOALLOC_DESC_OFF = 0;
+constexpr size_t NOALLOC_STATE_OFF = 512;
+constexpr size_t NOALLOC_PARTIAL_OFF = 1024;
+constexpr size_t NOALLOC_SCRATCH_BYTES = NOALLOC_PARTIAL_OFF + sizeof(double) * MAX_NORM_BLOCKS;  // 9 KiB
+static_assert(sizeof(Level<double>) <= NOALLOC_STATE_OFF - NOALLOC_DESC_OFF, "descriptor slot too small");
+static_assert(sizeof(SolveState) <= NOALLOC_PARTIAL_OFF - NOALLOC_STATE_OFF, "state slot too small");
+
+// Largest stored grid side the call accepts: the norm reduction's partial
+// sums (at most MAX_NORM_BLOCKS, however many rows) then fit the scratch.
+constexpr int NOALLOC_MAX_SIDE = 65537;
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Writes the descriptor and a cleared norm state into the scratch (kernel
+// arguments, so nothing is copied from host memory).
+__global__ void k_noalloc_init(Level<double>* dL, SolveState* dS, Level<double> L, double* partial) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  SolveState s{};
+  s.partial = partial;
+  *dS = s;
+  *dL = L;
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status mg_residual_noalloc(const mg_grid* grid, const mg_coeffs* coeffs, const double* rhs, const double* x,
+                              double* r, double* norm2, void* stream) {
+  g_thread_err.clear();
+  mg_status s = check_grid(grid);
+  if (s != MG_OK) return s;
+  if (grid->nx > NOALLOC_MAX_SIDE || grid->ny > NOALLOC_MAX_SIDE)
+    return fail(nullptr, MG_EINVAL,
+                "mg_residual_noalloc: nx and ny must be at most " + std::to_string(NOALLOC_MAX_SIDE) +
+                    " (the norm's partial sums must fit its fixed scratch of " +
+                    std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes)");
+  if (!coeffs) return fail(nullptr, MG_EINVAL, "coeffs is NULL");
+  if (!rhs || !x || !norm2) return fail(nullptr, MG_EINVAL, "rhs, x and norm2 must not be NULL");
+  const int py = grid->periodic_y ? 1 : 0;
+  const double hx = grid->lx / (grid->nx - 1);
+  const double hy = py ? grid->ly / grid->ny : grid->ly / (grid->ny - 1);
+  Level<double> L{};
+  L.x = const_cast<double*>(x);
+  L.b = const_cast<double*>(rhs);
+  L.nx = grid->nx;
+  L.ny = grid->ny;
+  L.pitch = grid->nx;
+  L.py = py;
+  bool oned = false;
+  if (coeffs->kind == MG_COEF_CONST5) {
+    if (!(finite_pos(coeffs->eps_x) && finite_pos(coeffs->eps_y)))
+      return fail(nullptr, MG_EINVAL, "eps_x and eps_y must be finite and > 0");
+    L.kind = ST5;
+    L.cx = coeffs->eps_x / (hx * hx);
+    L.cy = coeffs->eps_y / (hy * hy);
+    L.dg = 2.0 * (L.cx + L.cy);
+    L.inv_dg = 1.0 / L.dg;
+  } else if (coeffs->kind == MG_COEF_CELL9) {
+    if (!coeffs->kx || !coeffs->ky) return fail(nullptr, MG_EINVAL, "kx and ky must be device arrays");
+    // the couplings are formed from the caller's cells at every node
+    oned = coeffs->kx_1d_along_x != 0;
+    L.kind = ST9;
+    L.kcx = coeffs->kx;
+    L.kcy = coeffs->ky;
+    L.kcpitch = oned ? 0 : grid->nx - 1;
+    const double ax = 1.0 / (hx * hx), ay = 1.0 / (hy * hy);
+    L.kc3x = ax / 3.0;
+    L.kc3y = ay / 3.0;
+    L.kc6x = ax / 6.0;
+    L.kc6y = ay / 6.0;
+  } else {
+    return fail(nullptr, MG_EINVAL, "unknown coefficient kind");
+  }
+  void* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess)
+    return fail(nullptr, MG_EDEVICE, std::string("mg_residual_noalloc: scratch address: ") + hipGetErrorString(e));
+  unsigned char* sp = static_cast<unsigned char*>(base);
+  Level<double>* dL = reinterpret_cast<Level<double>*>(sp + NOALLOC_DESC_OFF);
+  SolveState* dS = reinterpret_cast<SolveState*>(sp + NOALLOC_STATE_OFF);
+  double* partial = reinterpret_cast<double*>(sp + NOALLOC_PARTIAL_OFF);
+  L.st = dS;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const LevelShape s0{grid->nx, grid->ny, py, py ? grid->ny : grid->ny - 2};
+#define NOALLOC_CHK(call)                                                                              \
+  do {                                                                                                 \
+    hipError_t e_ = (call);                                                                            \
+    if (e_ != hipSuccess)                                                                              \
+      return fail(nullptr, MG_EDEVICE, std::string("mg_residual_noalloc: ") + #call + ": " + hipGetErrorString(e_)); \
+  } while (0)
+  hipLaunchKernelGGL(k_noalloc_init, dim3(1), dim3(64), 0, st, dL, dS, L, partial);
+  NOALLOC_CHK(hipGetLastError());
+  // r: Dirichlet boundary nodes 0 (a fill kernel), every unknown written below
+  if (r) NOALLOC_CHK(launch_zero_boundary(r, grid->nx, grid->ny, grid->nx, py, st));
+  NOALLOC_CHK(launch_resnorm<double>(dL, s0, NORM_RESID, r, nullptr, L.kind, oned, 1, st));
+  SolveState cur{};
+  NOALLOC_CHK(hipMemcpyAsync(&cur, dS, sizeof(SolveState), hipMemcpyDeviceToHost, st));
+  NOALLOC_CHK(hipStreamSynchronize(st));
+#undef NOALLOC_CHK
+  *norm2 = cur.last;
   return MG_OK;
 }
 

@@ -37,7 +37,7 @@ PRECISIONS = {"fp64": MG_PREC_FP64, "mixed": MG_PREC_MIXED}
 EXPORTED = (
     "mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
     "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_shape", "mg_num_levels", "mg_profile_pass",
-    "mg_pass_info", "mg_start_nested", "mg_update_coeffs",
+    "mg_pass_info", "mg_start_nested", "mg_update_coeffs", "mg_residual_noalloc",
 )
 
 
@@ -101,9 +101,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_pass_info.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32)]
     lib.mg_start_nested.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.mg_update_coeffs.argtypes = [ctypes.c_void_p, P(mg_coeffs)]
+    lib.mg_residual_noalloc.argtypes = [P(mg_grid), P(mg_coeffs), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        P(ctypes.c_double), ctypes.c_void_p]
     for name in ("mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
                  "mg_destroy", "mg_level_shape", "mg_profile_pass", "mg_pass_info", "mg_start_nested",
-                 "mg_update_coeffs"):
+                 "mg_update_coeffs", "mg_residual_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     lib.mg_num_levels.restype = ctypes.c_int32
     _lib = lib
@@ -191,6 +193,19 @@ def mg_residual(h, rhs: torch.Tensor, x: torch.Tensor, r: torch.Tensor | None = 
     s = lib.mg_residual(h, _ptr(rhs), _ptr(x), _ptr(r), ctypes.byref(nrm))
     if s != MG_OK:
         raise MGError(s, last_error(h))
+    return nrm.value
+
+
+def mg_residual_noalloc(grid: mg_grid, coeffs: mg_coeffs, rhs: torch.Tensor, x: torch.Tensor,
+                        r: torch.Tensor | None = None, stream=None) -> float:
+    """r = rhs - A x and ||r||_2 without a handle and without device allocation
+    (the library's static scratch); arrays as for mg_residual."""
+    lib = load_library()
+    nrm = ctypes.c_double()
+    s = lib.mg_residual_noalloc(ctypes.byref(grid), ctypes.byref(coeffs), _ptr(rhs), _ptr(x), _ptr(r),
+                                ctypes.byref(nrm), _stream_ptr(stream))
+    if s != MG_OK:
+        raise MGError(s, last_error(None))
     return nrm.value
 
 
