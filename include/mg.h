@@ -139,7 +139,14 @@ typedef struct {
  *   problem takes the Galerkin product R A P.  MG_COARSE_GALERKIN on a 5-point
  *   problem: the coarse levels take R A P too (they are then 9-point, so the
  *   smoother must be MG_SMOOTH_JACOBI or MG_SMOOTH_GS4C; red-black and line
- *   smoothers are MG_EUNSUPPORTED, and so are batched handles). */
+ *   smoothers are MG_EUNSUPPORTED, and so are batched handles).
+ * adaptive_omega: 0 adds each coarse-grid correction with omega_l = 1; 1
+ *   takes the adaptive omega_l that "The Multigrid Technique" allows in place
+ *   of a fixed value: the weight that minimises the energy norm of the error
+ *   along the prolonged correction P v, omega_l = (d_l, P v) / (A_l P v, P v)
+ *   with d_l = g_l - A_l u_l the defect of the smoothed iterate (1 when
+ *   A_l P v = 0), computed on every level visit by a reduction over the
+ *   level (one extra pass over x, b and the coarse correction). */
 typedef struct {
   int32_t cycle;
   int32_t smoother;
@@ -153,6 +160,7 @@ typedef struct {
   double sor;
   int32_t inner_cycles;
   int32_t coarse_op;
+  int32_t adaptive_omega;
 } mg_options;
 
 enum { MG_COARSE_DEFAULT = 0, MG_COARSE_GALERKIN = 1 };

@@ -37,7 +37,7 @@ thread_local std::string g_thread_err;
 
 constexpr int MAX_BATCH = 4096;
 
-enum HostOpType { H_COLOR = 0, H_JACOBI, H_COPY, H_DR, H_PROLONG, H_COARSE, H_SUB, H_PRE, H_POST, H_LINE };
+enum HostOpType { H_COLOR = 0, H_JACOBI, H_COPY, H_DR, H_PROLONG, H_COARSE, H_SUB, H_PRE, H_POST, H_LINE, H_OMEGA };
 
 struct HostOp {
   int type, level, arg;
@@ -232,7 +232,8 @@ struct Gen {
     } else {
       expand(out, l + 1, MG_CYCLE_V);
     }
-    out.push_back({H_PROLONG, l, 0});
+    if (h->opts.adaptive_omega) out.push_back({H_OMEGA, l, 0});  // omega_l from x (the smoothed iterate)
+    out.push_back({H_PROLONG, l, h->opts.adaptive_omega ? 1 : 0});
     smooth(out, l, h->opts.nu_post);
   }
   // Host program: ops on large levels, one H_SUB per maximal small-level call.
@@ -269,10 +270,14 @@ struct Gen {
       host(out, subs, l + 1, MG_CYCLE_V);
     }
     if (fused) {
+      // omega_l from t, where the fused pre-pass left the smoothed iterate;
+      // the post-pass applies it (the level's descriptor carries the weight)
+      if (h->opts.adaptive_omega) out.push_back({H_OMEGA, l, 1, -1});
       out.push_back({H_POST, l, POST_PLAIN, -1});
       return;
     }
-    out.push_back({H_PROLONG, l, 0, -1});
+    if (h->opts.adaptive_omega) out.push_back({H_OMEGA, l, 0, -1});
+    out.push_back({H_PROLONG, l, h->opts.adaptive_omega ? 1 : 0, -1});
     tmp.clear();
     smooth(tmp, l, h->opts.nu_post);
     for (const Abs& a : tmp) out.push_back({a.type, a.level, a.arg, -1});
@@ -401,6 +406,7 @@ mg_status build_program(mg_handle h, Group& G) {
         case H_PROLONG: t = OP_PROLONG; break;
         case H_COARSE: t = OP_COARSE; break;
         case H_LINE: t = OP_LINE; break;
+        case H_OMEGA: t = OP_OMEGA; break;
       }
       flat.push_back({t, a.level, a.arg, 0});
     }
@@ -430,7 +436,8 @@ hipError_t run_op(mg_handle h, const Group& G, const HostOp& op, Level<T>* dL, L
     case H_JACOBI: return launch_jacobi<T>(Ls, s, op.arg, omega, ns, st);
     case H_COPY: return launch_copy<T>(Ls, s, ns, st);
     case H_DR: return launch_dr<T>(Ls, Cs, G.shp[l + 1], ns, st);
-    case H_PROLONG: return launch_prolong<T>(Ls, Cs, s, ns, st);
+    case H_PROLONG: return launch_prolong<T>(Ls, Cs, s, op.arg, ns, st);
+    case H_OMEGA: return launch_energy<T>(Ls, Cs, s, op.arg, stencil_kind(h), ns, st);
     case H_COARSE: return launch_coarse<T>(Ls, G.dcholp, G.ncu, ns, st);
     case H_LINE: return launch_line<T>(Ls, s, op.arg, omega, stencil_kind(h), ns, st);
     case H_PRE:
@@ -571,6 +578,7 @@ mg_status check_opts(const mg_options* o, int kind) {
   if (o->inner_cycles < 0 || o->inner_cycles > 16) return fail(nullptr, MG_EINVAL, "inner_cycles must be in [0, 16]");
   if (o->coarse_op != MG_COARSE_DEFAULT && o->coarse_op != MG_COARSE_GALERKIN)
     return fail(nullptr, MG_EINVAL, "coarse_op must be MG_COARSE_DEFAULT or MG_COARSE_GALERKIN");
+  if (o->adaptive_omega != 0 && o->adaptive_omega != 1) return fail(nullptr, MG_EINVAL, "adaptive_omega must be 0 or 1");
   if (o->coarse_op == MG_COARSE_GALERKIN && kind == MG_COEF_CONST5 && o->smoother != MG_SMOOTH_JACOBI &&
       o->smoother != MG_SMOOTH_GS4C)
     return fail(nullptr, MG_EUNSUPPORTED,
@@ -811,6 +819,28 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
         HIPCHK(h, h->dalloc(&L.b, (size_t)p * sh.ny * sizeof(float)));
         HIPCHK(h, h->dalloc(&L.t, (size_t)p * sh.ny * sizeof(float)));
       }
+    }
+  }
+  // adaptive omega_l: one device scalar per (level, slot) below the
+  // coarsest, in the precision of the cycle, starting at 1
+  if (h->opts.adaptive_omega) {
+    const size_t nw = (size_t)G.nlev * ns;
+    if (mixed) {
+      float* w = nullptr;
+      HIPCHK(h, h->dalloc(&w, nw * sizeof(float)));
+      const std::vector<float> ones(nw, 1.0f);
+      HIPCHK(h, hipMemcpyAsync(w, ones.data(), nw * sizeof(float), hipMemcpyHostToDevice, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      for (int s = 0; s < ns; ++s)
+        for (int l = 0; l + 1 < G.nlev; ++l) G.l32(l, s).wl = w + (size_t)l * ns + s;
+    } else {
+      double* w = nullptr;
+      HIPCHK(h, h->dalloc(&w, nw * sizeof(double)));
+      const std::vector<double> ones(nw, 1.0);
+      HIPCHK(h, hipMemcpyAsync(w, ones.data(), nw * sizeof(double), hipMemcpyHostToDevice, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      for (int s = 0; s < ns; ++s)
+        for (int l = 0; l + 1 < G.nlev; ++l) G.l64(l, s).wl = w + (size_t)l * ns + s;
     }
   }
 

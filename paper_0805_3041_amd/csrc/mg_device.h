@@ -66,6 +66,10 @@ struct Level {
   const T* kcy;
   int kcpitch;
   T kc3x, kc3y, kc6x, kc6y;  // 1/(3 hx^2), 1/(3 hy^2), 1/(6 hx^2), 1/(6 hy^2)
+  // Adaptive coarse-correction weight omega_l of this level (device scalar
+  // written by the energy reduction before each correction); null: the
+  // correction is added with weight 1.
+  T* wl;
 };
 
 // Host-built op of the coarse-level interpreter (one workgroup runs a list).
@@ -74,9 +78,10 @@ enum OpType {
   OP_JACOBI = 1,    // damped Jacobi x -> t (arg = 0) or t -> x (arg = 1)
   OP_COPY = 2,      // x <- t on `level`
   OP_DR = 3,        // restrict the defect of `level` into b of level+1, zero x of level+1
-  OP_PROLONG = 4,   // x(level) += P x(level+1)
+  OP_PROLONG = 4,   // x(level) += P x(level+1) (arg 1: times the level's adaptive omega_l)
   OP_COARSE = 5,    // exact solve on the coarsest `level`
   OP_LINE = 6,      // line sweep on `level`, arg as line_arg
+  OP_OMEGA = 7,     // adaptive omega_l of `level` from its x, b and the correction on level+1
 };
 
 // Argument of a line-smoothing op: bit 0 direction (0: lines along x, 1:
@@ -412,7 +417,9 @@ __device__ __forceinline__ T prolong_combine(T a00, T a10, T a01, T a11, int ox,
   return oy ? (T)0.5 * (s0 + s1) : s0;
 }
 
-// Bilinear interpolation of the coarse correction at fine node (i, j).
+// Bilinear interpolation of the coarse correction at fine node (i, j) (row
+// pitch pitchc).  At a Dirichlet boundary node it reads only stored coarse
+// boundary zeros.
 template <typename T>
 __device__ __forceinline__ T prolong_value(const T* __restrict__ xc, int pitchc, int nyc, int py, int i, int j) {
   const int I = i >> 1, J = j >> 1;
@@ -422,6 +429,49 @@ __device__ __forceinline__ T prolong_value(const T* __restrict__ xc, int pitchc,
   const int J1 = (py && J + 1 == nyc) ? 0 : J + 1;
   const T* r1 = xc + (size_t)J1 * pitchc;
   return prolong_combine(r0[I], ox ? r0[I + 1] : (T)0, r1[I], ox ? r1[I + 1] : (T)0, ox, 1);
+}
+
+// The same from a coarse level held in LDS.
+template <typename T>
+__device__ __forceinline__ T prolong_value(const MG_LDS T* xc, int pitchc, int nyc, int py, int i, int j) {
+  const int I = i >> 1, J = j >> 1;
+  const int ox = i & 1, oy = j & 1;
+  const MG_LDS T* r0 = xc + J * pitchc;
+  if (!oy) return prolong_combine(r0[I], ox ? r0[I + 1] : (T)0, (T)0, (T)0, ox, 0);
+  const int J1 = (py && J + 1 == nyc) ? 0 : J + 1;
+  const MG_LDS T* r1 = xc + J1 * pitchc;
+  return prolong_combine(r0[I], ox ? r0[I + 1] : (T)0, r1[I], ox ? r1[I + 1] : (T)0, ox, 1);
+}
+
+// Fine value plus the prolonged correction p, weighted by the level's
+// adaptive omega_l when it has one (w = 1 adds p itself).
+template <typename T>
+__device__ __forceinline__ T add_correction(T t, T p, bool weighted, T w) {
+  return weighted ? t + w * p : t + p;
+}
+
+// The prolonged coarse correction P e around fine node (i, j) as an x
+// accessor (rows jm, j, jp already wrapped); P is a global or LDS pointer.
+template <typename T, typename P>
+struct PX {
+  P xc;
+  int pitchc, nyc, py, i, jm, j, jp;
+  __device__ __forceinline__ T at(int di, int dj) const {
+    return prolong_value(xc, pitchc, nyc, py, i + di, dj < 0 ? jm : (dj > 0 ? jp : j));
+  }
+};
+
+// The two sums of the energy-minimising coarse-correction weight at node p
+// (adaptive omega_l of "The Multigrid Technique"): s1 += d_p (P e)_p with d
+// = b - A x, s2 += (A P e)_p (P e)_p; omega_l = s1 / s2 over the level.
+template <int K = KDYN, typename T, typename XA, typename PA>
+__device__ __forceinline__ void energy_terms(const Level<T>& L, const Cf<T>& a, const XA& x, T bp, const PA& pe,
+                                             double& s1, double& s2) {
+  const Nbr<T> vp = gather<K>(L, pe, true);
+  const T d = defect_v<K>(L, a, gather<K>(L, x, true), bp);
+  const T ape = -defect_v<K>(L, a, vp, (T)0);
+  s1 += (double)d * (double)vp.c;
+  s2 += (double)ape * (double)vp.c;
 }
 
 }  // namespace mg

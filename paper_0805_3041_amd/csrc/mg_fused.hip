@@ -423,6 +423,8 @@ __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, co
   const int done = st->done;  // one problem: tested once the region's loads are in flight
   if (gridDim.z > 1 && done) return;
   const Level<T> C = Cs[blockIdx.z];
+  const bool wtd = F.wl != nullptr;  // adaptive omega_l
+  const T wv = wtd ? *F.wl : (T)1;
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
   const int W = TX + 2 * H, R = TY + 2 * H;
@@ -490,7 +492,7 @@ __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, co
           const int I = gi[u] >> 1, J = gj[u] >> 1;
           const MG_LDS T* r0 = ec + (J - cJ0) * CW + (I - cI0);
           const MG_LDS T* r1 = r0 + CW;
-          xv = tv[u] + prolong_combine(r0[0], r0[1], r1[0], r1[1], gi[u] & 1, gj[u] & 1);
+          xv = add_correction(tv[u], prolong_combine(r0[0], r0[1], r1[0], r1[1], gi[u] & 1, gj[u] & 1), wtd, wv);
         }
         x[idx] = xv;
         b[idx] = bv[u];
@@ -920,6 +922,8 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
   const int done = st->done;  // one problem: tested once the region's loads are in flight
   if (gridDim.z > 1 && done) return;
   const Level<T> C = Cs[blockIdx.z];
+  const bool wtd = F.wl != nullptr;  // adaptive omega_l
+  const T wv = wtd ? *F.wl : (T)1;
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
   const int TX = WW - 2 * H, R = TY + 2 * H;
@@ -997,8 +1001,8 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
           const MG_LDS T* e0 = ec + ((gj >> 1) - cJ0) * CW;
           const MG_LDS T* e1 = e0 + CW;
           const int oy = gj & 1;
-          if (oka) xa = ta[u] + prolong_combine(e0[ea], e0[ea + 1], e1[ea], e1[ea + 1], ga & 1, oy);
-          if (okb) xb = tb[u] + prolong_combine(e0[eb], e0[eb + 1], e1[eb], e1[eb + 1], gb & 1, oy);
+          if (oka) xa = add_correction(ta[u], prolong_combine(e0[ea], e0[ea + 1], e1[ea], e1[ea + 1], ga & 1, oy), wtd, wv);
+          if (okb) xb = add_correction(tb[u], prolong_combine(e0[eb], e0[eb + 1], e1[eb], e1[eb + 1], gb & 1, oy), wtd, wv);
         }
         MG_LDS T* r = lds + lj * P;
         r[ca] = xa;

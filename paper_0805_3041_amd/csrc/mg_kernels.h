@@ -31,8 +31,16 @@ template <typename T>
 hipError_t launch_copy(const Level<T>* Ls, const LevelShape& s, int nslots, hipStream_t st);
 template <typename T>
 hipError_t launch_dr(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& c, int nslots, hipStream_t st);
+// x += P e on level f; weighted: x += omega_l P e with the level's adaptive weight
 template <typename T>
-hipError_t launch_prolong(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& f, int nslots, hipStream_t st);
+hipError_t launch_prolong(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& f, int weighted, int nslots,
+                          hipStream_t st);
+// adaptive omega_l of level f (written to each slot's Level::wl): the
+// energy-minimising weight of the prolonged correction; x read from the
+// level's t (src_t, after a fused pre-pass) or x
+template <typename T>
+hipError_t launch_energy(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& f, int src_t, int kind, int nslots,
+                         hipStream_t st);
 template <typename T>
 hipError_t launch_coarse(const Level<T>* Ls, const double* const* chol, int n, int nslots, hipStream_t st);
 // Thomas factors of the lines along `dir` of one level (L: host copy of its descriptor)

@@ -101,15 +101,35 @@ __device__ void body_dr(const Level<T>& F, const Level<T>& C, int tid, int nth) 
   }
 }
 
+// x += P e (weighted: x += w P e, the adaptive omega_l).
 template <typename T>
-__device__ void body_prolong(const Level<T>& F, const Level<T>& C, int tid, int nth) {
+__device__ void body_prolong(const Level<T>& F, const Level<T>& C, int tid, int nth, bool weighted, T w) {
   const int lo = row_lo(F), nr = row_hi(F) - lo + 1, ni = F.nx - 2;
   const int n = nr * ni;
   for (int idx = tid; idx < n; idx += nth) {
     const int r = idx / ni;
     const int i = idx - r * ni + 1;
     const int j = lo + r;
-    F.x[(size_t)j * F.pitch + i] += prolong_value(C.x, C.pitch, C.ny, C.py, i, j);
+    T* xp = F.x + (size_t)j * F.pitch + i;
+    *xp = add_correction(*xp, prolong_value(C.x, C.pitch, C.ny, C.py, i, j), weighted, w);
+  }
+}
+
+// Per-thread sums of the adaptive omega_l over the unknowns of F (x from a
+// global array xs: F.x, or F.t after a fused pre-pass), the coarse
+// correction from C.x.
+template <int K, bool CELLS, typename T>
+__device__ void body_energy(const Level<T>& F, const T* __restrict__ xs, const Level<T>& C, int tid, int nth,
+                            double& s1, double& s2) {
+  const int lo = row_lo(F), nr = row_hi(F) - lo + 1, ni = F.nx - 2;
+  const int n = nr * ni;
+  for (int idx = tid; idx < n; idx += nth) {
+    const int r = idx / ni;
+    const int i = idx - r * ni + 1;
+    const int j = lo + r;
+    const int jm = wrap_dn(j, F.ny, F.py), jp = wrap_up(j, F.ny, F.py);
+    energy_terms<K>(F, coefs<K, CELLS>(F, i, j, jm), gx(xs, F.pitch, i, j, jm, jp), F.b[(size_t)j * F.pitch + i],
+                    PX<T, const T*>{C.x, C.pitch, C.ny, C.py, i, jm, j, jp}, s1, s2);
   }
 }
 
@@ -168,11 +188,53 @@ __global__ void __launch_bounds__(NT) k_dr(const Level<T>* __restrict__ Fs, cons
 }
 
 template <typename T>
-__global__ void __launch_bounds__(NT) k_prolong(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs) {
+__global__ void __launch_bounds__(NT) k_prolong(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs,
+                                                int weighted) {
   const Level<T> F = Fs[blockIdx.z];
   if (F.st->done) return;
   const Level<T> C = Cs[blockIdx.z];
-  body_prolong(F, C, blockIdx.x * NT + threadIdx.x, gridDim.x * NT);
+  body_prolong(F, C, blockIdx.x * NT + threadIdx.x, gridDim.x * NT, weighted != 0, weighted ? *F.wl : (T)1);
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh);
+
+// Adaptive omega_l of level F: per-workgroup partial sums s1, s2 of
+// energy_terms into the slot's partial buffer (two per workgroup); x from
+// F.t when src_t (after a fused pre-pass), else from F.x.
+template <typename T, int K>
+__global__ void __launch_bounds__(NT) k_energy(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs,
+                                               int src_t) {
+  __shared__ double sh[NT / 64];
+  const Level<T> F = Fs[blockIdx.z];
+  SolveState* st = F.st;
+  if (st->done) return;
+  const Level<T> C = Cs[blockIdx.z];
+  double s1 = 0.0, s2 = 0.0;
+  body_energy<K, true>(F, src_t ? F.t : F.x, C, blockIdx.x * NT + threadIdx.x, gridDim.x * NT, s1, s2);
+  const double p1 = block_sum(s1, sh);
+  const double p2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    st->partial[2 * blockIdx.x] = p1;
+    st->partial[2 * blockIdx.x + 1] = p2;
+  }
+}
+
+// omega_l = s1 / s2 from the partial sums (fixed order), 1 when the
+// prolonged correction has no energy.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_energy_finish(const Level<T>* __restrict__ Fs, int nblocks) {
+  __shared__ double sh[NT / 64];
+  const Level<T> F = Fs[blockIdx.z];
+  SolveState* st = F.st;
+  if (st->done) return;
+  double v1 = 0.0, v2 = 0.0;
+  for (int k = threadIdx.x; k < nblocks; k += NT) {
+    v1 += st->partial[2 * k];
+    v2 += st->partial[2 * k + 1];
+  }
+  const double s1 = block_sum(v1, sh);
+  const double s2 = block_sum(v2, sh);
+  if (threadIdx.x == 0) *F.wl = (T)(s2 != 0.0 ? s1 / s2 : 1.0);
 }
 
 template <typename T>
@@ -634,7 +696,8 @@ __device__ void lds_dr(const Level<T>& F, const MG_LDS T* xf, const MG_LDS T* bf
 }
 
 template <typename T>
-__device__ void lds_prolong(const Level<T>& F, MG_LDS T* xf, const Level<T>& C, const MG_LDS T* xc, int tid) {
+__device__ void lds_prolong(const Level<T>& F, MG_LDS T* xf, const Level<T>& C, const MG_LDS T* xc, int tid,
+                            bool weighted, T w) {
   const int nx = F.nx, ny = F.ny, py = F.py;
   const int lo = py ? 0 : 1, hi = py ? ny - 1 : ny - 2;
   const int kl = ceil_log2(nx - 2);
@@ -652,7 +715,24 @@ __device__ void lds_prolong(const Level<T>& F, MG_LDS T* xf, const Level<T>& C, 
       const MG_LDS T* r1 = xc + J1 * C.nx + I;
       v = prolong_combine(r0[0], ox ? r0[1] : (T)0, r1[0], ox ? r1[1] : (T)0, ox, 1);
     }
-    xf[j * nx + i] += v;
+    xf[j * nx + i] = add_correction(xf[j * nx + i], v, weighted, w);
+  }
+}
+
+// Per-thread sums of the adaptive omega_l of an LDS level (threads mapped as
+// in lds_copy; threads past the last column add nothing).
+template <typename T, int K, bool B1>
+__device__ void lds_energy(const Level<T>& F, const MG_LDS T* xf, const MG_LDS T* bf, const MG_LDS T* bl,
+                           const Level<T>& C, const MG_LDS T* xc, int tid, double& s1, double& s2) {
+  const int nx = F.nx, ny = F.ny, py = F.py;
+  const int lo = py ? 0 : 1, hi = py ? ny - 1 : ny - 2;
+  const int kl = ceil_log2(nx - 2);
+  const int i = 1 + (tid & ((1 << kl) - 1));
+  if (i > nx - 2) return;
+  for (int j = lo + (tid >> kl); j <= hi; j += SUB_NT >> kl) {
+    const int jm = wrap_dn(j, ny, py), jp = wrap_up(j, ny, py);
+    energy_terms<K>(F, sub_coefs<T, K, B1>(F, bl, i, j, jm), lgx(xf, nx, i, j, jm, jp), bf[j * nx + i],
+                    PX<T, const MG_LDS T*>{xc, C.nx, C.ny, C.py, i, jm, j, jp}, s1, s2);
   }
 }
 
@@ -776,6 +856,8 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
   __shared__ int boffs[MAX_LEVELS];  // B1: LDS offset of each level's bands
   __shared__ int soff;               // LDS offset of the line-sweep scratch
   __shared__ int sops[MAX_SUB_OPS];
+  __shared__ double esh[SUB_NT / 64];  // workgroup sums of OP_OMEGA
+  __shared__ T wsh[MAX_LEVELS];        // adaptive omega_l per level, set by OP_OMEGA
   const int slot = blockIdx.z;
   const Level<T>* Ls = levs + (size_t)slot * nlev;
   if (Ls[0].st->done) return;
@@ -858,13 +940,21 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
           break;
         case OP_COPY: lds_copy(L, xl, tl, tid); break;
         case OP_DR:
-        case OP_PROLONG: {
+        case OP_PROLONG:
+        case OP_OMEGA: {
           const Level<T> C = Ls[l + 1];
           MG_LDS T* xc = lds + offs[l + 1];
-          if (type == OP_DR)
+          if (type == OP_DR) {
             lds_dr<T, K, B1>(L, xl, bl, bands, C, xc, xc + C.nx * C.ny, tid);
-          else
-            lds_prolong(L, xl, C, xc, tid);
+          } else if (type == OP_PROLONG) {
+            lds_prolong(L, xl, C, xc, tid, arg != 0, wsh[l]);
+          } else {
+            double s1 = 0.0, s2 = 0.0;
+            lds_energy<T, K, B1>(L, xl, bl, bands, C, xc, tid, s1, s2);
+            s1 = block_sum(s1, esh);
+            s2 = block_sum(s2, esh);
+            if (tid == 0) wsh[l] = (T)(s2 != 0.0 ? s1 / s2 : 1.0);
+          }
           break;
         }
         case OP_COARSE: body_coarse(L, chol[slot], ncu, tid, SUB_NT); break;
@@ -877,7 +967,15 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
         case OP_JACOBI: body_jacobi<T, false>(L, arg, omega, tid, SUB_NT); break;
         case OP_COPY: body_copy(L, tid, SUB_NT); break;
         case OP_DR: body_dr<T, false>(L, Ls[l + 1], tid, SUB_NT); break;
-        case OP_PROLONG: body_prolong(L, Ls[l + 1], tid, SUB_NT); break;
+        case OP_PROLONG: body_prolong(L, Ls[l + 1], tid, SUB_NT, arg != 0, wsh[l]); break;
+        case OP_OMEGA: {
+          double s1 = 0.0, s2 = 0.0;
+          body_energy<KDYN, false>(L, L.x, Ls[l + 1], tid, SUB_NT, s1, s2);
+          s1 = block_sum(s1, esh);
+          s2 = block_sum(s2, esh);
+          if (tid == 0) wsh[l] = (T)(s2 != 0.0 ? s1 / s2 : 1.0);
+          break;
+        }
         case OP_COARSE: body_coarse(L, chol[slot], ncu, tid, SUB_NT); break;
         case OP_LINE:
           for (int t0 = 0; t0 < L.nx + L.ny; t0 += SUB_NT) line_thomas<T, K, false>(L, arg, omega, t0 + tid);
@@ -1359,8 +1457,23 @@ hipError_t launch_dr(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& c
 }
 
 template <typename T>
-hipError_t launch_prolong(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& f, int nslots, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong<T>, dim3(blocks_for((long)(f.nx - 2) * f.nrows), 1, nslots), dim3(NT), 0, st, Fs, Cs);
+hipError_t launch_energy(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& f, int src_t, int kind, int nslots,
+                         hipStream_t st) {
+  int nb = blocks_for((long)(f.nx - 2) * f.nrows);
+  if (nb > MAX_NORM_BLOCKS / 2) nb = MAX_NORM_BLOCKS / 2;  // two partial sums per workgroup
+  auto k = kind == ST5 ? k_energy<T, ST5> : k_energy<T, ST9>;
+  hipLaunchKernelGGL(k, dim3(nb, 1, nslots), dim3(NT), 0, st, Fs, Cs, src_t);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_finish<T>, dim3(1, 1, nslots), dim3(NT), 0, st, Fs, nb);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong(const Level<T>* Fs, const Level<T>* Cs, const LevelShape& f, int weighted, int nslots,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_prolong<T>, dim3(blocks_for((long)(f.nx - 2) * f.nrows), 1, nslots), dim3(NT), 0, st, Fs, Cs,
+                     weighted);
   return hipGetLastError();
 }
 
@@ -1519,7 +1632,9 @@ hipError_t launch_coeff_grad(const double* u, const double* lam, double* g, int 
   template hipError_t launch_jacobi<T>(const Level<T>*, const LevelShape&, int, T, int, hipStream_t);             \
   template hipError_t launch_copy<T>(const Level<T>*, const LevelShape&, int, hipStream_t);                       \
   template hipError_t launch_dr<T>(const Level<T>*, const Level<T>*, const LevelShape&, int, hipStream_t);        \
-  template hipError_t launch_prolong<T>(const Level<T>*, const Level<T>*, const LevelShape&, int, hipStream_t);   \
+  template hipError_t launch_prolong<T>(const Level<T>*, const Level<T>*, const LevelShape&, int, int, hipStream_t); \
+  template hipError_t launch_energy<T>(const Level<T>*, const Level<T>*, const LevelShape&, int, int, int,       \
+                                       hipStream_t);                                                            \
   template hipError_t launch_coarse<T>(const Level<T>*, const double* const*, int, int, hipStream_t);             \
   template hipError_t launch_line_factor<T>(const Level<T>&, int, hipStream_t);                                    \
   template hipError_t prepare_line_cr<T>();                                                                        \

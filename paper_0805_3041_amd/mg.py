@@ -56,7 +56,7 @@ class mg_options(ctypes.Structure):
                 ("nu_post", ctypes.c_int32), ("omega", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("coarse_cta_nodes", ctypes.c_int32), ("tile_mode", ctypes.c_int32), ("tile_x", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("stream", ctypes.c_void_p), ("sor", ctypes.c_double),
-                ("inner_cycles", ctypes.c_int32), ("coarse_op", ctypes.c_int32)]
+                ("inner_cycles", ctypes.c_int32), ("coarse_op", ctypes.c_int32), ("adaptive_omega", ctypes.c_int32)]
 
 
 class mg_info(ctypes.Structure):
@@ -313,10 +313,11 @@ COARSE_OPS = {"default": MG_COARSE_DEFAULT, "galerkin": MG_COARSE_GALERKIN}
 
 def make_options(cycle="F", smoother="rbgs", nu_pre=2, nu_post=2, omega=0.8, precision="fp64",
                  coarse_cta_nodes=0, tile_mode="fused", tile_x=0, tile_y=0, stream=None, sor=1.0,
-                 inner_cycles=1, coarse_op="default") -> mg_options:
+                 inner_cycles=1, coarse_op="default", adaptive_omega=False) -> mg_options:
     return mg_options(CYCLES[cycle], SMOOTHERS[smoother], int(nu_pre), int(nu_post), float(omega),
                       PRECISIONS[precision], int(coarse_cta_nodes), TILE_MODES[tile_mode], int(tile_x), int(tile_y),
-                      _stream_ptr(stream), float(sor), int(inner_cycles), COARSE_OPS[coarse_op])
+                      _stream_ptr(stream), float(sor), int(inner_cycles), COARSE_OPS[coarse_op],
+                      1 if adaptive_omega else 0)
 
 
 class Solver:
