@@ -302,6 +302,55 @@ def assemble_q1_separable(g: Grid, kx_of_x: np.ndarray, ky_of_x: np.ndarray) -> 
     return (sp.kron(My, Kx) + sp.kron(Ky, Mx)).tocsr()
 
 
+def assemble_q1_graded(g: Grid, xs, ys, kx: np.ndarray, ky: np.ndarray) -> sp.csr_matrix:
+    """Bilinear-FEM matrix of -div(diag(kx, ky) grad u) on a tensor grid that
+    is refined rather than equidistant (the anisotropically refined grids of
+    the "Anisotropies" section; refinement toward one side in "Different
+    coordinate systems"): node (i, j) at (xs[i], ys[j]), cell (ci, cj) of
+    size hx_c = xs[ci+1] - xs[ci] by hy_c = ys[cj+1] - ys[cj] (Dirichlet y;
+    xs, ys may be None for equidistant).  On that rectangle the x part of the
+    element integral is kx hy_c/hx_c K1 (x) M1 and the y part ky hx_c/hy_c
+    M1 (x) K1; the matrix is divided by hx0 hy0 with hx0 = lx/(nx-1), hy0 =
+    ly/(ny-1), the scaling of :func:`assemble_q1`, which it equals on an
+    equidistant grid."""
+    assert not g.periodic_y or ys is None
+    xs = np.linspace(0.0, g.lx, g.nx) if xs is None else np.asarray(xs, dtype=np.float64)
+    ys = np.linspace(0.0, g.ly, g.ny) if ys is None else np.asarray(ys, dtype=np.float64)
+    kx = np.asarray(kx, dtype=np.float64).reshape(g.ncy, g.ncx)
+    ky = np.asarray(ky, dtype=np.float64).reshape(g.ncy, g.ncx)
+    hx0 = g.lx / (g.nx - 1)
+    hy0 = g.ly / (g.ny - 1)
+    Kx = np.zeros((4, 4))  # K1 (x) M1 and M1 (x) K1 in local order 2*b + a
+    Ky = np.zeros((4, 4))
+    for a in range(2):
+        for b in range(2):
+            for a2 in range(2):
+                for b2 in range(2):
+                    Kx[2 * b + a, 2 * b2 + a2] = K1[a, a2] * M1[b, b2]
+                    Ky[2 * b + a, 2 * b2 + a2] = M1[a, a2] * K1[b, b2]
+    idx = _unknown_index(g)
+    rows, cols, vals = [], [], []
+    for cj in range(g.ncy):
+        hy = ys[cj + 1] - ys[cj]
+        for ci in range(g.ncx):
+            hx = xs[ci + 1] - xs[ci]
+            E = (kx[cj, ci] * (hy / hx) * Kx + ky[cj, ci] * (hx / hy) * Ky) / (hx0 * hy0)
+            nodes = _cell_nodes(g, ci, cj)
+            for p_, (jp, ip) in enumerate(nodes):
+                rp = idx[jp, ip]
+                if rp < 0:
+                    continue
+                for q, (jq, iq) in enumerate(nodes):
+                    cq = idx[jq, iq]
+                    if cq < 0:
+                        continue
+                    rows.append(rp)
+                    cols.append(cq)
+                    vals.append(E[p_, q])
+    n = g.n_unknowns
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+
+
 def q1_row(g: Grid, kx: np.ndarray, ky: np.ndarray, i: int, j: int) -> dict:
     """Row of the Q1 matrix at unknown node (i, j): {(jq, iq): a_pq} over the
     unknown nodes q that share a cell with it, from the element matrices of
@@ -510,9 +559,15 @@ def hierarchy_5pt(g: Grid, eps_x=1.0, eps_y=1.0, opts=None, levels=0, galerkin=F
     return build_hierarchy(g, laplace5(g, eps_x, eps_y), opts, levels, rediscretise=redisc)
 
 
-def hierarchy_q1(g: Grid, kx, ky, opts=None, levels=0, separable=False) -> Hierarchy:
+def hierarchy_q1(g: Grid, kx, ky, opts=None, levels=0, separable=False, xs=None, ys=None) -> Hierarchy:
+    """Q1 hierarchy: the finest operator assembled from cells (on the refined
+    grid xs, ys when given), the coarse levels Galerkin R A P with the
+    transfers of the logically equidistant grid."""
     opts = opts or Options(smoother="gs4c")
-    A0 = assemble_q1_separable(g, kx, ky) if separable else assemble_q1(g, kx, ky)
+    if xs is not None or ys is not None:
+        A0 = assemble_q1_graded(g, xs, ys, kx, ky)
+    else:
+        A0 = assemble_q1_separable(g, kx, ky) if separable else assemble_q1(g, kx, ky)
     return build_hierarchy(g, A0, opts, levels, rediscretise=None)
 
 

@@ -89,6 +89,34 @@ def aniso_x0(n: int = 1025, kind: str = "zero", seed: int = 1) -> np.ndarray:
 ANNULUS_R0, ANNULUS_R1 = 0.5, 1.0
 
 
+def graded_nodes(n: int, a: float = 0.0, length: float = 1.0) -> np.ndarray:
+    """n node coordinates on [0, length], refined toward 0 for a > 0 (toward
+    `length` for a < 0): x = length (e^(a xi) - 1) / (e^a - 1) at equidistant
+    xi in [0, 1]; a = 0 gives the equidistant grid.  The spacing ratio between
+    the last and the first cell is about e^a."""
+    xi = np.linspace(0.0, 1.0, n)
+    if a == 0.0:
+        return length * xi
+    x = length * np.expm1(a * xi) / np.expm1(a)
+    x[0], x[-1] = 0.0, length
+    return x
+
+
+def lumped_rhs(f: np.ndarray, xs: np.ndarray, ys: np.ndarray) -> np.ndarray:
+    """Right-hand side of the Q1 operator on a refined tensor grid (Dirichlet
+    both ways) with a lumped mass: b = f times the node's dual area
+    (half-cells on each side), over hx0 hy0 of the equidistant grid of the
+    same extent; zero at boundary nodes."""
+    hx, hy = np.diff(xs), np.diff(ys)
+    dx = np.zeros(len(xs))
+    dy = np.zeros(len(ys))
+    dx[1:-1] = 0.5 * (hx[:-1] + hx[1:])
+    dy[1:-1] = 0.5 * (hy[:-1] + hy[1:])
+    hx0 = (xs[-1] - xs[0]) / (len(xs) - 1)
+    hy0 = (ys[-1] - ys[0]) / (len(ys) - 1)
+    return np.asarray(f, dtype=np.float64) * np.outer(dy, dx) / (hx0 * hy0)
+
+
 def annulus_cell_coefficients(nx: int):
     """Per radial cell (length nx - 1) coefficients of the annulus mapped to the
     unit square: with r = 0.5 + 0.5 xi and theta = 2 pi eta, the weak form of
