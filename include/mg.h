@@ -90,11 +90,23 @@ enum { MG_TILES_FUSED = 0, MG_TILES_PER_OP = 1, MG_TILES_NARROW = 2, MG_TILES_WI
 
 /* Grid: stored node counts and domain lengths.  A Dirichlet direction has
  * n = 2^k m + 1 nodes (h = l / (n - 1)); the periodic direction has n = 2^k m
- * nodes (h = l / n).  Only y may be periodic (periodic_x must be 0). */
+ * nodes (h = l / n).  Only y may be periodic (periodic_x must be 0).
+ * xs, ys (HOST arrays, nullable, read during the call only): node
+ * coordinates of a refined (graded) tensor grid -- the anisotropically
+ * refined grids of the "Anisotropies" section, refined toward one side in
+ * "Different coordinate systems" -- nx (ny) strictly increasing values
+ * spanning lx (ly); NULL means equidistant.  Refined grids need
+ * MG_COEF_CELL9 (the Q1 operator on each rectangle: kx hy_c/hx_c K1 (x) M1 +
+ * ky hx_c/hy_c M1 (x) K1, divided by the equidistant hx hy) and a Dirichlet
+ * y direction when ys is given; the coarse levels are the Galerkin products
+ * with the transfers of the logically equidistant grid.  Other uses are
+ * MG_EUNSUPPORTED. */
 typedef struct {
   int32_t nx, ny;
   int32_t periodic_x, periodic_y;
   double lx, ly;
+  const double* xs;
+  const double* ys;
 } mg_grid;
 
 /* Operator.

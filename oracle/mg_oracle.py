@@ -310,16 +310,17 @@ def assemble_q1_graded(g: Grid, xs, ys, kx: np.ndarray, ky: np.ndarray) -> sp.cs
     size hx_c = xs[ci+1] - xs[ci] by hy_c = ys[cj+1] - ys[cj] (Dirichlet y;
     xs, ys may be None for equidistant).  On that rectangle the x part of the
     element integral is kx hy_c/hx_c K1 (x) M1 and the y part ky hx_c/hy_c
-    M1 (x) K1; the matrix is divided by hx0 hy0 with hx0 = lx/(nx-1), hy0 =
-    ly/(ny-1), the scaling of :func:`assemble_q1`, which it equals on an
-    equidistant grid."""
+    M1 (x) K1; the matrix is divided by hx0 hy0, the equidistant spacings
+    (lx/(nx-1), and ly/(ny-1) or ly/ny for a periodic y), the scaling of
+    :func:`assemble_q1`, which it equals on an equidistant grid."""
     assert not g.periodic_y or ys is None
+    # cell boundaries: nx nodes along x; along y the ncy + 1 cell edges (a
+    # periodic direction's last cell closes on node 0)
     xs = np.linspace(0.0, g.lx, g.nx) if xs is None else np.asarray(xs, dtype=np.float64)
-    ys = np.linspace(0.0, g.ly, g.ny) if ys is None else np.asarray(ys, dtype=np.float64)
+    ys = np.linspace(0.0, g.ly, g.ncy + 1) if ys is None else np.asarray(ys, dtype=np.float64)
     kx = np.asarray(kx, dtype=np.float64).reshape(g.ncy, g.ncx)
     ky = np.asarray(ky, dtype=np.float64).reshape(g.ncy, g.ncx)
-    hx0 = g.lx / (g.nx - 1)
-    hy0 = g.ly / (g.ny - 1)
+    hx0, hy0 = g.hx, g.hy
     Kx = np.zeros((4, 4))  # K1 (x) M1 and M1 (x) K1 in local order 2*b + a
     Ky = np.zeros((4, 4))
     for a in range(2):

@@ -94,7 +94,15 @@ struct mg_handle_s {
   bool batched = false;
   int nprob = 1;
   int kind = MG_COEF_CONST5;
-  int oned = 0;
+  int oned = 0;                      // the hierarchy's 9-point bands vary along x only
+  int in_oned = 0;                   // layout of the caller's cell arrays (kx_1d_along_x)
+  // refined (graded) grid: cell widths over the equidistant ones, per cell
+  // column and row (host and device), and the caller's coefficients folded
+  // with them (device, `grows` rows of ncx)
+  bool graded = false;
+  std::vector<double> hrx, hry;
+  double *grx = nullptr, *gry = nullptr, *gkx = nullptr, *gky = nullptr;
+  int grows = 1;
   bool galerkin5 = false;            // 5-point problem with Galerkin coarse operators (levels kept as 1-D bands)
   mg_options opts{};
   int ncol = 0;                      // 0 Jacobi (and line smoothers), 2 red-black, 4 four-colour
@@ -536,6 +544,19 @@ mg_status check_grid(const mg_grid* g) {
     return fail(nullptr, MG_EINVAL, "ny must be >= 3");
   }
   if ((long)g->nx * g->ny > (1L << 31) / 2) return fail(nullptr, MG_EINVAL, "grid too large");
+  if (g->ys && g->periodic_y)
+    return fail(nullptr, MG_EUNSUPPORTED, "refined y coordinates need a Dirichlet y direction");
+  for (int d = 0; d < 2; ++d) {
+    const double* c = d == 0 ? g->xs : g->ys;
+    if (!c) continue;
+    const int n = d == 0 ? g->nx : g->ny;
+    const double len = d == 0 ? g->lx : g->ly;
+    for (int k = 0; k < n; ++k)
+      if (!std::isfinite(c[k]) || (k > 0 && !(c[k] > c[k - 1])))
+        return fail(nullptr, MG_EINVAL, "node coordinates must be finite and strictly increasing");
+    if (!(std::fabs(c[n - 1] - c[0] - len) <= 1e-12 * len))
+      return fail(nullptr, MG_EINVAL, "node coordinates must span the domain length (lx or ly)");
+  }
   return MG_OK;
 }
 
@@ -1000,7 +1021,7 @@ mg_status upload_descriptors(mg_handle h, Group& G) {
 mg_status check_cell_coeffs(mg_handle h, const mg_coeffs* coeffs) {
   const mg_grid& grid = h->groups[0].grid;
   const int ncx = grid.nx - 1, ncy = grid.periodic_y ? grid.ny : grid.ny - 1;
-  const long nc = h->oned ? ncx : (long)ncx * ncy;
+  const long nc = h->in_oned ? ncx : (long)ncx * ncy;
   HIPCHK(h, hipMemsetAsync(h->dcount, 0, sizeof(int), h->stream));
   HIPCHK(h, launch_count_bad(coeffs->kx, nc, h->dcount, h->stream));
   HIPCHK(h, launch_count_bad(coeffs->ky, nc, h->dcount, h->stream));
@@ -1030,10 +1051,31 @@ mg_status setup_handle(mg_handle h, const mg_coeffs* coeffs, int32_t levels) {
   for (int p = 0; p < h->nprob; ++p) HIPCHK(h, h->dalloc(&h->dhist[p], (size_t)h->hist_cap * sizeof(double)));
 
   // coefficient checks (read-only device pass)
+  mg_coeffs folded{};
   if (h->kind == MG_COEF_CELL9) {
     HIPCHK(h, h->dalloc(&h->dcount, sizeof(int)));
     mg_status s = check_cell_coeffs(h, coeffs);
     if (s != MG_OK) return s;
+    if (h->graded) {
+      // the hierarchy takes the caller's cells folded with the cell widths
+      const mg_grid& grid = h->groups[0].grid;
+      const int ncx = grid.nx - 1;
+      h->grows = h->oned ? 1 : (grid.periodic_y ? grid.ny : grid.ny - 1);
+      HIPCHK(h, h->dalloc(&h->grx, h->hrx.size() * sizeof(double)));
+      HIPCHK(h, h->dalloc(&h->gry, h->hry.size() * sizeof(double)));
+      HIPCHK(h, hipMemcpyAsync(h->grx, h->hrx.data(), h->hrx.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+      HIPCHK(h, hipMemcpyAsync(h->gry, h->hry.data(), h->hry.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+      HIPCHK(h, h->dalloc(&h->gkx, (size_t)ncx * h->grows * sizeof(double)));
+      HIPCHK(h, h->dalloc(&h->gky, (size_t)ncx * h->grows * sizeof(double)));
+      HIPCHK(h, launch_graded_cells(coeffs->kx, coeffs->ky, h->in_oned, h->grx, h->gry, h->gkx, h->gky, ncx, h->grows,
+                                    h->stream));
+      folded = *coeffs;
+      folded.kx = h->gkx;
+      folded.ky = h->gky;
+      folded.kx_1d_along_x = h->oned;
+      coeffs = &folded;
+      HIPCHK(h, hipStreamSynchronize(h->stream));  // the host ratio arrays stay, but settle the copies here
+    }
   }
   HIPCHK(h, h->mixed() ? prepare_subcycle_lds<float>() : prepare_subcycle_lds<double>());
   if (h->line) HIPCHK(h, h->mixed() ? prepare_line_cr<float>() : prepare_line_cr<double>());
@@ -1231,6 +1273,7 @@ mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, int32_t levels,
   if (coeffs->kind == MG_COEF_CONST5) {
     if (!(finite_pos(coeffs->eps_x) && finite_pos(coeffs->eps_y)))
       return fail(nullptr, MG_EINVAL, "eps_x and eps_y must be finite and > 0");
+    if (grid->xs || grid->ys) return fail(nullptr, MG_EUNSUPPORTED, "refined grids (xs, ys) need MG_COEF_CELL9");
   } else if (coeffs->kind == MG_COEF_CELL9) {
     if (!coeffs->kx || !coeffs->ky) return fail(nullptr, MG_EINVAL, "kx and ky must be device arrays");
   } else {
@@ -1245,12 +1288,29 @@ mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, int32_t levels,
   mg_handle h = new mg_handle_s();
   h->opts = *opts;
   h->kind = coeffs->kind;
-  h->oned = coeffs->kx_1d_along_x ? 1 : 0;
+  h->in_oned = coeffs->kx_1d_along_x ? 1 : 0;
+  h->oned = h->in_oned;
+  if (grid->xs || grid->ys) {
+    // cell widths over the equidistant width; the folded coefficients vary
+    // along x only if the caller's do and y is not refined
+    h->graded = true;
+    const int ncx = grid->nx - 1, ncy = grid->periodic_y ? grid->ny : grid->ny - 1;
+    const double hx0 = grid->lx / ncx, hy0 = grid->ly / ncy;
+    h->hrx.assign(ncx, 1.0);
+    h->hry.assign(grid->ys ? ncy : 1, 1.0);
+    if (grid->xs)
+      for (int i = 0; i < ncx; ++i) h->hrx[i] = (grid->xs[i + 1] - grid->xs[i]) / hx0;
+    if (grid->ys)
+      for (int j = 0; j < ncy; ++j) h->hry[j] = (grid->ys[j + 1] - grid->ys[j]) / hy0;
+    if (grid->ys) h->oned = 0;
+    if (!h->oned && h->hry.size() == 1) h->hry.assign(ncy, 1.0);
+  }
   h->nprob = 1;
   h->eps_x.assign(1, coeffs->eps_x);
   h->eps_y.assign(1, coeffs->eps_y);
   h->groups.resize(1);
   h->groups[0].grid = *grid;
+  h->groups[0].grid.xs = h->groups[0].grid.ys = nullptr;  // caller memory: not kept
   h->groups[0].ns = 1;
   h->groups[0].probs = {0};
   s = setup_handle(h, coeffs, levels);
@@ -1277,6 +1337,7 @@ mg_status mg_setup_batched(const mg_grid* grids, const mg_coeffs* coeffs, int32_
     if (s != MG_OK) return fail(nullptr, s, "problem " + std::to_string(p) + ": " + g_thread_err);
     if (coeffs[p].kind != MG_COEF_CONST5)
       return fail(nullptr, MG_EUNSUPPORTED, "batched solves take MG_COEF_CONST5 problems only");
+    if (grids[p].xs || grids[p].ys) return fail(nullptr, MG_EUNSUPPORTED, "batched solves take equidistant grids");
     if (!(finite_pos(coeffs[p].eps_x) && finite_pos(coeffs[p].eps_y)))
       return fail(nullptr, MG_EINVAL, "problem " + std::to_string(p) + ": eps_x and eps_y must be finite and > 0");
   }
@@ -1497,7 +1558,7 @@ mg_status mg_update_coeffs(mg_handle h, const mg_coeffs* coeffs) {
   if (!coeffs) return fail(h, MG_EINVAL, "coeffs is NULL");
   if (h->kind != MG_COEF_CELL9 || coeffs->kind != MG_COEF_CELL9)
     return fail(h, MG_EINVAL, "coefficient update needs cell coefficients, at setup and now");
-  if ((coeffs->kx_1d_along_x ? 1 : 0) != h->oned) return fail(h, MG_EINVAL, "kx_1d_along_x differs from setup");
+  if ((coeffs->kx_1d_along_x ? 1 : 0) != h->in_oned) return fail(h, MG_EINVAL, "kx_1d_along_x differs from setup");
   if (!coeffs->kx || !coeffs->ky) return fail(h, MG_EINVAL, "kx and ky must be device arrays");
   Group& G = h->groups[0];
   const Level<double>& L0 = G.l64(0, 0);
@@ -1505,6 +1566,15 @@ mg_status mg_update_coeffs(mg_handle h, const mg_coeffs* coeffs) {
     return fail(h, MG_EINVAL, "kx and ky were one array at setup and must be one array here");
   s = check_cell_coeffs(h, coeffs);
   if (s != MG_OK) return s;
+  mg_coeffs folded = *coeffs;
+  if (h->graded) {  // fold the new cells with the cell widths, as at setup
+    HIPCHK(h, launch_graded_cells(coeffs->kx, coeffs->ky, h->in_oned, h->grx, h->gry, h->gkx, h->gky,
+                                  G.grid.nx - 1, h->grows, h->stream));
+    folded.kx = h->gkx;
+    folded.ky = h->gky;
+    folded.kx_1d_along_x = h->oned;
+    coeffs = &folded;
+  }
   HIPCHK(h, assemble_cell9(h, G, coeffs));
   if (h->line) HIPCHK(h, assemble_line_factors(h, G));
   return assemble_coarsest(h, G);
@@ -1539,6 +1609,7 @@ mg_status mg_coeff_grad(mg_handle h, const double* u, const double* lam, double*
   mg_status s = single_only(h);
   if (s != MG_OK) return s;
   if (h->kind != MG_COEF_CELL9) return fail(h, MG_EUNSUPPORTED, "coefficient gradient needs MG_COEF_CELL9");
+  if (h->graded) return fail(h, MG_EUNSUPPORTED, "coefficient gradient on a refined grid is not built");
   if (!u || !lam || !dL_dk) return fail(h, MG_EINVAL, "u, lam and dL_dk must be device arrays");
   const Group& G = h->groups[0];
   const LevelShape& s0 = G.shp[0];
@@ -1627,6 +1698,7 @@ mg_status mg_residual_noalloc(const mg_grid* grid, const mg_coeffs* coeffs, cons
                     std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes)");
   if (!coeffs) return fail(nullptr, MG_EINVAL, "coeffs is NULL");
   if (!rhs || !x || !norm2) return fail(nullptr, MG_EINVAL, "rhs, x and norm2 must not be NULL");
+  if (grid->xs || grid->ys) return fail(nullptr, MG_EUNSUPPORTED, "mg_residual_noalloc: refined grids need a handle");
   const int py = grid->periodic_y ? 1 : 0;
   const double hx = grid->lx / (grid->nx - 1);
   const double hy = py ? grid->ly / grid->ny : grid->ly / (grid->ny - 1);

@@ -77,6 +77,9 @@ int norm_blocks(const LevelShape& s);
 hipError_t launch_outer_update(const Level<double>* L64, const Level<float>* L32, const LevelShape& s, int nslots,
                                hipStream_t st);
 hipError_t launch_zero_boundary(double* x, int nx, int ny, int pitch, int py, hipStream_t st);
+// cell coefficients of a refined grid in the equidistant form (kx ry/rx, ky rx/ry)
+hipError_t launch_graded_cells(const double* kx, const double* ky, int in_oned, const double* rx, const double* ry,
+                               double* kxo, double* kyo, int ncx, int nrows, hipStream_t st);
 hipError_t launch_q1_bands(double* band, int bstride, int bpitch, int nrows, int nx, int ny, int py, const double* kx,
                            const double* ky, int kpitch, double hx, double hy, hipStream_t st);
 hipError_t launch_rap(double* cband, int cbstride, int cbpitch, int cnrows, int ncx, int ncy, const double* fband,

@@ -1159,6 +1159,24 @@ __global__ void k_zero_boundary(double* x, int nx, int ny, int pitch, int py) {
 
 // --------------------------------------------------------------------------- setup kernels
 
+// Cell coefficients of a refined tensor grid folded into the equidistant
+// form: cell (i, j) of size hx_c = rx[i] hx0 by hy_c = ry[j] hy0 contributes
+// kx hy_c/hx_c K1 (x) M1 + ky hx_c/hy_c M1 (x) K1 over hx0 hy0, which is the
+// equidistant cell's kx'/hx0^2 K1 (x) M1 + ky'/hy0^2 M1 (x) K1 with kx' = kx
+// ry/rx and ky' = ky rx/ry.  Input [ncy][ncx] (or [ncx] when in_oned), output
+// nrows rows of ncx.
+__global__ void k_graded_cells(const double* __restrict__ kx, const double* __restrict__ ky, int in_oned,
+                               const double* __restrict__ rx, const double* __restrict__ ry, double* __restrict__ kxo,
+                               double* __restrict__ kyo, int ncx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= ncx) return;
+  const size_t src = in_oned ? (size_t)i : (size_t)j * ncx + i, dst = (size_t)j * ncx + i;
+  const double q = ry[j] / rx[i];
+  kxo[dst] = kx[src] * q;
+  kyo[dst] = ky[src] / q;
+}
+
+
 // Q1 bands C, E, N, NE, NW at every stored node from per-cell kx, ky
 // (cell (ci, cj) at kx[cj * kpitch + ci]; kpitch = 0 when they vary along x
 // only, then only row 0 of the bands is written).  Element matrix of a cell,
@@ -1552,6 +1570,13 @@ hipError_t launch_outer_update(const Level<double>* L64, const Level<float>* L32
 hipError_t launch_zero_boundary(double* x, int nx, int ny, int pitch, int py, hipStream_t st) {
   const int n = nx > ny ? nx : ny;
   hipLaunchKernelGGL(k_zero_boundary, dim3(blocks_for(n)), dim3(NT), 0, st, x, nx, ny, pitch, py);
+  return hipGetLastError();
+}
+
+hipError_t launch_graded_cells(const double* kx, const double* ky, int in_oned, const double* rx, const double* ry,
+                               double* kxo, double* kyo, int ncx, int nrows, hipStream_t st) {
+  hipLaunchKernelGGL(k_graded_cells, dim3(blocks_for(ncx), nrows), dim3(NT), 0, st, kx, ky, in_oned, rx, ry, kxo, kyo,
+                     ncx);
   return hipGetLastError();
 }
 

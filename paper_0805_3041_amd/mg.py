@@ -43,7 +43,8 @@ EXPORTED = (
 
 class mg_grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("periodic_x", ctypes.c_int32),
-                ("periodic_y", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double)]
+                ("periodic_y", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+                ("xs", ctypes.POINTER(ctypes.c_double)), ("ys", ctypes.POINTER(ctypes.c_double))]
 
 
 class mg_coeffs(ctypes.Structure):
@@ -325,9 +326,16 @@ class Solver:
 
     def __init__(self, nx: int, ny: int, *, periodic_y: bool = False, lx: float = 1.0, ly: float = 1.0,
                  eps_x: float = 1.0, eps_y: float = 1.0, kx: torch.Tensor | None = None,
-                 ky: torch.Tensor | None = None, kx_1d_along_x: bool = False, levels: int = 0, **opt):
+                 ky: torch.Tensor | None = None, kx_1d_along_x: bool = False, levels: int = 0,
+                 xs=None, ys=None, **opt):
+        """xs, ys: node coordinates of a refined (graded) grid (host arrays of
+        nx, ny values; None = equidistant)."""
         self.nx, self.ny, self.periodic_y = nx, ny, periodic_y
         self.grid = mg_grid(nx, ny, 0, 1 if periodic_y else 0, lx, ly)
+        self._coords = tuple(None if c is None else np.ascontiguousarray(c, dtype=np.float64) for c in (xs, ys))
+        for name, c in zip(("xs", "ys"), self._coords):
+            if c is not None:
+                setattr(self.grid, name, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         if kx is None:
             self.coeffs = mg_coeffs(MG_COEF_CONST5, eps_x, eps_y, None, None, 0)
             self._keep = ()

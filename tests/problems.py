@@ -27,6 +27,16 @@ class Problem:
     levels: int = 0
     coarse_op: str = "default"   # "galerkin": 5-point problems take R A P on the coarse levels
     adaptive_omega: bool = False  # energy-minimising coarse-correction weight
+    grade: tuple | None = None    # (ax, ay): refined grid, W.graded_nodes exponents along x and y
+
+    def coords(self):
+        """Node coordinates (xs, ys) of a refined grid, or (None, None)."""
+        if self.grade is None:
+            return None, None
+        ax, ay = self.grade
+        xs = W.graded_nodes(self.nx, ax) if ax else None
+        ys = W.graded_nodes(self.ny, ay) if ay else None
+        return xs, ys
 
     def grid(self):
         return O.Grid(self.nx, self.ny, self.periodic_y)
@@ -44,6 +54,10 @@ class Problem:
             assert ncy == self.nx - 1
             a = np.exp(W.gaussian_random_field(self.nx - 1, 5))
             return a, a, False
+        if self.q1 == "unit":
+            ncy = self.ny if self.periodic_y else self.ny - 1
+            one = np.ones((ncy, self.nx - 1))
+            return one, one, False
         return None
 
     def oracle(self):
@@ -54,6 +68,11 @@ class Problem:
         if c is None:
             return O.hierarchy_5pt(g, self.eps, 1.0, opts, self.levels, galerkin=self.coarse_op == "galerkin")
         kx, ky, oned = c
+        xs, ys = self.coords()
+        if xs is not None or ys is not None:
+            if oned:
+                kx, ky = np.broadcast_to(kx, (g.ncy, g.ncx)), np.broadcast_to(ky, (g.ncy, g.ncx))
+            return O.hierarchy_q1(g, kx, ky, opts, self.levels, xs=xs, ys=ys)
         if oned:
             return O.hierarchy_q1(g, kx, ky, opts, self.levels, separable=True)
         return O.hierarchy_q1(g, kx, ky, opts, self.levels)
@@ -71,8 +90,9 @@ class Problem:
             return mg.Solver(self.nx, self.ny, eps_x=self.eps, eps_y=1.0, **kw)
         kx, ky, oned = c
         dev = "cuda"
+        xs, ys = self.coords()
         return mg.Solver(self.nx, self.ny, kx=torch.tensor(kx, device=dev), ky=torch.tensor(ky, device=dev),
-                         kx_1d_along_x=oned, **kw)
+                         kx_1d_along_x=oned, xs=xs, ys=ys, **kw)
 
     def rhs(self, seed=2):
         return W.normal_field(self.nx, self.ny, seed, self.periodic_y)

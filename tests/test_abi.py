@@ -167,3 +167,37 @@ def test_setup_batched_rejects_invalid_arguments(mg, case):
                           **case.get("opt", {}))
     assert s == case.get("status", -1), mg.last_error(None)
     assert not h.value
+
+
+def _grid_with_coords(mg, nx, ny, xs=None, ys=None, periodic_y=0):
+    import numpy as np
+    g = mg.mg_grid(nx, ny, 0, periodic_y, 1.0, 1.0)
+    keep = []
+    for name, c in (("xs", xs), ("ys", ys)):
+        if c is not None:
+            a = np.ascontiguousarray(c, dtype=np.float64)
+            keep.append(a)
+            setattr(g, name, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return g, keep
+
+
+@pytest.mark.parametrize("case", [
+    dict(xs=[0.0, 0.5, 0.4, 0.7, 1.0], status=-1),                 # not increasing
+    dict(xs=[0.0, 0.2, 0.4, 0.6, 0.9], status=-1),                 # does not span lx
+    dict(xs=[0.0, 0.1, float("nan"), 0.6, 1.0], status=-1),
+    dict(ys=[0.0, 0.1, 0.3, 0.6], periodic_y=1, ny=4, status=-4),  # refined periodic direction
+    dict(xs=[0.0, 0.1, 0.3, 0.6, 1.0], const5=True, status=-4),    # 5-point operator on a refined grid
+])
+def test_refined_grid_arguments_rejected(mg, case):
+    ny = case.get("ny", 5)
+    g, keep = _grid_with_coords(mg, 5, ny, case.get("xs"), case.get("ys"), case.get("periodic_y", 0))
+    if case.get("const5"):
+        coeffs = mg.mg_coeffs(mg.MG_COEF_CONST5, 1.0, 1.0, None, None, 0)
+        opt = {}
+    else:
+        # device pointers are never touched: the grid check fails first
+        coeffs = mg.mg_coeffs(mg.MG_COEF_CELL9, 0, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), 0)
+        opt = dict(smoother=mg.MG_SMOOTH_GS4C)
+    s, h = _setup(mg, g, coeffs, **opt)
+    assert s == case["status"] and not h.value
+    assert mg.last_error(None)

@@ -92,3 +92,17 @@ def test_graded_nodes_refine_toward_one_side():
     h = np.diff(x)
     assert x[0] == 0.0 and x[-1] == 1.0 and np.all(h > 0) and np.all(np.diff(h) > 0)
     assert abs(h[-1] / h[0] - np.exp(2.0 * 63 / 64)) < 1e-9 * np.exp(2.0)
+
+
+def test_graded_x_on_a_periodic_grid_equals_elementwise_cells():
+    """Refinement along x of a periodic-y grid: the same matrix as the plain
+    assembly with the refinement folded into the cells by hand (the x part
+    scaled by hy0/hx_c / (hy0/hx0), the y part by hx_c/hx0)."""
+    g = O.Grid(9, 8, periodic_y=True)
+    xs = W.graded_nodes(9, 2.0)
+    rng = np.random.default_rng(33)
+    kx, ky = rng.uniform(0.5, 2.0, (2, g.ncy, g.ncx))
+    r = np.diff(xs) / g.hx
+    A = O.assemble_q1_graded(g, xs, None, kx, ky).toarray()
+    B = O.assemble_q1(g, kx / r[None, :], ky * r[None, :]).toarray()
+    np.testing.assert_allclose(A, B, rtol=0, atol=1e-12 * np.abs(B).max())
