@@ -53,6 +53,8 @@ def parse():
                     help="start vector; nested = mg_start_nested inside the timed region")
     ap.add_argument("--levels", type=int, default=0, help="number of levels (0 = coarsen as far as possible)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--tune", default="auto", choices=["auto", "off", "refresh"],
+                    help="tile shapes and coarse threshold: autotuned (cached), the fixed rule, or measured again")
     ap.add_argument("--max-cycles", type=int, default=20000)
     ap.add_argument("--eps", type=float, default=None, help="one eps of the workload only (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -437,7 +439,7 @@ def annulus(args, rates=None):
     def make(precision):
         return mg.Solver(nx, ny, periodic_y=True, kx=kxt, ky=kyt, kx_1d_along_x=True, smoother=smoother,
                          nu_pre=args.nu, nu_post=args.nu, omega=args.omega, sor=args.sor, precision=precision,
-                         levels=args.levels)
+                         levels=args.levels, tune=args.tune)
 
     def start(s, x):
         if args.x0 == "nested":
@@ -513,7 +515,8 @@ def annulus(args, rates=None):
                                f"Q1 with kx=4 pi r, ky=1/(4 pi r), 4097x4096 nodes, f = N(0,1), {smoothing} "
                                f"{args.nu}/{args.nu}, F-cycle to "
                                + (f"{args.levels} levels" if args.levels else "5x4")
-                               + f", x0={'nested' if args.x0 == 'nested' else '0'}, tol 1e-10", "precision": head},
+                               + f", x0={'nested' if args.x0 == 'nested' else '0'}, tol 1e-10", "precision": head,
+                   "tune": args.tune},
         "roofline": roofline,
         "cycles": info_h.cycles,
         "rel_res": info_h.rel_res,
@@ -624,14 +627,15 @@ def batch256(args, rates=None):
 
     head = args.precision
     other = "fp64" if head == "mixed" else "mixed"
-    B = mg.BatchedSolver([(n, n) for n in ns], eps, smoother="rbgs", nu_pre=args.nu, nu_post=args.nu, precision=head)
+    B = mg.BatchedSolver([(n, n) for n in ns], eps, smoother="rbgs", nu_pre=args.nu, nu_post=args.nu, precision=head,
+                         tune=args.tune)
     wall_h, infos_h = run(B, args.steps, args.warmup)
     B.close()
     bad = [i for i, info in enumerate(infos_h) if info.status != mg.MG_OK]
     if bad:
         raise SystemExit(f"{len(bad)} batched problems did not converge (first: {bad[0]})")
     B = mg.BatchedSolver([(n, n) for n in ns], eps, smoother="rbgs", nu_pre=args.nu, nu_post=args.nu,
-                         precision=other)
+                         precision=other, tune=args.tune)
     steps_o = max(1, args.steps // 2)
     wall_o, infos_o = run(B, steps_o, 1)
     B.close()
@@ -785,7 +789,7 @@ def sphere2049(args, rates=None):
 
     def make(precision):
         return mg.Solver(n, n, kx=kxt, ky=kyt, smoother=smoother, nu_pre=args.nu, nu_post=args.nu,
-                         omega=args.omega, sor=args.sor, precision=precision, levels=args.levels)
+                         omega=args.omega, sor=args.sor, precision=precision, levels=args.levels, tune=args.tune)
 
     def run(s, steps, warmup):
         x = torch.zeros_like(rhs)
@@ -912,7 +916,7 @@ def aniso1025(args, rates=None):
 
     def make(precision):
         return [mg.Solver(n, n, eps_x=e, smoother=smoother, nu_pre=args.nu, nu_post=args.nu, omega=args.omega,
-                          sor=args.sor, precision=precision, levels=args.levels) for e in eps_list]
+                          sor=args.sor, precision=precision, levels=args.levels, tune=args.tune) for e in eps_list]
 
     def start(s, x):
         if args.x0 == "nested":

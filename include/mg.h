@@ -173,7 +173,19 @@ typedef struct {
   int32_t inner_cycles;
   int32_t coarse_op;
   int32_t adaptive_omega;
+  int32_t tune;
 } mg_options;
+
+/* tune: MG_TUNE_AUTO (0, default) lets mg_setup choose the tile shape of
+ * every fused pass and the coarse-level threshold by timing candidates on the
+ * handle's own level buffers, and caches the choices (keyed by level shape,
+ * operator, precision, smoother, device architecture and kernel-source
+ * digest) in a JSON file: $MG_TUNE_CACHE, or libmg_tune.json beside the
+ * library (MG_TUNE_CACHE=off: no cache); MG_TUNE_OFF (1) takes the fixed
+ * rule; MG_TUNE_REFRESH (2) measures again and overwrites the cache.  Every
+ * choice gives the same iterates bit for bit.  Explicit tile_mode, tile_x,
+ * tile_y or coarse_cta_nodes values are kept as given. */
+enum { MG_TUNE_AUTO = 0, MG_TUNE_OFF = 1, MG_TUNE_REFRESH = 2 };
 
 enum { MG_COARSE_DEFAULT = 0, MG_COARSE_GALERKIN = 1 };
 

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmg.so")
-SOURCES = ["mg_kernels.hip", "mg_fused.hip", "mg_api.hip"]
+SOURCES = ["mg_kernels.hip", "mg_fused.hip", "mg_api.hip", "mg_tune.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -35,10 +35,23 @@ FLAGS = [
 ]
 
 
+def source_digest() -> str:
+    """sha256 (first 16 hex digits) over the kernel sources and headers: the
+    autotuner's cached choices are keyed by it."""
+    import hashlib
+
+    d = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                d.update(name.encode() + b"\0" + f.read())
+    return d.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *srcs]
+    cmd = [HIPCC, *FLAGS, f'-DMG_SOURCE_DIGEST="{source_digest()}"', "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

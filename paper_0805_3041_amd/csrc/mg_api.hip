@@ -21,6 +21,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -28,6 +29,7 @@
 #include "mg.h"
 #include "mg_fused.h"
 #include "mg_kernels.h"
+#include "mg_tune.h"
 
 using namespace mg;
 
@@ -60,6 +62,7 @@ struct Group {
   std::vector<int> probs;  // problem index of each slot
   mg_grid grid{};
   int nlev = 0, ncu = 0;
+  int threshold = 0;  // coarse-level kernel: levels of at most this many nodes (0: those whose sub-hierarchy fits LDS)
   std::vector<LevelShape> shp;
   std::vector<double> hx, hy;
   std::vector<Level<double>> L64;  // [level * ns + slot]
@@ -111,6 +114,7 @@ struct mg_handle_s {
   std::vector<double> eps_x, eps_y;  // per problem (5-point)
   int* dcount = nullptr;             // cell coefficients: count of invalid values (setup and update)
   hipStream_t stream = nullptr;
+  int ncus = 256;                    // compute units of the device (workgroups that fill it once)
   std::string err;
 
   std::vector<Group> groups;
@@ -303,10 +307,8 @@ double relax(mg_handle h) {
 // for the defect and its restriction (pre) or 1 for the residual (post).
 int sweeps(mg_handle h, int steps) { return h->ncol == 0 ? steps : steps * h->ncol; }
 
-// Compute units of the chip (MI355X): the workgroup count that fills it once.
-constexpr long CHIP_CUS = 256;
-
 TileGeom choose_tile(mg_handle h, const Group& G, int l, int H, bool post) {
+  const long CHIP_CUS = h->ncus;  // workgroups that fill the chip once
   const LevelShape& s = G.shp[l];
   const size_t elem = h->mixed() ? sizeof(float) : sizeof(double);
   const int narr = h->ncol == 0 ? 3 : 2;
@@ -374,7 +376,7 @@ TileGeom choose_tile(mg_handle h, const Group& G, int l, int H, bool post) {
 }
 
 mg_status build_program(mg_handle h, Group& G) {
-  Gen g{h, G, h->opts.coarse_cta_nodes};
+  Gen g{h, G, G.threshold};
   std::vector<std::vector<Abs>> subs;
   G.prog.clear();
   g.host(G.prog, subs, 0, h->opts.cycle);
@@ -600,6 +602,7 @@ mg_status check_opts(const mg_options* o, int kind) {
   if (o->coarse_op != MG_COARSE_DEFAULT && o->coarse_op != MG_COARSE_GALERKIN)
     return fail(nullptr, MG_EINVAL, "coarse_op must be MG_COARSE_DEFAULT or MG_COARSE_GALERKIN");
   if (o->adaptive_omega != 0 && o->adaptive_omega != 1) return fail(nullptr, MG_EINVAL, "adaptive_omega must be 0 or 1");
+  if (o->tune < MG_TUNE_AUTO || o->tune > MG_TUNE_REFRESH) return fail(nullptr, MG_EINVAL, "bad tune mode");
   if (o->coarse_op == MG_COARSE_GALERKIN && kind == MG_COEF_CONST5 && o->smoother != MG_SMOOTH_JACOBI &&
       o->smoother != MG_SMOOTH_GS4C)
     return fail(nullptr, MG_EUNSUPPORTED,
@@ -794,6 +797,7 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
     return fail(h, MG_EINVAL, "grid " + std::to_string(grid.nx) + "x" + std::to_string(grid.ny) +
                                   " supports at most " + std::to_string(maxlev) + " levels");
   G.nlev = levels ? levels : maxlev;
+  G.threshold = h->opts.coarse_cta_nodes;
   if (G.nlev > MAX_LEVELS) return fail(h, MG_EUNSUPPORTED, "more than " + std::to_string(MAX_LEVELS) + " levels");
   int nx = grid.nx, ny = grid.ny;
   for (int l = 0; l < G.nlev; ++l) {
@@ -918,7 +922,7 @@ mg_status setup_group(mg_handle h, Group& G, const mg_coeffs* coeffs, int32_t le
     // coarse-level interpreter: own copies of the per-cell kx, ky, from which
     // the kernels of that level form its couplings (one copy when the caller
     // passes the same array for both)
-    if (!h->oned && !Gen{h, G, h->opts.coarse_cta_nodes}.small(0)) {
+    if (!h->oned && !Gen{h, G, G.threshold}.small(0)) {
       const LevelShape& sh = G.shp[0];
       const size_t nc = (size_t)ncx * (sh.py ? sh.ny : sh.ny - 1);
       const bool same = coeffs->kx == coeffs->ky;
@@ -1033,6 +1037,241 @@ mg_status check_cell_coeffs(mg_handle h, const mg_coeffs* coeffs) {
   return MG_OK;
 }
 
+// ----------------------------------------------------------------------- autotuner
+//
+// Results are bitwise independent of the tile shape of a fused pass and of
+// the level from which the single-workgroup kernel takes over, so both are
+// free to choose for speed.  For each threshold candidate (the default, one
+// more fused level, one more interpreted level) the program is built, every
+// fused pass is timed on the handle's own buffers for each candidate tile
+// (wide tiles of several heights, small tiles of several shapes, and the
+// fixed rule's choice) and the fastest is kept; then whole cycles decide the
+// threshold.  Choices are cached (mg_tune.hip) under keys that carry the
+// device architecture and the kernel-source digest.
+
+bool tiles_fixed(mg_handle h) {
+  return h->opts.tile_mode != MG_TILES_FUSED || h->opts.tile_x != 0 || h->opts.tile_y != 0;
+}
+
+std::string geom_str(const TileGeom& g) {
+  return std::to_string(g.wide) + "," + std::to_string(g.TX) + "," + std::to_string(g.TY);
+}
+
+bool geom_parse(const std::string& v, const LevelShape& s, int H, TileGeom& g) {
+  int w = 0, tx = 0, ty = 0;
+  if (std::sscanf(v.c_str(), "%d,%d,%d", &w, &tx, &ty) != 3 || tx < 2 || ty < 2) return false;
+  g = w ? wide_geom(s.nx, s.ny, ty, H) : tile_geom(s.nx, s.ny, tx, ty, H);
+  return !w || g.TX == tx;
+}
+
+std::string pass_key(mg_handle h, const Group& G, const HostOp& op, int H) {
+  const LevelShape& s = G.shp[op.level];
+  std::ostringstream k;
+  k << "pass|" << tune_identity() << "|" << (h->mixed() ? "f32" : "f64") << "|st" << stencil_kind(h) << "|b1"
+    << (stencil_kind(h) == ST9 && h->oned) << "|cells" << (G.l64(op.level, 0).kcx != nullptr) << "|col" << h->ncol
+    << "|" << (op.type == H_PRE ? "pre" : "post") << op.arg << "|nu"
+    << (op.type == H_PRE ? h->opts.nu_pre : h->opts.nu_post) << "|H" << H << "|sor" << (relax(h) != 1.0)
+    << "|aw" << h->opts.adaptive_omega << "|" << s.nx << "x" << s.ny << "p" << s.py << "|z" << G.ns << "|fine"
+    << (op.level == 0) << "|cu" << h->ncus;
+  return k.str();
+}
+
+std::string threshold_key(mg_handle h, const Group& G) {
+  std::ostringstream k;
+  k << "coarse|" << tune_identity() << "|" << (h->mixed() ? "f32" : "f64") << "|st" << stencil_kind(h) << "|b1"
+    << (stencil_kind(h) == ST9 && h->oned) << "|sm" << h->opts.smoother << "|nu" << h->opts.nu_pre << ","
+    << h->opts.nu_post << "|cy" << h->opts.cycle << "|in" << inner_cycles(h) << "|aw" << h->opts.adaptive_omega
+    << "|tm" << h->opts.tile_mode << "|" << G.shp[0].nx << "x" << G.shp[0].ny << "p" << G.shp[0].py << "|L"
+    << G.nlev << "|z" << G.ns << "|cu" << h->ncus;
+  return k.str();
+}
+
+// Candidate tiles of one fused pass (LDS within the fused-pass cap).
+std::vector<TileGeom> tile_candidates(mg_handle h, const Group& G, int l, int H, bool post) {
+  const LevelShape& s = G.shp[l];
+  auto lds = [&](const TileGeom& g) {
+    if (h->mixed()) return post ? post_lds_bytes<float>(g, h->ncol) : pre_lds_bytes<float>(g, h->ncol);
+    return post ? post_lds_bytes<double>(g, h->ncol) : pre_lds_bytes<double>(g, h->ncol);
+  };
+  std::vector<TileGeom> out;
+  out.push_back(choose_tile(h, G, l, H, post));  // the fixed rule first
+  if (2 * H < wide_width())
+    for (int ty = 8; ty <= 64; ty += 8) {
+      const TileGeom g = wide_geom(s.nx, s.ny, ty, H);
+      if (lds(g) <= FUSED_LDS_MAX && (long)g.ntx * g.nty * G.ns <= 64L * h->ncus) out.push_back(g);
+    }
+  for (int tx : {16, 32, 64, 128})
+    for (int ty : {4, 8, 16, 32}) {
+      const TileGeom g = tile_geom(s.nx, s.ny, tx, ty, H);
+      if (lds(g) <= FUSED_LDS_MAX && (long)g.ntx * g.nty * G.ns <= 64L * h->ncus) out.push_back(g);
+    }
+  return out;
+}
+
+// Average device time (us) of `reps` runs of `ops` on the handle's stream
+// after one untimed run.
+template <typename T>
+hipError_t time_ops(mg_handle h, Group& G, const std::vector<HostOp>& ops, Level<T>* dL, Level<T>* dP, T omega,
+                    int reps, double* us) {
+  hipStream_t st = h->stream;
+  hipError_t e = hipSuccess;
+  for (int r = 0; r <= reps; ++r) {
+    if (r == 1 && (e = hipEventRecord(h->ev0, st)) != hipSuccess) return e;
+    for (const HostOp& op : ops)
+      if ((e = run_op<T>(h, G, op, dL, dP, omega, st)) != hipSuccess) return e;
+  }
+  if ((e = hipEventRecord(h->ev1, st)) != hipSuccess) return e;
+  if ((e = hipEventSynchronize(h->ev1)) != hipSuccess) return e;
+  float ms = 0.f;
+  if ((e = hipEventElapsedTime(&ms, h->ev0, h->ev1)) != hipSuccess) return e;
+  *us = 1e3 * ms / reps;
+  return hipSuccess;
+}
+
+hipError_t time_pass(mg_handle h, Group& G, const HostOp& op, double* us) {
+  const std::vector<HostOp> one{op};
+  if (h->mixed()) return time_ops<float>(h, G, one, G.dL32, G.dP32, (float)relax(h), 3, us);
+  return time_ops<double>(h, G, one, G.dL64, G.dP64, relax(h), 3, us);
+}
+
+hipError_t time_cycle(mg_handle h, Group& G, double* us) {
+  hipStream_t st = h->stream;
+  hipError_t e = hipSuccess;
+  for (int r = 0; r <= 3; ++r) {
+    if (r == 1 && (e = hipEventRecord(h->ev0, st)) != hipSuccess) return e;
+    if ((e = enqueue_cycle(h, G, st)) != hipSuccess) return e;
+  }
+  if ((e = hipEventRecord(h->ev1, st)) != hipSuccess) return e;
+  if ((e = hipEventSynchronize(h->ev1)) != hipSuccess) return e;
+  float ms = 0.f;
+  if ((e = hipEventElapsedTime(&ms, h->ev0, h->ev1)) != hipSuccess) return e;
+  *us = 1e3 * ms / 3;
+  return hipSuccess;
+}
+
+// Tile of every fused pass of the group's current program: cached, or the
+// fastest candidate (the rule's choice unless another is 2 % faster).
+mg_status tune_tiles(mg_handle h, Group& G) {
+  const bool refresh = h->opts.tune == MG_TUNE_REFRESH;
+  for (const HostOp& op : G.prog) {
+    if (op.type != H_PRE && op.type != H_POST) continue;
+    const bool post = op.type == H_POST;
+    TileGeom& slot = post ? G.gpost[op.level] : G.gpre[op.level];
+    const int H = slot.H;
+    const std::string key = pass_key(h, G, op, H);
+    TileGeom g{};
+    const std::string v = refresh ? std::string() : tune_lookup(key);
+    if (!v.empty() && geom_parse(v, G.shp[op.level], H, g)) {
+      slot = g;
+      continue;
+    }
+    const std::vector<TileGeom> cands = tile_candidates(h, G, op.level, H, post);
+    TileGeom best = cands[0];
+    double best_us = 0.0;
+    for (size_t c = 0; c < cands.size(); ++c) {
+      slot = cands[c];
+      double us = 0.0;
+      HIPCHK(h, time_pass(h, G, op, &us));
+      if (c == 0 || us < best_us * (best.TX == cands[0].TX && best.TY == cands[0].TY && best.wide == cands[0].wide
+                                        ? 0.98 : 1.0)) {
+        best = cands[c];
+        best_us = us;
+      }
+    }
+    slot = best;
+    tune_store(key, geom_str(best));
+  }
+  return MG_OK;
+}
+
+// Tiles and coarse threshold of every group (setup, after the descriptors
+// and partial-sum buffers exist).  The finest FP64 level borrows two
+// scratch arrays for the caller's x and b; the stopping states are set so
+// that no candidate run stops early, and reset by the next solve.
+mg_status tune_handle(mg_handle h) {
+  if (h->opts.tune == MG_TUNE_OFF) return MG_OK;
+  const bool tile_free = !tiles_fixed(h);
+  const bool thr_free = h->opts.coarse_cta_nodes == 0;
+  if (!tile_free && !thr_free) return MG_OK;
+  hipStream_t st = h->stream;
+  std::vector<SolveState> run(h->nprob);
+  for (int p = 0; p < h->nprob; ++p) {
+    run[p] = SolveState{};
+    run[p].r0 = 1e300;  // never converged (tol < 0), never diverged
+    run[p].tol = -1.0;
+    run[p].partial = h->dpartial[p];
+  }
+  HIPCHK(h, hipMemcpyAsync(h->dstate, run.data(), run.size() * sizeof(SolveState), hipMemcpyHostToDevice, st));
+  for (Group& G : h->groups) {
+    const LevelShape& s0 = G.shp[0];
+    const size_t n0 = (size_t)s0.nx * s0.ny;
+    double *tx = nullptr, *tb = nullptr;
+    HIPCHK(h, hipMalloc(&tx, n0 * sizeof(double)));
+    hipError_t e = hipMalloc(&tb, n0 * sizeof(double));
+    if (e == hipSuccess) e = hipMemsetAsync(tx, 0, n0 * sizeof(double), st);
+    if (e == hipSuccess) e = hipMemsetAsync(tb, 0, n0 * sizeof(double), st);
+    mg_status res = e == hipSuccess ? MG_OK : fail(h, MG_EDEVICE, std::string("tuning scratch: ") + hipGetErrorString(e));
+    if (res == MG_OK) {
+      for (int sl = 0; sl < G.ns; ++sl) {
+        G.l64(0, sl).x = tx;
+        G.l64(0, sl).b = tb;
+      }
+      res = upload_descriptors(h, G);
+    }
+    // threshold candidates: the default, one more fused level, one more
+    // level in the single-workgroup kernel (global memory)
+    std::vector<int> ths{0};
+    if (res == MG_OK && thr_free && h->groups.size() == 1) {
+      Gen g0{h, G, 0};
+      int top = 0;
+      while (top < G.nlev - 1 && !g0.small(top)) ++top;
+      const long ntop = (long)G.shp[top].nx * G.shp[top].ny;
+      if (top < G.nlev - 1) ths.push_back((int)(ntop - 1));
+      // (not the finest level when it forms its couplings from cells: the
+      // single-workgroup kernel reads bands, equal only up to rounding)
+      if (top > 0 && !(top == 1 && G.l64(0, 0).kcx))
+        ths.push_back((int)((long)G.shp[top - 1].nx * G.shp[top - 1].ny));
+      const std::string cached = h->opts.tune == MG_TUNE_REFRESH ? std::string() : tune_lookup(threshold_key(h, G));
+      if (!cached.empty()) ths.assign(1, std::atoi(cached.c_str()));
+    } else if (!thr_free) {
+      ths.assign(1, h->opts.coarse_cta_nodes);
+    }
+    int best_th = ths[0];
+    double best_us = 0.0;
+    for (size_t c = 0; c < ths.size() && res == MG_OK; ++c) {
+      G.threshold = ths[c];
+      res = build_program(h, G);
+      if (res == MG_OK && tile_free) res = tune_tiles(h, G);
+      if (res != MG_OK || ths.size() == 1) break;
+      double us = 0.0;
+      hipError_t te = time_cycle(h, G, &us);
+      if (te != hipSuccess) {
+        res = fail(h, MG_EDEVICE, std::string("tuning: ") + hipGetErrorString(te));
+        break;
+      }
+      if (c == 0 || us < best_us * (best_th == ths[0] ? 0.98 : 1.0)) {
+        best_th = ths[c];
+        best_us = us;
+      }
+    }
+    if (res == MG_OK && ths.size() > 1) {
+      tune_store(threshold_key(h, G), std::to_string(best_th));
+      G.threshold = best_th;
+      res = build_program(h, G);
+      if (res == MG_OK && tile_free) res = tune_tiles(h, G);  // cached by now
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(tx);
+    (void)hipFree(tb);
+    for (int sl = 0; sl < G.ns; ++sl) G.l64(0, sl).x = G.l64(0, sl).b = nullptr;
+    if (res != MG_OK) return res;
+    res = upload_descriptors(h, G);
+    if (res != MG_OK) return res;
+  }
+  HIPCHK(h, hipMemsetAsync(h->dstate, 0, (size_t)h->nprob * sizeof(SolveState), st));
+  return sync_check(h);
+}
+
 // Common part of mg_setup and mg_setup_batched after the groups are formed.
 mg_status setup_handle(mg_handle h, const mg_coeffs* coeffs, int32_t levels) {
   h->galerkin5 = h->kind == MG_COEF_CONST5 && h->opts.coarse_op == MG_COARSE_GALERKIN;
@@ -1041,6 +1280,7 @@ mg_status setup_handle(mg_handle h, const mg_coeffs* coeffs, int32_t levels) {
   h->line_jac = line_jacobi(h->opts.smoother);
   h->ncol = (h->opts.smoother == MG_SMOOTH_JACOBI || h->line) ? 0 : (h->opts.smoother == MG_SMOOTH_RBGS ? 2 : 4);
   h->stream = static_cast<hipStream_t>(h->opts.stream);
+  h->ncus = device_cus();
   HIPCHK(h, hipEventCreate(&h->ev0));
   HIPCHK(h, hipEventCreate(&h->ev1));
   HIPCHK(h, h->dalloc(&h->dstate, (size_t)h->nprob * sizeof(SolveState)));
@@ -1086,10 +1326,12 @@ mg_status setup_handle(mg_handle h, const mg_coeffs* coeffs, int32_t levels) {
   }
   // partial sums of a norm reduction: one per workgroup of the norm kernel or
   // of the finest post-pass when it carries the stopping test
+  // (the autotuner's candidates included: at most one workgroup per 16 x 4 nodes)
   h->dpartial.assign(h->nprob, nullptr);
   for (const Group& G : h->groups) {
     size_t nparts = MAX_NORM_BLOCKS;
-    if (G.norm_fused) nparts = std::max(nparts, (size_t)G.gpost[0].ntx * G.gpost[0].nty);
+    nparts = std::max(nparts, (size_t)G.gpost[0].ntx * G.gpost[0].nty);
+    nparts = std::max(nparts, (size_t)((G.shp[0].nx + 15) / 16) * ((G.shp[0].ny + 3) / 4));
     for (int s = 0; s < G.ns; ++s) HIPCHK(h, h->dalloc(&h->dpartial[G.probs[s]], nparts * sizeof(double)));
   }
   for (Group& G : h->groups) {
@@ -1097,6 +1339,8 @@ mg_status setup_handle(mg_handle h, const mg_coeffs* coeffs, int32_t levels) {
     if (s != MG_OK) return s;
   }
   mg_status s = sync_check(h);
+  if (s != MG_OK) return s;
+  s = tune_handle(h);
   if (s != MG_OK) return s;
   return build_graphs(h);
 }

@@ -57,7 +57,8 @@ class mg_options(ctypes.Structure):
                 ("nu_post", ctypes.c_int32), ("omega", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("coarse_cta_nodes", ctypes.c_int32), ("tile_mode", ctypes.c_int32), ("tile_x", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("stream", ctypes.c_void_p), ("sor", ctypes.c_double),
-                ("inner_cycles", ctypes.c_int32), ("coarse_op", ctypes.c_int32), ("adaptive_omega", ctypes.c_int32)]
+                ("inner_cycles", ctypes.c_int32), ("coarse_op", ctypes.c_int32), ("adaptive_omega", ctypes.c_int32),
+                ("tune", ctypes.c_int32)]
 
 
 class mg_info(ctypes.Structure):
@@ -310,15 +311,17 @@ TILE_MODES = {"fused": MG_TILES_FUSED, "per_op": MG_TILES_PER_OP, "narrow": MG_T
 
 
 COARSE_OPS = {"default": MG_COARSE_DEFAULT, "galerkin": MG_COARSE_GALERKIN}
+MG_TUNE_AUTO, MG_TUNE_OFF, MG_TUNE_REFRESH = 0, 1, 2
+TUNE_MODES = {"auto": MG_TUNE_AUTO, "off": MG_TUNE_OFF, "refresh": MG_TUNE_REFRESH}
 
 
 def make_options(cycle="F", smoother="rbgs", nu_pre=2, nu_post=2, omega=0.8, precision="fp64",
                  coarse_cta_nodes=0, tile_mode="fused", tile_x=0, tile_y=0, stream=None, sor=1.0,
-                 inner_cycles=1, coarse_op="default", adaptive_omega=False) -> mg_options:
+                 inner_cycles=1, coarse_op="default", adaptive_omega=False, tune="auto") -> mg_options:
     return mg_options(CYCLES[cycle], SMOOTHERS[smoother], int(nu_pre), int(nu_post), float(omega),
                       PRECISIONS[precision], int(coarse_cta_nodes), TILE_MODES[tile_mode], int(tile_x), int(tile_y),
                       _stream_ptr(stream), float(sor), int(inner_cycles), COARSE_OPS[coarse_op],
-                      1 if adaptive_omega else 0)
+                      1 if adaptive_omega else 0, TUNE_MODES[tune])
 
 
 class Solver:

@@ -86,6 +86,8 @@ def _setup(mg, grid, coeffs, levels=0, **opt):
     dict(opt=dict(inner_cycles=-1)),
     dict(opt=dict(coarse_op=2)),
     dict(opt=dict(adaptive_omega=2)),
+    dict(opt=dict(tune=3)),
+    dict(opt=dict(tune=-1)),
     dict(opt=dict(adaptive_omega=-1)),
     dict(opt=dict(coarse_op=1), status=-4),                 # Galerkin 5-point levels with red-black GS
     dict(opt=dict(coarse_op=1, smoother=6), status=-4),     # ... or with a line smoother

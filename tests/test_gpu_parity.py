@@ -424,7 +424,7 @@ def test_one_tile_per_cu_on_the_finest_level(precision):
     x0 = torch.tensor(W.uniform_field(n, n, 22), device="cuda")
     out = []
     for mode in ("per_op", "fused"):
-        s = p.solver(precision=precision, tile_mode=mode)
+        s = p.solver(precision=precision, tile_mode=mode, tune="off")
         try:
             if mode == "fused":
                 for which in (0, 1):
