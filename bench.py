@@ -630,6 +630,7 @@ def batch256(args, rates=None):
     B = mg.BatchedSolver([(n, n) for n in ns], eps, smoother="rbgs", nu_pre=args.nu, nu_post=args.nu, precision=head,
                          tune=args.tune)
     wall_h, infos_h = run(B, args.steps, args.warmup)
+    schedule = B.schedule()
     B.close()
     bad = [i for i, info in enumerate(infos_h) if info.status != mg.MG_OK]
     if bad:
@@ -661,6 +662,7 @@ def batch256(args, rates=None):
                                f"{args.nu}/{args.nu}, F-cycle, x0=0, tol 1e-10", "precision": head},
         "roofline": _roofline_single(1025, 1e-3, head, args.nu),
         "cycles": {"min": min(cycles), "max": max(cycles), "sum": sum(cycles)},
+        "schedule": schedule,
         f"value_{other}": unknowns * steps_o / wall_o,
         "speedup_mixed_over_fp64": ((wall_o / steps_o) / (wall_h / args.steps)) if head == "mixed"
         else ((wall_h / args.steps) / (wall_o / steps_o)),

@@ -183,8 +183,10 @@ typedef struct {
  * digest) in a JSON file: $MG_TUNE_CACHE, or libmg_tune.json beside the
  * library (MG_TUNE_CACHE=off: no cache); MG_TUNE_OFF (1) takes the fixed
  * rule; MG_TUNE_REFRESH (2) measures again and overwrites the cache.  Every
- * choice gives the same iterates bit for bit.  Explicit tile_mode, tile_x,
- * tile_y or coarse_cta_nodes values are kept as given. */
+ * choice gives the same iterates bit for bit (with adaptive_omega the
+ * threshold is not tuned: the single-workgroup kernel orders the level-wide
+ * sums of omega_l differently).  Explicit tile_mode, tile_x, tile_y or
+ * coarse_cta_nodes values are kept as given. */
 enum { MG_TUNE_AUTO = 0, MG_TUNE_OFF = 1, MG_TUNE_REFRESH = 2 };
 
 enum { MG_COARSE_DEFAULT = 0, MG_COARSE_GALERKIN = 1 };
@@ -314,6 +316,15 @@ mg_status mg_solve_batched(mg_handle h, const double* const* rhs, double* const*
  * and mg_residual's. */
 mg_status mg_residual_noalloc(const mg_grid* grid, const mg_coeffs* coeffs, const double* rhs, const double* x,
                               double* r, double* norm2, void* stream);
+
+/* How a handle runs its cycle, written to the host array out[4]: out[0]
+ * merged schedules (batched problems whose level chains end alike run one
+ * schedule in which each launch covers every problem on a level, the smaller
+ * problems taking part in the recursive call that is their own cycle),
+ * out[1] grid groups inside them, out[2] groups running their own cycle (a
+ * parallel graph branch each), out[3] launches in the graph of one cycle.
+ * Single-problem handles report 0, 0, 1 and their launch count. */
+mg_status mg_batch_schedule(mg_handle h, int32_t* out);
 
 /* Frees everything the handle owns (never caller memory).  NULL is accepted. */
 mg_status mg_destroy(mg_handle h);

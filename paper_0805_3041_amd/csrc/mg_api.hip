@@ -16,8 +16,10 @@
 // each masked once its own stopping test is met.  The groups of a batched
 // handle are captured as parallel branches of one graph.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -39,7 +41,10 @@ thread_local std::string g_thread_err;
 
 constexpr int MAX_BATCH = 4096;
 
-enum HostOpType { H_COLOR = 0, H_JACOBI, H_COPY, H_DR, H_PROLONG, H_COARSE, H_SUB, H_PRE, H_POST, H_LINE, H_OMEGA };
+enum HostOpType {
+  H_COLOR = 0, H_JACOBI, H_COPY, H_DR, H_PROLONG, H_COARSE, H_SUB, H_PRE, H_POST, H_LINE, H_OMEGA,
+  H_NORM  // merged batched schedule: stopping test of the problems whose cycle just ended
+};
 
 struct HostOp {
   int type, level, arg;
@@ -91,6 +96,40 @@ struct Group {
   const Level<double>& l64(int l, int s) const { return L64[(size_t)l * ns + s]; }
 };
 
+// Batched problems whose level chains end alike (each group's level shapes
+// are the last ones of the deepest group's) run one merged schedule: the
+// deepest group's cycle, in which every smaller group takes part in exactly
+// the recursive call that is its own cycle (the first call on its finest
+// level), each launch covering every problem on that level through a table
+// of their level descriptors.
+struct MOp {
+  int type = 0, level = 0, arg = 0;  // as HostOp; level counts on the deepest chain
+  int fine = 0;                      // the participants are on their finest level
+  int tab = -1, ctab = -1;           // descriptor tables of `level` and `level + 1` (H_SUB: problem-major)
+  int n = 0;                         // participants
+  int* dbeg = nullptr;               // H_SUB: per participant, the sub-program's begin and count
+  int* dcnt = nullptr;
+  double** dchol = nullptr;          // H_SUB: per participant, its coarsest inverse
+  TileGeom g{};                      // H_PRE, H_POST
+};
+
+struct MTab {
+  std::vector<std::array<int, 3>> mem;  // (group, slot, level of that group) per entry
+  Level<double>* d64 = nullptr;
+  Level<float>* d32 = nullptr;
+};
+
+struct Merge {
+  std::vector<int> groups;  // deepest first
+  std::vector<int> off;     // per group: level of the deepest chain holding its finest level
+  int nlev = 0;
+  std::vector<MOp> prog;
+  std::vector<MTab> tabs;
+  std::map<std::string, int> tab_index;
+  DOp* dprog = nullptr;     // sub-programs, levels relative to the sub-cycle's top
+  hipStream_t branch = nullptr;
+};
+
 }  // namespace
 
 struct mg_handle_s {
@@ -118,6 +157,8 @@ struct mg_handle_s {
   std::string err;
 
   std::vector<Group> groups;
+  std::vector<Merge> merges;      // batched: merged schedules
+  std::vector<int> standalone;    // batched: groups that run their own cycle (branch)
 
   // device memory
   std::vector<void*> allocs;
@@ -133,6 +174,7 @@ struct mg_handle_s {
   // one cycle and eight cycles captured as graphs (kernel nodes only)
   hipStream_t cap = nullptr;
   hipGraphExec_t g1 = nullptr, g8 = nullptr;
+  int graph_nodes = 0;  // nodes (launches) of the one-cycle graph
 
   bool mixed() const { return opts.precision == MG_PREC_MIXED; }
 
@@ -307,9 +349,8 @@ double relax(mg_handle h) {
 // for the defect and its restriction (pre) or 1 for the residual (post).
 int sweeps(mg_handle h, int steps) { return h->ncol == 0 ? steps : steps * h->ncol; }
 
-TileGeom choose_tile(mg_handle h, const Group& G, int l, int H, bool post) {
+TileGeom choose_tile_for(mg_handle h, const LevelShape& s, int ns, int H, bool post) {
   const long CHIP_CUS = h->ncus;  // workgroups that fill the chip once
-  const LevelShape& s = G.shp[l];
   const size_t elem = h->mixed() ? sizeof(float) : sizeof(double);
   const int narr = h->ncol == 0 ? 3 : 2;
   auto bytes = [&](int TX, int TY) {
@@ -322,7 +363,7 @@ TileGeom choose_tile(mg_handle h, const Group& G, int l, int H, bool post) {
   int TX = h->opts.tile_x > 0 ? h->opts.tile_x : 64;
   int TY = h->opts.tile_y > 0 ? h->opts.tile_y : 32;
   // tiles over all of the group's problems
-  auto ntiles = [&](int tx, int ty) { return (long)G.ns * ((s.nx + tx - 1) / tx) * ((s.ny + ty - 1) / ty); };
+  auto ntiles = [&](int tx, int ty) { return (long)ns * ((s.nx + tx - 1) / tx) * ((s.ny + ty - 1) / ty); };
   // wide tiles (fixed region width, output width WW - 2H) wherever they
   // still give the chip enough workgroups; at most WIDE_LDS_TARGET of LDS so
   // that two workgroups share a CU
@@ -373,6 +414,10 @@ TileGeom choose_tile(mg_handle h, const Group& G, int l, int H, bool post) {
   while (bytes(TX, TY) > FUSED_LDS_MAX && TY > 2) TY >>= 1;
   while (bytes(TX, TY) > FUSED_LDS_MAX && TX > 2) TX >>= 1;
   return tile_geom(s.nx, s.ny, TX, TY, H);
+}
+
+TileGeom choose_tile(mg_handle h, const Group& G, int l, int H, bool post) {
+  return choose_tile_for(h, G.shp[l], G.ns, H, post);
 }
 
 mg_status build_program(mg_handle h, Group& G) {
@@ -492,37 +537,436 @@ hipError_t enqueue_cycle(mg_handle h, const Group& G, hipStream_t st) {
   return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, G.dL32, stencil_kind(h), h->oned, G.ns, st);
 }
 
+// ----------------------------------------------------------------------- merged batched schedule
+
+// Groups, by chain: a group joins the first merge whose deepest chain ends
+// with the group's level shapes (same shapes level by level from its finest
+// down); groups that fit no merge, and merges of one group, run their own
+// cycles.  At most 32 groups per merge (participant sets are bit masks).
+void form_merges(mg_handle h) {
+  h->merges.clear();
+  h->standalone.clear();
+  if (!h->batched || h->groups.size() < 2) {
+    for (int g = 0; g < (int)h->groups.size(); ++g) h->standalone.push_back(g);
+    return;
+  }
+  std::vector<int> order(h->groups.size());
+  for (int g = 0; g < (int)order.size(); ++g) order[g] = g;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return h->groups[a].nlev > h->groups[b].nlev; });
+  auto ends_with = [&](const Group& D, const Group& G) {
+    if (G.nlev > D.nlev) return false;
+    const int o = D.nlev - G.nlev;
+    for (int k = 0; k < G.nlev; ++k) {
+      const LevelShape &a = D.shp[o + k], &b = G.shp[k];
+      if (a.nx != b.nx || a.ny != b.ny || a.py != b.py) return false;
+    }
+    return true;
+  };
+  for (int g : order) {
+    bool placed = false;
+    for (Merge& M : h->merges)
+      if (M.groups.size() < 32 && ends_with(h->groups[M.groups[0]], h->groups[g])) {
+        M.groups.push_back(g);
+        M.off.push_back(M.nlev - h->groups[g].nlev);
+        placed = true;
+        break;
+      }
+    if (!placed) {
+      Merge M;
+      M.groups = {g};
+      M.off = {0};
+      M.nlev = h->groups[g].nlev;
+      h->merges.push_back(M);
+    }
+  }
+  std::vector<Merge> keep;
+  for (Merge& M : h->merges) {
+    if (M.groups.size() == 1)
+      h->standalone.push_back(M.groups[0]);
+    else
+      keep.push_back(M);
+  }
+  h->merges.swap(keep);
+}
+
+// Table of the participants in `set` (bit k: group M.groups[k]) on deepest-
+// chain level l: level-major (one descriptor each) or, for the coarse-level
+// kernel, problem-major (the levels from l down to the coarsest each).
+int merge_table(Merge& M, const std::vector<Group>& groups, uint32_t set, int l, bool pm) {
+  const std::string key = std::to_string(set) + "|" + std::to_string(l) + "|" + (pm ? "p" : "l");
+  auto it = M.tab_index.find(key);
+  if (it != M.tab_index.end()) return it->second;
+  MTab t;
+  for (int k = 0; k < (int)M.groups.size(); ++k) {
+    if (!((set >> k) & 1)) continue;
+    const Group& G = groups[M.groups[k]];
+    const int ll = l - M.off[k];
+    for (int sl = 0; sl < G.ns; ++sl) {
+      if (pm)
+        for (int q = ll; q < G.nlev; ++q) t.mem.push_back({M.groups[k], sl, q});
+      else
+        t.mem.push_back({M.groups[k], sl, ll});
+    }
+  }
+  M.tabs.push_back(t);
+  M.tab_index[key] = (int)M.tabs.size() - 1;
+  return (int)M.tabs.size() - 1;
+}
+
+int participants(const Merge& M, const std::vector<Group>& groups, uint32_t set) {
+  int n = 0;
+  for (int k = 0; k < (int)M.groups.size(); ++k)
+    if ((set >> k) & 1) n += groups[M.groups[k]].ns;
+  return n;
+}
+
+// Walks the recursive cycle on the deepest chain (as Gen::host does) with
+// the set of participating groups; a group joins the first call on its
+// finest level.  Sub-cycles become H_SUB ops with their own program.
+struct MergeGen {
+  mg_handle h;
+  Merge& M;
+  const Gen& gen;  // on the deepest group
+  std::vector<std::vector<Abs>>& subs;
+  std::vector<uint32_t> sub_set;
+
+  uint32_t joiners(int l) const {
+    uint32_t m = 0;
+    for (int k = 0; k < (int)M.off.size(); ++k)
+      if (M.off[k] == l) m |= 1u << k;
+    return m;
+  }
+  void push(int type, int l, int arg, uint32_t set, int fine) {
+    if (!set) return;
+    MOp op;
+    op.type = type;
+    op.level = l;
+    op.arg = arg;
+    op.fine = fine;
+    op.n = (int)set;  // the set for now; replaced by the participant count when the tables are built
+    M.prog.push_back(op);
+  }
+  void walk(int l, int kind, uint32_t active, bool lead) {
+    const uint32_t fine = active & joiners(l), inner = active & ~fine;
+    if (gen.small(l) || l == M.nlev - 1) {
+      // groups whose finest level lies below this one run their own cycle,
+      // which this call's program contains, as a launch of their own
+      if (lead)
+        for (int t = l + 1; t < M.nlev; ++t) {
+          const uint32_t js = joiners(t);
+          if (!js) continue;
+          std::vector<Abs> own;
+          gen.expand(own, t, kind);
+          subs.push_back(own);
+          sub_set.push_back(js);
+          push(H_SUB, t, (int)subs.size() - 1, js, 0);
+          push(H_NORM, t, 0, js, 1);
+        }
+      std::vector<Abs> body;
+      gen.expand(body, l, kind);
+      if (!M.prog.empty() && M.prog.back().type == H_SUB && M.prog.back().level == l &&
+          sub_set[M.prog.back().arg] == active) {
+        std::vector<Abs>& prev = subs[M.prog.back().arg];  // F then V on the same level and set: one launch
+        for (const Abs& a : body)
+          if (!(a.type == H_COARSE && !prev.empty() && prev.back().type == H_COARSE)) prev.push_back(a);
+      } else {
+        subs.push_back(body);
+        sub_set.push_back(active);
+        push(H_SUB, l, (int)subs.size() - 1, active, 0);
+      }
+      push(H_NORM, l, 0, fine, 1);
+      return;
+    }
+    const bool fused = h->opts.tile_mode != MG_TILES_PER_OP;
+    if (fused) {
+      push(H_PRE, l, 0, fine, 1);
+      push(H_PRE, l, 0, inner, 0);
+    } else {
+      std::vector<Abs> tmp;
+      gen.smooth(tmp, l, h->opts.nu_pre);
+      for (const Abs& a : tmp) push(a.type, l, a.arg, active, 0);
+      push(H_DR, l, 0, active, 0);
+    }
+    // groups join only the leading call on their finest level (their cycle)
+    const uint32_t next = lead ? (active | joiners(l + 1)) : active;
+    if (kind == MG_CYCLE_F) {
+      walk(l + 1, MG_CYCLE_F, next, lead);
+      walk(l + 1, MG_CYCLE_V, active, false);
+    } else if (kind == MG_CYCLE_W) {
+      walk(l + 1, MG_CYCLE_W, next, lead);
+      walk(l + 1, MG_CYCLE_W, active, false);
+    } else {
+      walk(l + 1, MG_CYCLE_V, next, lead);
+    }
+    if (h->opts.adaptive_omega) push(H_OMEGA, l, fused ? 1 : 0, active, 0);
+    if (fused) {
+      push(H_POST, l, POST_PLAIN, fine, 1);
+      push(H_POST, l, POST_PLAIN, inner, 0);
+      push(H_NORM, l, 1, fine, 1);
+      return;
+    }
+    push(H_PROLONG, l, h->opts.adaptive_omega ? 1 : 0, active, 0);
+    std::vector<Abs> tmp;
+    gen.smooth(tmp, l, h->opts.nu_post);
+    for (const Abs& a : tmp) push(a.type, l, a.arg, active, 0);
+    push(H_NORM, l, 0, fine, 1);
+  }
+};
+
+template <typename T>
+Level<T>* table_ptr(const MTab& t);
+template <>
+Level<double>* table_ptr<double>(const MTab& t) { return t.d64; }
+template <>
+Level<float>* table_ptr<float>(const MTab& t) { return t.d32; }
+
+// Host copies of a table's descriptors, from the groups' current ones.
+template <typename T>
+std::vector<Level<T>> table_rows(mg_handle h, const MTab& t) {
+  std::vector<Level<T>> rows(t.mem.size());
+  for (size_t e = 0; e < t.mem.size(); ++e) {
+    const Group& G = h->groups[t.mem[e][0]];
+    if constexpr (std::is_same<T, double>::value)
+      rows[e] = G.l64(t.mem[e][2], t.mem[e][1]);
+    else
+      rows[e] = G.L32[(size_t)t.mem[e][2] * G.ns + t.mem[e][1]];
+  }
+  return rows;
+}
+
+mg_status upload_merge_tables(mg_handle h) {
+  for (Merge& M : h->merges)
+    for (MTab& t : M.tabs) {
+      const std::vector<Level<double>> r64 = table_rows<double>(h, t);
+      HIPCHK(h, hipMemcpyAsync(t.d64, r64.data(), r64.size() * sizeof(Level<double>), hipMemcpyHostToDevice, h->stream));
+      if (h->mixed()) {
+        const std::vector<Level<float>> r32 = table_rows<float>(h, t);
+        HIPCHK(h, hipMemcpyAsync(t.d32, r32.data(), r32.size() * sizeof(Level<float>), hipMemcpyHostToDevice, h->stream));
+      }
+    }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return MG_OK;
+}
+
+// The merged program of every merge: ops, descriptor tables, sub-programs
+// (levels relative to the sub-cycle's top) and tile shapes.
+mg_status build_merges(mg_handle h) {
+  form_merges(h);
+  for (Merge& M : h->merges) {
+    const Group& D = h->groups[M.groups[0]];
+    Gen gen{h, D, D.threshold};
+    std::vector<std::vector<Abs>> subs;
+    MergeGen mg{h, M, gen, subs, {}};
+    M.prog.clear();
+    mg.walk(0, h->opts.cycle, mg.joiners(0), true);
+    // tables, participant counts, tile shapes
+    std::vector<DOp> flat;
+    for (MOp& op : M.prog) {
+      const uint32_t set = (uint32_t)op.n;
+      op.n = participants(M, h->groups, set);
+      if (op.type == H_SUB) {
+        op.tab = merge_table(M, h->groups, set, op.level, true);
+        // the sub-program with levels counted from op.level
+        const std::vector<Abs>& body = subs[op.arg];
+        const int b = (int)flat.size();
+        for (const Abs& a : body) {
+          int t = OP_COLOR;
+          switch (a.type) {
+            case H_COLOR: t = OP_COLOR; break;
+            case H_JACOBI: t = OP_JACOBI; break;
+            case H_COPY: t = OP_COPY; break;
+            case H_DR: t = OP_DR; break;
+            case H_PROLONG: t = OP_PROLONG; break;
+            case H_COARSE: t = OP_COARSE; break;
+            case H_LINE: t = OP_LINE; break;
+            case H_OMEGA: t = OP_OMEGA; break;
+          }
+          flat.push_back({t, a.level - op.level, a.arg, 0});
+        }
+        std::vector<int> beg(op.n, b), cnt(op.n, (int)body.size());
+        std::vector<double*> chol;  // one per participant: the first entry of its levels
+        for (int k = 0; k < (int)M.groups.size(); ++k)
+          if ((set >> k) & 1)
+            for (int sl = 0; sl < h->groups[M.groups[k]].ns; ++sl) chol.push_back(h->groups[M.groups[k]].cinv[sl]);
+        HIPCHK(h, h->dalloc(&op.dbeg, beg.size() * sizeof(int)));
+        HIPCHK(h, h->dalloc(&op.dcnt, cnt.size() * sizeof(int)));
+        HIPCHK(h, h->dalloc(&op.dchol, chol.size() * sizeof(double*)));
+        HIPCHK(h, hipMemcpyAsync(op.dbeg, beg.data(), beg.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(op.dcnt, cnt.data(), cnt.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(op.dchol, chol.data(), chol.size() * sizeof(double*), hipMemcpyHostToDevice,
+                                 h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        continue;
+      }
+      op.tab = merge_table(M, h->groups, set, op.level, false);
+      if (op.type == H_PRE || op.type == H_POST || op.type == H_DR || op.type == H_PROLONG || op.type == H_OMEGA)
+        op.ctab = merge_table(M, h->groups, set, op.level + 1, false);
+      if (op.type == H_PRE)
+        op.g = choose_tile_for(h, D.shp[op.level], op.n, sweeps(h, h->opts.nu_pre) + 2, false);
+      if (op.type == H_POST)
+        op.g = choose_tile_for(h, D.shp[op.level], op.n,
+                               sweeps(h, h->opts.nu_post) + (op.fine && !h->mixed() ? 1 : 0), true);
+    }
+    if (std::getenv("MG_DEBUG_SCHEDULE")) {
+      static const char* names[] = {"COLOR", "JACOBI", "COPY", "DR", "PROLONG", "COARSE", "SUB", "PRE",
+                                    "POST", "LINE", "OMEGA", "NORM"};
+      std::fprintf(stderr, "merged schedule: %zu groups, deepest %dx%d, %d levels\n", M.groups.size(), D.shp[0].nx,
+                   D.shp[0].ny, M.nlev);
+      for (size_t k = 0; k < M.groups.size(); ++k)
+        std::fprintf(stderr, "  group %d (%dx%d, %d slots) joins at level %d\n", M.groups[k],
+                     h->groups[M.groups[k]].shp[0].nx, h->groups[M.groups[k]].shp[0].ny, h->groups[M.groups[k]].ns,
+                     M.off[k]);
+      for (const MOp& op : M.prog)
+        std::fprintf(stderr, "  %-7s level %d arg %d fine %d n %d tab %d ctab %d tile %d,%d,%d H %d\n",
+                     names[op.type], op.level, op.arg, op.fine, op.n, op.tab, op.ctab, op.g.wide, op.g.TX, op.g.TY,
+                     op.g.H);
+    }
+    if (!flat.empty()) {
+      HIPCHK(h, h->dalloc(&M.dprog, flat.size() * sizeof(DOp)));
+      HIPCHK(h, hipMemcpyAsync(M.dprog, flat.data(), flat.size() * sizeof(DOp), hipMemcpyHostToDevice, h->stream));
+    }
+    for (MTab& t : M.tabs) {
+      HIPCHK(h, h->dalloc(&t.d64, t.mem.size() * sizeof(Level<double>)));
+      if (h->mixed()) HIPCHK(h, h->dalloc(&t.d32, t.mem.size() * sizeof(Level<float>)));
+    }
+  }
+  return upload_merge_tables(h);
+}
+
+// One merged op (inner: the FP32 cycle's number within a mixed outer step).
+template <typename T>
+hipError_t run_mop(mg_handle h, const Merge& M, const MOp& op, T omega, bool last_inner, hipStream_t st) {
+  const Group& D = h->groups[M.groups[0]];
+  const LevelShape& s = D.shp[op.level];
+  Level<T>* Ls = table_ptr<T>(M.tabs[op.tab]);
+  Level<T>* Cs = op.ctab >= 0 ? table_ptr<T>(M.tabs[op.ctab]) : nullptr;
+  const int kind = stencil_kind(h);
+  switch (op.type) {
+    case H_COLOR: return launch_colour<T>(Ls, s, op.arg, h->ncol, omega, op.n, st);
+    case H_JACOBI: return launch_jacobi<T>(Ls, s, op.arg, omega, op.n, st);
+    case H_COPY: return launch_copy<T>(Ls, s, op.n, st);
+    case H_DR: return launch_dr<T>(Ls, Cs, D.shp[op.level + 1], op.n, st);
+    case H_PROLONG: return launch_prolong<T>(Ls, Cs, s, op.arg, op.n, st);
+    case H_OMEGA: return launch_energy<T>(Ls, Cs, s, op.arg, kind, op.n, st);
+    case H_PRE:
+      return launch_pre<T>(Ls, Cs, op.g, h->opts.nu_pre, h->ncol, omega, kind, h->oned, op.fine != 0, op.n, st);
+    case H_POST: {
+      int mode = POST_PLAIN;
+      if (op.fine) mode = h->mixed() ? (last_inner ? POST_MIXED : POST_PLAIN) : POST_NORM;
+      const Level<double>* X64 = op.fine ? M.tabs[op.tab].d64 : nullptr;
+      return launch_post<T>(Ls, Cs, op.g, h->opts.nu_post, h->ncol, omega, mode, X64, kind, h->oned, op.fine != 0,
+                            op.n, st);
+    }
+    case H_SUB: {
+      const int nl = D.nlev - op.level;
+      const size_t bytes = sub_footprint(h, D, op.level);
+      if (bytes <= SUB_LDS_BUDGET)
+        return launch_subcycle_lds<T>(Ls, nl, 0, M.dprog, op.dbeg, op.dcnt, op.dchol, D.ncu, omega, h->ncol,
+                                      h->ncol == 0 ? 3 : 2, kind, h->oned, bytes, op.n, st);
+      return launch_subcycle<T>(Ls, nl, M.dprog, op.dbeg, op.dcnt, op.dchol, D.ncu, omega, h->ncol, op.n, st);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+// One merged cycle plus the stopping tests of every participating problem.
+hipError_t enqueue_merged(mg_handle h, const Merge& M, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  const int kind = stencil_kind(h);
+  auto norm = [&](const MOp& op, bool mixed) -> hipError_t {
+    const LevelShape& s = h->groups[M.groups[0]].shp[op.level];
+    const MTab& t = M.tabs[op.tab];
+    if (!mixed) return op.arg ? hipSuccess : launch_resnorm<double>(t.d64, s, NORM_CHECK, nullptr, nullptr, kind,
+                                                                     h->oned, op.n, st);
+    hipError_t r = hipSuccess;
+    if (!op.arg && (r = launch_outer_update(t.d64, t.d32, s, op.n, st)) != hipSuccess) return r;
+    return launch_resnorm<double>(t.d64, s, NORM_CHECK, nullptr, t.d32, kind, h->oned, op.n, st);
+  };
+  if (!h->mixed()) {
+    for (const MOp& op : M.prog) {
+      e = op.type == H_NORM ? norm(op, false) : run_mop<double>(h, M, op, relax(h), true, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  const int inner = inner_cycles(h);
+  for (int c = 0; c < inner; ++c)
+    for (const MOp& op : M.prog) {
+      const bool last = c + 1 == inner;
+      if (op.type == H_NORM) {
+        if (last && (e = norm(op, true)) != hipSuccess) return e;
+        continue;
+      }
+      if ((e = run_mop<float>(h, M, op, (float)relax(h), last, st)) != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
 // Captures one cycle and eight cycles as graphs on a private stream (a graph
 // can then be launched on any stream, the null stream included).  The groups
 // of a batched handle become parallel branches (fork/join through events).
+// Destroys the cycle graphs and their capture streams and events.
+void drop_graphs(mg_handle h) {
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->g1) (void)hipGraphExecDestroy(h->g1);
+  if (h->g8) (void)hipGraphExecDestroy(h->g8);
+  h->g1 = h->g8 = nullptr;
+  for (Group& G : h->groups) {
+    if (G.branch && G.branch != h->cap) (void)hipStreamDestroy(G.branch);
+    G.branch = nullptr;
+  }
+  for (Merge& M : h->merges) {
+    if (M.branch && M.branch != h->cap) (void)hipStreamDestroy(M.branch);
+    M.branch = nullptr;
+  }
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  h->cap = nullptr;
+  for (auto& ev : h->fork)
+    if (ev) (void)hipEventDestroy(ev);
+  h->fork.clear();
+}
+
 mg_status build_graphs(mg_handle h) {
   HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-  const int ng = (int)h->groups.size();
-  h->fork.assign(2 * ng, nullptr);
+  // units: merged schedules, then groups that run their own cycle
+  const int nm = (int)h->merges.size();
+  const int nu = nm + (int)h->standalone.size();
+  auto branch = [&](int u) -> hipStream_t& {
+    return u < nm ? h->merges[u].branch : h->groups[h->standalone[u - nm]].branch;
+  };
+  auto enqueue = [&](int u, hipStream_t st) {
+    return u < nm ? enqueue_merged(h, h->merges[u], st) : enqueue_cycle(h, h->groups[h->standalone[u - nm]], st);
+  };
+  h->fork.assign(2 * nu, nullptr);
   for (auto& ev : h->fork) HIPCHK(h, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-  for (int g = 1; g < ng; ++g) HIPCHK(h, hipStreamCreateWithFlags(&h->groups[g].branch, hipStreamNonBlocking));
-  h->groups[0].branch = h->cap;
+  for (int u = 1; u < nu; ++u) HIPCHK(h, hipStreamCreateWithFlags(&branch(u), hipStreamNonBlocking));
+  branch(0) = h->cap;
   for (int k : {1, 8}) {
     hipGraph_t graph = nullptr;
     HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int c = 0; c < k && e == hipSuccess; ++c) {
-      if (ng == 1) {
-        e = enqueue_cycle(h, h->groups[0], h->cap);
+      if (nu == 1) {
+        e = enqueue(0, h->cap);
         continue;
       }
       e = hipEventRecord(h->fork[0], h->cap);
-      for (int g = 1; g < ng && e == hipSuccess; ++g) e = hipStreamWaitEvent(h->groups[g].branch, h->fork[0], 0);
-      for (int g = 0; g < ng && e == hipSuccess; ++g) e = enqueue_cycle(h, h->groups[g], h->groups[g].branch);
-      for (int g = 1; g < ng && e == hipSuccess; ++g) {
-        e = hipEventRecord(h->fork[ng + g], h->groups[g].branch);
-        if (e == hipSuccess) e = hipStreamWaitEvent(h->cap, h->fork[ng + g], 0);
+      for (int u = 1; u < nu && e == hipSuccess; ++u) e = hipStreamWaitEvent(branch(u), h->fork[0], 0);
+      for (int u = 0; u < nu && e == hipSuccess; ++u) e = enqueue(u, branch(u));
+      for (int u = 1; u < nu && e == hipSuccess; ++u) {
+        e = hipEventRecord(h->fork[nu + u], branch(u));
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->cap, h->fork[nu + u], 0);
       }
     }
     hipError_t e2 = hipStreamEndCapture(h->cap, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
       return fail(h, MG_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    if (k == 1) {
+      size_t nodes = 0;
+      if (hipGraphGetNodes(graph, nullptr, &nodes) == hipSuccess) h->graph_nodes = (int)nodes;
     }
     hipGraphExec_t ex = nullptr;
     hipError_t e3 = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
@@ -629,17 +1073,7 @@ mg_status sync_check(mg_handle h) {
 
 void release(mg_handle h) {
   if (!h) return;
-  if (h->stream) (void)hipStreamSynchronize(h->stream);
-  if (h->g1) (void)hipGraphExecDestroy(h->g1);
-  if (h->g8) (void)hipGraphExecDestroy(h->g8);
-  h->g1 = h->g8 = nullptr;
-  for (size_t g = 1; g < h->groups.size(); ++g)
-    if (h->groups[g].branch) (void)hipStreamDestroy(h->groups[g].branch);
-  if (h->cap) (void)hipStreamDestroy(h->cap);
-  h->cap = nullptr;
-  for (auto& ev : h->fork)
-    if (ev) (void)hipEventDestroy(ev);
-  h->fork.clear();
+  drop_graphs(h);
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
   if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -1087,23 +1521,22 @@ std::string threshold_key(mg_handle h, const Group& G) {
 }
 
 // Candidate tiles of one fused pass (LDS within the fused-pass cap).
-std::vector<TileGeom> tile_candidates(mg_handle h, const Group& G, int l, int H, bool post) {
-  const LevelShape& s = G.shp[l];
+std::vector<TileGeom> tile_candidates(mg_handle h, const LevelShape& s, int ns, int H, bool post) {
   auto lds = [&](const TileGeom& g) {
     if (h->mixed()) return post ? post_lds_bytes<float>(g, h->ncol) : pre_lds_bytes<float>(g, h->ncol);
     return post ? post_lds_bytes<double>(g, h->ncol) : pre_lds_bytes<double>(g, h->ncol);
   };
   std::vector<TileGeom> out;
-  out.push_back(choose_tile(h, G, l, H, post));  // the fixed rule first
+  out.push_back(choose_tile_for(h, s, ns, H, post));  // the fixed rule first
   if (2 * H < wide_width())
-    for (int ty = 8; ty <= 64; ty += 8) {
+    for (int ty = 8; ty <= 128; ty += (ty < 64 ? 8 : 16)) {
       const TileGeom g = wide_geom(s.nx, s.ny, ty, H);
-      if (lds(g) <= FUSED_LDS_MAX && (long)g.ntx * g.nty * G.ns <= 64L * h->ncus) out.push_back(g);
+      if (lds(g) <= FUSED_LDS_MAX && (long)g.ntx * g.nty * ns <= 64L * h->ncus) out.push_back(g);
     }
   for (int tx : {16, 32, 64, 128})
     for (int ty : {4, 8, 16, 32}) {
       const TileGeom g = tile_geom(s.nx, s.ny, tx, ty, H);
-      if (lds(g) <= FUSED_LDS_MAX && (long)g.ntx * g.nty * G.ns <= 64L * h->ncus) out.push_back(g);
+      if (lds(g) <= FUSED_LDS_MAX && (long)g.ntx * g.nty * ns <= 64L * h->ncus) out.push_back(g);
     }
   return out;
 }
@@ -1165,7 +1598,7 @@ mg_status tune_tiles(mg_handle h, Group& G) {
       slot = g;
       continue;
     }
-    const std::vector<TileGeom> cands = tile_candidates(h, G, op.level, H, post);
+    const std::vector<TileGeom> cands = tile_candidates(h, G.shp[op.level], G.ns, H, post);
     TileGeom best = cands[0];
     double best_us = 0.0;
     for (size_t c = 0; c < cands.size(); ++c) {
@@ -1188,6 +1621,158 @@ mg_status tune_tiles(mg_handle h, Group& G) {
 // and partial-sum buffers exist).  The finest FP64 level borrows two
 // scratch arrays for the caller's x and b; the stopping states are set so
 // that no candidate run stops early, and reset by the next solve.
+// Tiles of every fused op of a merged schedule (cached, or the fastest
+// candidate for its level shape and number of participants).
+mg_status tune_merge_tiles(mg_handle h, Merge& M) {
+  const bool refresh = h->opts.tune == MG_TUNE_REFRESH;
+  const Group& D = h->groups[M.groups[0]];
+  for (MOp& op : M.prog) {
+    if (op.type != H_PRE && op.type != H_POST) continue;
+    const bool post = op.type == H_POST;
+    const int H = op.g.H;
+    const LevelShape& s = D.shp[op.level];
+    std::ostringstream k;
+    k << "mpass|" << tune_identity() << "|" << (h->mixed() ? "f32" : "f64") << "|st" << stencil_kind(h) << "|col"
+      << h->ncol << "|" << (post ? "post" : "pre") << "|nu" << (post ? h->opts.nu_post : h->opts.nu_pre) << "|H" << H
+      << "|sor" << (relax(h) != 1.0) << "|aw" << h->opts.adaptive_omega << "|" << s.nx << "x" << s.ny << "p" << s.py
+      << "|z" << op.n << "|fine" << op.fine << "|cu" << h->ncus;
+    const std::string key = k.str();
+    TileGeom g{};
+    const std::string v = refresh ? std::string() : tune_lookup(key);
+    if (!v.empty() && geom_parse(v, s, H, g)) {
+      op.g = g;
+      continue;
+    }
+    const std::vector<TileGeom> cands = tile_candidates(h, s, op.n, H, post);
+    TileGeom best = cands[0];
+    double best_us = 0.0;
+    for (size_t c = 0; c < cands.size(); ++c) {
+      op.g = cands[c];
+      hipError_t e = hipSuccess;
+      for (int r = 0; r <= 3 && e == hipSuccess; ++r) {
+        if (r == 1) e = hipEventRecord(h->ev0, h->stream);
+        if (e == hipSuccess)
+          e = h->mixed() ? run_mop<float>(h, M, op, (float)relax(h), true, h->stream)
+                         : run_mop<double>(h, M, op, relax(h), true, h->stream);
+      }
+      if (e == hipSuccess) e = hipEventRecord(h->ev1, h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(h->ev1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->ev0, h->ev1);
+      if (e != hipSuccess) return fail(h, MG_EDEVICE, std::string("tuning: ") + hipGetErrorString(e));
+      const double us = 1e3 * ms / 3;
+      const bool rule = best.TX == cands[0].TX && best.TY == cands[0].TY && best.wide == cands[0].wide;
+      if (c == 0 || us < best_us * (rule ? 0.98 : 1.0)) {
+        best = cands[c];
+        best_us = us;
+      }
+    }
+    op.g = best;
+    tune_store(key, geom_str(best));
+  }
+  return MG_OK;
+}
+
+// Threshold and tiles of a group that runs its own cycle.
+mg_status tune_group(mg_handle h, Group& G, bool tile_free, bool thr_free) {
+  // threshold candidates: the default, one more fused level, one more
+  // level in the single-workgroup kernel (global memory)
+  // (not with the adaptive omega_l: the single-workgroup kernel sums its
+  // level-wide products in another order than the launched reduction, so
+  // moving a level between them changes the weight's rounding)
+  std::vector<int> ths{0};
+  if (thr_free && h->groups.size() == 1 && !h->opts.adaptive_omega) {
+    Gen g0{h, G, 0};
+    int top = 0;
+    while (top < G.nlev - 1 && !g0.small(top)) ++top;
+    const long ntop = (long)G.shp[top].nx * G.shp[top].ny;
+    if (top < G.nlev - 1) ths.push_back((int)(ntop - 1));
+    // (not the finest level when it forms its couplings from cells: the
+    // single-workgroup kernel reads bands, equal only up to rounding)
+    if (top > 0 && !(top == 1 && G.l64(0, 0).kcx)) ths.push_back((int)((long)G.shp[top - 1].nx * G.shp[top - 1].ny));
+    const std::string cached = h->opts.tune == MG_TUNE_REFRESH ? std::string() : tune_lookup(threshold_key(h, G));
+    if (!cached.empty()) ths.assign(1, std::atoi(cached.c_str()));
+  } else if (!thr_free) {
+    ths.assign(1, h->opts.coarse_cta_nodes);
+  }
+  int best_th = ths[0];
+  double best_us = 0.0;
+  mg_status res = MG_OK;
+  for (size_t c = 0; c < ths.size() && res == MG_OK; ++c) {
+    G.threshold = ths[c];
+    res = build_program(h, G);
+    if (res == MG_OK && tile_free) res = tune_tiles(h, G);
+    if (res != MG_OK || ths.size() == 1) break;
+    double us = 0.0;
+    hipError_t te = time_cycle(h, G, &us);
+    if (te != hipSuccess) return fail(h, MG_EDEVICE, std::string("tuning: ") + hipGetErrorString(te));
+    if (c == 0 || us < best_us * (best_th == ths[0] ? 0.98 : 1.0)) {
+      best_th = ths[c];
+      best_us = us;
+    }
+  }
+  if (res == MG_OK && ths.size() > 1) {
+    tune_store(threshold_key(h, G), std::to_string(best_th));
+    G.threshold = best_th;
+    res = build_program(h, G);
+    if (res == MG_OK && tile_free) res = tune_tiles(h, G);  // cached by now
+  }
+  return res;
+}
+
+// Batched handles with merged schedules: time one-cycle graph replays of
+// the merged layout and of every group on its own branch, keep the faster
+// (both give the same iterates bit for bit).
+mg_status tune_schedule(mg_handle h) {
+  std::ostringstream k;
+  k << "sched|" << tune_identity() << "|" << (h->mixed() ? "f32" : "f64") << "|sm" << h->opts.smoother << "|nu"
+    << h->opts.nu_pre << "," << h->opts.nu_post << "|cy" << h->opts.cycle << "|in" << inner_cycles(h) << "|aw"
+    << h->opts.adaptive_omega << "|tm" << h->opts.tile_mode << "|cu" << h->ncus;
+  for (const Group& G : h->groups) k << "|" << G.shp[0].nx << "x" << G.shp[0].ny << "p" << G.shp[0].py << "L" << G.nlev << "z" << G.ns;
+  const std::string key = k.str();
+  std::string choice = h->opts.tune == MG_TUNE_REFRESH ? std::string() : tune_lookup(key);
+  auto split = [&]() {  // every merged group back on a branch of its own
+    for (const Merge& M : h->merges)
+      for (int g : M.groups) h->standalone.push_back(g);
+    h->merges.clear();
+  };
+  if (choice == "branches") {
+    split();
+    return MG_OK;
+  }
+  if (choice == "merged") return MG_OK;
+  double t[2] = {0.0, 0.0};
+  std::vector<Merge> saved = h->merges;
+  std::vector<int> saved_alone = h->standalone;
+  for (int v = 0; v < 2; ++v) {
+    if (v == 1) split();
+    mg_status s = build_graphs(h);
+    if (s != MG_OK) return s;
+    for (int r = 0; r <= 3; ++r) {
+      if (r == 1) HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+      HIPCHK(h, hipGraphLaunch(h->g1, h->stream));
+    }
+    HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+    HIPCHK(h, hipEventSynchronize(h->ev1));
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    t[v] = ms;
+    drop_graphs(h);
+  }
+  const bool merged = t[0] <= t[1];
+  if (merged) {
+    h->merges = saved;
+    h->standalone = saved_alone;
+  }
+  tune_store(key, merged ? "merged" : "branches");
+  return MG_OK;
+}
+
+// Tiles and coarse threshold of every group and merged schedule (setup,
+// after the descriptors and partial-sum buffers exist).  Each group's finest
+// FP64 level borrows two scratch arrays for the caller's x and b; the
+// stopping states are set so that no candidate run stops early, and reset by
+// the next solve.
 mg_status tune_handle(mg_handle h) {
   if (h->opts.tune == MG_TUNE_OFF) return MG_OK;
   const bool tile_free = !tiles_fixed(h);
@@ -1202,70 +1787,45 @@ mg_status tune_handle(mg_handle h) {
     run[p].partial = h->dpartial[p];
   }
   HIPCHK(h, hipMemcpyAsync(h->dstate, run.data(), run.size() * sizeof(SolveState), hipMemcpyHostToDevice, st));
+  std::vector<double*> scratch;
+  mg_status res = MG_OK;
   for (Group& G : h->groups) {
-    const LevelShape& s0 = G.shp[0];
-    const size_t n0 = (size_t)s0.nx * s0.ny;
+    const size_t n0 = (size_t)G.shp[0].nx * G.shp[0].ny;
     double *tx = nullptr, *tb = nullptr;
-    HIPCHK(h, hipMalloc(&tx, n0 * sizeof(double)));
-    hipError_t e = hipMalloc(&tb, n0 * sizeof(double));
+    hipError_t e = hipMalloc(&tx, n0 * sizeof(double));
+    if (e == hipSuccess) scratch.push_back(tx);
+    if (e == hipSuccess) e = hipMalloc(&tb, n0 * sizeof(double));
+    if (e == hipSuccess) scratch.push_back(tb);
     if (e == hipSuccess) e = hipMemsetAsync(tx, 0, n0 * sizeof(double), st);
     if (e == hipSuccess) e = hipMemsetAsync(tb, 0, n0 * sizeof(double), st);
-    mg_status res = e == hipSuccess ? MG_OK : fail(h, MG_EDEVICE, std::string("tuning scratch: ") + hipGetErrorString(e));
-    if (res == MG_OK) {
-      for (int sl = 0; sl < G.ns; ++sl) {
-        G.l64(0, sl).x = tx;
-        G.l64(0, sl).b = tb;
-      }
-      res = upload_descriptors(h, G);
+    if (e != hipSuccess) {
+      res = fail(h, e == hipErrorOutOfMemory ? MG_ENOMEM : MG_EDEVICE, std::string("tuning scratch: ") +
+                                                                            hipGetErrorString(e));
+      break;
     }
-    // threshold candidates: the default, one more fused level, one more
-    // level in the single-workgroup kernel (global memory)
-    std::vector<int> ths{0};
-    if (res == MG_OK && thr_free && h->groups.size() == 1) {
-      Gen g0{h, G, 0};
-      int top = 0;
-      while (top < G.nlev - 1 && !g0.small(top)) ++top;
-      const long ntop = (long)G.shp[top].nx * G.shp[top].ny;
-      if (top < G.nlev - 1) ths.push_back((int)(ntop - 1));
-      // (not the finest level when it forms its couplings from cells: the
-      // single-workgroup kernel reads bands, equal only up to rounding)
-      if (top > 0 && !(top == 1 && G.l64(0, 0).kcx))
-        ths.push_back((int)((long)G.shp[top - 1].nx * G.shp[top - 1].ny));
-      const std::string cached = h->opts.tune == MG_TUNE_REFRESH ? std::string() : tune_lookup(threshold_key(h, G));
-      if (!cached.empty()) ths.assign(1, std::atoi(cached.c_str()));
-    } else if (!thr_free) {
-      ths.assign(1, h->opts.coarse_cta_nodes);
+    for (int sl = 0; sl < G.ns; ++sl) {
+      G.l64(0, sl).x = tx;
+      G.l64(0, sl).b = tb;
     }
-    int best_th = ths[0];
-    double best_us = 0.0;
-    for (size_t c = 0; c < ths.size() && res == MG_OK; ++c) {
-      G.threshold = ths[c];
-      res = build_program(h, G);
-      if (res == MG_OK && tile_free) res = tune_tiles(h, G);
-      if (res != MG_OK || ths.size() == 1) break;
-      double us = 0.0;
-      hipError_t te = time_cycle(h, G, &us);
-      if (te != hipSuccess) {
-        res = fail(h, MG_EDEVICE, std::string("tuning: ") + hipGetErrorString(te));
-        break;
-      }
-      if (c == 0 || us < best_us * (best_th == ths[0] ? 0.98 : 1.0)) {
-        best_th = ths[c];
-        best_us = us;
-      }
-    }
-    if (res == MG_OK && ths.size() > 1) {
-      tune_store(threshold_key(h, G), std::to_string(best_th));
-      G.threshold = best_th;
-      res = build_program(h, G);
-      if (res == MG_OK && tile_free) res = tune_tiles(h, G);  // cached by now
-    }
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(tx);
-    (void)hipFree(tb);
-    for (int sl = 0; sl < G.ns; ++sl) G.l64(0, sl).x = G.l64(0, sl).b = nullptr;
-    if (res != MG_OK) return res;
     res = upload_descriptors(h, G);
+    if (res != MG_OK) break;
+  }
+  if (res == MG_OK && !h->merges.empty()) res = upload_merge_tables(h);
+  for (size_t u = 0; u < h->standalone.size() && res == MG_OK; ++u)
+    res = tune_group(h, h->groups[h->standalone[u]], tile_free, thr_free);
+  for (size_t m = 0; m < h->merges.size() && res == MG_OK && tile_free; ++m) res = tune_merge_tiles(h, h->merges[m]);
+  if (res == MG_OK && !h->merges.empty()) res = tune_schedule(h);
+  (void)hipStreamSynchronize(st);
+  for (double* q : scratch) (void)hipFree(q);
+  for (Group& G : h->groups)
+    for (int sl = 0; sl < G.ns; ++sl) G.l64(0, sl).x = G.l64(0, sl).b = nullptr;
+  if (res != MG_OK) return res;
+  for (Group& G : h->groups) {
+    res = upload_descriptors(h, G);
+    if (res != MG_OK) return res;
+  }
+  if (!h->merges.empty()) {
+    res = upload_merge_tables(h);
     if (res != MG_OK) return res;
   }
   HIPCHK(h, hipMemsetAsync(h->dstate, 0, (size_t)h->nprob * sizeof(SolveState), st));
@@ -1340,6 +1900,8 @@ mg_status setup_handle(mg_handle h, const mg_coeffs* coeffs, int32_t levels) {
   }
   mg_status s = sync_check(h);
   if (s != MG_OK) return s;
+  s = build_merges(h);
+  if (s != MG_OK) return s;
   s = tune_handle(h);
   if (s != MG_OK) return s;
   return build_graphs(h);
@@ -1380,6 +1942,10 @@ mg_status begin_solve(mg_handle h, const double* const* rhs, double* const* x, d
       HIPCHK(h, launch_zero_boundary(x[p], s0.nx, s0.ny, s0.nx, s0.py, st));
     }
     mg_status s = upload_descriptors(h, G);  // also waits for the state upload above
+    if (s != MG_OK) return s;
+  }
+  if (!h->merges.empty()) {
+    mg_status s = upload_merge_tables(h);
     if (s != MG_OK) return s;
   }
   HIPCHK(h, hipEventRecord(h->ev0, st));
@@ -1859,6 +2425,17 @@ mg_status mg_coeff_grad(mg_handle h, const double* u, const double* lam, double*
   const LevelShape& s0 = G.shp[0];
   HIPCHK(h, launch_coeff_grad(u, lam, dL_dk, s0.nx, s0.ny, s0.py, G.hx[0], G.hy[0], h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  return MG_OK;
+}
+
+mg_status mg_batch_schedule(mg_handle h, int32_t* out) {
+  if (!h || !out) return fail(h, MG_EINVAL, "NULL argument");
+  int in_merges = 0;
+  for (const Merge& M : h->merges) in_merges += (int)M.groups.size();
+  out[0] = (int32_t)h->merges.size();
+  out[1] = in_merges;
+  out[2] = (int32_t)h->standalone.size();
+  out[3] = h->graph_nodes;
   return MG_OK;
 }
 

@@ -37,7 +37,7 @@ PRECISIONS = {"fp64": MG_PREC_FP64, "mixed": MG_PREC_MIXED}
 EXPORTED = (
     "mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
     "mg_destroy", "mg_status_string", "mg_last_error", "mg_level_shape", "mg_num_levels", "mg_profile_pass",
-    "mg_pass_info", "mg_start_nested", "mg_update_coeffs", "mg_residual_noalloc",
+    "mg_pass_info", "mg_start_nested", "mg_update_coeffs", "mg_residual_noalloc", "mg_batch_schedule",
 )
 
 
@@ -103,11 +103,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_pass_info.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32)]
     lib.mg_start_nested.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.mg_update_coeffs.argtypes = [ctypes.c_void_p, P(mg_coeffs)]
+    lib.mg_batch_schedule.argtypes = [ctypes.c_void_p, P(ctypes.c_int32)]
     lib.mg_residual_noalloc.argtypes = [P(mg_grid), P(mg_coeffs), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         P(ctypes.c_double), ctypes.c_void_p]
     for name in ("mg_setup", "mg_solve", "mg_residual", "mg_coeff_grad", "mg_setup_batched", "mg_solve_batched",
                  "mg_destroy", "mg_level_shape", "mg_profile_pass", "mg_pass_info", "mg_start_nested",
-                 "mg_update_coeffs", "mg_residual_noalloc"):
+                 "mg_update_coeffs", "mg_residual_noalloc", "mg_batch_schedule"):
         getattr(lib, name).restype = ctypes.c_int
     lib.mg_num_levels.restype = ctypes.c_int32
     _lib = lib
@@ -289,6 +290,14 @@ def mg_solve_batched(h, rhs: list, x: list, tol: float, max_cycles: int, history
     return s, out
 
 
+def mg_batch_schedule(h) -> dict:
+    out = (ctypes.c_int32 * 4)()
+    s = load_library().mg_batch_schedule(h, out)
+    if s != MG_OK:
+        raise MGError(s, last_error(h))
+    return {"merged": out[0], "groups_merged": out[1], "standalone": out[2], "launches_per_cycle": out[3]}
+
+
 def mg_destroy(h) -> None:
     if h is not None and h.value:
         load_library().mg_destroy(h)
@@ -439,6 +448,10 @@ class BatchedSolver:
         self.shapes = [(g.ny, g.nx) for g in gs]
         self.opts = make_options(**opt)
         self.h = mg_setup_batched(gs, cs, self.opts, levels)
+
+    def schedule(self) -> dict:
+        """How the batch runs (mg_batch_schedule)."""
+        return mg_batch_schedule(self.h)
 
     def solve(self, rhs: list, x: list, tol: float = 1e-10, max_cycles: int = 100, history: bool = False):
         """Returns (worst status, [SolveInfo per problem]); each info.status is

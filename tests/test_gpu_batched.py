@@ -166,3 +166,105 @@ def test_batched_levels_argument():
     with pytest.raises(mg.MGError) as err:
         mg.BatchedSolver([(65, 65), (17, 17)], [1.0, 1.0], levels=5)
     assert err.value.status == mg.MG_EINVAL
+
+
+MERGE_CASES = [
+    dict(precision="fp64"),
+    dict(precision="mixed"),
+    dict(precision="mixed", inner_cycles=2),
+    dict(precision="fp64", tile_mode="per_op"),
+    dict(precision="fp64", adaptive_omega=True),
+    dict(precision="fp64", cycle="V"),
+    dict(precision="mixed", cycle="W"),
+    dict(precision="fp64", smoother="jacobi", omega=0.8),
+]
+
+
+@pytest.mark.parametrize("case", MERGE_CASES, ids=[str(i) for i in range(len(MERGE_CASES))])
+def test_merged_schedule_equals_single_solves(case):
+    """Problems of 17^2 .. 257^2 (chains that end alike) and one 97 x 49 grid
+    (a chain of its own): the first run as one merged schedule, each launch
+    covering every problem on a level; every problem's iterates equal its own
+    single-problem solve bit for bit, cycle by cycle."""
+    mg = _mg()
+    opts = dict(case)
+    opts.setdefault("smoother", "rbgs")
+    grids = [(257, 257), (17, 17), (129, 129), (65, 65), (97, 49), (129, 129), (33, 33)]
+    eps = [0.3, 1.0, 0.05, 1e-2, 0.5, 1.0, 0.2]
+    rhs = [torch.tensor(W.normal_field(nx, ny, 900 + i), device="cuda") for i, (nx, ny) in enumerate(grids)]
+    B = mg.BatchedSolver(grids, eps, tune="off", **opts)  # the fixed rule keeps the merged schedule
+    try:
+        sch = B.schedule()
+        assert sch["merged"] == 1 and sch["groups_merged"] == 5 and sch["standalone"] == 1, sch
+        xb = [torch.zeros_like(r) for r in rhs]
+        outs = []
+        for _ in range(2):
+            B.solve(rhs, xb, 1e-300, 1)
+            outs.append([x.cpu().numpy().copy() for x in xb])
+    finally:
+        B.close()
+    for i, ((nx, ny), e) in enumerate(zip(grids, eps)):
+        s = mg.Solver(nx, ny, eps_x=e, **opts)
+        x = torch.zeros_like(rhs[i])
+        try:
+            for c in range(2):
+                s.solve(rhs[i], x, 1e-300, 1, history=False)
+                assert np.array_equal(x.cpu().numpy(), outs[c][i]), (i, c)
+        finally:
+            s.close()
+
+
+def test_merged_schedule_has_fewer_launches_than_branches():
+    """The merged schedule of 129^2 .. 1025^2 launches fewer kernels per cycle
+    than the sum of the problems' own cycles would (one launch per level
+    pass for all sizes), and solves to 1e-10 with each problem's status and
+    cycle count equal to its single solve's."""
+    mg = _mg()
+    sizes = [1025, 513, 257, 129]
+    eps = [0.5, 0.2, 0.1, 0.05]
+    rhs = [torch.tensor(W.normal_field(n, n, 950 + i), device="cuda") for i, n in enumerate(sizes)]
+    B = mg.BatchedSolver([(n, n) for n in sizes], eps, smoother="rbgs", precision="mixed", tune="off")
+    try:
+        assert B.schedule()["merged"] == 1
+        merged = B.schedule()["launches_per_cycle"]
+        xb = [torch.zeros_like(r) for r in rhs]
+        worst, infos = B.solve(rhs, xb, 1e-10, 500)
+    finally:
+        B.close()
+    assert worst == mg.MG_OK
+    separate = 0
+    for i, (n, e) in enumerate(zip(sizes, eps)):
+        s = mg.Solver(n, n, eps_x=e, smoother="rbgs", precision="mixed")
+        try:
+            x = torch.zeros_like(rhs[i])
+            info = s.solve(rhs[i], x, 1e-10, 500)
+            separate += mg.mg_batch_schedule(s.h)["launches_per_cycle"]
+        finally:
+            s.close()
+        assert info.status == mg.MG_OK and infos[i].cycles == info.cycles
+        assert torch.equal(x, xb[i])
+    assert merged < separate, (merged, separate)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tuned_schedule_choice_is_bitwise_invisible(precision):
+    """The autotuner times the merged schedule against per-size branches and
+    keeps the faster; either way every problem's iterate is the same bit for
+    bit."""
+    mg = _mg()
+    sizes = [513, 257, 129, 257, 65]
+    eps = [0.3, 0.05, 1.0, 0.2, 0.01]
+    rhs = [torch.tensor(W.normal_field(n, n, 960 + i), device="cuda") for i, n in enumerate(sizes)]
+    res = {}
+    for tune in ("off", "refresh"):
+        B = mg.BatchedSolver([(n, n) for n in sizes], eps, smoother="rbgs", precision=precision, tune=tune)
+        try:
+            sch = B.schedule()
+            assert sch["merged"] + sch["standalone"] >= 1
+            xs = [torch.zeros_like(r) for r in rhs]
+            B.solve(rhs, xs, 1e-300, 3)
+            res[tune] = xs
+        finally:
+            B.close()
+    for a, b in zip(res["off"], res["refresh"]):
+        assert torch.equal(a, b)
