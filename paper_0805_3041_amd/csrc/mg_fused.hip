@@ -639,10 +639,12 @@ __device__ __forceinline__ Cf<T> wcoef(const Level<T>& L, const WMap& m, const C
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Gauss-Seidel update of the column-parity-Q nodes of a colour on the rows
-// lj0 + rstep (wave + NWAVE k) < hiR, two rows per round.  Loads are issued
-// for every lane (addresses stay inside the region's rows); only lanes whose
-// column is an unknown of the colour store.
-template <typename T, int K, int NCOL, bool B1, int Q>
+// lj0 + rstep (wave + NWAVE k) < hiR that carry unknowns (a contiguous range
+// of local rows, found once), two rows per round.  Loads are issued for every
+// lane (addresses stay inside the region's rows); only lanes whose column is
+// an unknown of the colour store.  SOR: relaxation factor != 1 (a plain
+// Gauss-Seidel sweep then has no per-node test).
+template <typename T, int K, int NCOL, bool B1, int Q, bool SOR>
 __device__ void wcolour_rows(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG_LDS T* bl, int hiR, int lj0,
                              int rstep, int A, bool lane_ok, int gi, T omega) {
   constexpr int P = wide_narr<NCOL>() * WW;
@@ -654,26 +656,29 @@ __device__ void wcolour_rows(const Level<T>& L, const WMap& m, MG_LDS T* lds, co
   const int step = rstep * NWAVE;
   auto node = [&](int lj) -> T {
     const Nbr<T> v = wgather<T, K, P, Q, false>(lds + (lj - 1) * P + A);
-    return sor_v(gs_v<K>(L, wcoef<T, K, B1>(L, m, col, gi, lj), v, lds[lj * P + WW + own + A]), lds + lj * P + own + A,
-                 omega);
+    const T gs = gs_v<K>(L, wcoef<T, K, B1>(L, m, col, gi, lj), v, lds[lj * P + WW + own + A]);
+    if constexpr (SOR) {
+      return sor_v(gs, lds + lj * P + own + A, omega);
+    } else {
+      return gs;
+    }
   };
   int lj = lj0 + rstep * wave_id();
-  for (; lj + step < hiR; lj += 2 * step) {
+  int end = hiR;
+  if (!m.py) {  // rows of unknowns: 1 <= global row <= ny - 2
+    const int lo = 1 - m.j0 + m.H, hi = m.ny - 1 - m.j0 + m.H;
+    if (lj < lo) lj += (lo - lj + step - 1) / step * step;
+    end = min(end, hi);
+  }
+  for (; lj + step < end; lj += 2 * step) {
     const int lj2 = lj + step;
-    const bool r1 = m.row_ok(lj), r2 = m.row_ok(lj2);
-    if (r1 && r2) {
-      const T x1 = node(lj), x2 = node(lj2);
-      if (lane_ok) {
-        lds[lj * P + own + A] = x1;
-        lds[lj2 * P + own + A] = x2;
-      }
-    } else if (r1 || r2) {
-      const int l = r1 ? lj : lj2;
-      const T x1 = node(l);
-      if (lane_ok) lds[l * P + own + A] = x1;
+    const T x1 = node(lj), x2 = node(lj2);
+    if (lane_ok) {
+      lds[lj * P + own + A] = x1;
+      lds[lj2 * P + own + A] = x2;
     }
   }
-  if (lj < hiR && m.row_ok(lj)) {
+  if (lj < end) {
     const T x1 = node(lj);
     if (lane_ok) lds[lj * P + own + A] = x1;
   }
@@ -702,10 +707,17 @@ __device__ void wsweep_colour(const Level<T>& L, const WMap& m, MG_LDS T* lds, c
   // a lane outside the unknowns still loads (its results are not stored):
   // give it an interior column for global band reads
   const int gi = lane_ok ? m.gi(li) : 1;
-  if (q)
-    wcolour_rows<T, K, NCOL, B1, 1>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi, omega);
-  else
-    wcolour_rows<T, K, NCOL, B1, 0>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi, omega);
+  if (omega == (T)1) {
+    if (q)
+      wcolour_rows<T, K, NCOL, B1, 1, false>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi, omega);
+    else
+      wcolour_rows<T, K, NCOL, B1, 0, false>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi, omega);
+  } else {
+    if (q)
+      wcolour_rows<T, K, NCOL, B1, 1, true>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi, omega);
+    else
+      wcolour_rows<T, K, NCOL, B1, 0, true>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi, omega);
+  }
 }
 
 // Every node of the region shrunk by s, both column parities per lane and
