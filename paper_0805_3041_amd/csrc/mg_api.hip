@@ -420,6 +420,29 @@ TileGeom choose_tile(mg_handle h, const Group& G, int l, int H, bool post) {
   return choose_tile_for(h, G.shp[l], G.ns, H, post);
 }
 
+// Coarse-level kernel ops from flat[b] on: runs of Gauss-Seidel colour ops
+// that form whole sweeps of one level (colours 0 .. ncol - 1, repeated)
+// become one OP_SMOOTH op whose arg is the number of sweeps.
+void fold_sweeps(std::vector<DOp>& flat, size_t b, int ncol) {
+  if (ncol <= 0) return;
+  std::vector<DOp> out(flat.begin(), flat.begin() + b);
+  for (size_t k = b; k < flat.size();) {
+    size_t q = k;
+    while (q < flat.size() && flat[q].type == OP_COLOR && flat[q].level == flat[k].level &&
+           flat[q].arg == (int)((q - k) % ncol))
+      ++q;
+    const int sweeps = (int)((q - k) / ncol);
+    if (sweeps > 0) {
+      out.push_back({OP_SMOOTH, flat[k].level, sweeps, 0});
+      k += (size_t)sweeps * ncol;
+    } else {
+      out.push_back(flat[k]);
+      ++k;
+    }
+  }
+  flat.swap(out);
+}
+
 mg_status build_program(mg_handle h, Group& G) {
   Gen g{h, G, G.threshold};
   std::vector<std::vector<Abs>> subs;
@@ -465,6 +488,8 @@ mg_status build_program(mg_handle h, Group& G) {
       }
       flat.push_back({t, a.level, a.arg, 0});
     }
+    fold_sweeps(flat, (size_t)b, h->ncol);
+    for (size_t k = cnt.size() - G.ns; k < cnt.size(); ++k) cnt[k] = (int)(flat.size() - b);
   }
   G.nsub = (int)subs.size();
   if (!flat.empty()) {
@@ -784,7 +809,8 @@ mg_status build_merges(mg_handle h) {
           }
           flat.push_back({t, a.level - op.level, a.arg, 0});
         }
-        std::vector<int> beg(op.n, b), cnt(op.n, (int)body.size());
+        fold_sweeps(flat, (size_t)b, h->ncol);
+        std::vector<int> beg(op.n, b), cnt(op.n, (int)(flat.size() - b));
         std::vector<double*> chol;  // one per participant: the first entry of its levels
         for (int k = 0; k < (int)M.groups.size(); ++k)
           if ((set >> k) & 1)

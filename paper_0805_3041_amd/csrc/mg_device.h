@@ -82,6 +82,7 @@ enum OpType {
   OP_COARSE = 5,    // exact solve on the coarsest `level`
   OP_LINE = 6,      // line sweep on `level`, arg as line_arg
   OP_OMEGA = 7,     // adaptive omega_l of `level` from its x, b and the correction on level+1
+  OP_SMOOTH = 8,    // `arg` Gauss-Seidel sweeps (every colour in order) on `level`
 };
 
 // Argument of a line-smoothing op: bit 0 direction (0: lines along x, 1:

@@ -573,19 +573,17 @@ __device__ __forceinline__ void row_offsets(int j, int nx, int ny, int py, int& 
 // of rows, so the colour's column offset is the same on all its rows), its
 // rows advance by a uniform stride, and coefficients that depend on the
 // column only are read once.
-template <typename T, int K, bool B1>
-__device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int c, int ncol,
-                           T omega, int tid) {
-  constexpr int NB = nbatch(K);
-  const int nx = L.nx, ny = L.ny, py = L.py;
-  const int lo = py ? 0 : 1, hi = py ? ny - 1 : ny - 2;
-  const int kl = ceil_log2((nx - 1) >> 1);
+//
+// Column i, first row j and row stride of thread `tid` for colour c.
+template <typename T>
+__device__ __forceinline__ void colour_plan(const Level<T>& L, int c, int ncol, int tid, int& i, int& j, int& jstep) {
+  const int lo = L.py ? 0 : 1;
+  const int kl = ceil_log2((L.nx - 1) >> 1);
   const int k = tid & ((1 << kl) - 1);
   const int rg = SUB_NT >> kl;  // even: kl <= 9 for every LDS level
-  int j, jstep, first;
+  int first;
   if (ncol == 4) {
-    const int j0 = lo + (((lo & 1) != (c >> 1)) ? 1 : 0);
-    j = j0 + 2 * (tid >> kl);
+    j = lo + (((lo & 1) != (c >> 1)) ? 1 : 0) + 2 * (tid >> kl);
     jstep = 2 * rg;
     first = (c & 1) ? 1 : 2;
   } else {
@@ -593,11 +591,17 @@ __device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, co
     jstep = rg;
     first = 1 + ((((1 + j) & 1) != c) ? 1 : 0);
   }
-  const int i = first + 2 * k;
-  if (i > nx - 2) return;
+  i = first + 2 * k;
+}
+
+// The colour's nodes of column i on rows j, j + jstep, ... <= hi.
+template <typename T, int K, bool B1>
+__device__ __forceinline__ void colour_rows(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl,
+                                            int i, int j, int jstep, const Cf<T>& col, T omega) {
+  constexpr int NB = nbatch(K);
+  const int nx = L.nx, ny = L.ny, py = L.py;
+  const int hi = py ? ny - 1 : ny - 2;
   const bool col_only = K == ST5 || B1;
-  Cf<T> col{};
-  if (col_only) col = sub_coefs<T, K, B1>(L, bl, i, 0, 0);
   const int dpos = jstep * nx;
   int pos = j * nx + i;
   for (; j <= hi; j += NB * jstep, pos += NB * dpos) {
@@ -617,6 +621,132 @@ __device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, co
 #pragma unroll
     for (int u = 0; u < NB; ++u)
       if (j + u * jstep <= hi) x[pos + u * dpos] = sor_v(gs_v<K>(L, a[u], v[u], bp[u]), x + pos + u * dpos, omega);
+  }
+}
+
+template <typename T, int K, bool B1>
+__device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int c, int ncol,
+                           T omega, int tid) {
+  int i, j, jstep;
+  colour_plan(L, c, ncol, tid, i, j, jstep);
+  if (i > L.nx - 2) return;
+  Cf<T> col{};
+  if (K == ST5 || B1) col = sub_coefs<T, K, B1>(L, bl, i, 0, 0);
+  colour_rows<T, K, B1>(L, x, b, bl, i, j, jstep, col, omega);
+}
+
+// `nsw` whole Gauss-Seidel sweeps (colours 0 .. ncol - 1 in order) as one op:
+// the same node updates as nsw * ncol OP_COLOR ops, with each thread's
+// columns and column coefficients found once and a workgroup barrier
+// between colours (the interpreter's own barrier follows the last).  Even
+// and odd colours differ in their column parity only (4 colours) or are the
+// two colours (2 colours), so two coefficient sets cover every colour.
+template <typename T, int K, bool B1, int NCOL>
+__device__ void lds_smooth_n(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int nsw, T omega,
+                             int tid) {
+  const int last = L.nx - 2;
+  int ic[NCOL], jc[NCOL], js[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) colour_plan(L, c, NCOL, tid, ic[c], jc[c], js[c]);
+  Cf<T> c0{}, c1{};
+  if (K == ST5 || B1) {
+    if (ic[0] <= last) c0 = sub_coefs<T, K, B1>(L, bl, ic[0], 0, 0);
+    if (ic[1] <= last) c1 = sub_coefs<T, K, B1>(L, bl, ic[1], 0, 0);
+  }
+  for (int s = 0; s < nsw; ++s) {
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) {
+      if (ic[c] <= last) colour_rows<T, K, B1>(L, x, b, bl, ic[c], jc[c], js[c], (c & 1) ? c1 : c0, omega);
+      if (s + 1 < nsw || c + 1 < NCOL) __syncthreads();
+    }
+  }
+}
+
+// Same sweeps when no thread has more than M rows of any colour (the levels
+// at the bottom of the hierarchy): each thread's nodes, their row offsets
+// and right-hand sides (fixed while smoothing) are found once, so a colour
+// step is the gather, the update and the store.
+template <typename T, int K, bool B1, int NCOL, int M>
+__device__ void lds_smooth_few(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int nsw,
+                               T omega, int tid) {
+  const int nx = L.nx, ny = L.ny, py = L.py;
+  const int hi = py ? ny - 1 : ny - 2, last = nx - 2;
+  constexpr bool col_only = K == ST5 || B1;
+  int ic[NCOL], pos[NCOL][M], so[NCOL][M], no[NCOL][M], jr[NCOL][M];
+  T bv[NCOL][M];
+  bool on[NCOL][M];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) {
+    int j, jstep;
+    colour_plan(L, c, NCOL, tid, ic[c], j, jstep);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int jm = j + m * jstep;
+      on[c][m] = ic[c] <= last && jm <= hi;
+      jr[c][m] = jm;
+      pos[c][m] = jm * nx + ic[c];
+      so[c][m] = no[c][m] = 0;
+      bv[c][m] = (T)0;
+      if (on[c][m]) {
+        row_offsets(jm, nx, ny, py, so[c][m], no[c][m]);
+        bv[c][m] = b[pos[c][m]];
+      }
+    }
+  }
+  Cf<T> c0{}, c1{};
+  if (col_only) {
+    if (ic[0] <= last) c0 = sub_coefs<T, K, B1>(L, bl, ic[0], 0, 0);
+    if (ic[1] <= last) c1 = sub_coefs<T, K, B1>(L, bl, ic[1], 0, 0);
+  }
+  for (int s = 0; s < nsw; ++s) {
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) {
+      Nbr<T> v[M];
+      Cf<T> a[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+        if (on[c][m]) {
+          v[m] = gather<K>(L, LXO<T>{x + pos[c][m], so[c][m], no[c][m]}, false);
+          a[m] = col_only ? ((c & 1) ? c1 : c0)
+                          : sub_coefs<T, K, B1>(L, bl, ic[c], jr[c][m], wrap_dn(jr[c][m], ny, py));
+        }
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+        if (on[c][m]) x[pos[c][m]] = sor_v(gs_v<K>(L, a[m], v[m], bv[c][m]), x + pos[c][m], omega);
+      if (s + 1 < nsw || c + 1 < NCOL) __syncthreads();
+    }
+  }
+}
+
+// Rows per thread of one colour: at most ceil(rows / row stride); the
+// register-resident form where that is 1 (or 2 with two colours).
+template <typename T, int K, bool B1, int NCOL>
+__device__ __forceinline__ void lds_smooth_c(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl,
+                                             int nsw, T omega, int tid) {
+  const int kl = ceil_log2((L.nx - 1) >> 1);
+  const int rstride = (NCOL == 4 ? 2 : 1) * (SUB_NT >> kl);
+  const int rows = L.py ? L.ny : L.ny - 2;
+  const int m = (rows + rstride - 1) / rstride;
+  if (m <= 1)
+    lds_smooth_few<T, K, B1, NCOL, 1>(L, x, b, bl, nsw, omega, tid);
+  else if (NCOL == 2 && m <= 2)  // (two rows of four colours would spill registers)
+    lds_smooth_few<T, K, B1, NCOL, 2>(L, x, b, bl, nsw, omega, tid);
+  else
+    lds_smooth_n<T, K, B1, NCOL>(L, x, b, bl, nsw, omega, tid);
+}
+
+// (9-point operators are smoothed with four colours only: setup rejects
+// red-black Gauss-Seidel for them.)
+template <typename T, int K, bool B1>
+__device__ void lds_smooth(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int nsw, int ncol,
+                           T omega, int tid) {
+  if constexpr (K == ST9) {
+    lds_smooth_c<T, K, B1, 4>(L, x, b, bl, nsw, omega, tid);
+  } else {
+    if (ncol == 4)
+      lds_smooth_c<T, K, B1, 4>(L, x, b, bl, nsw, omega, tid);
+    else
+      lds_smooth_c<T, K, B1, 2>(L, x, b, bl, nsw, omega, tid);
   }
 }
 
@@ -935,6 +1065,7 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
       const MG_LDS T* bands = B1 ? lds + boffs[l] : nullptr;
       switch (type) {
         case OP_COLOR: lds_colour<T, K, B1>(L, xl, bl, bands, arg, ncol, omega, tid); break;
+        case OP_SMOOTH: lds_smooth<T, K, B1>(L, xl, bl, bands, arg, ncol, omega, tid); break;
         case OP_JACOBI:
           lds_jacobi<T, K, B1>(L, arg == 0 ? xl : tl, arg == 0 ? tl : xl, bl, bands, omega, tid);
           break;
@@ -964,6 +1095,12 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
     } else {
       switch (type) {
         case OP_COLOR: body_colour<T, false>(L, arg, ncol, omega, tid, SUB_NT); break;
+        case OP_SMOOTH:
+          for (int k2 = 0; k2 < arg * ncol; ++k2) {
+            body_colour<T, false>(L, k2 % ncol, ncol, omega, tid, SUB_NT);
+            if (k2 + 1 < arg * ncol) __syncthreads();
+          }
+          break;
         case OP_JACOBI: body_jacobi<T, false>(L, arg, omega, tid, SUB_NT); break;
         case OP_COPY: body_copy(L, tid, SUB_NT); break;
         case OP_DR: body_dr<T, false>(L, Ls[l + 1], tid, SUB_NT); break;
