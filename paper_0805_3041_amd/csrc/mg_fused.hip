@@ -25,6 +25,8 @@
 // no boundary tests; node positions advance incrementally instead of being
 // divided out of a flat index; 9-point operators whose coefficients vary
 // along x only keep the tile's columns of their bands in LDS.
+#include <type_traits>
+
 #include "mg_fused.h"
 
 namespace mg {
@@ -49,6 +51,16 @@ struct TileMap {
     return j;
   }
 };
+
+// Solve-finished flag of a tile kernel's problem, batched launches: tested at
+// once (most slots are finished in most cycles).  Its own branch, so that a
+// one-problem launch never waits on the flag before issuing its loads; that
+// launch reads the flag after its region loads and tests it at the first
+// barrier (a finished problem's kernels store nothing).
+__device__ __forceinline__ bool batched_done(const SolveState* st) {
+  if (gridDim.z > 1) return st->done != 0;
+  return false;
+}
 
 // Tile index -> (tx, ty).  Consecutive workgroup ids go to different XCDs
 // (round-robin dispatch over 8), so ids are regrouped to give each XCD a
@@ -320,12 +332,7 @@ __global__ void __launch_bounds__(FT) k_pre(const Level<T>* __restrict__ Fs, con
                                             int TY, int H, int ntx, int nty, int nsteps, T omega) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Level<T> F = Fs[blockIdx.z];
-  // the solve-finished flag is read now and, for one problem, tested once the
-  // region's loads are in flight (a finished problem's kernels store
-  // nothing); a batched launch tests it at once, since most of its slots are
-  // finished in most cycles
-  const int done = F.st->done;
-  if (gridDim.z > 1 && done) return;
+  if (batched_done(F.st)) return;
   const Level<T> C = Cs[blockIdx.z];
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
@@ -364,6 +371,7 @@ __global__ void __launch_bounds__(FT) k_pre(const Level<T>* __restrict__ Fs, con
       }
     }
   }
+  const int done = F.st->done;
   __syncthreads();
   if (done) return;
 
@@ -420,8 +428,7 @@ __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, co
   __shared__ double sh[FT / 64];
   const Level<T> F = Fs[blockIdx.z];
   SolveState* st = F.st;
-  const int done = st->done;  // one problem: tested once the region's loads are in flight
-  if (gridDim.z > 1 && done) return;
+  if (batched_done(st)) return;
   const Level<T> C = Cs[blockIdx.z];
   const bool wtd = F.wl != nullptr;  // adaptive omega_l
   const T wv = wtd ? *F.wl : (T)1;
@@ -500,6 +507,7 @@ __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, co
       }
     }
   }
+  const int done = F.st->done;
   __syncthreads();
   if (done) return;
 
@@ -554,6 +562,7 @@ constexpr int WW = 128;
 constexpr int WH = WW / 2;
 constexpr int NWAVE = FT / 64;
 constexpr int UL = 4;  // rows whose global loads a wave issues before its first wait
+constexpr int ULR = 8;  // region rows a wave loads per round in the wide passes (one round up to 64 rows)
 
 template <int NCOL>
 constexpr int wide_narr() {
@@ -789,12 +798,37 @@ __device__ int wsmooth(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG
   }
 }
 
+// Bands that vary along x only, at the region's columns (clamped to the
+// grid): fetched into registers (each thread at most two values) together
+// with a kernel's other first loads, stored to LDS after them.
+static_assert(NBANDS * WW >= FT && NBANDS * WW <= 2 * FT, "band fetch covers NBANDS * WW with two rounds");
 template <typename T>
-__device__ void wload_bands(const Level<T>& F, const WMap& m, MG_LDS T* bl) {
-  for (int idx = threadIdx.x; idx < NBANDS * WW; idx += FT) {
-    const int k = idx / WW, li = idx - k * WW;
-    const int g = min(max(m.gi(li), 0), F.nx - 1);
-    bl[k * WW + wcol(li)] = bandp(F, k)[g];
+struct WBands {
+  T v0, v1;
+};
+template <typename T>
+__device__ __forceinline__ WBands<T> wfetch_bands(const Level<T>& F, const WMap& m) {
+  WBands<T> r{(T)0, (T)0};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int idx = threadIdx.x + h * FT;
+    if (idx < NBANDS * WW) {
+      const int k = idx / WW, li = idx - k * WW;
+      const int g = min(max(m.gi(li), 0), F.nx - 1);
+      (h ? r.v1 : r.v0) = bandp(F, k)[g];
+    }
+  }
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ void wstore_bands(MG_LDS T* bl, const WBands<T>& r) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int idx = threadIdx.x + h * FT;
+    if (idx < NBANDS * WW) {
+      const int k = idx / WW, li = idx - k * WW;
+      bl[k * WW + wcol(li)] = h ? r.v1 : r.v0;
+    }
   }
 }
 
@@ -804,8 +838,7 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
   constexpr int P = wide_narr<NCOL>() * WW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Level<T> F = Fs[blockIdx.z];
-  const int done = F.st->done;  // one problem: tested once the region's loads are in flight
-  if (gridDim.z > 1 && done) return;
+  if (batched_done(F.st)) return;
   const Level<T> C = Cs[blockIdx.z];
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
@@ -814,17 +847,18 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
   MG_LDS T* bl = lds + R * P;
   const WMap m{tx * TX, ty * TY, H, F.nx, F.ny, F.py};
   const int wave = wave_id(), lane = threadIdx.x & 63;
-  if constexpr (B1) wload_bands(F, m, bl);
+  WBands<T> bands{};
+  if constexpr (B1) bands = wfetch_bands(F, m);
 
   {
     const int la = lane, lb = lane + 64;
     const int ca = wcol(la), cb = wcol(lb);
     const bool oka = m.col_ok(la), okb = m.col_ok(lb);
     const int ga = m.gi(la), gb = m.gi(lb);
-    for (int lj0 = wave; lj0 < R; lj0 += NWAVE * UL) {
-      T xa[UL], xb[UL], ba[UL], bb[UL];
+    for (int lj0 = wave; lj0 < R; lj0 += NWAVE * ULR) {
+      T xa[ULR], xb[ULR], ba[ULR], bb[ULR];
 #pragma unroll
-      for (int u = 0; u < UL; ++u) {
+      for (int u = 0; u < ULR; ++u) {
         const int lj = lj0 + u * NWAVE;
         xa[u] = xb[u] = ba[u] = bb[u] = (T)0;
         if (lj < R && m.row_ok(lj)) {
@@ -840,7 +874,7 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
         }
       }
 #pragma unroll
-      for (int u = 0; u < UL; ++u) {
+      for (int u = 0; u < ULR; ++u) {
         const int lj = lj0 + u * NWAVE;
         if (lj >= R) break;
         MG_LDS T* r = lds + lj * P;
@@ -855,6 +889,8 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
       }
     }
   }
+  if constexpr (B1) wstore_bands(bl, bands);
+  const int done = F.st->done;
   __syncthreads();
   if (done) return;
 
@@ -931,8 +967,7 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
   __shared__ double sh[FT / 64];
   const Level<T> F = Fs[blockIdx.z];
   SolveState* st = F.st;
-  const int done = st->done;  // one problem: tested once the region's loads are in flight
-  if (gridDim.z > 1 && done) return;
+  if (batched_done(st)) return;
   const Level<T> C = Cs[blockIdx.z];
   const bool wtd = F.wl != nullptr;  // adaptive omega_l
   const T wv = wtd ? *F.wl : (T)1;
@@ -945,14 +980,64 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
   MG_LDS T* bl = ec + CW * CR;
   const WMap m{tx * TX, ty * TY, H, F.nx, F.ny, F.py};
   const int wave = wave_id(), lane = threadIdx.x & 63;
-  if constexpr (B1) wload_bands(F, m, bl);
+  WBands<T> bands{};
+  if constexpr (B1) bands = wfetch_bands(F, m);
+
+  // Every global load of the region's first rows, of the coarse correction
+  // and (POST_MIXED) of the FP64 iterate at the wave's first output rows is
+  // issued before the first wait, so the pass waits on memory about once.
+  const int la = lane, lb = lane + 64;
+  const int ca = wcol(la), cb = wcol(lb);
+  const bool oka = m.col_ok(la), okb = m.col_ok(lb);
+  const int ga = m.gi(la), gb = m.gi(lb);
+  T ta[ULR], tb[ULR], ba[ULR], bb[ULR];
+  auto load_rows = [&](int lj0, auto nrows) {
+    constexpr int NR = decltype(nrows)::value;
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const int lj = lj0 + u * NWAVE;
+      ta[u] = tb[u] = ba[u] = bb[u] = (T)0;
+      if (lj < R && m.row_ok(lj)) {
+        const size_t row = (size_t)m.wrapj(m.gj(lj)) * F.pitch;
+        if (oka) {
+          ta[u] = F.t[row + ga];
+          ba[u] = F.b[row + ga];
+        }
+        if (okb) {
+          tb[u] = F.t[row + gb];
+          bb[u] = F.b[row + gb];
+        }
+      }
+    }
+  };
+  load_rows(wave, std::integral_constant<int, ULR>{});
+
+  const int oa = H + lane, ob = H + lane + 64;
+  const bool ooka = m.col_ok(oa), ookb = ob < H + TX && m.col_ok(ob);
+  const int oga = m.gi(oa), ogb = m.gi(ob);
+  // (only the FP32 finest level runs POST_MIXED)
+  constexpr bool MIX = FINE && std::is_same<T, float>::value;
+  double pxa[UL], pxb[UL];
+  if (MIX && mode == POST_MIXED) {
+    const Level<double>& X = X64s[blockIdx.z];
+#pragma unroll
+    for (int u = 0; u < UL; ++u) {
+      const int lj = H + wave + u * NWAVE, gj = m.gj(lj);
+      pxa[u] = pxb[u] = 0.0;
+      if (lj < H + TY && m.row_ok(lj) && gj < F.ny) {
+        const double* xrow = X.x + (size_t)gj * X.pitch;
+        if (ooka) pxa[u] = xrow[oga];
+        if (ookb) pxb[u] = xrow[ogb];
+      }
+    }
+  }
 
   // coarse correction covering the region
   const int cI0 = m.gi(0) >> 1, cJ0 = m.gj(0) >> 1;
   {
     const int clo = C.py ? 0 : 1, chi = C.py ? C.ny - 1 : C.ny - 2;
     const int Ia = cI0 + lane, Ib = cI0 + lane + 64;
-    const bool oka = Ia >= 1 && Ia <= C.nx - 2, okb = lane + 64 < CW && Ib >= 1 && Ib <= C.nx - 2;
+    const bool eoka = Ia >= 1 && Ia <= C.nx - 2, eokb = lane + 64 < CW && Ib >= 1 && Ib <= C.nx - 2;
     for (int r0 = wave; r0 < CR; r0 += NWAVE * UL) {
       T va[UL], vb[UL];
 #pragma unroll
@@ -965,8 +1050,8 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
         va[u] = vb[u] = (T)0;
         if (r0 + u * NWAVE < CR && J >= clo && J <= chi) {
           const T* row = C.x + (size_t)J * C.pitch;
-          if (oka) va[u] = row[Ia];
-          if (okb) vb[u] = row[Ib];
+          if (eoka) va[u] = row[Ia];
+          if (eokb) vb[u] = row[Ib];
         }
       }
 #pragma unroll
@@ -978,33 +1063,14 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
       }
     }
   }
+  if constexpr (B1) wstore_bands(bl, bands);
   __syncthreads();
   {
-    const int la = lane, lb = lane + 64;
-    const int ca = wcol(la), cb = wcol(lb);
-    const bool oka = m.col_ok(la), okb = m.col_ok(lb);
-    const int ga = m.gi(la), gb = m.gi(lb);
     const int ea = (ga >> 1) - cI0, eb = (gb >> 1) - cI0;
-    for (int lj0 = wave; lj0 < R; lj0 += NWAVE * UL) {
-      T ta[UL], tb[UL], ba[UL], bb[UL];
+    auto store_rows = [&](int lj0, auto nrows) {
+      constexpr int NR = decltype(nrows)::value;
 #pragma unroll
-      for (int u = 0; u < UL; ++u) {
-        const int lj = lj0 + u * NWAVE;
-        ta[u] = tb[u] = ba[u] = bb[u] = (T)0;
-        if (lj < R && m.row_ok(lj)) {
-          const size_t row = (size_t)m.wrapj(m.gj(lj)) * F.pitch;
-          if (oka) {
-            ta[u] = F.t[row + ga];
-            ba[u] = F.b[row + ga];
-          }
-          if (okb) {
-            tb[u] = F.t[row + gb];
-            bb[u] = F.b[row + gb];
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < UL; ++u) {
+      for (int u = 0; u < NR; ++u) {
         const int lj = lj0 + u * NWAVE;
         if (lj >= R) break;
         const int gj = m.gj(lj);
@@ -1026,57 +1092,63 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
           r[2 * WW + cb] = (T)0;
         }
       }
+    };
+    store_rows(wave, std::integral_constant<int, ULR>{});
+    for (int lj0 = wave + NWAVE * ULR; lj0 < R; lj0 += NWAVE * UL) {
+      load_rows(lj0, std::integral_constant<int, UL>{});
+      store_rows(lj0, std::integral_constant<int, UL>{});
     }
   }
+  const int done = F.st->done;
   __syncthreads();
   if (done) return;
 
   const int xsrc = wsmooth<T, K, NCOL, B1>(F, m, lds, bl, R, nsteps, omega);
 
-  {
-    const int la = H + lane, lb = H + lane + 64;
-    const bool oka = m.col_ok(la), okb = lb < H + TX && m.col_ok(lb);
-    const int ga = m.gi(la), gb = m.gi(lb);
-    if (mode == POST_MIXED) {
-      const Level<double>& X = X64s[blockIdx.z];
-      for (int lj0 = H + wave; lj0 < H + TY; lj0 += NWAVE * UL) {
-        double xa[UL], xb[UL];
+  if (MIX && mode == POST_MIXED) {
+    const Level<double>& X = X64s[blockIdx.z];
+    for (int lj0 = H + wave; lj0 < H + TY; lj0 += NWAVE * UL) {
+      double xa[UL], xb[UL];
+      const bool first = lj0 == H + wave;  // loaded before the sweeps
 #pragma unroll
-        for (int u = 0; u < UL; ++u) {
-          const int lj = lj0 + u * NWAVE, gj = m.gj(lj);
+      for (int u = 0; u < UL; ++u) {
+        const int lj = lj0 + u * NWAVE, gj = m.gj(lj);
+        xa[u] = pxa[u];
+        xb[u] = pxb[u];
+        if (!first) {
           xa[u] = xb[u] = 0.0;
           if (lj < H + TY && m.row_ok(lj) && gj < F.ny) {
             const double* xrow = X.x + (size_t)gj * X.pitch;
-            if (oka) xa[u] = xrow[ga];
-            if (okb) xb[u] = xrow[gb];
+            if (ooka) xa[u] = xrow[oga];
+            if (ookb) xb[u] = xrow[ogb];
           }
         }
+      }
 #pragma unroll
-        for (int u = 0; u < UL; ++u) {
-          const int lj = lj0 + u * NWAVE, gj = m.gj(lj);
-          if (!(lj < H + TY && m.row_ok(lj) && gj < F.ny)) continue;
-          const MG_LDS T* r = lds + lj * P + xsrc * WW;
-          double* xrow = X.x + (size_t)gj * X.pitch;
-          T* row = F.x + (size_t)gj * F.pitch;
-          if (oka) {
-            xrow[ga] = xa[u] + (double)r[wcol(la)];
-            row[ga] = (T)0;
-          }
-          if (okb) {
-            xrow[gb] = xb[u] + (double)r[wcol(lb)];
-            row[gb] = (T)0;
-          }
+      for (int u = 0; u < UL; ++u) {
+        const int lj = lj0 + u * NWAVE, gj = m.gj(lj);
+        if (!(lj < H + TY && m.row_ok(lj) && gj < F.ny)) continue;
+        const MG_LDS T* r = lds + lj * P + xsrc * WW;
+        double* xrow = X.x + (size_t)gj * X.pitch;
+        T* row = F.x + (size_t)gj * F.pitch;
+        if (ooka) {
+          xrow[oga] = xa[u] + (double)r[wcol(oa)];
+          row[oga] = (T)0;
+        }
+        if (ookb) {
+          xrow[ogb] = xb[u] + (double)r[wcol(ob)];
+          row[ogb] = (T)0;
         }
       }
-    } else {
-      for (int lj = H + wave; lj < H + TY; lj += NWAVE) {
-        const int gj = m.gj(lj);
-        if (!m.row_ok(lj) || gj >= F.ny) continue;
-        const MG_LDS T* r = lds + lj * P + xsrc * WW;
-        T* row = F.x + (size_t)gj * F.pitch;
-        if (oka) row[ga] = r[wcol(la)];
-        if (okb) row[gb] = r[wcol(lb)];
-      }
+    }
+  } else {
+    for (int lj = H + wave; lj < H + TY; lj += NWAVE) {
+      const int gj = m.gj(lj);
+      if (!m.row_ok(lj) || gj >= F.ny) continue;
+      const MG_LDS T* r = lds + lj * P + xsrc * WW;
+      T* row = F.x + (size_t)gj * F.pitch;
+      if (ooka) row[oga] = r[wcol(oa)];
+      if (ookb) row[ogb] = r[wcol(ob)];
     }
   }
   if (mode == POST_NORM) {
