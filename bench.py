@@ -67,6 +67,13 @@ def parse():
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the HBM traffic summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
                          "this bench with --calibrate-copy, and exit")
+    ap.add_argument("--trace", metavar="KERNEL_TRACE_CSV",
+                    help="with --stats-summary: also break the time down by kernel and grid size (level)")
+    ap.add_argument("--counters-summary", nargs="+", metavar="COUNTER_CSV",
+                    help="print a markdown summary of rocprofv3 --pmc counter_collection.csv files (SQ counters "
+                         "per dispatch of each kernel) and exit")
+    ap.add_argument("--durations", metavar="KERNEL_STATS_CSV",
+                    help="with --counters-summary: kernel durations for per-CU issue rates")
     ap.add_argument("--command", default="", help="command line recorded in a summary")
     return ap.parse_args()
 
@@ -125,7 +132,81 @@ def _csv_rows(path):
         return list(csv.DictReader(f))
 
 
-def stats_summary(path: str, command: str) -> str:
+def trace_breakdown(path: str, top: int = 30) -> list:
+    """Markdown rows: time per (kernel, grid size) from a kernel_trace.csv;
+    the grid size tells the levels of one kernel apart."""
+    acc = {}
+    for r in _csv_rows(path):
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        key = (name, int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]), int(r["Workgroup_Size_X"]))
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        a = acc.setdefault(key, [0, 0.0])
+        a[0] += 1
+        a[1] += d
+    out = ["", "Time by kernel and grid (workgroups = grid / workgroup size; one grid size per level):", "",
+           "| calls | total ms | avg us | workgroups | kernel |", "|---|---|---|---|---|"]
+    for (name, grid, wg), (n, t) in sorted(acc.items(), key=lambda kv: -kv[1][1])[:top]:
+        out.append(f"| {n} | {t / 1e3:.3f} | {t / n:.2f} | {grid // wg} | `{name}` |")
+    return out
+
+
+# counters of a --counters-summary table, in this order, and derived ratios
+SQ_ORDER = ["SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS",
+            "SQ_INSTS_SMEM", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INSTS_BRANCH", "SQ_ACTIVE_INST_ANY",
+            "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_SCA", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+            "SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT"]
+CHIP_CUS, CLOCK_GHZ = 256, 2.4
+
+
+def counters_summary(paths, durations, command: str) -> str:
+    """Per kernel: each SQ counter's mean per dispatch over the given
+    counter_collection.csv files, and the ratios that tell what bounds it.
+    With kernel durations, instructions per CU per cycle at 2.4 GHz (a CU
+    issues at most one VALU and one SALU wave-instruction per cycle)."""
+    per = {}
+    for path in paths:
+        seen = {}
+        for r in _csv_rows(path):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            c = per.setdefault(name, {})
+            c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            seen.setdefault((name, r["Counter_Name"]), set()).add(r["Dispatch_Id"])
+        for (name, cn), ds in seen.items():
+            per[name][cn] /= len(ds)
+    dur = {}
+    if durations:
+        for r in _csv_rows(durations):
+            dur[r["Name"].split("(")[0].replace("void ", "")] = float(r["AverageNs"])
+    names = sorted(per)
+    out = ["# SQ counters per dispatch (rocprofv3 --pmc)", "", f"Command: `{command}`", "",
+           "| counter | " + " | ".join(f"`{n}`" for n in names) + " |", "|---|" + "---|" * len(names)]
+    for cn in SQ_ORDER:
+        if any(cn in per[n] for n in names):
+            out.append(f"| {cn} | " + " | ".join(f"{per[n].get(cn, float('nan')):.4g}" for n in names) + " |")
+
+    def ratio(n, a, b):
+        x, y = per[n].get(a), per[n].get(b)
+        return f"{x / y:.3f}" if x is not None and y else "-"
+
+    out.append("| SALU / VALU instructions | " + " | ".join(ratio(n, "SQ_INSTS_SALU", "SQ_INSTS_VALU") for n in names) + " |")
+    out.append("| waiting (any) / wave cycles | " + " | ".join(ratio(n, "SQ_WAIT_ANY", "SQ_WAVE_CYCLES") for n in names) + " |")
+    out.append("| waiting on dependencies / wave cycles | " + " | ".join(ratio(n, "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES") for n in names) + " |")
+    out.append("| issuing / wave cycles | " + " | ".join(ratio(n, "SQ_ACTIVE_INST_ANY", "SQ_WAVE_CYCLES") for n in names) + " |")
+    out.append("| LDS bank conflicts / LDS active | " + " | ".join(ratio(n, "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS") for n in names) + " |")
+    if dur:
+        def per_cu(n, cn):
+            if cn not in per[n] or n not in dur:
+                return "-"
+            cycles = dur[n] * CLOCK_GHZ
+            return f"{per[n][cn] / CHIP_CUS / cycles:.2f}"
+        out.append("| average duration us | " + " | ".join(f"{dur.get(n, float('nan')) / 1e3:.2f}" for n in names) + " |")
+        out.append("| VALU issue per CU per cycle | " + " | ".join(per_cu(n, "SQ_INSTS_VALU") for n in names) + " |")
+        out.append("| SALU issue per CU per cycle | " + " | ".join(per_cu(n, "SQ_INSTS_SALU") for n in names) + " |")
+        out.append("| LDS instructions per CU per cycle | " + " | ".join(per_cu(n, "SQ_INSTS_LDS") for n in names) + " |")
+    return "\n".join(out) + "\n"
+
+
+def stats_summary(path: str, command: str, trace: str = None) -> str:
     rows = _csv_rows(path)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
@@ -137,6 +218,8 @@ def stats_summary(path: str, command: str) -> str:
         out.append(f"| {int(r['Calls'])} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                    f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                    f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} | `{name}` |")
+    if trace:
+        out += trace_breakdown(trace)
     return "\n".join(out) + "\n"
 
 
@@ -873,7 +956,10 @@ def sphere2049(args, rates=None):
 def main():
     args = parse()
     if args.stats_summary:
-        sys.stdout.write(stats_summary(args.stats_summary, args.command))
+        sys.stdout.write(stats_summary(args.stats_summary, args.command, args.trace))
+        return
+    if args.counters_summary:
+        sys.stdout.write(counters_summary(args.counters_summary, args.durations, args.command))
         return
     if args.traffic_summary:
         sys.stdout.write(traffic_summary(*args.traffic_summary, args.command))
