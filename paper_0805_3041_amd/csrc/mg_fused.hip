@@ -654,14 +654,10 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // an unknown of the colour store.  SOR: relaxation factor != 1 (a plain
 // Gauss-Seidel sweep then has no per-node test).
 template <typename T, int K, int NCOL, bool B1, int Q, bool SOR>
-__device__ void wcolour_rows(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG_LDS T* bl, int hiR, int lj0,
+__device__ void wcolour_rows(const Level<T>& L, const WMap& m, MG_LDS T* lds, const Cf<T>& col, int hiR, int lj0,
                              int rstep, int A, bool lane_ok, int gi, T omega) {
   constexpr int P = wide_narr<NCOL>() * WW;
   constexpr int own = Q ? WH : 0;
-  Cf<T> col{};
-  if constexpr (K == ST9 && B1) {
-    if (lane_ok) col = wcoef_cols<T, Q>(bl, A);
-  }
   const int step = rstep * NWAVE;
   auto node = [&](int lj) -> T {
     const Nbr<T> v = wgather<T, K, P, Q, false>(lds + (lj - 1) * P + A);
@@ -693,10 +689,41 @@ __device__ void wcolour_rows(const Level<T>& L, const WMap& m, MG_LDS T* lds, co
   }
 }
 
+// Lane plan of a pass's colour sweeps: lane l owns column q + 2 l of each
+// local column parity q for every sweep (half-index A = l), so whether the
+// column is an unknown, its global index and (1-D bands) its coefficients
+// are found once per pass; a sweep only masks the columns outside the
+// region shrunk by s.  A lane outside the unknowns still loads (its results
+// are not stored), at an interior column for global band reads.
+template <typename T>
+struct WLanes {
+  bool ok[2];
+  int gi[2];
+  Cf<T> col[2];
+};
+
+template <typename T, int K, bool B1>
+__device__ __forceinline__ WLanes<T> wlanes(const WMap& m, const MG_LDS T* bl) {
+  const int lane = threadIdx.x & 63;
+  WLanes<T> w;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int li = q + 2 * lane;
+    w.ok[q] = m.col_ok(li);
+    w.gi[q] = w.ok[q] ? m.gi(li) : 1;
+    w.col[q] = Cf<T>{};
+  }
+  if constexpr (K == ST9 && B1) {
+    w.col[0] = wcoef_cols<T, 0>(bl, lane);
+    w.col[1] = wcoef_cols<T, 1>(bl, lane);
+  }
+  return w;
+}
+
 // One Gauss-Seidel colour sweep over the region shrunk by s (colours as in
 // sweep_colour; i0, j0 are even, so local and global parities agree up to H).
 template <typename T, int K, int NCOL, bool B1>
-__device__ void wsweep_colour(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG_LDS T* bl, int R, int s,
+__device__ void wsweep_colour(const Level<T>& L, const WMap& m, MG_LDS T* lds, const WLanes<T>& w, int R, int s,
                               int c, T omega) {
   const int wave = wave_id(), lane = threadIdx.x & 63;
   int q, lj0, rstep;
@@ -711,21 +738,21 @@ __device__ void wsweep_colour(const Level<T>& L, const WMap& m, MG_LDS T* lds, c
     rstep = 1;
     q = (c + s + wave) & 1;
   }
-  const int li = s + ((s ^ q) & 1) + 2 * lane;
-  const bool lane_ok = li < WW - s && m.col_ok(li);
-  // a lane outside the unknowns still loads (its results are not stored):
-  // give it an interior column for global band reads
-  const int gi = lane_ok ? m.gi(li) : 1;
+  const int li = q + 2 * lane;
   if (omega == (T)1) {
     if (q)
-      wcolour_rows<T, K, NCOL, B1, 1, false>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi, omega);
+      wcolour_rows<T, K, NCOL, B1, 1, false>(L, m, lds, w.col[1], R - s, lj0, rstep, lane,
+                                             w.ok[1] && li >= s && li < WW - s, w.gi[1], omega);
     else
-      wcolour_rows<T, K, NCOL, B1, 0, false>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi, omega);
+      wcolour_rows<T, K, NCOL, B1, 0, false>(L, m, lds, w.col[0], R - s, lj0, rstep, lane,
+                                             w.ok[0] && li >= s && li < WW - s, w.gi[0], omega);
   } else {
     if (q)
-      wcolour_rows<T, K, NCOL, B1, 1, true>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi, omega);
+      wcolour_rows<T, K, NCOL, B1, 1, true>(L, m, lds, w.col[1], R - s, lj0, rstep, lane,
+                                            w.ok[1] && li >= s && li < WW - s, w.gi[1], omega);
     else
-      wcolour_rows<T, K, NCOL, B1, 0, true>(L, m, lds, bl, R - s, lj0, rstep, li >> 1, lane_ok, gi, omega);
+      wcolour_rows<T, K, NCOL, B1, 0, true>(L, m, lds, w.col[0], R - s, lj0, rstep, lane,
+                                            w.ok[0] && li >= s && li < WW - s, w.gi[0], omega);
   }
 }
 
@@ -788,10 +815,11 @@ __device__ int wsmooth(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG
     }
     return (nsteps & 1) ? 2 : 0;
   } else {
+    const WLanes<T> w = wlanes<T, K, B1>(m, bl);
     int s = 1;
     for (int k = 0; k < nsteps; ++k)
       for (int c = 0; c < NCOL; ++c, ++s) {
-        wsweep_colour<T, K, NCOL, B1>(L, m, lds, bl, R, s, c, omega);
+        wsweep_colour<T, K, NCOL, B1>(L, m, lds, w, R, s, c, omega);
         __syncthreads();
       }
     return 0;

@@ -990,7 +990,12 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
   __shared__ T wsh[MAX_LEVELS];        // adaptive omega_l per level, set by OP_OMEGA
   const int slot = blockIdx.z;
   const Level<T>* Ls = levs + (size_t)slot * nlev;
-  if (Ls[0].st->done) return;
+  // A batched launch skips a finished problem at once; one problem reads the
+  // flag with its first loads and tests it before the first op (nothing is
+  // stored before that), so the preamble's loads do not wait on it.
+  if (gridDim.z > 1) {
+    if (Ls[0].st->done) return;
+  }
   const int tid = threadIdx.x;
   const int b0 = beg[slot], nops = cnt[slot];
   const bool ops_in_lds = nops <= MAX_SUB_OPS;
@@ -1010,32 +1015,75 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
       }
     soff = o;
   }
+  const int done = Ls[0].st->done;
   __syncthreads();
   if (IN_LDS) {
-    const int total = offs[nlev];
-    for (int k = tid; k < total; k += SUB_NT) lds[k] = (T)0;
-    if (B1)
-      for (int l = top; l < nlev; ++l) {
-        const Level<T>& Lb = Ls[l];
-        MG_LDS T* dst = lds + boffs[l];
-        for (int k = tid; k < NBANDS * Lb.nx; k += SUB_NT) {
-          const int band = k / Lb.nx, i = k - band * Lb.nx;
-          dst[k] = bandp(Lb, band)[i];
+    // One phase, one barrier: the top level's interior x and b and every
+    // level's 1-D bands are loaded (several loads in flight per thread)
+    // while every other entry of the levels is zeroed.
+    const Level<T> G = Ls[top];
+    const int gnx = G.nx, gny = G.ny, gn = gnx * gny;
+    const int lo = row_lo(G), nr = row_hi(G) - lo + 1, ni = gnx - 2, n = nr * ni;
+    MG_LDS T* xl = lds + offs[top];
+    MG_LDS T* bl = xl + gn;
+    constexpr int UB = 4;
+    const FDiv dni(ni);
+    for (int idx0 = tid; idx0 < n; idx0 += UB * SUB_NT) {
+      T xv[UB], bv[UB];
+      int pos[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int idx = idx0 + u * SUB_NT;
+        pos[u] = -1;
+        if (idx < n) {
+          const int r = dni.q(idx);
+          const int i = idx - r * ni + 1, j = lo + r;
+          pos[u] = j * gnx + i;
+          xv[u] = G.x[(size_t)j * G.pitch + i];
+          bv[u] = G.b[(size_t)j * G.pitch + i];
         }
       }
-    __syncthreads();
-    const Level<T> G = Ls[top];
-    const int lo = row_lo(G), nr = row_hi(G) - lo + 1, ni = G.nx - 2, n = nr * ni;
-    MG_LDS T* xl = lds + offs[top];
-    MG_LDS T* bl = xl + G.nx * G.ny;
-    for (int idx = tid; idx < n; idx += SUB_NT) {
-      const int r = idx / ni;
-      const int i = idx - r * ni + 1, j = lo + r;
-      xl[j * G.nx + i] = G.x[(size_t)j * G.pitch + i];
-      bl[j * G.nx + i] = G.b[(size_t)j * G.pitch + i];
+#pragma unroll
+      for (int u = 0; u < UB; ++u)
+        if (pos[u] >= 0) {
+          xl[pos[u]] = xv[u];
+          bl[pos[u]] = bv[u];
+        }
     }
+    if (B1) {
+      int nb = 0;
+      for (int l = top; l < nlev; ++l) nb += NBANDS * Ls[l].nx;
+      for (int e = tid; e < nb; e += SUB_NT) {
+        int l = top, k = e;
+        while (k >= NBANDS * Ls[l].nx) {
+          k -= NBANDS * Ls[l].nx;
+          ++l;
+        }
+        const Level<T>& Lb = Ls[l];
+        const int band = k / Lb.nx, i = k - band * Lb.nx;
+        lds[boffs[l] + k] = bandp(Lb, band)[i];
+      }
+    }
+    // zeros: the top level's boundary nodes of x and b, its t (Jacobi), and
+    // every coarser level
+    for (int k = tid; k < 2 * gny; k += SUB_NT) {
+      const int arr = k / gny, j = k - arr * gny;
+      MG_LDS T* a = xl + arr * gn + j * gnx;
+      a[0] = (T)0;
+      a[gnx - 1] = (T)0;
+    }
+    if (!G.py)
+      for (int k = tid; k < 2 * gnx; k += SUB_NT) {
+        const int arr = k / gnx, i = k - arr * gnx;
+        MG_LDS T* a = xl + arr * gn + i;
+        a[0] = (T)0;
+        a[(gny - 1) * gnx] = (T)0;
+      }
+    const int total = offs[nlev];
+    for (int k = offs[top] + 2 * gn + tid; k < total; k += SUB_NT) lds[k] = (T)0;
     __syncthreads();
   }
+  if (done) return;
   for (int k = 0; k < nops; ++k) {
     // op and level descriptor through the scalar cache (uniform index)
     int type, l, arg;
