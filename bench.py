@@ -621,10 +621,16 @@ def annulus(args, rates=None):
     print(json.dumps(out), flush=True)
 
 
-# Line sweep (one launch of k_line), per node of the lines it solves: read b,
-# the off-line neighbours (once), the two Thomas factors, write and re-read the
-# forward-sweep value, write x: 7 values (+ six bands when they vary in 2-D).
-LINE_VALUES_PER_NODE = 7
+# Line sweep, per node of the lines it solves.  The kernels that hold a
+# line in LDS (k_line_cr, k_line_y) read b and the off-line neighbours (each
+# once; Jacobi: x itself once) and write x: 3 values.  The thread-per-line
+# Thomas kernel (k_line, lines too long for LDS) also reads the two Thomas
+# factors and writes and re-reads the forward-sweep value: 7 values.  Both
+# add six bands when the coefficients vary in 2-D.
+LINE_VALUES_PER_NODE = {"lds": 3, "thomas": 7}
+# y lines of at least this many unknowns whose four LDS arrays for 4 lines
+# fit in 140 KB run k_line_y (segments), other LDS-fitting lines k_line_cr
+LINE_Y_MIN = 128
 
 SMOOTHER_NAMES = {"tri_x": "TRI (x lines)", "tri_y": "TRI (y lines)", "adi": "ADI", "gstri_x": "GSTRI (x lines)",
                   "gstri_y": "GSTRI (y lines)", "gsadi": "GSADI"}
@@ -644,12 +650,16 @@ def line_roofline(s, rhs, scratch, head, nx, ny, periodic_y, smoother, stencil, 
         lines = [j for j in rows if jac or j % 2 == 0]
         m = nx - 2
     nodes = len(lines) * m
-    bpn = (LINE_VALUES_PER_NODE + (6 if bands_2d else 0) + cells) * w
+    t = "float" if head == "mixed" else "double"
+    if first_y and m >= LINE_Y_MIN and 4 * 4 * (m + m // 32 + 1) * w <= 140 * 1024:
+        kernel = "k_line_y"
+    elif 4 * m * w <= 140 * 1024:
+        kernel = "k_line_cr"
+    else:
+        kernel = "k_line"
+    bpn = (LINE_VALUES_PER_NODE["thomas" if kernel == "k_line" else "lds"] + (6 if bands_2d else 0) + cells) * w
     alg = bpn * nodes
     ach = alg / (us * 1e-6) / 1e9
-    t = "float" if head == "mixed" else "double"
-    # lines whose 4 m values fit 140 KB of LDS run the cyclic-reduction kernel
-    kernel = "k_line_cr" if 4 * m * w <= 140 * 1024 else "k_line"
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": None, "kernel": f"mg::{kernel}<{t}, {stencil}>", "avg_us": us, "bytes_per_launch": alg,
             "bytes_per_node": bpn, "nodes": nodes}

@@ -466,6 +466,244 @@ __global__ void __launch_bounds__(LCR_NT) k_line_cr(const Level<T>* __restrict__
   }
 }
 
+// The same op for lines along y (columns, strided in memory) by segments:
+// a workgroup takes LY_LINES neighbouring lines of the op and LY_SEG
+// threads per line.  Phase 0 reads the lines' rows (consecutive threads on
+// neighbouring lines of one row, so a row's values share cache lines) into
+// LDS as a, d, c and the right-hand side.  A line's nodes are cut by
+// separator nodes every B-th node into LY_SEG segments; phase 1: thread k
+// eliminates segment k forward, for the right-hand side and for the
+// couplings to its two separators (f: left, g: right), keeping in LDS the
+// values its back substitution needs, and forms the segment's end values of
+// the three solutions (first node by the running product of -c'_n, last
+// node directly).  Phase 2 substitutes them into the separators' own
+// equations, a tridiagonal system of LY_SEG - 1 unknowns per line, solved by
+// parallel cyclic reduction in the line's wavefront.  Phase 3 substitutes
+// the separator values back into every segment; phase 4 writes the rows.
+// The result is the exact solution of the same systems as k_line_cr, up to
+// rounding.
+constexpr int LY_SEG = 64;   // segments, and threads, per line (one wavefront)
+constexpr int LY_LINES = 4;  // lines per workgroup
+constexpr int LY_NT = LY_SEG * LY_LINES;
+constexpr int LY_MIN = 2 * LY_SEG;  // shorter lines use k_line_cr
+
+// LDS index of node n of line li (one pad per 32 nodes: segment threads
+// reading their n-th nodes at stride B hit distinct banks for B = 16, 32).
+__device__ __forceinline__ int ly_at(int li, int n, int mp) { return li * mp + n + (n >> 5); }
+
+template <typename T, int K>
+__global__ void __launch_bounds__(LY_NT) k_line_y(const Level<T>* __restrict__ Ls, int arg, T omega) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ T ends[LY_LINES][6][LY_SEG];  // per segment: y, f, g at its first node, then at its last
+  __shared__ T xsep[LY_LINES][LY_SEG + 1];  // separator values, [0] and [nseg] zero
+  const Level<T> L = Ls[blockIdx.z];
+  if (gridDim.z > 1) {
+    if (L.st->done) return;
+  }
+  const int sel = arg >> 2;
+  const bool jac = (arg >> 1) & 1;
+  const int tid = threadIdx.x;
+  const int m = L.ny - 2;
+  const int mp = m + (m >> 5) + 1;
+  MG_LDS T* A = lds_cast<T>(smem_raw);
+  MG_LDS T* D = A + LY_LINES * mp;
+  MG_LDS T* C = D + LY_LINES * mp;
+  MG_LDS T* R = C + LY_LINES * mp;
+  const T* src = (jac && sel) ? L.t : L.x;
+  T* dst = jac ? (sel ? L.x : L.t) : L.x;
+  const int line0 = blockIdx.x * LY_LINES;
+
+  // phase 0: the lines' systems, row by row (a thread's rows of lines up to
+  // 1024 unknowns in one batch of loads)
+  constexpr int UB = 16;
+  for (int idx0 = tid; idx0 < LY_LINES * m; idx0 += UB * LY_NT) {
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int idx = idx0 + u * LY_NT;
+      const int li = idx % LY_LINES, n = idx / LY_LINES;
+      const int line = idx < LY_LINES * m ? line_of(L, 1, jac, sel, line0 + li) : -1;
+      if (line < 0) continue;
+      int i, j;
+      line_node(1, line, n, i, j);
+      const int jm = wrap_dn(j, L.ny, L.py), jp = wrap_up(j, L.ny, L.py);
+      const size_t q = (size_t)j * L.pitch + i;
+      const GX<T> g{src + (size_t)jm * L.pitch + i, src + q, src + (size_t)jp * L.pitch + i};
+      const Cf<T> cf = coefs<K>(L, i, j, jm);
+      T a, d, c;
+      line_coefs<K>(L, 1, cf, a, d, c);
+      const int at = ly_at(li, n, mp);
+      A[at] = n == 0 ? (T)0 : a;
+      C[at] = n == m - 1 ? (T)0 : c;
+      D[at] = d;
+      R[at] = jac ? defect_v<K>(L, cf, gather<K>(L, g, true), L.b[q])
+                  : L.b[q] - off_line<K>(L, 1, cf, gather<K>(L, g, false));
+    }
+  }
+  const int done = L.st->done;
+  __syncthreads();
+  if (done) return;
+
+  // segments: k < nseg; segment k is nodes [k B, e_k], separator k + 1 at
+  // node (k + 1) B - 1 (k < nseg - 1); the last segment ends at m - 1
+  const int li = tid / LY_SEG, k = tid % LY_SEG;
+  const bool live = line_of(L, 1, jac, sel, line0 + li) >= 0;
+  const int nseg = min(LY_SEG, (m + 1) / 2);
+  const int B = (m + 1) / nseg;
+  const int s0 = k * B, e0 = k == nseg - 1 ? m - 1 : (k + 1) * B - 2;
+  const bool seg = live && k < nseg;
+
+  // phase 1: forward elimination of the segment, in place: C <- c'_n, R <- y'_n, A <- f'_n;
+  // the segment moves through registers in chunks of LY_CH nodes (one LDS
+  // round trip per chunk, not per node)
+  constexpr int LY_CH = 16;
+  if (seg) {
+    T cpp = (T)0, ypp = (T)0, fpp = (T)0, P = (T)1, sy = (T)0, sf = (T)0, gl = (T)0, sg = (T)0;
+    T yl = (T)0, fl = (T)0;
+    for (int c0 = s0; c0 <= e0; c0 += LY_CH) {
+      T a[LY_CH], d[LY_CH], c[LY_CH], r[LY_CH];
+#pragma unroll
+      for (int u = 0; u < LY_CH; ++u)
+        if (c0 + u <= e0) {
+          const int at = ly_at(li, c0 + u, mp);
+          a[u] = A[at];
+          d[u] = D[at];
+          c[u] = C[at];
+          r[u] = R[at];
+        }
+#pragma unroll
+      for (int u = 0; u < LY_CH; ++u) {
+        const int n = c0 + u;
+        if (n > e0) continue;
+        const T inv = (T)1 / (d[u] - a[u] * cpp);
+        const T cp = c[u] * inv;
+        const T yp = (r[u] - a[u] * ypp) * inv;
+        const T fp = (n == s0 ? -a[u] : -(a[u] * fpp)) * inv;
+        c[u] = cp;
+        r[u] = yp;
+        a[u] = fp;
+        sy += P * yp;
+        sf += P * fp;
+        if (n == e0) {
+          yl = yp;
+          fl = fp;
+          gl = k < nseg - 1 ? -cp : (T)0;
+          sg = P * gl;
+        }
+        P *= -cp;
+        cpp = cp;
+        ypp = yp;
+        fpp = fp;
+      }
+#pragma unroll
+      for (int u = 0; u < LY_CH; ++u)
+        if (c0 + u <= e0) {
+          const int at = ly_at(li, c0 + u, mp);
+          A[at] = a[u];
+          C[at] = c[u];
+          R[at] = r[u];
+        }
+    }
+    ends[li][0][k] = sy;
+    ends[li][1][k] = sf;
+    ends[li][2][k] = sg;
+    ends[li][3][k] = yl;
+    ends[li][4][k] = fl;
+    ends[li][5][k] = gl;
+  }
+  __syncthreads();
+
+  // phase 2: separator equations (thread k holds separator k, 1 <= k < nseg),
+  // parallel cyclic reduction within the line's wavefront
+  {
+    const bool own = live && k >= 1 && k < nseg;
+    T lo = (T)0, di = (T)1, up = (T)0, rh = (T)0;
+    if (own) {
+      const int at = ly_at(li, k * B - 1, mp);
+      const T a = A[at], d = D[at], c = C[at], r = R[at];
+      lo = a * ends[li][4][k - 1];
+      di = d + a * ends[li][5][k - 1] + c * ends[li][1][k];
+      up = k + 1 < nseg ? c * ends[li][2][k] : (T)0;
+      rh = r - a * ends[li][3][k - 1] - c * ends[li][0][k];
+      if (k == 1) lo = (T)0;  // segment 0 has no left separator (its f is zero)
+    }
+    for (int h = 1; h < nseg; h *= 2) {
+      T lo_m = __shfl_up(lo, h, LY_SEG), di_m = __shfl_up(di, h, LY_SEG), up_m = __shfl_up(up, h, LY_SEG),
+        rh_m = __shfl_up(rh, h, LY_SEG);
+      T lo_p = __shfl_down(lo, h, LY_SEG), di_p = __shfl_down(di, h, LY_SEG), up_p = __shfl_down(up, h, LY_SEG),
+        rh_p = __shfl_down(rh, h, LY_SEG);
+      if (k - h < 1) {  // no equation at k - h: identity
+        lo_m = (T)0;
+        di_m = (T)1;
+        up_m = (T)0;
+        rh_m = (T)0;
+      }
+      if (k + h >= nseg) {
+        lo_p = (T)0;
+        di_p = (T)1;
+        up_p = (T)0;
+        rh_p = (T)0;
+      }
+      const T al = -lo / di_m, ga = -up / di_p;
+      const T ndi = di + al * up_m + ga * lo_p;
+      const T nrh = rh + al * rh_m + ga * rh_p;
+      lo = al * lo_m;
+      up = ga * up_p;
+      di = ndi;
+      rh = nrh;
+    }
+    if (own) xsep[li][k] = rh / di;
+    if (k == 0) {
+      xsep[li][0] = (T)0;
+      xsep[li][nseg] = (T)0;
+    }
+  }
+  __syncthreads();
+
+  // phase 3: back substitution of each segment with its separators' values
+  // (chunks of LY_CH nodes from the segment's end)
+  if (seg) {
+    const T xl = xsep[li][k], xr = xsep[li][k + 1];
+    T xn = (T)0;
+    for (int c1 = e0; c1 >= s0; c1 -= LY_CH) {
+      T a[LY_CH], c[LY_CH], r[LY_CH];
+#pragma unroll
+      for (int u = 0; u < LY_CH; ++u)
+        if (c1 - u >= s0) {
+          const int at = ly_at(li, c1 - u, mp);
+          a[u] = A[at];
+          c[u] = C[at];
+          r[u] = R[at];
+        }
+#pragma unroll
+      for (int u = 0; u < LY_CH; ++u) {
+        const int n = c1 - u;
+        if (n < s0) continue;
+        T v = r[u] + a[u] * xl;
+        v = n == e0 ? v + (k < nseg - 1 ? -c[u] : (T)0) * xr : v - c[u] * xn;
+        r[u] = v;
+        xn = v;
+      }
+#pragma unroll
+      for (int u = 0; u < LY_CH; ++u)
+        if (c1 - u >= s0) R[ly_at(li, c1 - u, mp)] = r[u];
+    }
+    if (k >= 1) R[ly_at(li, k * B - 1, mp)] = xsep[li][k];
+  }
+  __syncthreads();
+
+  // phase 4: the lines' new values, row by row
+  for (int idx = tid; idx < LY_LINES * m; idx += LY_NT) {
+    const int li2 = idx % LY_LINES, n = idx / LY_LINES;
+    const int line = line_of(L, 1, jac, sel, line0 + li2);
+    if (line < 0) continue;
+    int i, j;
+    line_node(1, line, n, i, j);
+    const size_t q = (size_t)j * L.pitch + i;
+    const T u = R[ly_at(li2, n, mp)];
+    dst[q] = jac ? src[q] + omega * u : u;
+  }
+}
+
 template <typename T>
 int line_count(const Level<T>& L, int dir) {
   return dir == 0 ? (L.py ? L.ny : L.ny - 2) : L.nx - 2;
@@ -483,7 +721,8 @@ hipError_t launch_line_factor(const Level<T>& L, int dir, hipStream_t st) {
 
 template <typename T>
 hipError_t prepare_line_cr() {
-  for (const void* k : {(const void*)k_line_cr<T, ST5>, (const void*)k_line_cr<T, ST9>}) {
+  for (const void* k : {(const void*)k_line_cr<T, ST5>, (const void*)k_line_cr<T, ST9>, (const void*)k_line_y<T, ST5>,
+                        (const void*)k_line_y<T, ST9>}) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LCR_LDS_MAX);
     if (e != hipSuccess) return e;
   }
@@ -498,6 +737,15 @@ hipError_t launch_line(const Level<T>* Ls, const LevelShape& s, int arg, T omega
   int lines = dir == 0 ? s.nrows : s.nx - 2;
   if (!jac) lines = (lines + 1) / 2;
   const int m = dir == 0 ? s.nx - 2 : s.ny - 2;
+  const size_t ylds = 4 * (size_t)LY_LINES * (m + (m >> 5) + 1) * sizeof(T);
+  if (dir == 1 && m >= LY_MIN && ylds <= LCR_LDS_MAX) {
+    const dim3 grid((lines + LY_LINES - 1) / LY_LINES, 1, nslots);
+    if (kind == ST5)
+      hipLaunchKernelGGL((k_line_y<T, ST5>), grid, dim3(LY_NT), ylds, st, Ls, arg, omega);
+    else
+      hipLaunchKernelGGL((k_line_y<T, ST9>), grid, dim3(LY_NT), ylds, st, Ls, arg, omega);
+    return hipGetLastError();
+  }
   const size_t lds = 4 * (size_t)m * sizeof(T);
   if (lds <= LCR_LDS_MAX) {
     const dim3 grid(lines, 1, nslots);

@@ -136,8 +136,9 @@ def test_coarse_levels_in_global_memory(smoother, cta):
 ], ids=["gstri_x", "tri_x", "gstri_y", "tri_y"])
 def test_long_lines_by_cyclic_reduction(case):
     """Lines of 1023 unknowns (the finest lines of the 1025^2 workload) through
-    the launched cyclic-reduction kernel: coarse_cta_nodes = 1 keeps every
-    level but the coarsest out of the one-workgroup kernel.  Per cycle 1e-12
+    the launched kernels (x lines: cyclic reduction; y lines of 128 or more
+    unknowns: segments and separators, k_line_y): coarse_cta_nodes = 1 keeps
+    every level but the coarsest out of the one-workgroup kernel.  Per cycle 1e-12
     against the oracle.  Cyclic reduction's forward error on a line is about
     cond(T) log2(m) u, against cond(T) u for the oracle's sparse LU, so the
     cases keep cond(T) near 1e2: 1025 x 33 with eps = 0.05 (x lines:
@@ -147,3 +148,29 @@ def test_long_lines_by_cyclic_reduction(case):
     2.7e-12 after one cycle, the size that bound predicts."""
     p = Problem(**case)
     check_parity(p, W.normal_field(p.nx, p.ny, 2), W.uniform_field(p.nx, p.ny, 1), 3, coarse_cta_nodes=1)
+
+
+@pytest.mark.parametrize("case", [
+    dict(nx=45, ny=257, eps=1.0, smoother="gstri_y"),
+    dict(nx=45, ny=257, eps=10.0, smoother="tri_y", omega=0.8),
+    dict(nx=33, ny=513, eps=10.0, smoother="gsadi"),
+    dict(nx=161, ny=129, eps=1.0, smoother="gsadi"),
+], ids=["gstri_y-257", "tri_y-257", "gsadi-513", "gsadi-129"])
+def test_segmented_y_lines_per_cycle(case):
+    """y lines through the segment-and-separator kernel (k_line_y): 43 or 31
+    lines (colours of 22/21 and 16/15 lines, so the last workgroup of four
+    lines is ragged), lines of 255 and 511 unknowns (4 and 8 nodes per
+    segment, 63 separators) and, on 161 x 129, lines of 127 unknowns that
+    stay on cyclic reduction beside 159-long x lines.  Per cycle 1e-12
+    against the oracle; the y lines keep cond(T) below 1e2."""
+    p = Problem(**case)
+    check_parity(p, W.normal_field(p.nx, p.ny, 2), W.uniform_field(p.nx, p.ny, 1), 3, coarse_cta_nodes=1)
+
+
+def test_segmented_y_lines_nine_point_cells():
+    """y lines of a 9-point operator with per-cell coefficients on the finest
+    level (Gaussian random field, 257^2): the line couplings and the six
+    off-line couplings come from the cells, the coarser levels' from the
+    Galerkin bands."""
+    p = Problem(257, 257, q1="grf", smoother="gstri_y")
+    check_parity(p, W.normal_field(257, 257, 4), np.zeros((257, 257)), 2, coarse_cta_nodes=1)
