@@ -279,14 +279,16 @@ def traffic_summary(fetch_csv: str, write_csv: str, command: str) -> str:
 # (5-point operator): reads and writes the pass cannot avoid.
 #   FP64 pre-pass : read x, b; write smoothed x; write coarse b and x (1/4 node each)
 #   FP64 post-pass: read smoothed x, b, coarse x (1/4); write x
-#   FP32 pre-pass : same with 4-byte values
-#   FP32 post-pass (mixed, finest level): read e, r, coarse e (1/4); read and
-#                   write the FP64 iterate; write e = 0
+#   FP32 pre-pass (mixed, finest level): the correction e starts at 0 and is
+#                   not read: read r; write smoothed e; coarse b and x
+#   FP32 post-pass (mixed, finest level): read smoothed e, r, coarse e (1/4);
+#                   read and write the FP64 iterate (e itself is left as it
+#                   is: the next pre-pass does not read it)
 BYTES_PER_NODE = {
     ("fp64", 0): 8 + 8 + 8 + 2 + 2,
     ("fp64", 1): 8 + 8 + 2 + 8,
-    ("mixed", 0): 4 + 4 + 4 + 1 + 1,
-    ("mixed", 1): 4 + 4 + 1 + 8 + 8 + 4,
+    ("mixed", 0): 4 + 4 + 1 + 1,
+    ("mixed", 1): 4 + 4 + 1 + 8 + 8,
 }
 # Level 1 (a coarse level: plain post-pass, 4- or 8-byte values):
 #   pre-pass : read x, b; write t; write coarse b and x (1/4 node each) = 3.5 w

@@ -522,7 +522,7 @@ hipError_t run_op(mg_handle h, const Group& G, const HostOp& op, Level<T>* dL, L
     case H_LINE: return launch_line<T>(Ls, s, op.arg, omega, stencil_kind(h), ns, st);
     case H_PRE:
       return launch_pre<T>(Ls, Cs, G.gpre[l], h->opts.nu_pre, h->ncol, omega, stencil_kind(h), h->oned, l == 0, ns,
-                           st);
+                           st, op.arg != 0);
     case H_POST:
       return launch_post<T>(Ls, Cs, G.gpost[l], h->opts.nu_post, h->ncol, omega, op.arg, G.dL64, stencil_kind(h),
                             h->oned, l == 0, ns, st);
@@ -539,6 +539,16 @@ hipError_t run_op(mg_handle h, const Group& G, const HostOp& op, Level<T>* dL, L
   return hipErrorInvalidValue;
 }
 
+// Mixed form: the first inner cycle's finest pre-pass takes e = 0 without
+// reading it (so the finest post-pass need not write e = 0) when the cycle
+// starts with that level's wide pre-pass and ends with its fused mixed
+// post-pass (not with the adaptive weight, whose energy sums read the
+// finest iterate).
+bool mixed_zero_start(mg_handle h, const Group& G) {
+  return h->mixed() && G.mixed_fused && !h->opts.adaptive_omega && !G.prog.empty() && G.prog[0].type == H_PRE &&
+         G.prog[0].level == 0 && G.gpre[0].wide;
+}
+
 // One cycle of a group plus its stopping test, on stream st.
 hipError_t enqueue_cycle(mg_handle h, const Group& G, hipStream_t st) {
   hipError_t e = hipSuccess;
@@ -550,12 +560,19 @@ hipError_t enqueue_cycle(mg_handle h, const Group& G, hipStream_t st) {
                                   st);
   }
   // inner FP32 cycles on A e = r32 from e = 0; only the last one adds e into
-  // the FP64 iterate (the finest post-pass of the others keeps e)
+  // the FP64 iterate (the finest post-pass of the others keeps e).  When
+  // the cycle starts with the finest level's wide pre-pass, the first inner
+  // cycle's pre-pass takes e = 0 without reading it, so the last post-pass
+  // need not write e = 0 (not with the adaptive weight, whose energy sums
+  // read the finest iterate)
   const int inner = inner_cycles(h);
+  const bool zero_start = mixed_zero_start(h, G);
   for (int c = 0; c < inner; ++c)
     for (size_t k = 0; k < G.prog.size(); ++k) {
       HostOp op = G.prog[k];
       if (G.mixed_fused && c + 1 < inner && k + 1 == G.prog.size()) op.arg = POST_PLAIN;
+      if (zero_start && c == 0 && k == 0) op.arg = 1;
+      if (zero_start && c + 1 == inner && k + 1 == G.prog.size() && op.arg == POST_MIXED) op.arg = POST_MIXED_KEEP;
       if ((e = run_op<float>(h, G, op, G.dL32, G.dP32, (float)relax(h), st)) != hipSuccess) return e;
     }
   if (!G.mixed_fused && (e = launch_outer_update(G.dL64, G.dL32, G.shp[0], G.ns, st)) != hipSuccess) return e;
@@ -2365,11 +2382,14 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
       return launch_line<double>(G.dL64 + l, G.shp[l], found->arg, h->opts.omega, kind, 1, st);
     }
     if (h->mixed()) {
+      // level 0 as the solve runs it (zero start, e left for the next pre-pass)
+      const bool zs = l == 0 && mixed_zero_start(h, G);
       if (which == 0)
         return launch_pre<float>(G.dL32 + l, G.dL32 + l + 1, G.gpre[l], h->opts.nu_pre, h->ncol,
-                                 (float)relax(h), kind, h->oned, l == 0, 1, st);
+                                 (float)relax(h), kind, h->oned, l == 0, 1, st, zs);
+      const int mode = zs && found->arg == POST_MIXED ? POST_MIXED_KEEP : found->arg;
       return launch_post<float>(G.dL32 + l, G.dL32 + l + 1, G.gpost[l], h->opts.nu_post, h->ncol,
-                                (float)relax(h), found->arg, G.dL64, kind, h->oned, l == 0, 1, st, false);
+                                (float)relax(h), mode, G.dL64, kind, h->oned, l == 0, 1, st, false);
     }
     if (which == 0)
       return launch_pre<double>(G.dL64 + l, G.dL64 + l + 1, G.gpre[l], h->opts.nu_pre, h->ncol, relax(h),

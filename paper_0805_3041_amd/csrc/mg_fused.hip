@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, co
     if (!m.unknown(gi, gj) || gj >= F.ny) continue;
     const size_t p = (size_t)gj * F.pitch + gi;
     const int q = lj * W + li;
-    if (mode == POST_MIXED) {
+    if (mode == POST_MIXED || mode == POST_MIXED_KEEP) {
       const Level<double>& X = X64s[blockIdx.z];
       X.x[(size_t)gj * X.pitch + gi] += (double)xs[q];
       F.x[p] = (T)0;
@@ -862,7 +862,7 @@ __device__ __forceinline__ void wstore_bands(MG_LDS T* bl, const WBands<T>& r) {
 
 template <typename T, int K, bool FINE, int NCOL, bool B1>
 __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs,
-                                              int TY, int H, int ntx, int nty, int nsteps, T omega) {
+                                              int TY, int H, int ntx, int nty, int nsteps, T omega, int zero_x) {
   constexpr int P = wide_narr<NCOL>() * WW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Level<T> F = Fs[blockIdx.z];
@@ -892,11 +892,11 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
         if (lj < R && m.row_ok(lj)) {
           const size_t row = (size_t)m.wrapj(m.gj(lj)) * F.pitch;
           if (oka) {
-            xa[u] = F.x[row + ga];
+            if (!zero_x) xa[u] = F.x[row + ga];
             ba[u] = F.b[row + ga];
           }
           if (okb) {
-            xb[u] = F.x[row + gb];
+            if (!zero_x) xb[u] = F.x[row + gb];
             bb[u] = F.b[row + gb];
           }
         }
@@ -1045,8 +1045,9 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
   const int oga = m.gi(oa), ogb = m.gi(ob);
   // (only the FP32 finest level runs POST_MIXED)
   constexpr bool MIX = FINE && std::is_same<T, float>::value;
+  const bool mixed = mode == POST_MIXED || mode == POST_MIXED_KEEP;
   double pxa[UL], pxb[UL];
-  if (MIX && mode == POST_MIXED) {
+  if (MIX && mixed) {
     const Level<double>& X = X64s[blockIdx.z];
 #pragma unroll
     for (int u = 0; u < UL; ++u) {
@@ -1133,8 +1134,9 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
 
   const int xsrc = wsmooth<T, K, NCOL, B1>(F, m, lds, bl, R, nsteps, omega);
 
-  if (MIX && mode == POST_MIXED) {
+  if (MIX && mixed) {
     const Level<double>& X = X64s[blockIdx.z];
+    const bool zero_e = mode == POST_MIXED;
     for (int lj0 = H + wave; lj0 < H + TY; lj0 += NWAVE * UL) {
       double xa[UL], xb[UL];
       const bool first = lj0 == H + wave;  // loaded before the sweeps
@@ -1161,11 +1163,11 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
         T* row = F.x + (size_t)gj * F.pitch;
         if (ooka) {
           xrow[oga] = xa[u] + (double)r[wcol(oa)];
-          row[oga] = (T)0;
+          if (zero_e) row[oga] = (T)0;
         }
         if (ookb) {
           xrow[ogb] = xb[u] + (double)r[wcol(ob)];
-          row[ogb] = (T)0;
+          if (zero_e) row[ogb] = (T)0;
         }
       }
     }
@@ -1237,7 +1239,7 @@ using PreFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int
 template <typename T>
 using PostFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, int, T, int, const Level<double>*);
 template <typename T>
-using PreWFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, T);
+using PreWFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, T, int);
 template <typename T>
 using PostWFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, T, int, const Level<double>*);
 
@@ -1331,16 +1333,16 @@ hipError_t prepare_fused() {
 
 template <typename T>
 hipError_t launch_pre(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g, int nsteps, int ncol, T omega,
-                      int kind, bool oned, bool fine, int nslots, hipStream_t st) {
+                      int kind, bool oned, bool fine, int nslots, hipStream_t st, bool zero_x) {
   const dim3 grid(g.ntx * g.nty, 1, nslots);
   const size_t lds = pre_lds_bytes<T>(g, ncol);
   if (g.wide) {
     PreWFn<T> k = pick_pre_w<T>(kind, oned, fine, ncol);
     if (!k || g.TX != WW - 2 * g.H) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TY, g.H, g.ntx, g.nty, nsteps, omega);
+    hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TY, g.H, g.ntx, g.nty, nsteps, omega, zero_x ? 1 : 0);
   } else {
     PreFn<T> k = pick_pre<T>(kind, oned, fine, ncol);
-    if (!k) return hipErrorInvalidValue;
+    if (!k || zero_x) return hipErrorInvalidValue;  // zero start: wide tiles only
     hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TX, g.TY, g.H, g.ntx, g.nty, nsteps, omega);
   }
   return hipGetLastError();
@@ -1372,7 +1374,7 @@ hipError_t launch_post(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g
   template size_t post_lds_bytes<T>(const TileGeom&, int);                                                         \
   template hipError_t prepare_fused<T>();                                                                          \
   template hipError_t launch_pre<T>(const Level<T>*, const Level<T>*, const TileGeom&, int, int, T, int, bool,     \
-                                    bool, int, hipStream_t);                                                       \
+                                    bool, int, hipStream_t, bool);                                                 \
   template hipError_t launch_post<T>(const Level<T>*, const Level<T>*, const TileGeom&, int, int, T, int,         \
                                      const Level<double>*, int, bool, bool, int, hipStream_t, bool);
 
