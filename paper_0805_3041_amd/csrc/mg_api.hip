@@ -431,7 +431,7 @@ void fold_sweeps(std::vector<DOp>& flat, size_t b, int ncol) {
     while (q < flat.size() && flat[q].type == OP_COLOR && flat[q].level == flat[k].level &&
            flat[q].arg == (int)((q - k) % ncol))
       ++q;
-    const int sweeps = (int)((q - k) / ncol);
+    const int sweeps = (int)std::min<size_t>((q - k) / ncol, SM_NSW);
     if (sweeps > 0) {
       out.push_back({OP_SMOOTH, flat[k].level, sweeps, 0});
       k += (size_t)sweeps * ncol;
@@ -439,6 +439,32 @@ void fold_sweeps(std::vector<DOp>& flat, size_t b, int ncol) {
       out.push_back(flat[k]);
       ++k;
     }
+  }
+  flat.swap(out);
+}
+
+// Transfers folded into the smoothing blocks beside them (ops from flat[b]
+// on): a prolongation followed by a block on its level becomes that block's
+// SM_PRO (SM_WTD when weighted by omega_l); a block followed by a
+// restriction of its level takes SM_DR.
+void fold_transfers(std::vector<DOp>& flat, size_t b) {
+  std::vector<DOp> out(flat.begin(), flat.begin() + b);
+  for (size_t k = b; k < flat.size(); ++k) {
+    const DOp& o = flat[k];
+    if (o.type == OP_PROLONG && k + 1 < flat.size() && flat[k + 1].type == OP_SMOOTH &&
+        flat[k + 1].level == o.level && !(flat[k + 1].arg & SM_PRO)) {
+      DOp sm = flat[k + 1];
+      sm.arg |= SM_PRO | (o.arg ? SM_WTD : 0);
+      out.push_back(sm);
+      ++k;
+      continue;
+    }
+    if (o.type == OP_DR && out.size() > b && out.back().type == OP_SMOOTH && out.back().level == o.level &&
+        !(out.back().arg & SM_DR)) {
+      out.back().arg |= SM_DR;
+      continue;
+    }
+    out.push_back(o);
   }
   flat.swap(out);
 }
@@ -489,6 +515,7 @@ mg_status build_program(mg_handle h, Group& G) {
       flat.push_back({t, a.level, a.arg, 0});
     }
     fold_sweeps(flat, (size_t)b, h->ncol);
+    fold_transfers(flat, (size_t)b);
     for (size_t k = cnt.size() - G.ns; k < cnt.size(); ++k) cnt[k] = (int)(flat.size() - b);
   }
   G.nsub = (int)subs.size();
@@ -827,6 +854,7 @@ mg_status build_merges(mg_handle h) {
           flat.push_back({t, a.level - op.level, a.arg, 0});
         }
         fold_sweeps(flat, (size_t)b, h->ncol);
+        fold_transfers(flat, (size_t)b);
         std::vector<int> beg(op.n, b), cnt(op.n, (int)(flat.size() - b));
         std::vector<double*> chol;  // one per participant: the first entry of its levels
         for (int k = 0; k < (int)M.groups.size(); ++k)

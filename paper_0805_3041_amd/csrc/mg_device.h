@@ -82,7 +82,17 @@ enum OpType {
   OP_COARSE = 5,    // exact solve on the coarsest `level`
   OP_LINE = 6,      // line sweep on `level`, arg as line_arg
   OP_OMEGA = 7,     // adaptive omega_l of `level` from its x, b and the correction on level+1
-  OP_SMOOTH = 8,    // `arg` Gauss-Seidel sweeps (every colour in order) on `level`
+  OP_SMOOTH = 8,    // Gauss-Seidel sweeps (every colour in order) on `level`, with transfers (SmoothFlags)
+};
+
+// OP_SMOOTH arg: the number of sweeps (bits 0-4); SM_PRO: the level's
+// coarse-grid correction is added first (SM_WTD: times the level's omega_l);
+// SM_DR: the defect is restricted into level + 1 after the sweeps.
+enum SmoothFlags {
+  SM_NSW = 31,
+  SM_PRO = 32,
+  SM_WTD = 64,
+  SM_DR = 128,
 };
 
 // Argument of a line-smoothing op: bit 0 direction (0: lines along x, 1:

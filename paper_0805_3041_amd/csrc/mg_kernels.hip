@@ -883,121 +883,6 @@ __device__ void lds_colour(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, co
   colour_rows<T, K, B1>(L, x, b, bl, i, j, jstep, col, omega);
 }
 
-// `nsw` whole Gauss-Seidel sweeps (colours 0 .. ncol - 1 in order) as one op:
-// the same node updates as nsw * ncol OP_COLOR ops, with each thread's
-// columns and column coefficients found once and a workgroup barrier
-// between colours (the interpreter's own barrier follows the last).  Even
-// and odd colours differ in their column parity only (4 colours) or are the
-// two colours (2 colours), so two coefficient sets cover every colour.
-template <typename T, int K, bool B1, int NCOL>
-__device__ void lds_smooth_n(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int nsw, T omega,
-                             int tid) {
-  const int last = L.nx - 2;
-  int ic[NCOL], jc[NCOL], js[NCOL];
-#pragma unroll
-  for (int c = 0; c < NCOL; ++c) colour_plan(L, c, NCOL, tid, ic[c], jc[c], js[c]);
-  Cf<T> c0{}, c1{};
-  if (K == ST5 || B1) {
-    if (ic[0] <= last) c0 = sub_coefs<T, K, B1>(L, bl, ic[0], 0, 0);
-    if (ic[1] <= last) c1 = sub_coefs<T, K, B1>(L, bl, ic[1], 0, 0);
-  }
-  for (int s = 0; s < nsw; ++s) {
-#pragma unroll
-    for (int c = 0; c < NCOL; ++c) {
-      if (ic[c] <= last) colour_rows<T, K, B1>(L, x, b, bl, ic[c], jc[c], js[c], (c & 1) ? c1 : c0, omega);
-      if (s + 1 < nsw || c + 1 < NCOL) __syncthreads();
-    }
-  }
-}
-
-// Same sweeps when no thread has more than M rows of any colour (the levels
-// at the bottom of the hierarchy): each thread's nodes, their row offsets
-// and right-hand sides (fixed while smoothing) are found once, so a colour
-// step is the gather, the update and the store.
-template <typename T, int K, bool B1, int NCOL, int M>
-__device__ void lds_smooth_few(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int nsw,
-                               T omega, int tid) {
-  const int nx = L.nx, ny = L.ny, py = L.py;
-  const int hi = py ? ny - 1 : ny - 2, last = nx - 2;
-  constexpr bool col_only = K == ST5 || B1;
-  int ic[NCOL], pos[NCOL][M], so[NCOL][M], no[NCOL][M], jr[NCOL][M];
-  T bv[NCOL][M];
-  bool on[NCOL][M];
-#pragma unroll
-  for (int c = 0; c < NCOL; ++c) {
-    int j, jstep;
-    colour_plan(L, c, NCOL, tid, ic[c], j, jstep);
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int jm = j + m * jstep;
-      on[c][m] = ic[c] <= last && jm <= hi;
-      jr[c][m] = jm;
-      pos[c][m] = jm * nx + ic[c];
-      so[c][m] = no[c][m] = 0;
-      bv[c][m] = (T)0;
-      if (on[c][m]) {
-        row_offsets(jm, nx, ny, py, so[c][m], no[c][m]);
-        bv[c][m] = b[pos[c][m]];
-      }
-    }
-  }
-  Cf<T> c0{}, c1{};
-  if (col_only) {
-    if (ic[0] <= last) c0 = sub_coefs<T, K, B1>(L, bl, ic[0], 0, 0);
-    if (ic[1] <= last) c1 = sub_coefs<T, K, B1>(L, bl, ic[1], 0, 0);
-  }
-  for (int s = 0; s < nsw; ++s) {
-#pragma unroll
-    for (int c = 0; c < NCOL; ++c) {
-      Nbr<T> v[M];
-      Cf<T> a[M];
-#pragma unroll
-      for (int m = 0; m < M; ++m)
-        if (on[c][m]) {
-          v[m] = gather<K>(L, LXO<T>{x + pos[c][m], so[c][m], no[c][m]}, false);
-          a[m] = col_only ? ((c & 1) ? c1 : c0)
-                          : sub_coefs<T, K, B1>(L, bl, ic[c], jr[c][m], wrap_dn(jr[c][m], ny, py));
-        }
-#pragma unroll
-      for (int m = 0; m < M; ++m)
-        if (on[c][m]) x[pos[c][m]] = sor_v(gs_v<K>(L, a[m], v[m], bv[c][m]), x + pos[c][m], omega);
-      if (s + 1 < nsw || c + 1 < NCOL) __syncthreads();
-    }
-  }
-}
-
-// Rows per thread of one colour: at most ceil(rows / row stride); the
-// register-resident form where that is 1 (or 2 with two colours).
-template <typename T, int K, bool B1, int NCOL>
-__device__ __forceinline__ void lds_smooth_c(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl,
-                                             int nsw, T omega, int tid) {
-  const int kl = ceil_log2((L.nx - 1) >> 1);
-  const int rstride = (NCOL == 4 ? 2 : 1) * (SUB_NT >> kl);
-  const int rows = L.py ? L.ny : L.ny - 2;
-  const int m = (rows + rstride - 1) / rstride;
-  if (m <= 1)
-    lds_smooth_few<T, K, B1, NCOL, 1>(L, x, b, bl, nsw, omega, tid);
-  else if (NCOL == 2 && m <= 2)  // (two rows of four colours would spill registers)
-    lds_smooth_few<T, K, B1, NCOL, 2>(L, x, b, bl, nsw, omega, tid);
-  else
-    lds_smooth_n<T, K, B1, NCOL>(L, x, b, bl, nsw, omega, tid);
-}
-
-// (9-point operators are smoothed with four colours only: setup rejects
-// red-black Gauss-Seidel for them.)
-template <typename T, int K, bool B1>
-__device__ void lds_smooth(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int nsw, int ncol,
-                           T omega, int tid) {
-  if constexpr (K == ST9) {
-    lds_smooth_c<T, K, B1, 4>(L, x, b, bl, nsw, omega, tid);
-  } else {
-    if (ncol == 4)
-      lds_smooth_c<T, K, B1, 4>(L, x, b, bl, nsw, omega, tid);
-    else
-      lds_smooth_c<T, K, B1, 2>(L, x, b, bl, nsw, omega, tid);
-  }
-}
-
 template <typename T, int K, bool B1>
 __device__ void lds_jacobi(const Level<T>& L, const MG_LDS T* src, MG_LDS T* dst, const MG_LDS T* b,
                            const MG_LDS T* bl, T omega, int tid) {
@@ -1094,6 +979,159 @@ __device__ void lds_prolong(const Level<T>& F, MG_LDS T* xf, const Level<T>& C, 
       v = prolong_combine(r0[0], ox ? r0[1] : (T)0, r1[0], ox ? r1[1] : (T)0, ox, 1);
     }
     xf[j * nx + i] = add_correction(xf[j * nx + i], v, weighted, w);
+  }
+}
+
+// `nsw` whole Gauss-Seidel sweeps (colours 0 .. ncol - 1 in order) as one op:
+// the same node updates as nsw * ncol OP_COLOR ops, with each thread's
+// columns and column coefficients found once and a workgroup barrier
+// between colours (the interpreter's own barrier follows the last).  Even
+// and odd colours differ in their column parity only (4 colours) or are the
+// two colours (2 colours), so two coefficient sets cover every colour.
+template <typename T, int K, bool B1, int NCOL>
+__device__ void lds_smooth_n(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int nsw, T omega,
+                             int tid) {
+  const int last = L.nx - 2;
+  int ic[NCOL], jc[NCOL], js[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) colour_plan(L, c, NCOL, tid, ic[c], jc[c], js[c]);
+  Cf<T> c0{}, c1{};
+  if (K == ST5 || B1) {
+    if (ic[0] <= last) c0 = sub_coefs<T, K, B1>(L, bl, ic[0], 0, 0);
+    if (ic[1] <= last) c1 = sub_coefs<T, K, B1>(L, bl, ic[1], 0, 0);
+  }
+  for (int s = 0; s < nsw; ++s) {
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) {
+      if (ic[c] <= last) colour_rows<T, K, B1>(L, x, b, bl, ic[c], jc[c], js[c], (c & 1) ? c1 : c0, omega);
+      if (s + 1 < nsw || c + 1 < NCOL) __syncthreads();
+    }
+  }
+}
+
+// Same sweeps when no thread has more than M rows of any colour (the levels
+// at the bottom of the hierarchy): each thread's nodes, their row offsets
+// and right-hand sides (fixed while smoothing) are found once, so a colour
+// step is the gather, the update and the store.
+template <typename T, int K, bool B1, int NCOL, int M>
+__device__ void lds_smooth_few(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int nsw,
+                               T omega, int tid, const Level<T>& C, const MG_LDS T* xc, int flags, T wl) {
+  const int nx = L.nx, ny = L.ny, py = L.py;
+  const int hi = py ? ny - 1 : ny - 2, last = nx - 2;
+  constexpr bool col_only = K == ST5 || B1;
+  int ic[NCOL], pos[NCOL][M], so[NCOL][M], no[NCOL][M], jr[NCOL][M];
+  T bv[NCOL][M];
+  bool on[NCOL][M];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) {
+    int j, jstep;
+    colour_plan(L, c, NCOL, tid, ic[c], j, jstep);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int jm = j + m * jstep;
+      on[c][m] = ic[c] <= last && jm <= hi;
+      jr[c][m] = jm;
+      pos[c][m] = jm * nx + ic[c];
+      so[c][m] = no[c][m] = 0;
+      bv[c][m] = (T)0;
+      if (on[c][m]) {
+        row_offsets(jm, nx, ny, py, so[c][m], no[c][m]);
+        bv[c][m] = b[pos[c][m]];
+      }
+    }
+  }
+  Cf<T> c0{}, c1{};
+  if (col_only) {
+    if (ic[0] <= last) c0 = sub_coefs<T, K, B1>(L, bl, ic[0], 0, 0);
+    if (ic[1] <= last) c1 = sub_coefs<T, K, B1>(L, bl, ic[1], 0, 0);
+  }
+  if (flags & SM_PRO) {
+    // the coarse-grid correction, node by node as lds_prolong forms it, on
+    // the nodes this thread owns (the colours' plans cover every unknown once)
+    const bool wtd = (flags & SM_WTD) != 0;
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c)
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+        if (on[c][m]) {
+          const int i = ic[c], j = jr[c][m];
+          const int I = i >> 1, ox = i & 1, J = j >> 1;
+          const MG_LDS T* r0 = xc + J * C.nx + I;
+          T v;
+          if (!(j & 1)) {
+            v = prolong_combine(r0[0], ox ? r0[1] : (T)0, (T)0, (T)0, ox, 0);
+          } else {
+            const int J1 = (py && J + 1 == C.ny) ? 0 : J + 1;
+            const MG_LDS T* r1 = xc + J1 * C.nx + I;
+            v = prolong_combine(r0[0], ox ? r0[1] : (T)0, r1[0], ox ? r1[1] : (T)0, ox, 1);
+          }
+          x[pos[c][m]] = add_correction(x[pos[c][m]], v, wtd, wl);
+        }
+    __syncthreads();
+  }
+  for (int s = 0; s < nsw; ++s) {
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) {
+      Nbr<T> v[M];
+      Cf<T> a[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+        if (on[c][m]) {
+          v[m] = gather<K>(L, LXO<T>{x + pos[c][m], so[c][m], no[c][m]}, false);
+          a[m] = col_only ? ((c & 1) ? c1 : c0)
+                          : sub_coefs<T, K, B1>(L, bl, ic[c], jr[c][m], wrap_dn(jr[c][m], ny, py));
+        }
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+        if (on[c][m]) x[pos[c][m]] = sor_v(gs_v<K>(L, a[m], v[m], bv[c][m]), x + pos[c][m], omega);
+      if (s + 1 < nsw || c + 1 < NCOL) __syncthreads();
+    }
+  }
+}
+
+// Rows per thread of one colour: at most ceil(rows / row stride); the
+// register-resident form where that is 1 (or 2 with two colours).  The
+// block's transfers (flags): SM_PRO adds the level's coarse-grid
+// correction before the sweeps (the register-resident form on its own
+// nodes, otherwise as its own pass), SM_DR restricts the defect into level
+// + 1 after them; C and xc are level + 1 and its x in LDS.
+template <typename T, int K, bool B1, int NCOL>
+__device__ __forceinline__ void lds_smooth_c(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl,
+                                             int nsw, T omega, int tid, const Level<T>& C, MG_LDS T* xc, int flags,
+                                             T wl) {
+  const int kl = ceil_log2((L.nx - 1) >> 1);
+  const int rstride = (NCOL == 4 ? 2 : 1) * (SUB_NT >> kl);
+  const int rows = L.py ? L.ny : L.ny - 2;
+  const int m = (rows + rstride - 1) / rstride;
+  if (m <= 1) {
+    lds_smooth_few<T, K, B1, NCOL, 1>(L, x, b, bl, nsw, omega, tid, C, xc, flags, wl);
+  } else if (NCOL == 2 && m <= 2) {  // (two rows of four colours would spill registers)
+    lds_smooth_few<T, K, B1, NCOL, 2>(L, x, b, bl, nsw, omega, tid, C, xc, flags, wl);
+  } else {
+    if (flags & SM_PRO) {
+      lds_prolong(L, x, C, xc, tid, (flags & SM_WTD) != 0, wl);
+      __syncthreads();
+    }
+    lds_smooth_n<T, K, B1, NCOL>(L, x, b, bl, nsw, omega, tid);
+  }
+  if (flags & SM_DR) {
+    __syncthreads();
+    lds_dr<T, K, B1>(L, x, b, bl, C, xc, xc + C.nx * C.ny, tid);
+  }
+}
+
+// (9-point operators are smoothed with four colours only: setup rejects
+// red-black Gauss-Seidel for them.)
+template <typename T, int K, bool B1>
+__device__ void lds_smooth(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int nsw, int ncol,
+                           T omega, int tid, const Level<T>& C, MG_LDS T* xc, int flags, T wl) {
+  if constexpr (K == ST9) {
+    lds_smooth_c<T, K, B1, 4>(L, x, b, bl, nsw, omega, tid, C, xc, flags, wl);
+  } else {
+    if (ncol == 4)
+      lds_smooth_c<T, K, B1, 4>(L, x, b, bl, nsw, omega, tid, C, xc, flags, wl);
+    else
+      lds_smooth_c<T, K, B1, 2>(L, x, b, bl, nsw, omega, tid, C, xc, flags, wl);
   }
 }
 
@@ -1361,7 +1399,13 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
       const MG_LDS T* bands = B1 ? lds + boffs[l] : nullptr;
       switch (type) {
         case OP_COLOR: lds_colour<T, K, B1>(L, xl, bl, bands, arg, ncol, omega, tid); break;
-        case OP_SMOOTH: lds_smooth<T, K, B1>(L, xl, bl, bands, arg, ncol, omega, tid); break;
+        case OP_SMOOTH: {
+          const bool tr = (arg & (SM_PRO | SM_DR)) != 0;  // level + 1 exists then
+          const Level<T> C = tr ? Ls[l + 1] : L;
+          lds_smooth<T, K, B1>(L, xl, bl, bands, arg & SM_NSW, ncol, omega, tid, C, tr ? lds + offs[l + 1] : xl,
+                               arg, tr ? wsh[l] : (T)1);
+          break;
+        }
         case OP_JACOBI:
           lds_jacobi<T, K, B1>(L, arg == 0 ? xl : tl, arg == 0 ? tl : xl, bl, bands, omega, tid);
           break;
@@ -1391,12 +1435,22 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
     } else {
       switch (type) {
         case OP_COLOR: body_colour<T, false>(L, arg, ncol, omega, tid, SUB_NT); break;
-        case OP_SMOOTH:
-          for (int k2 = 0; k2 < arg * ncol; ++k2) {
+        case OP_SMOOTH: {
+          const int nsw = arg & SM_NSW;
+          if (arg & SM_PRO) {
+            body_prolong(L, Ls[l + 1], tid, SUB_NT, (arg & SM_WTD) != 0, wsh[l]);
+            __syncthreads();
+          }
+          for (int k2 = 0; k2 < nsw * ncol; ++k2) {
             body_colour<T, false>(L, k2 % ncol, ncol, omega, tid, SUB_NT);
-            if (k2 + 1 < arg * ncol) __syncthreads();
+            if (k2 + 1 < nsw * ncol) __syncthreads();
+          }
+          if (arg & SM_DR) {
+            __syncthreads();
+            body_dr<T, false>(L, Ls[l + 1], tid, SUB_NT);
           }
           break;
+        }
         case OP_JACOBI: body_jacobi<T, false>(L, arg, omega, tid, SUB_NT); break;
         case OP_COPY: body_copy(L, tid, SUB_NT); break;
         case OP_DR: body_dr<T, false>(L, Ls[l + 1], tid, SUB_NT); break;
