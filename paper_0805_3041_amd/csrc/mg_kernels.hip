@@ -156,6 +156,30 @@ __device__ void body_coarse(const Level<T>& L, const double* __restrict__ Ainv, 
   }
 }
 
+// The same solve on an LDS-resident coarsest level (row pitch nx) with the
+// inverse in LDS (coarsest grids of at most COARSE_LDS_MAX unknowns): the
+// same products in the same order.
+constexpr int COARSE_LDS_MAX = 16;
+template <typename T>
+__device__ void lds_coarse(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS double* Ainv, int n,
+                           int tid) {
+  const int lo = row_lo(L), ni = L.nx - 2;
+  for (int r = tid; r < n; r += SUB_NT) {
+    const MG_LDS double* row = Ainv + r * n;
+    double s = 0.0;
+    int i = 1, j = lo;
+    for (int k = 0; k < n; ++k) {
+      s = fma(row[k], (double)b[j * L.nx + i], s);
+      if (++i > ni) {
+        i = 1;
+        ++j;
+      }
+    }
+    const int rr = r / ni;
+    x[(lo + rr) * L.nx + (r - rr * ni + 1)] = (T)s;
+  }
+}
+
 // --------------------------------------------------------------------------- per-op kernels
 
 template <typename T>
@@ -1274,6 +1298,7 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
   __shared__ int sops[MAX_SUB_OPS];
   __shared__ double esh[SUB_NT / 64];  // workgroup sums of OP_OMEGA
   __shared__ T wsh[MAX_LEVELS];        // adaptive omega_l per level, set by OP_OMEGA
+  __shared__ double ainv_sh[COARSE_LDS_MAX * COARSE_LDS_MAX];  // small coarsest inverse
   const int slot = blockIdx.z;
   const Level<T>* Ls = levs + (size_t)slot * nlev;
   // A batched launch skips a finished problem at once; one problem reads the
@@ -1350,6 +1375,8 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
         lds[boffs[l] + k] = bandp(Lb, band)[i];
       }
     }
+    if (ncu <= COARSE_LDS_MAX)
+      for (int k = tid; k < ncu * ncu; k += SUB_NT) ainv_sh[k] = chol[slot][k];
     // zeros: the top level's boundary nodes of x and b, its t (Jacobi), and
     // every coarser level
     for (int k = tid; k < 2 * gny; k += SUB_NT) {
@@ -1428,7 +1455,12 @@ __global__ void __launch_bounds__(SUB_NT) k_subcycle(const Level<T>* __restrict_
           }
           break;
         }
-        case OP_COARSE: body_coarse(L, chol[slot], ncu, tid, SUB_NT); break;
+        case OP_COARSE:
+          if (ncu <= COARSE_LDS_MAX)
+            lds_coarse(L, xl, bl, lds_cast<double>(ainv_sh), ncu, tid);
+          else
+            body_coarse(L, chol[slot], ncu, tid, SUB_NT);
+          break;
         case OP_LINE: lds_line<T, K, B1>(L, xl, bl, tl, bands, lds + soff, arg, omega, tid); break;
         default: break;
       }
