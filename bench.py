@@ -284,12 +284,24 @@ def traffic_summary(fetch_csv: str, write_csv: str, command: str) -> str:
 #   FP32 post-pass (mixed, finest level): read smoothed e, r, coarse e (1/4);
 #                   read and write the FP64 iterate (e itself is left as it
 #                   is: the next pre-pass does not read it)
+#   FP32 pre-pass forming the residual itself (mixed, finest level, when
+#                   the solver reports forms_residual): read the FP64 x and
+#                   b; write r (for the passes after it), smoothed e, coarse
+#                   b and x; no separate residual kernel runs
 BYTES_PER_NODE = {
     ("fp64", 0): 8 + 8 + 8 + 2 + 2,
     ("fp64", 1): 8 + 8 + 2 + 8,
     ("mixed", 0): 4 + 4 + 1 + 1,
     ("mixed", 1): 4 + 4 + 1 + 8 + 8,
 }
+BYTES_PER_NODE_PRE_RESID = 8 + 8 + 4 + 4 + 1 + 1
+
+
+def pass_bytes_per_node(s, head, which):
+    """Algorithmic bytes per finest node of solver s's finest fused pass."""
+    if head == "mixed" and which == 0 and s.pass_info(0, 0).get("forms_residual"):
+        return BYTES_PER_NODE_PRE_RESID
+    return BYTES_PER_NODE[(head, which)]
 # Level 1 (a coarse level: plain post-pass, 4- or 8-byte values):
 #   pre-pass : read x, b; write t; write coarse b and x (1/4 node each) = 3.5 w
 #   post-pass: read t, b, coarse x (1/4); write x                      = 3.25 w
@@ -303,7 +315,7 @@ def fine_levels_roofline(s, rhs, scratch, head, times0, reps):
     """Algorithmic bytes of the fused passes of levels 0 and 1 (the levels
     that carry most of a cycle's bytes) over their summed device time."""
     shape1 = s.level_shape(1) if s.nlevels > 1 else None
-    total_b = sum(BYTES_PER_NODE[(head, w)] for w in (0, 1)) * rhs.numel()
+    total_b = sum(pass_bytes_per_node(s, head, w) for w in (0, 1)) * rhs.numel()
     total_t = times0[0] + times0[1]
     per = {}
     if shape1 is not None:
@@ -562,12 +574,13 @@ def annulus(args, rates=None):
         dom = 1 if times[1] >= times[0] else 0
         kernel_name = s.pass_kernel_name(0, dom)
         levels01 = fine_levels_roofline(s, rhs, scratch, head, times, 20)
-        alg_bytes = BYTES_PER_NODE[(head, dom)] * nx * ny
+        bpn = pass_bytes_per_node(s, head, dom)
+        alg_bytes = bpn * nx * ny
         achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic("annulus4097", kernel_name),
                     "kernel": kernel_name, "avg_us": times[dom], "bytes_per_launch": alg_bytes,
-                    "bytes_per_node": BYTES_PER_NODE[(head, dom)], "nodes": nx * ny,
+                    "bytes_per_node": bpn, "nodes": nx * ny,
                     "other_pass_us": times[1 - dom], "levels_0_1": levels01}
     s.close()
     del scratch
@@ -681,12 +694,13 @@ def _roofline_single(n, eps, head, nu):
     times = {which: s.profile_pass(rhs, scratch, 0, which, reps=50) for which in (0, 1)}
     dom = 1 if times[1] >= times[0] else 0
     kernel = s.pass_kernel_name(0, dom)
+    bpn = pass_bytes_per_node(s, head, dom)
     s.close()
-    alg = BYTES_PER_NODE[(head, dom)] * n * n
+    alg = bpn * n * n
     ach = alg / (times[dom] * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": None, "kernel": kernel, "avg_us": times[dom], "bytes_per_launch": alg,
-            "bytes_per_node": BYTES_PER_NODE[(head, dom)], "nodes": n * n, "other_pass_us": times[1 - dom],
+            "bytes_per_node": bpn, "nodes": n * n, "other_pass_us": times[1 - dom],
             "note": f"one {n}x{n} problem of the batch"}
 
 
@@ -916,7 +930,7 @@ def sphere2049(args, rates=None):
         times = {which: s.profile_pass(rhs, scratch, 0, which, reps=20) for which in (0, 1)}
         dom = 1 if times[1] >= times[0] else 0
         kernel_name = s.pass_kernel_name(0, dom)
-        bpn = BYTES_PER_NODE[(head, dom)] + 2 * w  # + the two cell coefficients
+        bpn = pass_bytes_per_node(s, head, dom) + 2 * w  # + the two cell coefficients
         alg = bpn * n * n
         achieved = alg / (times[dom] * 1e-6) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -1060,14 +1074,15 @@ def aniso1025(args, rates=None):
         kernel_name = s0.pass_kernel_name(0, dom)
         levels01 = fine_levels_roofline(s0, rhs, scratch, head, times, 100)
         nodes = n * n
-        alg_bytes = BYTES_PER_NODE[(head, dom)] * nodes
+        bpn = pass_bytes_per_node(s0, head, dom)
+        alg_bytes = bpn * nodes
         achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
         roofline = {"bound": "hbm", "measured": "L2-miss bandwidth: the 1025^2 working set stays in the 256 MB "
                                                 "last-level cache",
                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic("aniso1025", kernel_name),
                     "kernel": kernel_name, "avg_us": times[dom], "bytes_per_launch": alg_bytes,
-                    "bytes_per_node": BYTES_PER_NODE[(head, dom)], "nodes": nodes,
+                    "bytes_per_node": bpn, "nodes": nodes,
                     "other_pass_us": times[1 - dom], "levels_0_1": levels01}
     for s in solvers:
         s.close()

@@ -84,6 +84,7 @@ struct Group {
   std::vector<TileGeom> gpre, gpost;
   bool norm_fused = false;   // FP64: the finest post-pass applies the stopping test
   bool mixed_fused = false;  // mixed: the finest post-pass adds e into the FP64 iterate
+  bool resid_kernel = false;  // mixed: keep the residual kernel where the pre-pass could form r (tuned)
   std::vector<HostOp> prog;
   DOp* dprog = nullptr;
   int* dbeg = nullptr;  // [sub * ns + slot]
@@ -549,7 +550,7 @@ hipError_t run_op(mg_handle h, const Group& G, const HostOp& op, Level<T>* dL, L
     case H_LINE: return launch_line<T>(Ls, s, op.arg, omega, stencil_kind(h), ns, st);
     case H_PRE:
       return launch_pre<T>(Ls, Cs, G.gpre[l], h->opts.nu_pre, h->ncol, omega, stencil_kind(h), h->oned, l == 0, ns,
-                           st, op.arg != 0);
+                           st, op.arg, l == 0 ? G.dL64 : nullptr);
     case H_POST:
       return launch_post<T>(Ls, Cs, G.gpost[l], h->opts.nu_post, h->ncol, omega, op.arg, G.dL64, stencil_kind(h),
                             h->oned, l == 0, ns, st);
@@ -576,6 +577,27 @@ bool mixed_zero_start(mg_handle h, const Group& G) {
          G.prog[0].level == 0 && G.gpre[0].wide;
 }
 
+// Mixed form with a zero start whose pre-pass tile fits the residual modes:
+// the first finest pre-pass of an outer step forms r = b - A x (FP64) and
+// its norm itself, and the stopping test of a cycle's result is taken at
+// the start of the next cycle (or by tail_check) instead of by a residual
+// kernel after the cycle.
+bool resid_possible(mg_handle h, const Group& G) {
+  return mixed_zero_start(h, G) && pre_resid_fits(G.gpre[0]) && pre_resid_kind(stencil_kind(h), h->oned);
+}
+bool resid_fused(mg_handle h, const Group& G) { return resid_possible(h, G) && !G.resid_kernel; }
+
+// The stopping test of the iterate the last queued cycle left (groups whose
+// cycles test at their start): its residual norm by the finest pre-pass in
+// PRE_RESID_ONLY mode, then the test, if that iterate was not tested yet.
+hipError_t tail_check(mg_handle h, const Group& G, hipStream_t st) {
+  const TileGeom& g = G.gpre[0];
+  hipError_t e = launch_pre<float>(G.dL32, G.dL32 + 1, g, h->opts.nu_pre, h->ncol, (float)relax(h), stencil_kind(h),
+                                   h->oned, true, G.ns, st, PRE_RESID_ONLY, G.dL64);
+  if (e != hipSuccess) return e;
+  return launch_norm_finish<double>(G.dL64, g.ntx * g.nty, NORM_LAG, G.ns, st);
+}
+
 // One cycle of a group plus its stopping test, on stream st.
 hipError_t enqueue_cycle(mg_handle h, const Group& G, hipStream_t st) {
   hipError_t e = hipSuccess;
@@ -594,15 +616,21 @@ hipError_t enqueue_cycle(mg_handle h, const Group& G, hipStream_t st) {
   // read the finest iterate)
   const int inner = inner_cycles(h);
   const bool zero_start = mixed_zero_start(h, G);
+  const bool rf = resid_fused(h, G);
   for (int c = 0; c < inner; ++c)
     for (size_t k = 0; k < G.prog.size(); ++k) {
       HostOp op = G.prog[k];
       if (G.mixed_fused && c + 1 < inner && k + 1 == G.prog.size()) op.arg = POST_PLAIN;
-      if (zero_start && c == 0 && k == 0) op.arg = 1;
+      if (zero_start && c == 0 && k == 0) op.arg = rf ? PRE_RESID : PRE_ZERO;
       if (zero_start && c + 1 == inner && k + 1 == G.prog.size() && op.arg == POST_MIXED) op.arg = POST_MIXED_KEEP;
       if ((e = run_op<float>(h, G, op, G.dL32, G.dP32, (float)relax(h), st)) != hipSuccess) return e;
+      // the test of the iterate this pre-pass formed the residual of
+      if (rf && c == 0 && k == 0 &&
+          (e = launch_norm_finish<double>(G.dL64, G.gpre[0].ntx * G.gpre[0].nty, NORM_LAG, G.ns, st)) != hipSuccess)
+        return e;
     }
   if (!G.mixed_fused && (e = launch_outer_update(G.dL64, G.dL32, G.shp[0], G.ns, st)) != hipSuccess) return e;
+  if (rf) return hipSuccess;
   return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, G.dL32, stencil_kind(h), h->oned, G.ns, st);
 }
 
@@ -1788,6 +1816,28 @@ mg_status tune_group(mg_handle h, Group& G, bool tile_free, bool thr_free) {
     res = build_program(h, G);
     if (res == MG_OK && tile_free) res = tune_tiles(h, G);  // cached by now
   }
+  // mixed form: the finest pre-pass forming the residual itself, or the
+  // residual kernel after each cycle (same iterates bit for bit): the
+  // pre-pass then loads the FP64 x and b over its whole region, halo
+  // included, so whether it pays depends on the tile (kept only when 1 %
+  // faster).  Tiles given by the caller keep the in-pass residual.
+  G.resid_kernel = false;
+  if (res == MG_OK && tile_free && resid_possible(h, G)) {
+    const std::string key = threshold_key(h, G) + "|resid|" + geom_str(G.gpre[0]);
+    const std::string cached = h->opts.tune == MG_TUNE_REFRESH ? std::string() : tune_lookup(key);
+    if (!cached.empty()) {
+      G.resid_kernel = cached == "kernel";
+    } else {
+      double us[2] = {0.0, 0.0};
+      for (int v = 0; v < 2; ++v) {
+        G.resid_kernel = v == 1;
+        hipError_t te = time_cycle(h, G, &us[v]);
+        if (te != hipSuccess) return fail(h, MG_EDEVICE, std::string("tuning: ") + hipGetErrorString(te));
+      }
+      G.resid_kernel = !(us[0] < 0.99 * us[1]);
+      tune_store(key, G.resid_kernel ? "kernel" : "pass");
+    }
+  }
   return res;
 }
 
@@ -2037,6 +2087,8 @@ mg_status run_cycles(mg_handle h, int max_cycles, double tol, std::vector<SolveS
     for (int k = 0; k + 8 <= nb; k += 8) HIPCHK(h, hipGraphLaunch(h->g8, st));
     for (int k = 0; k < nb % 8; ++k) HIPCHK(h, hipGraphLaunch(h->g1, st));
     queued += nb;
+    for (int u : h->standalone)
+      if (resid_fused(h, h->groups[u])) HIPCHK(h, tail_check(h, h->groups[u], st));
     HIPCHK(h, hipMemcpyAsync(cur.data(), h->dstate, (size_t)h->nprob * sizeof(SolveState), hipMemcpyDeviceToHost,
                              st));
     HIPCHK(h, hipStreamSynchronize(st));
@@ -2379,6 +2431,7 @@ mg_status mg_pass_info(mg_handle h, int32_t level, int32_t which, int32_t* out) 
   out[5] = h->ncol;
   out[6] = stencil_kind(h);
   out[7] = stencil_kind(h) == ST9 && h->oned ? 1 : 0;
+  out[8] = level == 0 && which == 0 && resid_fused(h, G) ? 1 : 0;
   return MG_OK;
 }
 
@@ -2414,7 +2467,8 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
       const bool zs = l == 0 && mixed_zero_start(h, G);
       if (which == 0)
         return launch_pre<float>(G.dL32 + l, G.dL32 + l + 1, G.gpre[l], h->opts.nu_pre, h->ncol,
-                                 (float)relax(h), kind, h->oned, l == 0, 1, st, zs);
+                                 (float)relax(h), kind, h->oned, l == 0, 1, st,
+                                 zs ? (resid_fused(h, G) ? PRE_RESID : PRE_ZERO) : PRE_LOAD, G.dL64);
       const int mode = zs && found->arg == POST_MIXED ? POST_MIXED_KEEP : found->arg;
       return launch_post<float>(G.dL32 + l, G.dL32 + l + 1, G.gpost[l], h->opts.nu_post, h->ncol,
                                 (float)relax(h), mode, G.dL64, kind, h->oned, l == 0, 1, st, false);

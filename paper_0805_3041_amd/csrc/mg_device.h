@@ -34,6 +34,7 @@ struct SolveState {
   int cycles;             // completed cycles
   unsigned int counter;   // workgroups finished in the running norm reduction
   double* partial;        // per-workgroup partial sums of the running norm
+  int pending;            // the iterate changed since its last stopping test
 };
 
 enum StencilKind { ST5 = 0, ST9 = 1 };

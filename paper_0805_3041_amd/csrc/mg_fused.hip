@@ -539,6 +539,7 @@ __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, co
       }
     }
   }
+  if ((mode == POST_MIXED || mode == POST_MIXED_KEEP) && blockIdx.x == 0 && threadIdx.x == 0) st->pending = 1;
   if (mode == POST_NORM) {
     const double part = wg_sum(acc, sh);
     if (threadIdx.x == 0) st->partial[blockIdx.x] = part;
@@ -860,9 +861,136 @@ __device__ __forceinline__ void wstore_bands(MG_LDS T* bl, const WBands<T>& r) {
   }
 }
 
+// Residual of the FP64 finest level at a region's nodes, for the mixed
+// form's correction equation A e = r: r = b - A x formed in FP64 by the
+// same products in the same order as the residual kernel, rounded to FP32.
+// The region's x (FP64) is first staged in the LDS rows themselves (a row's
+// x and b arrays, two FP32 rows, hold one FP64 row); once every wave has
+// formed its rows' r in registers, each row gets x = 0 (the correction
+// starts from zero) and b = r.  At the output nodes r also goes into F.b
+// (for the passes after this one) and r^2 into the workgroup's partial sum
+// of the norm.  A wave holds region rows wave, wave + NWAVE, ... : at most
+// RESID_ROWS of them, so R <= RESID_ROWS * NWAVE.  Returns false when the
+// workgroup stops here (solve finished, or only the residual was asked).
+constexpr int RESID_ROWS = 12;
+template <typename T, int K, bool B1, int NCOL, int P>
+__device__ bool wresid(const Level<T>& F, const Level<double>& X, const WMap& m, MG_LDS T* lds, MG_LDS double* xs,
+                       int R, int TX, int TY, bool only, double* sh) {
+  constexpr int PD = P / 2;  // FP64 values per LDS row
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int la = lane, lb = lane + 64;
+  const bool oka = m.col_ok(la), okb = m.col_ok(lb);
+  const int ga = m.gi(la), gb = m.gi(lb);
+  // r is needed at the unknowns inside the region's outer ring
+  const bool na = oka && la >= 1, nb = okb && lb <= WW - 2;
+  const int done = F.st->done;
+  double ba[RESID_ROWS], bb[RESID_ROWS];
+#pragma unroll
+  for (int u = 0; u < RESID_ROWS; ++u) {
+    const int lj = wave + u * NWAVE;
+    ba[u] = bb[u] = 0.0;
+    if (lj >= 1 && lj <= R - 2 && m.row_ok(lj)) {
+      const double* row = X.b + (size_t)m.wrapj(m.gj(lj)) * X.pitch;
+      if (na) ba[u] = row[ga];
+      if (nb) bb[u] = row[gb];
+    }
+  }
+  // x of the region, Dirichlet boundary nodes (and nodes off the grid) as 0
+  for (int lj0 = wave; lj0 < R; lj0 += NWAVE * ULR) {
+    double xa[ULR], xb[ULR];
+#pragma unroll
+    for (int u = 0; u < ULR; ++u) {
+      const int lj = lj0 + u * NWAVE;
+      xa[u] = xb[u] = 0.0;
+      if (lj < R && m.row_ok(lj)) {
+        const double* row = X.x + (size_t)m.wrapj(m.gj(lj)) * X.pitch;
+        if (oka) xa[u] = row[ga];
+        if (okb) xb[u] = row[gb];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < ULR; ++u) {
+      const int lj = lj0 + u * NWAVE;
+      if (lj >= R) break;
+      xs[lj * PD + la] = xa[u];
+      xs[lj * PD + lb] = xb[u];
+    }
+  }
+  __syncthreads();
+  if (done) return false;
+
+  Cf<double> cola{}, colb{};
+  if constexpr (K == ST9 && B1) {
+    cola = coefs<K>(X, na ? ga : 1, 0, 0);
+    colb = coefs<K>(X, nb ? gb : 1, 0, 0);
+  }
+  const bool oa = la >= m.H && la < m.H + TX, ob = lb < m.H + TX;  // output columns
+  float ra[RESID_ROWS], rb[RESID_ROWS];
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < RESID_ROWS; ++u) {
+    const int lj = wave + u * NWAVE;
+    ra[u] = rb[u] = 0.f;
+    if (!(lj >= 1 && lj <= R - 2 && m.row_ok(lj))) continue;
+    const int gj = m.wrapj(m.gj(lj));
+    const bool orow = lj >= m.H && lj < m.H + TY && m.gj(lj) < F.ny;
+    auto defect = [&](int li, int gi, const Cf<double>& col, double bp) {
+      const MG_LDS double* p = xs + (lj - 1) * PD + li;
+      Nbr<double> v;
+      v.sw = p[-1];
+      v.s = p[0];
+      v.se = p[1];
+      v.w = p[PD - 1];
+      v.c = p[PD];
+      v.e = p[PD + 1];
+      v.nw = p[2 * PD - 1];
+      v.n = p[2 * PD];
+      v.ne = p[2 * PD + 1];
+      const Cf<double> a = (K == ST9 && !B1) ? coefs<K>(X, gi, gj, wrap_dn(gj, X.ny, X.py)) : col;
+      return defect_v<K>(X, a, v, bp);
+    };
+    if (na) {
+      const double d = defect(la, ga, cola, ba[u]);
+      ra[u] = (float)d;
+      if (orow && oa) {
+        F.b[(size_t)gj * F.pitch + ga] = ra[u];
+        acc += d * d;
+      }
+    }
+    if (nb) {
+      const double d = defect(lb, gb, colb, bb[u]);
+      rb[u] = (float)d;
+      if (orow && ob) {
+        F.b[(size_t)gj * F.pitch + gb] = rb[u];
+        acc += d * d;
+      }
+    }
+  }
+  const double part = wg_sum(acc, sh);  // ends with a barrier: the staged x is no longer read
+  if (threadIdx.x == 0) X.st->partial[blockIdx.x] = part;
+  if (only) return false;
+  const int ca = wcol(la), cb = wcol(lb);
+#pragma unroll
+  for (int u = 0; u < RESID_ROWS; ++u) {
+    const int lj = wave + u * NWAVE;
+    if (lj >= R) break;
+    MG_LDS T* r = lds + lj * P;
+    r[ca] = (T)0;
+    r[cb] = (T)0;
+    r[WW + ca] = (T)ra[u];
+    r[WW + cb] = (T)rb[u];
+    if constexpr (NCOL == 0) {
+      r[2 * WW + ca] = (T)0;
+      r[2 * WW + cb] = (T)0;
+    }
+  }
+  return true;
+}
+
 template <typename T, int K, bool FINE, int NCOL, bool B1>
 __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs,
-                                              int TY, int H, int ntx, int nty, int nsteps, T omega, int zero_x) {
+                                              int TY, int H, int ntx, int nty, int nsteps, T omega, int start,
+                                              const Level<double>* __restrict__ X64s) {
   constexpr int P = wide_narr<NCOL>() * WW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Level<T> F = Fs[blockIdx.z];
@@ -878,7 +1006,18 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
   WBands<T> bands{};
   if constexpr (B1) bands = wfetch_bands(F, m);
 
-  {
+  // (only the FP32 finest level of the mixed form forms its residual, not
+  // with per-node 9-point coefficients, whose loads would cost the pass its
+  // occupancy)
+  constexpr bool MIX = FINE && std::is_same<T, float>::value && (K != ST9 || B1);
+  if (MIX && start >= PRE_RESID) {
+    if constexpr (MIX) {
+      __shared__ double sh[FT / 64];
+      if (!wresid<T, K, B1, NCOL, P>(F, X64s[blockIdx.z], m, lds, lds_cast<double>(smem_raw), R, TX, TY,
+                                     start == PRE_RESID_ONLY, sh))
+        return;
+    }
+  } else {
     const int la = lane, lb = lane + 64;
     const int ca = wcol(la), cb = wcol(lb);
     const bool oka = m.col_ok(la), okb = m.col_ok(lb);
@@ -892,11 +1031,11 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
         if (lj < R && m.row_ok(lj)) {
           const size_t row = (size_t)m.wrapj(m.gj(lj)) * F.pitch;
           if (oka) {
-            if (!zero_x) xa[u] = F.x[row + ga];
+            if (!start) xa[u] = F.x[row + ga];
             ba[u] = F.b[row + ga];
           }
           if (okb) {
-            if (!zero_x) xb[u] = F.x[row + gb];
+            if (!start) xb[u] = F.x[row + gb];
             bb[u] = F.b[row + gb];
           }
         }
@@ -1137,6 +1276,7 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
   if (MIX && mixed) {
     const Level<double>& X = X64s[blockIdx.z];
     const bool zero_e = mode == POST_MIXED;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->pending = 1;
     for (int lj0 = H + wave; lj0 < H + TY; lj0 += NWAVE * UL) {
       double xa[UL], xb[UL];
       const bool first = lj0 == H + wave;  // loaded before the sweeps
@@ -1239,7 +1379,7 @@ using PreFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int
 template <typename T>
 using PostFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, int, T, int, const Level<double>*);
 template <typename T>
-using PreWFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, T, int);
+using PreWFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, T, int, const Level<double>*);
 template <typename T>
 using PostWFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, T, int, const Level<double>*);
 
@@ -1331,18 +1471,27 @@ hipError_t prepare_fused() {
   return hipSuccess;
 }
 
+bool pre_resid_fits(const TileGeom& g) { return g.wide && g.TY + 2 * g.H <= RESID_ROWS * NWAVE; }
+bool pre_resid_kind(int kind, bool oned) { return kind == ST5 || oned; }
+
 template <typename T>
 hipError_t launch_pre(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g, int nsteps, int ncol, T omega,
-                      int kind, bool oned, bool fine, int nslots, hipStream_t st, bool zero_x) {
+                      int kind, bool oned, bool fine, int nslots, hipStream_t st, int mode,
+                      const Level<double>* X64s) {
   const dim3 grid(g.ntx * g.nty, 1, nslots);
   const size_t lds = pre_lds_bytes<T>(g, ncol);
+  if (mode < PRE_LOAD || mode > PRE_RESID_ONLY) return hipErrorInvalidValue;
+  // residual modes: FP32 finest level, wide tiles
+  if (mode >= PRE_RESID &&
+      !(std::is_same<T, float>::value && fine && X64s && pre_resid_fits(g) && pre_resid_kind(kind, oned)))
+    return hipErrorInvalidValue;
   if (g.wide) {
     PreWFn<T> k = pick_pre_w<T>(kind, oned, fine, ncol);
     if (!k || g.TX != WW - 2 * g.H) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TY, g.H, g.ntx, g.nty, nsteps, omega, zero_x ? 1 : 0);
+    hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TY, g.H, g.ntx, g.nty, nsteps, omega, mode, X64s);
   } else {
     PreFn<T> k = pick_pre<T>(kind, oned, fine, ncol);
-    if (!k || zero_x) return hipErrorInvalidValue;  // zero start: wide tiles only
+    if (!k || mode != PRE_LOAD) return hipErrorInvalidValue;  // zero start: wide tiles only
     hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TX, g.TY, g.H, g.ntx, g.nty, nsteps, omega);
   }
   return hipGetLastError();
@@ -1374,7 +1523,7 @@ hipError_t launch_post(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g
   template size_t post_lds_bytes<T>(const TileGeom&, int);                                                         \
   template hipError_t prepare_fused<T>();                                                                          \
   template hipError_t launch_pre<T>(const Level<T>*, const Level<T>*, const TileGeom&, int, int, T, int, bool,     \
-                                    bool, int, hipStream_t, bool);                                                 \
+                                    bool, int, hipStream_t, int, const Level<double>*);                            \
   template hipError_t launch_post<T>(const Level<T>*, const Level<T>*, const TileGeom&, int, int, T, int,         \
                                      const Level<double>*, int, bool, bool, int, hipStream_t, bool);
 

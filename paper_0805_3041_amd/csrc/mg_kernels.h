@@ -15,7 +15,11 @@ constexpr int MAX_LEVELS = 24;
 constexpr int MAX_SUB_OPS = 1024;  // ops of a coarse-level program kept in LDS
 constexpr size_t SUB_LDS_BUDGET = 140 * 1024;  // dynamic LDS of the coarse-level kernel (160 KB per CU)
 
-enum NormMode { NORM_INIT = 0, NORM_CHECK = 1, NORM_RESID = 2 };
+// NORM_LAG: the stopping test of the iterate the norm was just formed from,
+// taken only if a cycle has changed that iterate since the last test
+// (SolveState::pending); the norm of a cycle's result is then formed at the
+// start of the next cycle or by a check of its own.
+enum NormMode { NORM_INIT = 0, NORM_CHECK = 1, NORM_RESID = 2, NORM_LAG = 3 };
 
 // Stored shape of a level plus its number of rows that carry unknowns.
 struct LevelShape {

@@ -1540,7 +1540,8 @@ template <typename T>
 __global__ void __launch_bounds__(NT) k_norm_finish(const Level<T>* __restrict__ Ls, int nblocks, int mode) {
   __shared__ double sh[NT / 64];
   SolveState* st = Ls[blockIdx.z].st;
-  if (mode == NORM_CHECK && st->done) return;
+  if ((mode == NORM_CHECK || mode == NORM_LAG) && st->done) return;
+  if (mode == NORM_LAG && !st->pending) return;  // this iterate's test was taken
   double v = 0.0;
   for (int k = threadIdx.x; k < nblocks; k += NT) v += st->partial[k];
   const double s = block_sum(v, sh);
@@ -1551,9 +1552,11 @@ __global__ void __launch_bounds__(NT) k_norm_finish(const Level<T>* __restrict__
   if (mode == NORM_INIT) {
     st->r0 = nrm;
     st->cycles = 0;
+    st->pending = 0;
     if (st->hist_cap > 0) st->history[0] = nrm;
     st->done = (nrm == 0.0) ? 1 : 0;
-  } else if (mode == NORM_CHECK) {
+  } else if (mode == NORM_CHECK || mode == NORM_LAG) {
+    st->pending = 0;
     const int c = st->cycles + 1;
     st->cycles = c;
     if (c < st->hist_cap) st->history[c] = nrm;
@@ -1661,6 +1664,7 @@ __global__ void __launch_bounds__(NT) k_outer_update(const Level<double>* __rest
     X.x[(size_t)j * X.pitch + i] += (double)(*ep);
     *ep = 0.0f;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) X.st->pending = 1;
 }
 
 // Zero the Dirichlet boundary nodes of x.
