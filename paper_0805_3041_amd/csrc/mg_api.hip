@@ -598,12 +598,23 @@ hipError_t tail_check(mg_handle h, const Group& G, hipStream_t st) {
   return launch_norm_finish<double>(G.dL64, g.ntx * g.nty, NORM_LAG, G.ns, st);
 }
 
+// A wide pre-pass that directly follows the pre-pass of the next finer
+// level starts from x = 0 (that pass's restriction cleared it), so it need
+// not read x.
+HostOp with_zero_start(const Group& G, size_t k) {
+  HostOp op = G.prog[k];
+  if (op.type == H_PRE && op.arg == PRE_LOAD && k > 0 && G.prog[k - 1].type == H_PRE &&
+      G.prog[k - 1].level + 1 == op.level && G.gpre[op.level].wide)
+    op.arg = PRE_ZERO;
+  return op;
+}
+
 // One cycle of a group plus its stopping test, on stream st.
 hipError_t enqueue_cycle(mg_handle h, const Group& G, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (!h->mixed()) {
-    for (const HostOp& op : G.prog)
-      if ((e = run_op<double>(h, G, op, G.dL64, G.dP64, relax(h), st)) != hipSuccess) return e;
+    for (size_t k = 0; k < G.prog.size(); ++k)
+      if ((e = run_op<double>(h, G, with_zero_start(G, k), G.dL64, G.dP64, relax(h), st)) != hipSuccess) return e;
     if (G.norm_fused) return hipSuccess;
     return launch_resnorm<double>(G.dL64, G.shp[0], NORM_CHECK, nullptr, nullptr, stencil_kind(h), h->oned, G.ns,
                                   st);
@@ -619,7 +630,7 @@ hipError_t enqueue_cycle(mg_handle h, const Group& G, hipStream_t st) {
   const bool rf = resid_fused(h, G);
   for (int c = 0; c < inner; ++c)
     for (size_t k = 0; k < G.prog.size(); ++k) {
-      HostOp op = G.prog[k];
+      HostOp op = with_zero_start(G, k);
       if (G.mixed_fused && c + 1 < inner && k + 1 == G.prog.size()) op.arg = POST_PLAIN;
       if (zero_start && c == 0 && k == 0) op.arg = rf ? PRE_RESID : PRE_ZERO;
       if (zero_start && c + 1 == inner && k + 1 == G.prog.size() && op.arg == POST_MIXED) op.arg = POST_MIXED_KEEP;
