@@ -94,11 +94,14 @@ def calibrate_copy():
 
 
 def source_digest() -> str:
-    """sha256 over the kernel sources: a stored counter measurement is only
-    reported while the kernels it was taken on are unchanged."""
+    """sha256 over the compile flags and the kernel sources: a stored counter
+    measurement is only reported while the kernels it was taken on are
+    unchanged."""
     import hashlib
 
-    d = hashlib.sha256()
+    from paper_0805_3041_amd.build import flags_key
+
+    d = hashlib.sha256(flags_key().encode() + b"\0")
     csrc = os.path.join(ROOT, "paper_0805_3041_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".h")):
