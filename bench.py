@@ -308,13 +308,22 @@ BYTES_PER_NODE = {
     ("mixed", 1): 4 + 4 + 1 + 8 + 8,
 }
 BYTES_PER_NODE_PRE_RESID = 8 + 8 + 4 + 4 + 1 + 1
+# Mixed form with K > 1 inner cycles per outer step: the finest passes of
+# the other K - 1 inner cycles are plain FP32 passes (pre: read e, r; write
+# smoothed e, coarse b and x; post: read smoothed e, r, coarse e; write e).
+BYTES_PER_NODE_MIXED_INNER = {0: 4 + 4 + 4 + 1 + 1, 1: 4 + 4 + 1 + 4}
 
 
-def pass_bytes_per_node(s, head, which):
-    """Algorithmic bytes per finest node of solver s's finest fused pass."""
-    if head == "mixed" and which == 0 and s.pass_info(0, 0).get("forms_residual"):
-        return BYTES_PER_NODE_PRE_RESID
-    return BYTES_PER_NODE[(head, which)]
+def pass_bytes_per_node(s, head, which, inner=1):
+    """Algorithmic bytes per finest node of solver s's finest fused pass,
+    averaged over the launches of one outer step of `inner` cycles (the
+    launch mix that mg_profile_pass times with reps a multiple of inner)."""
+    if head != "mixed":
+        return BYTES_PER_NODE[(head, which)]
+    first = BYTES_PER_NODE[(head, which)]
+    if which == 0 and s.pass_info(0, 0).get("forms_residual"):
+        first = BYTES_PER_NODE_PRE_RESID
+    return (first + (inner - 1) * BYTES_PER_NODE_MIXED_INNER[which]) / inner
 # Level 1 (a coarse level: plain post-pass, 4- or 8-byte values):
 #   pre-pass : read x, b; write t; write coarse b and x (1/4 node each) = 3.5 w
 #   post-pass: read t, b, coarse x (1/4); write x                      = 3.25 w
@@ -324,11 +333,11 @@ BYTES_PER_NODE_L1 = {
 }
 
 
-def fine_levels_roofline(s, rhs, scratch, head, times0, reps):
+def fine_levels_roofline(s, rhs, scratch, head, times0, reps, inner=1):
     """Algorithmic bytes of the fused passes of levels 0 and 1 (the levels
     that carry most of a cycle's bytes) over their summed device time."""
     shape1 = s.level_shape(1) if s.nlevels > 1 else None
-    total_b = sum(pass_bytes_per_node(s, head, w) for w in (0, 1)) * rhs.numel()
+    total_b = sum(pass_bytes_per_node(s, head, w, inner) for w in (0, 1)) * rhs.numel()
     total_t = times0[0] + times0[1]
     per = {}
     if shape1 is not None:
@@ -588,11 +597,13 @@ def annulus(args, rates=None):
     if args.smoother:
         roofline = line_roofline(s, rhs, scratch, head, nx, ny, True, smoother, 1)
     else:
-        times = {which: s.profile_pass(rhs, scratch, 0, which, reps=20) for which in (0, 1)}
+        k = inner if head == "mixed" else 1
+        reps = k * max(1, 20 // k)  # whole outer steps
+        times = {which: s.profile_pass(rhs, scratch, 0, which, reps=reps) for which in (0, 1)}
         dom = 1 if times[1] >= times[0] else 0
         kernel_name = s.pass_kernel_name(0, dom)
-        levels01 = fine_levels_roofline(s, rhs, scratch, head, times, 20)
-        bpn = pass_bytes_per_node(s, head, dom)
+        levels01 = fine_levels_roofline(s, rhs, scratch, head, times, reps, k)
+        bpn = pass_bytes_per_node(s, head, dom, k)
         alg_bytes = bpn * nx * ny
         achieved = alg_bytes / (times[dom] * 1e-6) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -600,6 +611,10 @@ def annulus(args, rates=None):
                     "kernel": kernel_name, "avg_us": times[dom], "bytes_per_launch": alg_bytes,
                     "bytes_per_node": bpn, "nodes": nx * ny,
                     "other_pass_us": times[1 - dom], "levels_0_1": levels01}
+        if k > 1:
+            roofline["launch_mix"] = (f"averaged over the {k} launches of an outer step: the first pre-pass from "
+                                      f"e = 0, the last post-pass adding e into the FP64 iterate, the other "
+                                      f"{k - 1} plain FP32 passes")
     s.close()
     del scratch
     s = make(other)

@@ -265,9 +265,13 @@ mg_status mg_start_nested(mg_handle h, const double* rhs, double* x);
  * `reps` more times between two HIP events on the handle's stream, and
  * returns the average device time per launch in *avg_us.  rhs and x are the
  * finest-level arrays as for mg_solve; x is used as scratch and its content
- * is overwritten.  MG_EUNSUPPORTED if that level has no such pass (it runs in
- * the single-workgroup coarse kernel, tile_mode is MG_TILES_PER_OP, or the
- * smoother is not of the asked kind). */
+ * is overwritten.  On the finest level of the mixed form with inner_cycles
+ * = K, timed launch r runs as inner cycle r % K does in a solve (the first
+ * pre-pass of an outer step from a zero start, the last post-pass adding the
+ * correction into the FP64 iterate), so reps a multiple of K give the
+ * solve's average.  MG_EUNSUPPORTED if that level has no such pass (it runs
+ * in the single-workgroup coarse kernel, tile_mode is MG_TILES_PER_OP, or
+ * the smoother is not of the asked kind). */
 mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t level, int32_t which, int32_t reps,
                           double* avg_us);
 

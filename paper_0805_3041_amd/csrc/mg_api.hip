@@ -2468,19 +2468,27 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
   if (s != MG_OK) return s;
   const int l = level;
   const int kind = stencil_kind(h);
-  auto launch = [&]() -> hipError_t {
+  // the finest level of the mixed form runs its passes as an outer step of
+  // `inner` cycles does: launch r as inner cycle r % inner
+  const int inner = l == 0 && h->mixed() && G.mixed_fused ? inner_cycles(h) : 1;
+  auto launch = [&](int r) -> hipError_t {
+    const int c = r % inner;
     if (which == 2) {
       if (h->mixed()) return launch_line<float>(G.dL32 + l, G.shp[l], found->arg, (float)h->opts.omega, kind, 1, st);
       return launch_line<double>(G.dL64 + l, G.shp[l], found->arg, h->opts.omega, kind, 1, st);
     }
     if (h->mixed()) {
-      // level 0 as the solve runs it (zero start, e left for the next pre-pass)
+      // level 0 as the solve runs it: the first inner cycle's pre-pass from
+      // a zero start (forming the residual when that is the solve's path),
+      // the last one's post-pass adding e into the FP64 iterate (e left for
+      // the next pre-pass), the others keeping e
       const bool zs = l == 0 && mixed_zero_start(h, G);
       if (which == 0)
         return launch_pre<float>(G.dL32 + l, G.dL32 + l + 1, G.gpre[l], h->opts.nu_pre, h->ncol,
                                  (float)relax(h), kind, h->oned, l == 0, 1, st,
-                                 zs ? (resid_fused(h, G) ? PRE_RESID : PRE_ZERO) : PRE_LOAD, G.dL64);
-      const int mode = zs && found->arg == POST_MIXED ? POST_MIXED_KEEP : found->arg;
+                                 zs && c == 0 ? (resid_fused(h, G) ? PRE_RESID : PRE_ZERO) : PRE_LOAD, G.dL64);
+      int mode = zs && found->arg == POST_MIXED ? POST_MIXED_KEEP : found->arg;
+      if (c + 1 < inner) mode = POST_PLAIN;
       return launch_post<float>(G.dL32 + l, G.dL32 + l + 1, G.gpost[l], h->opts.nu_post, h->ncol,
                                 (float)relax(h), mode, G.dL64, kind, h->oned, l == 0, 1, st, false);
     }
@@ -2490,9 +2498,9 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
     return launch_post<double>(G.dL64 + l, G.dL64 + l + 1, G.gpost[l], h->opts.nu_post, h->ncol, relax(h),
                                found->arg, G.dL64, kind, h->oned, l == 0, 1, st, false);
   };
-  HIPCHK(h, launch());
+  HIPCHK(h, launch(inner - 1));
   HIPCHK(h, hipEventRecord(h->ev0, st));
-  for (int r = 0; r < reps; ++r) HIPCHK(h, launch());
+  for (int r = 0; r < reps; ++r) HIPCHK(h, launch(r));
   HIPCHK(h, hipEventRecord(h->ev1, st));
   HIPCHK(h, hipEventSynchronize(h->ev1));
   float ms = 0.f;
