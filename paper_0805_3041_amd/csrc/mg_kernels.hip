@@ -847,12 +847,12 @@ __device__ __forceinline__ void row_offsets(int j, int nx, int ny, int py, int& 
 // column only are read once.
 //
 // Column i, first row j and row stride of thread `tid` for colour c.
-template <typename T>
+template <typename T, int NTH = SUB_NT>
 __device__ __forceinline__ void colour_plan(const Level<T>& L, int c, int ncol, int tid, int& i, int& j, int& jstep) {
   const int lo = L.py ? 0 : 1;
   const int kl = ceil_log2((L.nx - 1) >> 1);
   const int k = tid & ((1 << kl) - 1);
-  const int rg = SUB_NT >> kl;  // even: kl <= 9 for every LDS level
+  const int rg = NTH >> kl;  // even: kl <= 9 for every LDS level (kl <= 5 with one wave)
   int first;
   if (ncol == 4) {
     j = lo + (((lo & 1) != (c >> 1)) ? 1 : 0) + 2 * (tid >> kl);
@@ -1037,7 +1037,26 @@ __device__ void lds_smooth_n(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, 
 // at the bottom of the hierarchy): each thread's nodes, their row offsets
 // and right-hand sides (fixed while smoothing) are found once, so a colour
 // step is the gather, the update and the store.
-template <typename T, int K, bool B1, int NCOL, int M>
+//
+// SOLO: wavefront 0 alone owns every node (the plan over 64 threads; levels
+// whose colours have at most one row per lane), and its colour steps are
+// ordered by waiting for its own LDS writes instead of by workgroup
+// barriers (a wavefront's LDS operations complete in issue order; the wait
+// makes every store land before the next step's gathers issue).  The other
+// wavefronts do not enter: nothing in here may wait on them.
+template <bool SOLO>
+__device__ __forceinline__ void step_sync() {
+  if constexpr (SOLO) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // (keeps the compiler's order of LDS accesses)
+    __builtin_amdgcn_s_waitcnt(0xc07f);                       // lgkmcnt(0): this wave's LDS stores have landed
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <typename T, int K, bool B1, int NCOL, int M, bool SOLO = false>
 __device__ void lds_smooth_few(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b, const MG_LDS T* bl, int nsw,
                                T omega, int tid, const Level<T>& C, const MG_LDS T* xc, int flags, T wl) {
   const int nx = L.nx, ny = L.ny, py = L.py;
@@ -1049,7 +1068,7 @@ __device__ void lds_smooth_few(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b
 #pragma unroll
   for (int c = 0; c < NCOL; ++c) {
     int j, jstep;
-    colour_plan(L, c, NCOL, tid, ic[c], j, jstep);
+    colour_plan<T, SOLO ? 64 : SUB_NT>(L, c, NCOL, tid, ic[c], j, jstep);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       const int jm = j + m * jstep;
@@ -1091,7 +1110,7 @@ __device__ void lds_smooth_few(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b
           }
           x[pos[c][m]] = add_correction(x[pos[c][m]], v, wtd, wl);
         }
-    __syncthreads();
+    step_sync<SOLO>();
   }
   for (int s = 0; s < nsw; ++s) {
 #pragma unroll
@@ -1108,9 +1127,10 @@ __device__ void lds_smooth_few(const Level<T>& L, MG_LDS T* x, const MG_LDS T* b
 #pragma unroll
       for (int m = 0; m < M; ++m)
         if (on[c][m]) x[pos[c][m]] = sor_v(gs_v<K>(L, a[m], v[m], bv[c][m]), x + pos[c][m], omega);
-      if (s + 1 < nsw || c + 1 < NCOL) __syncthreads();
+      if (s + 1 < nsw || c + 1 < NCOL) step_sync<SOLO>();
     }
   }
+  if constexpr (SOLO) step_sync<true>();
 }
 
 // Rows per thread of one colour: at most ceil(rows / row stride); the
@@ -1127,7 +1147,11 @@ __device__ __forceinline__ void lds_smooth_c(const Level<T>& L, MG_LDS T* x, con
   const int rstride = (NCOL == 4 ? 2 : 1) * (SUB_NT >> kl);
   const int rows = L.py ? L.ny : L.ny - 2;
   const int m = (rows + rstride - 1) / rstride;
-  if (m <= 1) {
+  // one row per lane of wavefront 0 for every colour: that wave alone
+  const bool solo = kl <= 5 && rows <= (NCOL == 4 ? 2 : 1) * (64 >> kl);
+  if (solo) {
+    if (tid < 64) lds_smooth_few<T, K, B1, NCOL, 1, true>(L, x, b, bl, nsw, omega, tid, C, xc, flags, wl);
+  } else if (m <= 1) {
     lds_smooth_few<T, K, B1, NCOL, 1>(L, x, b, bl, nsw, omega, tid, C, xc, flags, wl);
   } else if (NCOL == 2 && m <= 2) {  // (two rows of four colours would spill registers)
     lds_smooth_few<T, K, B1, NCOL, 2>(L, x, b, bl, nsw, omega, tid, C, xc, flags, wl);
