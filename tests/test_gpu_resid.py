@@ -137,3 +137,28 @@ def test_batched_slots_form_their_residual():
         cycles.add(info.cycles)
         assert torch.equal(x, xb[k]), k
     assert len(cycles) > 1
+
+
+def test_in_pass_residual_with_three_inner_cycles():
+    """Three FP32 cycles per outer step (the first pre-pass of a step forms
+    the residual, the two later ones read e): iterates equal the residual
+    kernel's path bit for bit, capped and to tolerance."""
+    mg = _mg()
+    p = Problem(257, 256, periodic_y=True, q1="annulus", smoother="gs4c")
+    rhs = torch.tensor(p.rhs(51), device="cuda")
+    x0 = torch.zeros_like(rhs)
+    a = p.solver(precision="mixed", tile_mode="wide", tile_y=16, inner_cycles=3)
+    h = a.pass_info(0, 0)["halo"]
+    b = p.solver(precision="mixed", tile_mode="wide", tile_y=RESID_ROWS_MAX + 2 - 2 * h, inner_cycles=3)
+    try:
+        assert a.pass_info(0, 0)["forms_residual"] == 1 and b.pass_info(0, 0)["forms_residual"] == 0
+        for tol, cap in ((1e-10, 100), (1e-300, 2)):
+            ia, xa = _solve(a, rhs, x0, tol, cap)
+            ib, xb = _solve(b, rhs, x0, tol, cap)
+            assert ia.status == ib.status and ia.cycles == ib.cycles, (ia, ib)
+            assert ia.status == (mg.MG_OK if tol == 1e-10 else mg.MG_NOT_CONVERGED)
+            assert np.array_equal(xa, xb)
+            np.testing.assert_allclose(ia.history, ib.history, rtol=1e-13, atol=0)
+    finally:
+        a.close()
+        b.close()
