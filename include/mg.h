@@ -276,14 +276,16 @@ mg_status mg_profile_pass(mg_handle h, const double* rhs, double* x, int32_t lev
                           double* avg_us);
 
 /* Measurement helper: the launch shape of the fused pre-pass (which = 0) or
- * post-pass (which = 1) of `level`, written to the host array out[9]:
+ * post-pass (which = 1) of `level`, written to the host array out[10]:
  * out[0] wide tiles (1) or small tiles (0), out[1] TX, out[2] TY, out[3]
- * halo H, out[4] workgroups per problem, out[5] colours per smoothing step
- * (0 Jacobi, 2, 4), out[6] stencil (0 5-point, 1 9-point), out[7] 1 if the
- * 9-point bands vary along x only, out[8] 1 if the pass forms the FP64
- * residual b - A x itself (the mixed form's first finest pre-pass of an
- * outer step; no separate residual kernel then runs).  Same errors as
- * mg_profile_pass; no device work. */
+ * halo H (columns), out[4] workgroups per problem, out[5] colours per
+ * smoothing step (0 Jacobi, 2, 4), out[6] stencil (0 5-point, 1 9-point),
+ * out[7] 1 if the 9-point bands vary along x only, out[8] 1 if the pass
+ * forms the FP64 residual b - A x itself (the mixed form's first finest
+ * pre-pass of an outer step; no separate residual kernel then runs), out[9]
+ * the row halo (smaller than H on wide tiles with four colours: a tile's
+ * region is TY + 2 out[9] rows).  Same errors as mg_profile_pass; no device
+ * work. */
 mg_status mg_pass_info(mg_handle h, int32_t level, int32_t which, int32_t* out);
 
 /* Batched: nprob independent 5-point problems (MG_COEF_CONST5 only) with

@@ -350,6 +350,17 @@ double relax(mg_handle h) {
 // for the defect and its restriction (pre) or 1 for the residual (post).
 int sweeps(mg_handle h, int steps) { return h->ncol == 0 ? steps : steps * h->ncol; }
 
+// Row halo of a wide-tile pass whose column halo is H: with four colours the
+// stale rows advance one per two colour steps (wrow_shrink in
+// mg_fused.hip), so the sweeps need half their steps in rows; the rest of H
+// (defect and restriction rows of a pre-pass, the residual's ring of a
+// post-pass) carries over.  Other smoothers: H.
+int row_halo(mg_handle h, int H, bool post) {
+  if (h->ncol != 4) return H;
+  const int steps = sweeps(h, post ? h->opts.nu_post : h->opts.nu_pre);
+  return (steps + 1) / 2 + (H - steps);
+}
+
 TileGeom choose_tile_for(mg_handle h, const LevelShape& s, int ns, int H, bool post) {
   const long CHIP_CUS = h->ncus;  // workgroups that fill the chip once
   const size_t elem = h->mixed() ? sizeof(float) : sizeof(double);
@@ -370,9 +381,9 @@ TileGeom choose_tile_for(mg_handle h, const LevelShape& s, int ns, int H, bool p
   // that two workgroups share a CU
   const int mode = h->opts.tile_mode;
   if (mode != MG_TILES_NARROW && h->opts.tile_x == 0 && H <= 24) {
-    const int WW = wide_width(), TXw = WW - 2 * H;
+    const int WW = wide_width(), TXw = WW - 2 * H, Hy = row_halo(h, H, post);
     auto wbytes = [&](int ty) {
-      const size_t R = ty + 2 * H;
+      const size_t R = ty + 2 * Hy;
       size_t n = R * narr * WW + NBANDS * WW;
       if (post) n += (size_t)(WW / 2 + 2) * ((R >> 1) + 2);
       return n * elem;
@@ -393,11 +404,11 @@ TileGeom choose_tile_for(mg_handle h, const LevelShape& s, int ns, int H, bool p
     if (h->opts.tile_y == 0 && !force) {
       const long nt = ntiles(TXw, TYw);
       if (nt > CHIP_CUS && nt <= 2 * CHIP_CUS)
-        for (int ty = TYw + 2; 4 * (ty + 2 * H) <= 5 * (TYw + 2 * H) && wbytes(ty) <= FUSED_LDS_MAX; ty += 2)
-          if (ntiles(TXw, ty) <= CHIP_CUS) return wide_geom(s.nx, s.ny, ty, H);
+        for (int ty = TYw + 2; 4 * (ty + 2 * Hy) <= 5 * (TYw + 2 * Hy) && wbytes(ty) <= FUSED_LDS_MAX; ty += 2)
+          if (ntiles(TXw, ty) <= CHIP_CUS) return wide_geom(s.nx, s.ny, ty, H, Hy);
     }
     if ((force || ntiles(TXw, TYw) >= CHIP_CUS) && wbytes(TYw) <= FUSED_LDS_MAX)
-      return wide_geom(s.nx, s.ny, TYw, H);
+      return wide_geom(s.nx, s.ny, TYw, H, Hy);
   }
   if (!fixed) {
     while (ntiles(TX, TY) < CHIP_CUS && TY > 8) TY >>= 1;
@@ -1601,10 +1612,10 @@ std::string geom_str(const TileGeom& g) {
   return std::to_string(g.wide) + "," + std::to_string(g.TX) + "," + std::to_string(g.TY);
 }
 
-bool geom_parse(const std::string& v, const LevelShape& s, int H, TileGeom& g) {
+bool geom_parse(const std::string& v, const LevelShape& s, int H, int Hy, TileGeom& g) {
   int w = 0, tx = 0, ty = 0;
   if (std::sscanf(v.c_str(), "%d,%d,%d", &w, &tx, &ty) != 3 || tx < 2 || ty < 2) return false;
-  g = w ? wide_geom(s.nx, s.ny, ty, H) : tile_geom(s.nx, s.ny, tx, ty, H);
+  g = w ? wide_geom(s.nx, s.ny, ty, H, Hy) : tile_geom(s.nx, s.ny, tx, ty, H);
   return !w || g.TX == tx;
 }
 
@@ -1640,7 +1651,7 @@ std::vector<TileGeom> tile_candidates(mg_handle h, const LevelShape& s, int ns, 
   out.push_back(choose_tile_for(h, s, ns, H, post));  // the fixed rule first
   if (2 * H < wide_width())
     for (int ty = 8; ty <= 128; ty += (ty < 64 ? 8 : 16)) {
-      const TileGeom g = wide_geom(s.nx, s.ny, ty, H);
+      const TileGeom g = wide_geom(s.nx, s.ny, ty, H, row_halo(h, H, post));
       if (lds(g) <= FUSED_LDS_MAX && (long)g.ntx * g.nty * ns <= 64L * h->ncus) out.push_back(g);
     }
   for (int tx : {16, 32, 64, 128})
@@ -1704,7 +1715,7 @@ mg_status tune_tiles(mg_handle h, Group& G) {
     const std::string key = pass_key(h, G, op, H);
     TileGeom g{};
     const std::string v = refresh ? std::string() : tune_lookup(key);
-    if (!v.empty() && geom_parse(v, G.shp[op.level], H, g)) {
+    if (!v.empty() && geom_parse(v, G.shp[op.level], H, row_halo(h, H, post), g)) {
       slot = g;
       continue;
     }
@@ -1749,7 +1760,7 @@ mg_status tune_merge_tiles(mg_handle h, Merge& M) {
     const std::string key = k.str();
     TileGeom g{};
     const std::string v = refresh ? std::string() : tune_lookup(key);
-    if (!v.empty() && geom_parse(v, s, H, g)) {
+    if (!v.empty() && geom_parse(v, s, H, row_halo(h, H, post), g)) {
       op.g = g;
       continue;
     }
@@ -2443,6 +2454,7 @@ mg_status mg_pass_info(mg_handle h, int32_t level, int32_t which, int32_t* out) 
   out[6] = stencil_kind(h);
   out[7] = stencil_kind(h) == ST9 && h->oned ? 1 : 0;
   out[8] = level == 0 && which == 0 && resid_fused(h, G) ? 1 : 0;
+  out[9] = g.Hy;
   return MG_OK;
 }
 

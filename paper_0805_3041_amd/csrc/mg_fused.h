@@ -23,13 +23,14 @@ enum PreMode { PRE_LOAD = 0, PRE_ZERO = 1, PRE_RESID = 2, PRE_RESID_ONLY = 3 };
 
 // Output tile TX x TY (both even), halo H, and the tile grid of a level.
 // wide: the region is wide_width() columns (TX = wide_width() - 2 H) in the
-// parity-split LDS layout of the wide-tile kernels.
+// parity-split LDS layout of the wide-tile kernels, and TY + 2 Hy rows (the
+// row halo Hy is smaller than H with four colours; small tiles: Hy = H).
 struct TileGeom {
-  int TX, TY, H, ntx, nty, wide;
+  int TX, TY, H, ntx, nty, wide, Hy;
 };
 
 TileGeom tile_geom(int nx, int ny, int TX, int TY, int H);
-TileGeom wide_geom(int nx, int ny, int TY, int H);
+TileGeom wide_geom(int nx, int ny, int TY, int H, int Hy);
 int wide_width();
 
 template <typename T>

@@ -571,9 +571,9 @@ constexpr int wide_narr() {
 }
 
 struct WMap {
-  int i0, j0, H, nx, ny, py;
+  int i0, j0, H, Hy, nx, ny, py;  // column halo H, row halo Hy
   __device__ __forceinline__ int gi(int li) const { return i0 - H + li; }
-  __device__ __forceinline__ int gj(int lj) const { return j0 - H + lj; }
+  __device__ __forceinline__ int gj(int lj) const { return j0 - Hy + lj; }
   __device__ __forceinline__ bool col_ok(int li) const { return (unsigned)(gi(li) - 1) < (unsigned)(nx - 2); }
   __device__ __forceinline__ bool row_ok(int lj) const {
     return py ? true : (unsigned)(gj(lj) - 1) < (unsigned)(ny - 2);
@@ -672,7 +672,7 @@ __device__ void wcolour_rows(const Level<T>& L, const WMap& m, MG_LDS T* lds, co
   int lj = lj0 + rstep * wave_id();
   int end = hiR;
   if (!m.py) {  // rows of unknowns: 1 <= global row <= ny - 2
-    const int lo = 1 - m.j0 + m.H, hi = m.ny - 1 - m.j0 + m.H;
+    const int lo = 1 - m.j0 + m.Hy, hi = m.ny - 1 - m.j0 + m.Hy;
     if (lj < lo) lj += (lo - lj + step - 1) / step * step;
     end = min(end, hi);
   }
@@ -721,49 +721,51 @@ __device__ __forceinline__ WLanes<T> wlanes(const WMap& m, const MG_LDS T* bl) {
   return w;
 }
 
-// One Gauss-Seidel colour sweep over the region shrunk by s (colours as in
-// sweep_colour; i0, j0 are even, so local and global parities agree up to H).
+// One Gauss-Seidel colour sweep over the region shrunk by s columns and sr
+// rows (colours as in sweep_colour; i0, j0 are even, so local and global
+// parities agree up to H and Hy).
 template <typename T, int K, int NCOL, bool B1>
 __device__ void wsweep_colour(const Level<T>& L, const WMap& m, MG_LDS T* lds, const WLanes<T>& w, int R, int s,
-                              int c, T omega) {
+                              int sr, int c, T omega) {
   const int wave = wave_id(), lane = threadIdx.x & 63;
   int q, lj0, rstep;
   if constexpr (NCOL == 4) {
-    const int qr = ((c >> 1) + m.H) & 1;
-    lj0 = s + ((s ^ qr) & 1);
+    const int qr = ((c >> 1) + m.Hy) & 1;
+    lj0 = sr + ((sr ^ qr) & 1);
     rstep = 2;
     q = ((c & 1) + m.H) & 1;
   } else {
     // the wave's rows s + wave + NWAVE k share the parity of s + wave
-    lj0 = s;
+    // (two colours: rows and columns shrink alike, sr = s, Hy = H)
+    lj0 = sr;
     rstep = 1;
-    q = (c + s + wave) & 1;
+    q = (c + sr + wave) & 1;
   }
   const int li = q + 2 * lane;
   if (omega == (T)1) {
     if (q)
-      wcolour_rows<T, K, NCOL, B1, 1, false>(L, m, lds, w.col[1], R - s, lj0, rstep, lane,
+      wcolour_rows<T, K, NCOL, B1, 1, false>(L, m, lds, w.col[1], R - sr, lj0, rstep, lane,
                                              w.ok[1] && li >= s && li < WW - s, w.gi[1], omega);
     else
-      wcolour_rows<T, K, NCOL, B1, 0, false>(L, m, lds, w.col[0], R - s, lj0, rstep, lane,
+      wcolour_rows<T, K, NCOL, B1, 0, false>(L, m, lds, w.col[0], R - sr, lj0, rstep, lane,
                                              w.ok[0] && li >= s && li < WW - s, w.gi[0], omega);
   } else {
     if (q)
-      wcolour_rows<T, K, NCOL, B1, 1, true>(L, m, lds, w.col[1], R - s, lj0, rstep, lane,
+      wcolour_rows<T, K, NCOL, B1, 1, true>(L, m, lds, w.col[1], R - sr, lj0, rstep, lane,
                                             w.ok[1] && li >= s && li < WW - s, w.gi[1], omega);
     else
-      wcolour_rows<T, K, NCOL, B1, 0, true>(L, m, lds, w.col[0], R - s, lj0, rstep, lane,
+      wcolour_rows<T, K, NCOL, B1, 0, true>(L, m, lds, w.col[0], R - sr, lj0, rstep, lane,
                                             w.ok[0] && li >= s && li < WW - s, w.gi[0], omega);
   }
 }
 
-// Every node of the region shrunk by s, both column parities per lane and
-// row.  DST == 1: defect b - A src in place into b (0 at region nodes that
-// are not unknowns).  Otherwise damped Jacobi src -> dst.  Array indices:
-// 0 x, 1 b, 2 t.
+// Every node of the region shrunk by s columns and sr rows, both column
+// parities per lane and row.  DST == 1: defect b - A src in place into b (0
+// at region nodes that are not unknowns).  Otherwise damped Jacobi src ->
+// dst.  Array indices: 0 x, 1 b, 2 t.
 template <typename T, int K, int NCOL, bool B1, int SRC, int DST>
 __device__ void wsweep_region(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG_LDS T* bl, int R, int s,
-                              T omega) {
+                              int sr, T omega) {
   constexpr int P = wide_narr<NCOL>() * WW;
   const int lane = threadIdx.x & 63;
   const int li0 = 2 * (((s + 1) >> 1) + lane), li1 = 2 * ((s >> 1) + lane) + 1;
@@ -776,7 +778,7 @@ __device__ void wsweep_region(const Level<T>& L, const WMap& m, MG_LDS T* lds, c
     if (ok0) c0 = wcoef_cols<T, 0>(bl, A0);
     if (ok1) c1 = wcoef_cols<T, 1>(bl, A1);
   }
-  for (int lj = s + wave_id(); lj < R - s; lj += NWAVE) {
+  for (int lj = sr + wave_id(); lj < R - sr; lj += NWAVE) {
     MG_LDS T* row = lds + lj * P;
     if (!m.row_ok(lj)) {
       if constexpr (DST == 1) {
@@ -802,6 +804,18 @@ __device__ void wsweep_region(const Level<T>& L, const WMap& m, MG_LDS T* lds, c
   }
 }
 
+// Rows of the region that may be stale after s colour steps.  A colour step
+// leaves stale the nodes it updates next to stale ones.  With four colours
+// the column parity alternates from step to step, so stale columns advance
+// one per step, but the row parity changes every second step only, so stale
+// rows advance at most one per two steps: (s + 1) / 2 after s steps (the
+// row halo Hy is that many rows for the sweeps, plus the defect and
+// restriction rows).  Other smoothers: one per step in both directions.
+template <int NCOL>
+__device__ __forceinline__ int wrow_shrink(int s) {
+  return NCOL == 4 ? (s + 1) >> 1 : s;
+}
+
 // nsteps smoothing steps; returns the array index (0 x, 2 t) of the result.
 template <typename T, int K, int NCOL, bool B1>
 __device__ int wsmooth(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG_LDS T* bl, int R, int nsteps,
@@ -809,9 +823,9 @@ __device__ int wsmooth(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG
   if constexpr (NCOL == 0) {
     for (int k = 0; k < nsteps; ++k) {
       if (k & 1)
-        wsweep_region<T, K, NCOL, B1, 2, 0>(L, m, lds, bl, R, k + 1, omega);
+        wsweep_region<T, K, NCOL, B1, 2, 0>(L, m, lds, bl, R, k + 1, k + 1, omega);
       else
-        wsweep_region<T, K, NCOL, B1, 0, 2>(L, m, lds, bl, R, k + 1, omega);
+        wsweep_region<T, K, NCOL, B1, 0, 2>(L, m, lds, bl, R, k + 1, k + 1, omega);
       __syncthreads();
     }
     return (nsteps & 1) ? 2 : 0;
@@ -820,7 +834,7 @@ __device__ int wsmooth(const Level<T>& L, const WMap& m, MG_LDS T* lds, const MG
     int s = 1;
     for (int k = 0; k < nsteps; ++k)
       for (int c = 0; c < NCOL; ++c, ++s) {
-        wsweep_colour<T, K, NCOL, B1>(L, m, lds, w, R, s, c, omega);
+        wsweep_colour<T, K, NCOL, B1>(L, m, lds, w, R, s, wrow_shrink<NCOL>(s), c, omega);
         __syncthreads();
       }
     return 0;
@@ -933,7 +947,7 @@ __device__ bool wresid(const Level<T>& F, const Level<double>& X, const WMap& m,
     ra[u] = rb[u] = 0.f;
     if (!(lj >= 1 && lj <= R - 2 && m.row_ok(lj))) continue;
     const int gj = m.wrapj(m.gj(lj));
-    const bool orow = lj >= m.H && lj < m.H + TY && m.gj(lj) < F.ny;
+    const bool orow = lj >= m.Hy && lj < m.Hy + TY && m.gj(lj) < F.ny;
     auto defect = [&](int li, int gi, const Cf<double>& col, double bp) {
       const MG_LDS double* p = xs + (lj - 1) * PD + li;
       Nbr<double> v;
@@ -989,8 +1003,8 @@ __device__ bool wresid(const Level<T>& F, const Level<double>& X, const WMap& m,
 
 template <typename T, int K, bool FINE, int NCOL, bool B1>
 __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs,
-                                              int TY, int H, int ntx, int nty, int nsteps, T omega, int start,
-                                              const Level<double>* __restrict__ X64s) {
+                                              int TY, int H, int Hy, int ntx, int nty, int nsteps, T omega,
+                                              int start, const Level<double>* __restrict__ X64s) {
   constexpr int P = wide_narr<NCOL>() * WW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Level<T> F = Fs[blockIdx.z];
@@ -998,10 +1012,10 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
   const Level<T> C = Cs[blockIdx.z];
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
-  const int TX = WW - 2 * H, R = TY + 2 * H;
+  const int TX = WW - 2 * H, R = TY + 2 * Hy;
   MG_LDS T* lds = lds_cast<T>(smem_raw);
   MG_LDS T* bl = lds + R * P;
-  const WMap m{tx * TX, ty * TY, H, F.nx, F.ny, F.py};
+  const WMap m{tx * TX, ty * TY, H, Hy, F.nx, F.ny, F.py};
   const int wave = wave_id(), lane = threadIdx.x & 63;
   WBands<T> bands{};
   if constexpr (B1) bands = wfetch_bands(F, m);
@@ -1063,9 +1077,9 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
 
   const int xsrc = wsmooth<T, K, NCOL, B1>(F, m, lds, bl, R, nsteps, omega);
   if (xsrc == 0)
-    wsweep_region<T, K, NCOL, B1, 0, 1>(F, m, lds, bl, R, H - 1, omega);
+    wsweep_region<T, K, NCOL, B1, 0, 1>(F, m, lds, bl, R, H - 1, Hy - 1, omega);
   else
-    wsweep_region<T, K, NCOL, B1, 2, 1>(F, m, lds, bl, R, H - 1, omega);
+    wsweep_region<T, K, NCOL, B1, 2, 1>(F, m, lds, bl, R, H - 1, Hy - 1, omega);
   __syncthreads();
 
   // full weighting at the coarse nodes of the tile; zero coarse start
@@ -1078,7 +1092,7 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
     for (int rb = wave; rb < nrb; rb += NWAVE) {
       const int J = (m.j0 >> 1) + rb;
       if (!iok || J < lo || J > hi) continue;
-      const MG_LDS T* p = lds + WW + (H + 2 * rb - 1) * P + A;
+      const MG_LDS T* p = lds + WW + (Hy + 2 * rb - 1) * P + A;
       const Nbr<T> d = (H & 1) ? wgather<T, ST9, P, 1, true>(p) : wgather<T, ST9, P, 0, true>(p);
       const T g = fw_combine(fw_row(d.sw, d.s, d.se), fw_row(d.w, d.c, d.e), fw_row(d.nw, d.n, d.ne));
       const size_t q = (size_t)J * C.pitch + I;
@@ -1091,7 +1105,7 @@ __global__ void __launch_bounds__(FT) k_pre_w(const Level<T>* __restrict__ Fs, c
     const int la = H + lane, lb = H + lane + 64;
     const bool oka = m.col_ok(la), okb = lb < H + TX && m.col_ok(lb);
     const int ga = m.gi(la), gb = m.gi(lb);
-    for (int lj = H + wave; lj < H + TY; lj += NWAVE) {
+    for (int lj = Hy + wave; lj < Hy + TY; lj += NWAVE) {
       const int gj = m.gj(lj);
       if (!m.row_ok(lj) || gj >= F.ny) continue;
       const MG_LDS T* r = lds + lj * P + xsrc * WW;
@@ -1115,7 +1129,7 @@ __device__ double wnorm_part(const Level<T>& F, const WMap& m, const MG_LDS T* l
   if constexpr (K == ST9 && B1) col = wcoef_cols<T, Q>(bl, A);
   constexpr int own = Q ? WH : 0;
   double acc = 0.0;
-  for (int lj = H + wave; lj < H + TY; lj += NWAVE) {
+  for (int lj = m.Hy + wave; lj < m.Hy + TY; lj += NWAVE) {
     if (!m.row_ok(lj) || m.gj(lj) >= F.ny) continue;
     const Nbr<T> v = wgather<T, K, P, Q, true>(lds + xsrc * WW + (lj - 1) * P + A);
     const T d = defect_v<K>(F, wcoef<T, K, B1>(F, m, col, gi, lj), v, lds[lj * P + WW + own + A]);
@@ -1126,8 +1140,8 @@ __device__ double wnorm_part(const Level<T>& F, const WMap& m, const MG_LDS T* l
 
 template <typename T, int K, bool FINE, int NCOL, bool B1>
 __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, const Level<T>* __restrict__ Cs,
-                                               int TY, int H, int ntx, int nty, int nsteps, T omega, int mode,
-                                               const Level<double>* __restrict__ X64s) {
+                                               int TY, int H, int Hy, int ntx, int nty, int nsteps, T omega,
+                                               int mode, const Level<double>* __restrict__ X64s) {
   constexpr int P = wide_narr<NCOL>() * WW;
   constexpr int CW = WH + 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1140,12 +1154,12 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
   const T wv = wtd ? *F.wl : (T)1;
   int tx, ty;
   tile_coords(ntx, nty, tx, ty);
-  const int TX = WW - 2 * H, R = TY + 2 * H;
+  const int TX = WW - 2 * H, R = TY + 2 * Hy;
   const int CR = (R >> 1) + 2;
   MG_LDS T* lds = lds_cast<T>(smem_raw);
   MG_LDS T* ec = lds + R * P;
   MG_LDS T* bl = ec + CW * CR;
-  const WMap m{tx * TX, ty * TY, H, F.nx, F.ny, F.py};
+  const WMap m{tx * TX, ty * TY, H, Hy, F.nx, F.ny, F.py};
   const int wave = wave_id(), lane = threadIdx.x & 63;
   WBands<T> bands{};
   if constexpr (B1) bands = wfetch_bands(F, m);
@@ -1190,9 +1204,9 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
     const Level<double>& X = X64s[blockIdx.z];
 #pragma unroll
     for (int u = 0; u < UL; ++u) {
-      const int lj = H + wave + u * NWAVE, gj = m.gj(lj);
+      const int lj = Hy + wave + u * NWAVE, gj = m.gj(lj);
       pxa[u] = pxb[u] = 0.0;
-      if (lj < H + TY && m.row_ok(lj) && gj < F.ny) {
+      if (lj < Hy + TY && m.row_ok(lj) && gj < F.ny) {
         const double* xrow = X.x + (size_t)gj * X.pitch;
         if (ooka) pxa[u] = xrow[oga];
         if (ookb) pxb[u] = xrow[ogb];
@@ -1277,9 +1291,9 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
     const Level<double>& X = X64s[blockIdx.z];
     const bool zero_e = mode == POST_MIXED;
     if (blockIdx.x == 0 && threadIdx.x == 0) st->pending = 1;
-    for (int lj0 = H + wave; lj0 < H + TY; lj0 += NWAVE * UL) {
+    for (int lj0 = Hy + wave; lj0 < Hy + TY; lj0 += NWAVE * UL) {
       double xa[UL], xb[UL];
-      const bool first = lj0 == H + wave;  // loaded before the sweeps
+      const bool first = lj0 == Hy + wave;  // loaded before the sweeps
 #pragma unroll
       for (int u = 0; u < UL; ++u) {
         const int lj = lj0 + u * NWAVE, gj = m.gj(lj);
@@ -1287,7 +1301,7 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
         xb[u] = pxb[u];
         if (!first) {
           xa[u] = xb[u] = 0.0;
-          if (lj < H + TY && m.row_ok(lj) && gj < F.ny) {
+          if (lj < Hy + TY && m.row_ok(lj) && gj < F.ny) {
             const double* xrow = X.x + (size_t)gj * X.pitch;
             if (ooka) xa[u] = xrow[oga];
             if (ookb) xb[u] = xrow[ogb];
@@ -1297,7 +1311,7 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
 #pragma unroll
       for (int u = 0; u < UL; ++u) {
         const int lj = lj0 + u * NWAVE, gj = m.gj(lj);
-        if (!(lj < H + TY && m.row_ok(lj) && gj < F.ny)) continue;
+        if (!(lj < Hy + TY && m.row_ok(lj) && gj < F.ny)) continue;
         const MG_LDS T* r = lds + lj * P + xsrc * WW;
         double* xrow = X.x + (size_t)gj * X.pitch;
         T* row = F.x + (size_t)gj * F.pitch;
@@ -1312,7 +1326,7 @@ __global__ void __launch_bounds__(FT) k_post_w(const Level<T>* __restrict__ Fs, 
       }
     }
   } else {
-    for (int lj = H + wave; lj < H + TY; lj += NWAVE) {
+    for (int lj = Hy + wave; lj < Hy + TY; lj += NWAVE) {
       const int gj = m.gj(lj);
       if (!m.row_ok(lj) || gj >= F.ny) continue;
       const MG_LDS T* r = lds + lj * P + xsrc * WW;
@@ -1336,14 +1350,16 @@ TileGeom tile_geom(int nx, int ny, int TX, int TY, int H) {
   g.TX = TX;
   g.TY = TY;
   g.H = H;
+  g.Hy = H;
   g.ntx = (nx + TX - 1) / TX;
   g.nty = (ny + TY - 1) / TY;
   g.wide = 0;
   return g;
 }
 
-TileGeom wide_geom(int nx, int ny, int TY, int H) {
+TileGeom wide_geom(int nx, int ny, int TY, int H, int Hy) {
   TileGeom g = tile_geom(nx, ny, WW - 2 * H, TY, H);
+  g.Hy = Hy;
   g.wide = 1;
   return g;
 }
@@ -1353,7 +1369,7 @@ int wide_width() { return WW; }
 template <typename T>
 size_t pre_lds_bytes(const TileGeom& g, int ncol) {
   const size_t narr = ncol == 0 ? 3 : 2;
-  if (g.wide) return ((g.TY + 2 * g.H) * narr * WW + NBANDS * WW) * sizeof(T);
+  if (g.wide) return ((g.TY + 2 * g.Hy) * narr * WW + NBANDS * WW) * sizeof(T);
   const size_t W = g.TX + 2 * g.H, R = g.TY + 2 * g.H;
   return (W * R * narr + NBANDS * W) * sizeof(T);
 }
@@ -1362,7 +1378,7 @@ template <typename T>
 size_t post_lds_bytes(const TileGeom& g, int ncol) {
   const size_t narr = ncol == 0 ? 3 : 2;
   if (g.wide) {
-    const size_t R = g.TY + 2 * g.H;
+    const size_t R = g.TY + 2 * g.Hy;
     return (R * narr * WW + (WH + 2) * ((R >> 1) + 2) + NBANDS * WW) * sizeof(T);
   }
   const size_t W = g.TX + 2 * g.H, R = g.TY + 2 * g.H;
@@ -1379,9 +1395,11 @@ using PreFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int
 template <typename T>
 using PostFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, int, T, int, const Level<double>*);
 template <typename T>
-using PreWFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, T, int, const Level<double>*);
+using PreWFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, int, T, int,
+                        const Level<double>*);
 template <typename T>
-using PostWFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, T, int, const Level<double>*);
+using PostWFn = void (*)(const Level<T>*, const Level<T>*, int, int, int, int, int, int, T, int,
+                         const Level<double>*);
 
 // f(NCOL, B1) -> kernel for the valid (stencil, smoother, bands) triples.
 #define MG_VARIANT(K, ncol, b1, F)                                                        \
@@ -1471,7 +1489,7 @@ hipError_t prepare_fused() {
   return hipSuccess;
 }
 
-bool pre_resid_fits(const TileGeom& g) { return g.wide && g.TY + 2 * g.H <= RESID_ROWS * NWAVE; }
+bool pre_resid_fits(const TileGeom& g) { return g.wide && g.TY + 2 * g.Hy <= RESID_ROWS * NWAVE; }
 bool pre_resid_kind(int kind, bool oned) { return kind == ST5 || oned; }
 
 template <typename T>
@@ -1488,7 +1506,7 @@ hipError_t launch_pre(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g,
   if (g.wide) {
     PreWFn<T> k = pick_pre_w<T>(kind, oned, fine, ncol);
     if (!k || g.TX != WW - 2 * g.H) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TY, g.H, g.ntx, g.nty, nsteps, omega, mode, X64s);
+    hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TY, g.H, g.Hy, g.ntx, g.nty, nsteps, omega, mode, X64s);
   } else {
     PreFn<T> k = pick_pre<T>(kind, oned, fine, ncol);
     if (!k || mode != PRE_LOAD) return hipErrorInvalidValue;  // zero start: wide tiles only
@@ -1506,7 +1524,7 @@ hipError_t launch_post(const Level<T>* Fs, const Level<T>* Cs, const TileGeom& g
   if (g.wide) {
     PostWFn<T> k = pick_post_w<T>(kind, oned, fine, ncol);
     if (!k || g.TX != WW - 2 * g.H) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TY, g.H, g.ntx, g.nty, nsteps, omega, mode, X64s);
+    hipLaunchKernelGGL(k, grid, dim3(FT), lds, st, Fs, Cs, g.TY, g.H, g.Hy, g.ntx, g.nty, nsteps, omega, mode, X64s);
   } else {
     PostFn<T> k = pick_post<T>(kind, oned, fine, ncol);
     if (!k) return hipErrorInvalidValue;

@@ -243,12 +243,13 @@ def mg_profile_pass(h, rhs: torch.Tensor, x: torch.Tensor, level: int, which: in
     return us.value
 
 
-PASS_INFO_KEYS = ("wide", "tx", "ty", "halo", "workgroups", "colours", "stencil", "bands_1d", "forms_residual")
+PASS_INFO_KEYS = ("wide", "tx", "ty", "halo", "workgroups", "colours", "stencil", "bands_1d", "forms_residual",
+                  "halo_y")
 
 
 def mg_pass_info(h, level: int, which: int) -> dict:
     lib = load_library()
-    out = (ctypes.c_int32 * 9)()
+    out = (ctypes.c_int32 * 10)()
     s = lib.mg_pass_info(h, int(level), int(which), out)
     if s != MG_OK:
         raise MGError(s, last_error(h))

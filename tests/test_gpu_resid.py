@@ -19,7 +19,7 @@ from tests.problems import Problem
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-RESID_ROWS_MAX = 96  # region rows (TY + 2 H) the in-pass residual holds per tile
+RESID_ROWS_MAX = 96  # region rows (TY + 2 Hy) the in-pass residual holds per tile
 
 CASES = [
     # 9-point, bands constant along y (the annulus operator), four colours
@@ -41,11 +41,11 @@ def _pair(p, fit):
     residual, one whose pre-pass tile is too tall for it."""
     a = p.solver(precision="mixed", tile_mode="wide", tile_y=fit)
     ia = a.pass_info(0, 0)
-    tall = RESID_ROWS_MAX + 2 - 2 * ia["halo"]
+    tall = RESID_ROWS_MAX + 2 - 2 * ia["halo_y"]
     b = p.solver(precision="mixed", tile_mode="wide", tile_y=tall)
     ib = b.pass_info(0, 0)
-    assert ia["wide"] == 1 and ia["ty"] + 2 * ia["halo"] <= RESID_ROWS_MAX and ia["forms_residual"] == 1, ia
-    assert ib["wide"] == 1 and ib["ty"] + 2 * ib["halo"] > RESID_ROWS_MAX and ib["forms_residual"] == 0, ib
+    assert ia["wide"] == 1 and ia["ty"] + 2 * ia["halo_y"] <= RESID_ROWS_MAX and ia["forms_residual"] == 1, ia
+    assert ib["wide"] == 1 and ib["ty"] + 2 * ib["halo_y"] > RESID_ROWS_MAX and ib["forms_residual"] == 0, ib
     return a, b
 
 
@@ -148,7 +148,7 @@ def test_in_pass_residual_with_three_inner_cycles():
     rhs = torch.tensor(p.rhs(51), device="cuda")
     x0 = torch.zeros_like(rhs)
     a = p.solver(precision="mixed", tile_mode="wide", tile_y=16, inner_cycles=3)
-    h = a.pass_info(0, 0)["halo"]
+    h = a.pass_info(0, 0)["halo_y"]
     b = p.solver(precision="mixed", tile_mode="wide", tile_y=RESID_ROWS_MAX + 2 - 2 * h, inner_cycles=3)
     try:
         assert a.pass_info(0, 0)["forms_residual"] == 1 and b.pass_info(0, 0)["forms_residual"] == 0
