@@ -549,7 +549,8 @@ __global__ void __launch_bounds__(FT) k_post(const Level<T>* __restrict__ Fs, co
 // ------------------------------------------------------------------ wide tiles
 //
 // Variant for large levels.  The region is WW = 128 columns wide (output
-// width TX = WW - 2H) and each LDS row holds the arrays side by side, every
+// width TX = WW - 2H) and TY + 2Hy rows tall (row halo Hy: see
+// wrow_shrink), and each LDS row holds the arrays side by side, every
 // array split by column parity:
 //   [x even | x odd | b even | b odd (| t even | t odd)],  WH = 64 per half.
 // A colour sweep updates one column parity, so lane l owns the column of
