@@ -647,3 +647,39 @@ def test_galerkin_coarse_levels_of_5point_problems(case, cta):
     p = Problem(coarse_op="galerkin", **case)
     check_parity(p, W.normal_field(p.nx, p.ny, 3, p.periodic_y), np.zeros((p.ny, p.nx)), 3,
                  coarse_cta_nodes=300 if cta else 0)
+
+
+ROW_HALO_CASES = [
+    # (problem, nu_pre/nu_post): four colours take a row halo of half their
+    # colour steps (+ 2 rows for the pre-pass's defect and restriction)
+    dict(p=dict(nx=129, ny=129, eps=0.3, smoother="gs4c")),
+    dict(p=dict(nx=129, ny=128, periodic_y=True, q1="annulus", smoother="gs4c")),
+    dict(p=dict(nx=129, ny=129, eps=1.0, smoother="gs4c", nu_pre=1, nu_post=3)),
+    dict(p=dict(nx=97, ny=97, q1="grf", smoother="gs4c", sor=1.2)),
+]
+
+
+@pytest.mark.parametrize("ty", [2, 4, 6, 10, 16])
+@pytest.mark.parametrize("case", ROW_HALO_CASES, ids=[str(i) for i in range(len(ROW_HALO_CASES))])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_four_colour_row_halo_is_bitwise_invisible(case, ty, precision):
+    """Wide tiles with four colours sweep TY + 2 Hy rows, Hy about half the
+    column halo: from tiles of two output rows (every row of the region in
+    the halo) to sixteen, two cycles give the per-op kernels' iterates bit
+    for bit (the mixed form's FP32 cycles included)."""
+    p = Problem(**case["p"])
+    rhs = W.normal_field(p.nx, p.ny, 61, p.periodic_y)
+    x0 = W.uniform_field(p.nx, p.ny, 62, p.periodic_y)
+    a = p.solver(precision=precision, coarse_cta_nodes=300, tile_mode="per_op")
+    b = p.solver(precision=precision, coarse_cta_nodes=300, tile_mode="wide", tile_y=ty)
+    try:
+        info = b.pass_info(0, 0)
+        nu = p.nu_pre
+        assert info["wide"] == 1 and info["halo"] == 4 * nu + 2 and info["halo_y"] == 2 * nu + 2, info
+        xa = gpu_iterates(a, rhs, x0, 2)
+        xb = gpu_iterates(b, rhs, x0, 2)
+    finally:
+        a.close()
+        b.close()
+    for u, v in zip(xa, xb):
+        assert np.array_equal(u, v)
